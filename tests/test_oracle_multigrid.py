@@ -1,0 +1,237 @@
+"""Pins of the oracle's multigrid (paper section 3.4: damped Jacobi, full weighting,
+trilinear interpolation, rediscretised coarse operators; Algorithm 1 applied
+recursively as a V-cycle)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.discretization import DIRICHLET, SOMMERFELD, Level, boundary_directions, unknown_mask
+from oracle.multigrid import build_hierarchy, coarsen_shape, level_shapes, vcycle
+
+from test_oracle_operator import sine_eigenvalue, sine_mode
+
+
+def coords(shape, h):
+    z, y, x = np.meshgrid(*[np.arange(m) * h for m in shape], indexing="ij")
+    return z, y, x
+
+
+@pytest.mark.parametrize("mode", [(1, 1, 1), (2, 3, 1), (5, 5, 6)])
+def test_jacobi_sine_mode_amplification(mode):
+    """Closed form: one damped-Jacobi step with b = 0 multiplies phi by
+    1 - omega (lambda - (1 + 0.5i) k^2) / (6/h^2 - (1 + 0.5i) k^2)."""
+    n, k, w = 17, 6.0, 0.8
+    h = 1.0 / (n - 1)
+    lvl = Level((n, n, n), h, np.full((n, n, n), k), DIRICHLET)
+    phi = sine_mode(n, *mode).astype(np.complex128)
+    d = O.diag_M(lvl)
+    u = O.jacobi_sweep(phi, np.zeros_like(phi), lvl, w / d)
+    sig = (1 + 0.5j) * k * k
+    g = 1 - w * (sine_eigenvalue(h, *mode) - sig) / (6 / h**2 - sig)
+    assert np.abs(u - g * phi).max() <= 1e-13 * np.abs(phi).max()
+
+
+def test_jacobi_fixed_point():
+    shape = (9, 9, 9)
+    rng = np.random.default_rng(0)
+    lvl = Level(shape, 0.1, rng.uniform(1, 4, shape), SOMMERFELD)
+    u = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    b = O.apply_M(u, lvl)
+    u2 = O.jacobi_sweep(u, b, lvl, 0.8 / O.diag_M(lvl))
+    assert np.abs(u2 - u).max() <= 1e-13 * np.abs(u).max()
+
+
+def test_restriction_preserves_constants_everywhere_and_linears_inside():
+    fine = (9, 13, 17)
+    h = 0.1
+    z, y, x = coords(fine, h)
+    c = np.full(fine, 2.5 - 1.0j)
+    assert np.abs(O.restrict_fw(c, SOMMERFELD) - (2.5 - 1.0j)).max() <= 1e-14
+    lin = 1.0 + 2.0 * x - 3.0 * y + 0.5 * z
+    zc, yc, xc = coords(coarsen_shape(fine), 2 * h)
+    r = O.restrict_fw(lin, SOMMERFELD)
+    expect = 1.0 + 2.0 * xc - 3.0 * yc + 0.5 * zc
+    assert np.abs(r - expect)[1:-1, 1:-1, 1:-1].max() <= 1e-13
+
+
+def test_restriction_of_quadratic():
+    """FW(x^2) = x^2 + h^2/2 per axis at interior coarse nodes."""
+    fine = (9, 9, 9)
+    h = 0.25
+    z, y, x = coords(fine, h)
+    zc, yc, xc = coords(coarsen_shape(fine), 2 * h)
+    r = O.restrict_fw(x**2 + y**2 + z**2, SOMMERFELD)
+    expect = xc**2 + yc**2 + zc**2 + 3 * h**2 / 2
+    assert np.abs(r - expect)[1:-1, 1:-1, 1:-1].max() <= 1e-13
+
+
+def test_restriction_single_fine_delta_gives_full_weighting_stencil():
+    """The 27 weights of the full-weighting stencil (8/4/2/1 over 64)."""
+    fine = (9, 9, 9)
+    coarse = coarsen_shape(fine)
+    Rt = np.zeros((3, 3, 3))
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                r = np.zeros(fine)
+                r[4 + dz, 4 + dy, 4 + dx] = 1.0
+                Rt[dz + 1, dy + 1, dx + 1] = O.restrict_fw(r, DIRICHLET)[2, 2, 2]
+    w = np.array([1, 2, 1])
+    assert np.array_equal(Rt * 64, np.einsum("i,j,k->ijk", w, w, w))
+    assert coarse == (5, 5, 5)
+
+
+def test_prolongation_reproduces_trilinear_functions():
+    coarse = (4 + 1, 3, 6 + 1)
+    H = 0.2
+    zc, yc, xc = coords(coarse, H)
+    f = lambda z, y, x: (1 + 2 * x) * (3 - y) * (0.5 + z) + x * y * z
+    fine = tuple(2 * (m - 1) + 1 for m in coarse)
+    zf, yf, xf = coords(fine, H / 2)
+    p = O.prolong_trilinear(f(zc, yc, xc).astype(np.complex128), fine)
+    assert np.abs(p - f(zf, yf, xf)).max() <= 1e-14
+
+
+def test_prolongation_of_coarse_delta_is_the_interpolation_stencil():
+    coarse = (5, 5, 5)
+    e = np.zeros(coarse)
+    e[2, 2, 2] = 1.0
+    p = O.prolong_trilinear(e, (9, 9, 9))
+    w = np.array([0.5, 1.0, 0.5])
+    stencil = np.einsum("i,j,k->ijk", w, w, w)
+    assert np.array_equal(p[3:6, 3:6, 3:6], stencil)
+    assert np.count_nonzero(p) == 27
+
+
+def test_restriction_is_scaled_adjoint_of_prolongation():
+    """<R r, e> = 1/8 <r, P e> (Dirichlet, interior unknowns) and the same with
+    the D weights 2^(-n_j) on both grids at Sommerfeld boundaries (mirror
+    extension makes R = D_H^-1 (P^T / 8) D_h)."""
+    rng = np.random.default_rng(3)
+    fine = (9, 11, 13)
+    coarse = coarsen_shape(fine)
+    for bc in (DIRICHLET, SOMMERFELD):
+        r = rng.standard_normal(fine) * unknown_mask(fine, bc)
+        e = rng.standard_normal(coarse) * unknown_mask(coarse, bc)
+        Dh = 2.0 ** (-boundary_directions(fine)) if bc == SOMMERFELD else 1.0
+        DH = 2.0 ** (-boundary_directions(coarse)) if bc == SOMMERFELD else 1.0
+        Rr = O.restrict_fw(r, bc) * unknown_mask(coarse, bc)
+        lhs = np.sum(DH * Rr * e)
+        rhs = np.sum(Dh * r * O.prolong_trilinear(e, fine)) / 8.0
+        assert abs(lhs - rhs) <= 1e-13 * abs(rhs)
+
+
+def test_level_shapes():
+    assert level_shapes((33, 33, 33)) == [(33,) * 3, (17,) * 3, (9,) * 3, (5,) * 3, (3,) * 3]
+    assert level_shapes((257, 129, 129))[-1] == (5, 3, 3)
+    assert len(level_shapes((257, 129, 129))) == 7
+    assert len(level_shapes((513, 513, 513), n_levels=8)) == 8
+    assert level_shapes((513, 513, 513), n_levels=8)[-1] == (5, 5, 5)
+    # the paper's "stop at 17" rule reproduces its 17^3 and 41 x 41 x 13 grids (section 4.2, 5.1.2)
+    assert level_shapes((65, 65, 65), rule="paper17")[-1] == (17, 17, 17)
+    assert level_shapes((193, 641, 641), rule="paper17")[-1] == (13, 41, 41)
+    with pytest.raises(ValueError):
+        level_shapes((32, 33, 33))
+
+
+def _dense(fn, shape_in, mask_in, mask_out):
+    """Dense matrix of a linear map restricted to the unknowns."""
+    idx_in = np.flatnonzero(mask_in.ravel())
+    cols = []
+    for j in idx_in:
+        e = np.zeros(shape_in, dtype=np.complex128)
+        e.ravel()[j] = 1.0
+        cols.append(fn(e).ravel()[np.flatnonzero(mask_out.ravel())])
+    return np.array(cols).T
+
+
+@pytest.mark.parametrize("bc", [DIRICHLET, SOMMERFELD])
+def test_vcycle_equals_explicit_matrix_composition(bc):
+    """Two routes on a 9^3 grid (3 levels): the recursive matrix-free V(1,1) cycle
+    against the matrix V_l = W + (I - W M_l)(W + P V_{l+1} R (I - M_l W)),
+    W = omega D_l^-1, assembled from dense R, P, M_l, D_l and the exact coarse inverse."""
+    n = 9
+    rng = np.random.default_rng(4)
+    k = rng.uniform(3.0, 8.0, (n, n, n))
+    h = 1.0 / (n - 1)
+    hier = build_hierarchy(k, h, bc)
+    assert len(hier.levels) == 3
+    mats = {}
+    L = len(hier.levels)
+    lv = hier.levels[L - 1]
+    mc = unknown_mask(lv.shape, bc)
+    Mc = _dense(lambda x: O.apply_M(x, lv), lv.shape, mc, mc)
+    mats[L - 1] = np.linalg.inv(Mc)
+    for l in range(L - 2, -1, -1):
+        lv, lc = hier.levels[l], hier.levels[l + 1]
+        mf, mcm = unknown_mask(lv.shape, bc), unknown_mask(lc.shape, bc)
+        M = _dense(lambda x: O.apply_M(x, lv), lv.shape, mf, mf)
+        W = np.diag(0.8 / O.diag_M(lv)[mf])
+        R = _dense(lambda x: O.restrict_fw(x, bc), lv.shape, mf, mcm)
+        P = _dense(lambda x: O.prolong_trilinear(x, lv.shape), lc.shape, mcm, mf)
+        I = np.eye(M.shape[0])
+        mats[l] = W + (I - W @ M) @ (W + P @ mats[l + 1] @ R @ (I - M @ W))
+    mf = unknown_mask((n, n, n), bc)
+    b = (rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))) * mf
+    u = vcycle(b, hier)
+    u_dense = mats[0] @ b[mf]
+    assert np.abs(u[mf] - u_dense).max() <= 1e-12 * np.abs(u_dense).max()
+
+
+def test_vcycle_is_linear():
+    n = 17
+    rng = np.random.default_rng(5)
+    hier = build_hierarchy(rng.uniform(5, 12, (n, n, n)), 1 / 16, SOMMERFELD)
+    x = rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
+    y = rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
+    a, c = 0.3 - 1.2j, 2.0 + 0.5j
+    lhs = vcycle(a * x + c * y, hier)
+    rhs = a * vcycle(x, hier) + c * vcycle(y, hier)
+    assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+
+
+def test_vcycle_batched_equals_single():
+    n = 9
+    rng = np.random.default_rng(6)
+    hier = build_hierarchy(rng.uniform(5, 12, (n, n, n)), 1 / 8, SOMMERFELD)
+    b = rng.standard_normal((3, n, n, n)) + 1j * rng.standard_normal((3, n, n, n))
+    ub = vcycle(b, hier)
+    for r in range(3):
+        assert np.array_equal(ub[r], vcycle(b[r], hier))
+
+
+def _contraction(n, iters=12):
+    h = 1.0 / (n - 1)
+    k = np.zeros((n, n, n))
+    hier = build_hierarchy(k, h, DIRICHLET)
+    lvl = hier.levels[0]
+    mask = unknown_mask(lvl.shape, DIRICHLET)
+    rng = np.random.default_rng(7)
+    e = rng.standard_normal((n, n, n)) * mask + 0j
+    # stationary iteration e <- e - V(A e) on A u = 0 (k = 0: A = M = -Laplace_h)
+    norms = []
+    for _ in range(iters):
+        e = e - vcycle(O.apply_A(e, lvl), hier)
+        norms.append(np.linalg.norm(e))
+    return (norms[-1] / norms[-5]) ** 0.25
+
+
+def test_vcycle_contracts_mesh_independently_for_k0():
+    """k = 0 Dirichlet: u <- u + V(b - A u) converges with a factor that does not
+    grow with the grid (textbook multigrid property)."""
+    rhos = [_contraction(n) for n in (17, 33, 65)]
+    assert all(r < 0.6 for r in rhos), rhos
+    assert max(rhos) - min(rhos) < 0.05, rhos
+
+
+def test_vcycle_mixed_precision_close_to_double():
+    n = 33
+    rng = np.random.default_rng(8)
+    k = rng.uniform(5, 10, (n, n, n))
+    h64 = build_hierarchy(k, 1 / 32, SOMMERFELD)
+    h32 = build_hierarchy(k, 1 / 32, SOMMERFELD, dtype=np.complex64)
+    b = rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
+    u64 = vcycle(b, h64)
+    u32 = vcycle(b.astype(np.complex64), h32)
+    assert u32.dtype == np.complex64
+    assert np.linalg.norm(u32 - u64) <= 1e-5 * np.linalg.norm(u64)
