@@ -1,0 +1,245 @@
+"""Benchmark: DoF-iterations/s of CSLP-preconditioned Bi-CGSTAB on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload wedge|cube513|batched]
+
+One step = one complete solve to ||b - A x|| / ||b|| <= 1e-6 of the workload
+(model and sources resident in HBM before the timed region).  The default
+workload is the three-layer wedge, 129 x 129 x 257 nodes (4,276,737
+unknowns, h = 4.6875 m, f = 10 Hz, first-order Sommerfeld boundaries, one
+point source at the centre of the top face).  ``value`` is the mixed-precision
+solve (complex64 V-cycle inside complex128 Bi-CGSTAB); the plain complex128
+solve is timed the same way and reported under ``fp64``.
+
+DoF-iterations/s = unknowns x Bi-CGSTAB iterations (half step = 0.5, summed
+over right-hand sides) / solve time.
+
+``roofline`` reports the kernel with the largest share of an iteration,
+timed with HIP events on the solver's stream by ``hh_time_kernel`` (the same
+launch shape as inside the solve); ``achieved`` = its algorithmic bytes per
+launch / its average duration, against 8 TB/s HBM3E peak.
+``cpu_baseline`` times the CPU oracle on a bounded sample (a few Bi-CGSTAB
+steps of the same workload) on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "DoF-iterations/s of CSLP-Bi-CGSTAB, mixed vs FP64 at 1e-6 rel residual; %HBM"
+
+# Kernel ids of hh_time_kernel, launches per Bi-CGSTAB step and algorithmic
+# bytes per fine-grid node per right-hand side for (fp64, mixed) precision:
+# every array the kernel must read or write once (complex128 16 B, complex64
+# 8 B, real k^2 8 B, Jacobi factor W complex in the multigrid precision).
+KERNELS = {
+    0: ("apply_A+dots", 2, (16 + 8 + 16 + 16, 16 + 8 + 16 + 16)),
+    1: ("update_xr+dots", 1, (6 * 16 + 2 * 16, 6 * 16 + 2 * 16)),
+    2: ("mg_resid_L0", 2, (16 + 16 + 16, 16 + 8 + 8)),
+    3: ("mg_restrict_L0", 2, (16 + 2, 8 + 1)),
+    4: ("mg_correct_L0", 2, (16 + 16 + 2 + 16, 16 + 8 + 1 + 8)),
+    5: ("mg_smooth_L0", 2, (16 + 16 + 16 + 16, 8 + 16 + 8 + 16)),
+}
+
+# HBM traffic per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# (profiles/*_pmc.md), keyed by kernel name and workload; valid only for the
+# kernel source it was measured on (sha256 of hh_kernels.hip).
+TRAFFIC = {}
+
+
+def kernel_source_sha() -> str:
+    p = os.path.join(ROOT, "paper_2308_06085_amd", "csrc", "hh_kernels.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def make_workload(name):
+    import workloads as W
+
+    if name == "wedge":
+        wl = W.wedge(10.0)
+        return wl, wl.sources, "wedge 129x129x257 f=10Hz h=4.6875m Sommerfeld, 1 source"
+    if name == "cube513":
+        wl = W.big_cube()
+        return wl, wl.sources, "cube 513^3 k=160 kh=0.3125 Sommerfeld, 8 levels, 1 source"
+    if name == "batched":
+        wl = W.wedge(10.0)
+        src = W.batched_wedge_sources(16, seed=4)
+        return wl, src, "wedge 129x129x257 f=10Hz, 16 seeded top-face sources, one batched solve"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def dof(wl):
+    nz, ny, nx = wl.shape
+    if wl.bc == "sommerfeld":
+        return nz * ny * nx
+    return (nz - 2) * (ny - 2) * (nx - 2)
+
+
+def run_solves(solver, steps, warmup, rtol=1e-6):
+    import torch
+
+    x = None
+    for _ in range(warmup):
+        x, st = solver.solve(rtol=rtol, out=x)
+    torch.cuda.synchronize()
+    times, iters, stats = [], [], None
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        x, stats = solver.solve(rtol=rtol, out=x)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        iters.append(sum(s.iterations for s in stats))
+    return x, stats, times, iters
+
+
+def true_relres(wl, x, nodes):
+    """||b - A x|| / ||b|| per right-hand side with the oracle's operator (CPU)."""
+    import oracle as O
+    from oracle.discretization import Level
+
+    lvl = Level(wl.shape, wl.h, wl.k, wl.bc)
+    b = O.point_source_rhs(wl.shape, wl.h, nodes)
+    xs = x.cpu().numpy()
+    out = []
+    for r in range(len(nodes)):
+        out.append(float(np.linalg.norm(b[r] - O.apply_A(xs[r], lvl)) / np.linalg.norm(b[r])))
+    return out
+
+
+def kernel_roofline(solver, nrhs, prec_idx, n_nodes, reps=20):
+    rows = {}
+    for kid, (name, per_iter, nbytes) in KERNELS.items():
+        ms = solver.time_kernel(kid, nrhs=nrhs, reps=reps)
+        algo = nbytes[prec_idx] * n_nodes * nrhs
+        rows[name] = {"ms": ms, "per_iter": per_iter, "bytes": algo, "GBs": algo / (ms * 1e-3) / 1e9}
+    dom = max(rows, key=lambda k: rows[k]["ms"] * rows[k]["per_iter"])
+    return dom, rows
+
+
+def cpu_baseline(wl, nodes, n_iter):
+    import oracle as O
+    from oracle.discretization import Level
+    from oracle.multigrid import build_hierarchy, vcycle
+
+    lvl = Level(wl.shape, wl.h, wl.k, wl.bc)
+    hier = build_hierarchy(wl.k, wl.h, wl.bc, n_levels=wl.n_levels)
+    b = O.point_source_rhs(wl.shape, wl.h, nodes[:1])[0]
+    t0 = time.perf_counter()
+    O.bicgstab(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, fixed_iterations=n_iter)
+    dt = time.perf_counter() - t0
+    return {"value": dof(wl) * n_iter / dt, "unit": "DoF-iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_iter} complex128 Bi-CGSTAB steps of the same workload, one source, "
+                      f"NumPy/SciPy single thread on the host ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="wedge", choices=["wedge", "cube513", "batched"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 comparison solve")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the solver keeps the whole grid on one device "
+              "(multi-GPU sharding is not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2308_06085_amd import Solver
+
+    torch.cuda.set_device(0)
+    wl, nodes, desc = make_workload(args.workload)
+    nrhs = len(nodes)
+    n_nodes = int(np.prod(wl.shape))
+    k = torch.from_numpy(wl.k).cuda()
+
+    def make(prec):
+        s = Solver(wl.shape, wl.h, bc=wl.bc, prec=prec, n_levels=wl.n_levels, nrhs_max=nrhs)
+        s.set_model(k)
+        s.set_point_sources(nodes)
+        if args.autotune:
+            s.autotune(nrhs)
+        return s
+
+    log = (lambda *a: print(*a, file=sys.stderr, flush=True)) if args.verbose else (lambda *a: None)
+    results = {}
+    for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
+        s = make(prec)
+        x, stats, times, iters = run_solves(s, args.steps, args.warmup)
+        t = float(np.sum(times))
+        it = float(np.mean(iters))
+        rel = true_relres(wl, x, nodes) if args.workload != "cube513" else [s_.relres_true for s_ in stats]
+        dom, rows = kernel_roofline(s, nrhs, 0 if prec == "fp64" else 1, n_nodes)
+        results[prec] = {
+            "value": dof(wl) * float(np.sum(iters)) / t,
+            "ms_per_step": 1e3 * t / args.steps,
+            "iterations": it,
+            "matvecs": int(sum(st.matvecs for st in stats)),
+            "relres_true_max": max(rel),
+            "status": sorted({st.status for st in stats}),
+            "block": s.get_option("block"), "zb": s.get_option("zb"),
+            "dominant": dom, "kernels": rows,
+        }
+        log(prec, json.dumps(results[prec]))
+        s.close()
+        del x
+        torch.cuda.empty_cache()
+
+    head = results["mixed"]
+    dom = head["dominant"]
+    row = head["kernels"][dom]
+    traffic = None
+    key = (dom, args.workload, "mixed")
+    if key in TRAFFIC and TRAFFIC[key][2] == kernel_source_sha():
+        traffic = TRAFFIC[key][0] + TRAFFIC[key][1]
+    line = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "DoF-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 V-cycle / c128 Krylov",
+        "data": "synthetic",
+        "config": {"workload": desc, "unknowns": dof(wl), "nrhs": nrhs, "rtol": 1e-6,
+                   "precision": "mixed"},
+        "iterations": head["iterations"],
+        "relres_true_max": head["relres_true_max"],
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": row["GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": row["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": row["bytes"], "avg_ms": row["ms"]},
+        "kernels_mixed": {k_: {"ms": v["ms"], "GBs": round(v["GBs"], 1)} for k_, v in head["kernels"].items()},
+    }
+    if "fp64" in results:
+        f = results["fp64"]
+        line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "iterations": f["iterations"],
+                        "relres_true_max": f["relres_true_max"], "dominant": f["dominant"],
+                        "kernels": {k_: {"ms": v["ms"], "GBs": round(v["GBs"], 1)} for k_, v in f["kernels"].items()}}
+        line["mixed_speedup_time_to_solution"] = f["ms_per_step"] / head["ms_per_step"]
+    if not args.no_cpu and args.workload != "cube513":
+        line["cpu_baseline"] = cpu_baseline(wl, nodes, args.cpu_iters)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

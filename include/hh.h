@@ -1,0 +1,183 @@
+/*
+ * hh.h - C ABI of the MI355X (gfx950) matrix-free Helmholtz solver.
+ *
+ * Solves A u = b with A = -Laplace_h - k(x)^2 I, the second-order 7-point
+ * finite-difference Helmholtz operator on a vertex-centred grid with equal
+ * spacing h (Chen, Dwarka, Vuik, arXiv 2308.06085, section 2.4, eq. Helmstencil),
+ * with homogeneous Dirichlet or first-order Sommerfeld boundary conditions
+ * (section 2; Sommerfeld ghost points eliminated by eq. elimination), by
+ * right-preconditioned Bi-CGSTAB (section 3.1, 3.2) stopped at
+ * ||b - A u|| / ||b|| <= rtol (section 5).  The preconditioner is the complex
+ * shifted Laplacian M = -Laplace_h - (beta1 - beta2 i) k^2 I (section 3.3,
+ * eq. preconditioner) inverted approximately by one geometric multigrid
+ * V(1,1)-cycle: damped Jacobi (section 3.4.1), full-weighting restriction
+ * (section 3.4.2), trilinear interpolation (section 3.4.3), rediscretised
+ * coarse operators (section 3.4.4), recursive two-grid cycle (Algorithm 1),
+ * exact solve on the coarsest grid.  Everything is matrix-free (Algorithm 2).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - All array pointers are DEVICE pointers unless the name ends in _host.
+ * - Complex numbers are interleaved {re, im} doubles (complex128) unless
+ *   stated; real arrays are double.
+ * - Grid arrays are C-contiguous (nrhs, nz, ny, nx), x fastest, and include
+ *   the boundary nodes.  Node (iz, iy, ix) sits at (ix h, iy h, iz h).
+ * - Dirichlet: the unknowns are the interior nodes.  Boundary entries of every
+ *   input are ignored (read as 0) and are written as 0 in every output.
+ *   Non-homogeneous boundary data must be lifted into b by the caller.
+ * - Sommerfeld: every node is an unknown.
+ * - Ownership: the caller owns every pointer it passes; the library copies what
+ *   it keeps (model, sources) and never retains a caller pointer after a call
+ *   returns.  All scratch (Krylov vectors, grid hierarchy, coarse inverse,
+ *   graphs) is owned by the context and allocated in hh_create / hh_set_model;
+ *   hh_solve and the hh_apply_* calls allocate nothing.
+ * - Streams: all device work is enqueued on the stream given to hh_create.
+ *   hh_create, hh_set_model, hh_solve return after the work has completed;
+ *   hh_set_sources, hh_apply_*, hh_adjoint_rhs and hh_grad_slowness2 return
+ *   after enqueue (synchronise the stream before reading results on the host).
+ * - Errors: every call returns an hh_status; nothing throws or aborts across
+ *   the ABI.  hh_last_error(ctx) gives a text description of the last failure.
+ *   On HH_ERR_NOT_CONVERGED and HH_ERR_BREAKDOWN, x holds the last iterate and
+ *   the statistics are valid; after any other error outputs are unspecified.
+ * - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef HH_H
+#define HH_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hh_ctx hh_ctx; /* opaque, owned by the library */
+
+typedef enum {
+    HH_OK = 0,
+    HH_ERR_ARG = 1,           /* invalid argument or configuration */
+    HH_ERR_HIP = 2,           /* a HIP runtime call failed */
+    HH_ERR_OOM = 3,           /* device allocation failed */
+    HH_ERR_NUMERIC = 4,       /* NaN/Inf in the model, the RHS or a reduction */
+    HH_ERR_BREAKDOWN = 5,     /* Bi-CGSTAB breakdown (rho, r^H v or t^H t vanished) */
+    HH_ERR_NOT_CONVERGED = 6, /* maxit reached; x holds the last iterate */
+    HH_ERR_STATE = 7          /* call out of order (e.g. solve before set_model) */
+} hh_status;
+
+typedef enum { HH_BC_DIRICHLET = 0, HH_BC_SOMMERFELD = 1 } hh_bc;
+
+/* HH_PREC_MIXED: the V-cycle runs in complex64 with float32 coefficients; the
+ * Krylov vectors, inner products, residuals and the operator A stay complex128. */
+typedef enum { HH_PREC_FP64 = 0, HH_PREC_MIXED = 1 } hh_prec;
+
+typedef struct {
+    int nx, ny, nz;   /* nodes per axis incl. boundary; each odd and >= 3 */
+    double h;         /* grid spacing, > 0 */
+    int bc;           /* hh_bc */
+    double beta1;     /* CSLP: M = -Laplace - (beta1 - beta2 i) k^2 ; paper default 1 */
+    double beta2;     /* paper default -0.5 (section 3.3) */
+    double omega;     /* damped-Jacobi weight, paper value 0.8 (section 3.4.1) */
+    int n_levels;     /* multigrid levels incl. the finest; 0 = coarsen while the
+                         next grid keeps >= 3 nodes on every axis.  (n_d - 1) must
+                         be divisible by 2^(n_levels-1) on every axis. */
+    int prec;         /* hh_prec */
+    int nrhs_max;     /* 1..16 right-hand sides solved together */
+} hh_config;
+
+typedef struct {
+    double iterations;  /* Bi-CGSTAB steps; a half-step exit counts 0.5 */
+    int matvecs;        /* products with A, counting the initial residual (the
+                           convention of the paper's Table 1) */
+    double relres;      /* recursive residual norm / ||b|| at exit */
+    double relres_true; /* ||b - A x|| / ||b|| recomputed at exit */
+    int status;         /* hh_status of this right-hand side */
+    int restarts;       /* restarts after a true-residual check missed rtol */
+} hh_stats;
+
+/* Fill *cfg with the paper's defaults (beta1 = 1, beta2 = -0.5, omega = 0.8,
+ * Sommerfeld, FP64, n_levels = 0, nrhs_max = 1) for an nx x ny x nz grid. */
+void hh_default_config(hh_config* cfg, int nx, int ny, int nz, double h);
+
+/* Validate cfg, allocate every device buffer for up to nrhs_max right-hand sides
+ * (grid hierarchy, Krylov vectors, reductions) on the current HIP device, and
+ * bind the context to hip_stream (a hipStream_t; NULL = the default stream).
+ * HH_ERR_ARG for an invalid configuration, HH_ERR_OOM if allocation fails. */
+hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out);
+
+/* Free every resource of ctx.  ctx may be NULL. */
+hh_status hh_destroy(hh_ctx* ctx);
+
+/* Text of the last error on ctx (or of the last failed hh_create when ctx is NULL). */
+const char* hh_last_error(const hh_ctx* ctx);
+
+/* Number of levels and the node counts of level l (finest = 0). */
+hh_status hh_level_shape(const hh_ctx* ctx, int l, int* nx, int* ny, int* nz, int* n_levels);
+
+/* Set the real wavenumber k(x) >= 0 (section 2: k = 2 pi f / c), device array
+ * (nz, ny, nx) of doubles, copied.  Builds the hierarchy: coarse k by injection
+ * k_{l+1}(i) = k_l(2i), per-level Jacobi factors omega D^-1 of the
+ * rediscretised M, and the dense inverse of the coarsest M (host LU with
+ * partial pivoting).  HH_ERR_NUMERIC if k holds NaN/Inf or a negative value. */
+hh_status hh_set_model(hh_ctx* ctx, const double* k);
+
+/* Copy nrhs right-hand sides (nrhs, nz, ny, nx) complex128 into the context. */
+hh_status hh_set_sources(hh_ctx* ctx, const void* b, int nrhs);
+
+/* Right-hand sides of Dirac sources (section 2.4): b_r = 1/h^3 at node
+ * ijk_host[3r .. 3r+2] = (iz, iy, ix), 0 elsewhere.  HH_ERR_ARG if a node is
+ * outside the grid (or on the boundary for Dirichlet). */
+hh_status hh_set_point_sources(hh_ctx* ctx, const int* ijk_host, int nrhs);
+
+/* Solve A x_r = b_r for the right-hand sides of the last hh_set_*sources call.
+ * x: (nrhs, nz, ny, nx) complex128; read as the initial guess when use_x0 != 0,
+ * else x0 = 0; overwritten with the solution.  rtol > 0, maxit >= 1 (full
+ * Bi-CGSTAB steps).  stats_host: nrhs entries (may be NULL).  Returns HH_OK if
+ * every right-hand side converged, else the first failing status. */
+hh_status hh_solve(hh_ctx* ctx, void* x, double rtol, int maxit, int use_x0,
+                   hh_stats* stats_host);
+
+/* y = A x (complex128), nrhs vectors. */
+hh_status hh_apply_operator(hh_ctx* ctx, const void* x, void* y, int nrhs);
+
+/* y = M x on the finest grid (complex128 arithmetic). */
+hh_status hh_apply_shifted(hh_ctx* ctx, const void* x, void* y, int nrhs);
+
+/* z = V(r): one V(1,1)-cycle with zero initial guess approximating M^-1 r, in
+ * the context's precision (complex128 in and out in both precisions). */
+hh_status hh_apply_vcycle(hh_ctx* ctx, const void* r, void* z, int nrhs);
+
+/* Adjoint right-hand side rhs = D^-1 conj(g), D_j = 2^(-n_j) with n_j the number
+ * of grid faces node j lies on (Sommerfeld; D = I for Dirichlet).  With
+ * A^T = D A D^-1, the adjoint solve A^H lam = g becomes A w = D^-1 conj(g),
+ * conj(lam) = D w. */
+hh_status hh_adjoint_rhs(hh_ctx* ctx, const void* g, void* rhs, int nrhs);
+
+/* Gradient of a real misfit with respect to the squared slowness s (k = omega sqrt(s)):
+ * grad_j = -sum_r Re(D_j w_rj a'_j u_rj), a'_j = -omega^2 - i n_j omega / (h sqrt(s_j)).
+ * u: forward solutions, w: adjoint solutions (nrhs, nz, ny, nx) complex128;
+ * s, grad: (nz, ny, nx) double.  grad is overwritten. */
+hh_status hh_grad_slowness2(hh_ctx* ctx, const void* u, const void* w, const double* s,
+                            double omega, double* grad, int nrhs);
+
+/* Options: "graph" (1 = replay each Bi-CGSTAB step as a captured hipGraph,
+ * default 1), "check_every" (steps between host convergence checks, default 4),
+ * "block" (threads per workgroup of the fine-grid kernels: 64, 128, 256, 512),
+ * "zb" (z-planes per workgroup, 0 = automatic). */
+hh_status hh_set_option(hh_ctx* ctx, const char* name, long long value);
+hh_status hh_get_option(const hh_ctx* ctx, const char* name, long long* value);
+
+/* Measurement hook: launch one of the solver's fine-grid kernels `reps` times
+ * on the context stream, exactly as hh_solve launches it (same grid, same
+ * workgroup shape), on the context's scratch vectors, and return the average
+ * duration in milliseconds measured with HIP events on that stream.
+ * which: 0 = y = A x with fused partial dot products, 1 = the Krylov x/r update,
+ * 2 = fine-level smoother + residual, 3 = fine-level restriction,
+ * 4 = fine-level prolongation + correction, 5 = fine-level post-smoother.
+ * Requires hh_set_model.  Overwrites internal scratch only. */
+hh_status hh_time_kernel(hh_ctx* ctx, int which, int nrhs, int reps, float* ms_avg_host);
+
+/* Sweep workgroup shapes of the fine-grid kernels for the current grid and
+ * keep the fastest (by HIP-event timing on the context stream). */
+hh_status hh_autotune(hh_ctx* ctx, int nrhs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HH_H */

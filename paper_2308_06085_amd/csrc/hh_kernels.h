@@ -1,0 +1,75 @@
+// Host-callable launchers of the gfx950 kernels (internal to the library).
+#pragma once
+#include "hh_common.h"
+
+namespace hh {
+
+// Launch shape of the fine-grid kernels: `block` lanes over a flattened x-y
+// plane, `zb` z-planes per workgroup.  The flat (grid-stride) Krylov vector
+// kernels launch exactly `flat_cap` workgroups, set to the workgroup count of
+// the fine-grid kernels so every reduction slot holds the same number of
+// partial sums.
+struct Launch {
+    int block = 256;
+    int zb = 8;
+    int flat_cap = 2048;
+};
+
+enum OpMode : int { OP_PLAIN = 0, OP_V = 1, OP_T = 2 };
+enum FinMode : int { FIN_INIT = 0, FIN_RHO = 1, FIN_ALPHA = 2, FIN_S = 3, FIN_OMEGA = 4, FIN_TRUE = 5 };
+constexpr int GATE_ALL = -1;       // act on every right-hand side
+constexpr int GATE_FINISHED = -2;  // act on right-hand sides that stopped iterating
+
+long long nblk_of(const Geo& g, const Launch& L);
+
+void launch_apply(hipStream_t s, int bc, int mode, const Geo& g, const Launch& L, int nrhs,
+                  const c128* x, c128* y, const double* k2, const double* kb, double sr, double si,
+                  const c128* aux, double* part, long long nblk_max, const RhsState* st, int gate);
+void launch_init(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs, const c128* b,
+                 c128* x, c128* r, c128* rhat, c128* p, c128* v, const double* k2, const double* kb,
+                 int use_x0, double* part, long long nblk_max, const RhsState* st, int gate);
+
+template <typename TB, typename R>
+void launch_mg_resid(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs,
+                     const cx<TB>* b, long long b_rstride, const cx<R>* w, double omega, cx<R>* out,
+                     const RhsState* st, int gate);
+template <typename R>
+void launch_mg_restrict(hipStream_t s, int bc, const Geo& gf, const Geo& gc, const Launch& L,
+                        int nrhs, const cx<R>* rf, cx<R>* bc_out, const RhsState* st, int gate);
+template <typename TB, typename R>
+void launch_mg_correct(hipStream_t s, int bc, const Geo& g, const Geo& gc, const Launch& L, int nrhs,
+                       const cx<TB>* b, long long b_rstride, const cx<R>* w, const cx<R>* ec,
+                       cx<R>* u2, const RhsState* st, int gate);
+template <typename TB, typename R, typename TO>
+void launch_mg_smooth(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs,
+                      const cx<R>* u2, const cx<TB>* b, long long b_rstride, const cx<R>* w,
+                      double omega, cx<TO>* out, long long o_rstride, const RhsState* st, int gate);
+template <typename R>
+void launch_coarse(hipStream_t s, int nrhs, int n_nodes, int n_unk, const int* cidx,
+                   const cx<R>* minv, const cx<R>* b, cx<R>* e, const RhsState* st, int gate);
+
+void launch_p_update(hipStream_t s, long long n, int nrhs, c128* p, const c128* r, const c128* v,
+                     const RhsState* st, const Launch& L);
+void launch_s_update(hipStream_t s, long long n, int nrhs, c128* sv, const c128* r, const c128* v,
+                     const RhsState* st, double* part, long long nblk_max, const Launch& L);
+void launch_x_half(hipStream_t s, long long n, int nrhs, c128* x, const c128* ph,
+                   const RhsState* st, const Launch& L);
+void launch_update_xr(hipStream_t s, long long n, int nrhs, c128* x, c128* r, const c128* ph,
+                      const c128* sh, const c128* sv, const c128* t, const c128* rhat,
+                      const RhsState* st, double* part, long long nblk_max, const Launch& L);
+void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const double* part,
+                     long long nblk, long long nblk_max, double tol);
+
+void launch_model_check(hipStream_t s, long long n, const double* k, double* k2, double* kb, int* bad);
+void launch_inject(hipStream_t s, const Geo& gf, const Geo& gc, const double* kf, double* kc);
+template <typename R>
+void launch_make_w(hipStream_t s, const Geo& g, int bc, const double* k, double beta1, double beta2,
+                   double omega, cx<R>* w);
+void launch_copy_rhs(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* src, c128* dst);
+void launch_adjoint_rhs(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* gin, c128* out);
+void launch_grad_s(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* u, const c128* w,
+                   const double* sl, double omega, double* grad);
+void launch_set_point(hipStream_t s, long long off, double val, c128* b);
+void launch_fill_status(hipStream_t s, int n, RhsState* st, int status, int maxit2);
+
+}  // namespace hh

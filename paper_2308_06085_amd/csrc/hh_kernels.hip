@@ -1,0 +1,1075 @@
+// gfx950 kernels of the matrix-free CSLP / multigrid / Bi-CGSTAB Helmholtz solver.
+//
+// Launch shape of every fine-grid kernel: a workgroup owns `blockDim.x`
+// consecutive nodes of one x-y plane (the plane is flattened, so a row of
+// length nx never leaves lanes idle except in the last workgroup of a plane)
+// and marches along z over `zb` planes, keeping the z-1 / z / z+1 values of its
+// own column in registers; the four in-plane neighbours are read from the
+// caches.  gridDim = (plane blocks, z chunks, right-hand sides).
+//
+// The operator (paper section 2.4, eq. Helmstencil; Algorithm 2):
+//   (A x)_j = D_j x_j - (1/h^2) sum'_nb x_nb,
+//   D_j = 6/h^2 - sigma k_j^2 - n_j 2 i k_j / h,
+// where sum' replaces a neighbour outside the domain by its mirror image
+// (Sommerfeld ghost elimination, eq. elimination, applied independently per
+// axis) or by 0 (Dirichlet), n_j is the number of faces node j lies on
+// (Sommerfeld only) and sigma = 1 for A, beta1 - beta2 i for the CSLP M
+// (section 3.3).
+//
+// Damped Jacobi with zero initial guess (section 3.4.1), u1 = W b with
+// W = omega D^-1 (precomputed per level), and the residual then reads
+//   b - M u1 = (1 - omega) b + (1/h^2) sum'_nb (W b)_nb
+// because D_j W_j = omega; the post-smoother similarly reads
+//   u + W (b - M u) = (1 - omega) u + W_j (b_j + (1/h^2) sum'_nb u_nb).
+// No division is done in the multigrid kernels.
+#include "hh_common.h"
+#include "hh_kernels.h"
+
+namespace hh {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool gate_ok(const RhsState* st, int r, int gate) {
+    if (st == nullptr || gate == GATE_ALL) return true;
+    int s = st[r].status;
+    if (gate == GATE_FINISHED) return s != ST_RUN && s != ST_IDLE && s != ST_HALF;
+    return s == gate;
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> czero() { return cx<R>{R(0), R(0)}; }
+
+// Deterministic block reduction of NT doubles: butterfly within each 64-lane
+// wavefront, then wavefront partials summed by thread 0 in wave order.  The
+// result goes to out[t * stride] for t < NT.
+template <int NT>
+__device__ __forceinline__ void block_sum_store(double (&v)[NT], double* out, long long stride) {
+    __shared__ double sm[NT][16];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) v[t] += __shfl_xor(v[t], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) sm[t][wid] = v[t];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += sm[t][w];
+            out[t * stride] = s;
+        }
+    }
+}
+
+__device__ __forceinline__ long long part_index(int r, int slot, int term, long long nblk_max) {
+    return ((long long)(r * NSLOT + slot) * MAX_TERMS + term) * nblk_max;
+}
+
+struct Pos {
+    int i, j;        // x, y of this lane's column
+    bool valid;      // lane owns a node of the plane
+};
+
+__device__ __forceinline__ Pos plane_pos(int nx, int plane) {
+    Pos q;
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    q.valid = p < plane;
+    if (!q.valid) p = 0;
+    q.j = p / nx;
+    q.i = p - q.j * nx;
+    return q;
+}
+
+// Neighbour sum with the boundary rule of the level.  `ld(i, j)` returns the
+// value at in-plane position (i, j) of the current plane; zm / zp are the
+// column's values on the planes below / above (already mirrored or zeroed).
+template <int BC, typename R, typename LD>
+__device__ __forceinline__ cx<R> inplane_sum(const LD& ld, int i, int j, int nx, int ny) {
+    cx<R> s;
+    if (BC == BC_SOMMERFELD) {
+        int im = i > 0 ? i - 1 : 1;
+        int ip = i < nx - 1 ? i + 1 : nx - 2;
+        int jm = j > 0 ? j - 1 : 1;
+        int jp = j < ny - 1 ? j + 1 : ny - 2;
+        s = ld(im, j) + ld(ip, j);
+        s = s + ld(i, jm);
+        s = s + ld(i, jp);
+    } else {
+        s = czero<R>();
+        if (i > 1) s = s + ld(i - 1, j);
+        if (i < nx - 2) s = s + ld(i + 1, j);
+        if (j > 1) s = s + ld(i, j - 1);
+        if (j < ny - 2) s = s + ld(i, j + 1);
+    }
+    return s;
+}
+
+__device__ __forceinline__ int faces(int i, int j, int z, int nx, int ny, int nz) {
+    return (i == 0) + (i == nx - 1) + (j == 0) + (j == ny - 1) + (z == 0) + (z == nz - 1);
+}
+
+__device__ __forceinline__ bool on_boundary(int i, int j, int z, int nx, int ny, int nz) {
+    return i == 0 || j == 0 || z == 0 || i == nx - 1 || j == ny - 1 || z == nz - 1;
+}
+
+// ---------------------------------------------------------------------------
+// Operator apply, complex128.  MODE selects the fused epilogue:
+//   OP_PLAIN : y = Op x
+//   OP_V     : y = A x, partials Re/Im sum conj(rhat) y          (slot V)
+//   OP_T     : y = A x, partials Re/Im sum conj(y) s, sum |y|^2   (slot T)
+// ---------------------------------------------------------------------------
+template <int BC, int MODE>
+__global__ __launch_bounds__(512) void k_apply(Geo g, int zb, const c128* __restrict__ x,
+                                               c128* __restrict__ y, const double* __restrict__ k2,
+                                               const double* __restrict__ kb, double sr, double si,
+                                               const c128* __restrict__ aux, double* __restrict__ part,
+                                               long long nblk_max, const RhsState* st, int gate) {
+    const int r = blockIdx.z;
+    if (!gate_ok(st, r, gate)) return;
+    const Pos q = plane_pos(g.nx, g.plane);
+    const int z0 = blockIdx.y * zb;
+    const int z1 = min(g.nz, z0 + zb);
+    const double ih2 = 1.0 / (g.h * g.h);
+    const double two_over_h = 2.0 / g.h;
+    const long long roff = (long long)r * g.n;
+    const c128* xr = x + roff;
+    c128* yr = y + roff;
+    const long long col = (long long)q.j * g.nx + q.i;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (q.valid) {
+        auto ldz = [&](int z) -> c128 {
+            if (BC == BC_DIRICHLET && (z < 1 || z > g.nz - 2)) return czero<double>();
+            return xr[(long long)z * g.plane + col];
+        };
+        const bool bnd_col = BC == BC_DIRICHLET &&
+                             (q.i == 0 || q.j == 0 || q.i == g.nx - 1 || q.j == g.ny - 1);
+        c128 xm = z0 > 0 ? ldz(z0 - 1) : czero<double>();
+        c128 xc = ldz(z0);
+        for (int z = z0; z < z1; ++z) {
+            c128 xp = z + 1 < g.nz ? ldz(z + 1) : czero<double>();
+            const long long idx = (long long)z * g.plane + col;
+            c128 out;
+            if (BC == BC_DIRICHLET && (bnd_col || z == 0 || z == g.nz - 1)) {
+                out = czero<double>();
+            } else {
+                const c128* pl = xr + (long long)z * g.plane;
+                auto ld = [&](int ii, int jj) -> c128 { return pl[(long long)jj * g.nx + ii]; };
+                c128 s = inplane_sum<BC, double>(ld, q.i, q.j, g.nx, g.ny);
+                c128 zm = xm, zpv = xp;
+                if (BC == BC_SOMMERFELD) {
+                    if (z == 0) zm = xp;
+                    if (z == g.nz - 1) zpv = xm;
+                }
+                s = s + zm;
+                s = s + zpv;
+                const double kk = k2[idx];
+                c128 d = mk(6.0 * ih2 - sr * kk, -si * kk);
+                if (BC == BC_SOMMERFELD) {
+                    const int nf = faces(q.i, q.j, z, g.nx, g.ny, g.nz);
+                    if (nf) d.im -= nf * two_over_h * kb[idx];
+                }
+                out = d * xc - ih2 * s;
+            }
+            yr[idx] = out;
+            if (MODE == OP_V) {
+                c128 rh = aux[roff + idx];
+                c128 t = cdot(rh, out);
+                acc[0] += t.re;
+                acc[1] += t.im;
+            } else if (MODE == OP_T) {
+                c128 sv = aux[roff + idx];
+                c128 t = cdot(out, sv);
+                acc[0] += t.re;
+                acc[1] += t.im;
+                acc[2] += abs2(out);
+            }
+            xm = xc;
+            xc = xp;
+        }
+    }
+    if (MODE == OP_V || MODE == OP_T) {
+        const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+        const int slot = MODE == OP_V ? SLOT_V : SLOT_T;
+        if (MODE == OP_V) {
+            double v[2] = {acc[0], acc[1]};
+            block_sum_store<2>(v, part + part_index(r, slot, 0, nblk_max) + blk, nblk_max);
+        } else {
+            block_sum_store<3>(acc, part + part_index(r, slot, 0, nblk_max) + blk, nblk_max);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Start of a (re)start: r = b - A x (use_x0) or r = b (x := 0); r_hat = r;
+// p = v = 0; partials ||r||^2, Re/Im r_hat^H r (= ||r||^2, 0), ||b||^2 (slot R).
+// ---------------------------------------------------------------------------
+template <int BC>
+__global__ __launch_bounds__(512) void k_init(Geo g, int zb, const c128* __restrict__ b,
+                                              c128* __restrict__ x, c128* __restrict__ rr,
+                                              c128* __restrict__ rhat, c128* __restrict__ p,
+                                              c128* __restrict__ v, const double* __restrict__ k2,
+                                              const double* __restrict__ kb, int use_x0,
+                                              double* __restrict__ part, long long nblk_max,
+                                              const RhsState* st, int gate) {
+    const int r = blockIdx.z;
+    if (!gate_ok(st, r, gate)) return;
+    const Pos q = plane_pos(g.nx, g.plane);
+    const int z0 = blockIdx.y * zb;
+    const int z1 = min(g.nz, z0 + zb);
+    const double ih2 = 1.0 / (g.h * g.h);
+    const double two_over_h = 2.0 / g.h;
+    const long long roff = (long long)r * g.n;
+    const long long col = (long long)q.j * g.nx + q.i;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (q.valid) {
+        const c128* xr = x + roff;
+        auto ldz = [&](int z) -> c128 {
+            if (BC == BC_DIRICHLET && (z < 1 || z > g.nz - 2)) return czero<double>();
+            return xr[(long long)z * g.plane + col];
+        };
+        const bool bnd_col = BC == BC_DIRICHLET &&
+                             (q.i == 0 || q.j == 0 || q.i == g.nx - 1 || q.j == g.ny - 1);
+        c128 xm = czero<double>(), xc = czero<double>();
+        if (use_x0) {
+            xm = z0 > 0 ? ldz(z0 - 1) : czero<double>();
+            xc = ldz(z0);
+        }
+        for (int z = z0; z < z1; ++z) {
+            const long long idx = (long long)z * g.plane + col;
+            const bool bnd = BC == BC_DIRICHLET && (bnd_col || z == 0 || z == g.nz - 1);
+            c128 bv = bnd ? czero<double>() : b[roff + idx];
+            c128 res = bv;
+            c128 xp = czero<double>();
+            if (use_x0) {
+                xp = z + 1 < g.nz ? ldz(z + 1) : czero<double>();
+                if (!bnd) {
+                    const c128* pl = xr + (long long)z * g.plane;
+                    auto ld = [&](int ii, int jj) -> c128 { return pl[(long long)jj * g.nx + ii]; };
+                    c128 s = inplane_sum<BC, double>(ld, q.i, q.j, g.nx, g.ny);
+                    c128 zm = xm, zpv = xp;
+                    if (BC == BC_SOMMERFELD) {
+                        if (z == 0) zm = xp;
+                        if (z == g.nz - 1) zpv = xm;
+                    }
+                    s = s + zm;
+                    s = s + zpv;
+                    const double kk = k2[idx];
+                    c128 d = mk(6.0 * ih2 - kk, 0.0);
+                    if (BC == BC_SOMMERFELD) {
+                        const int nf = faces(q.i, q.j, z, g.nx, g.ny, g.nz);
+                        if (nf) d.im -= nf * two_over_h * kb[idx];
+                    }
+                    res = bv - (d * xc - ih2 * s);
+                }
+            } else {
+                x[roff + idx] = czero<double>();
+            }
+            rr[roff + idx] = res;
+            rhat[roff + idx] = res;
+            p[roff + idx] = czero<double>();
+            v[roff + idx] = czero<double>();
+            const double n2 = abs2(res);
+            acc[0] += n2;
+            acc[1] += n2;
+            acc[3] += abs2(bv);
+            xm = xc;
+            xc = xp;
+        }
+    }
+    const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    block_sum_store<4>(acc, part + part_index(r, SLOT_R, 0, nblk_max) + blk, nblk_max);
+}
+
+// ---------------------------------------------------------------------------
+// Multigrid, down pass of level l: r = b - M (W b) = (1 - omega) b + (1/h^2) sum'_nb (W b)_nb
+// (pre-smoothing from zero + residual, Algorithm 1 steps 1-2).
+// ---------------------------------------------------------------------------
+template <int BC, typename TB, typename R>
+__global__ __launch_bounds__(512) void k_mg_resid(Geo g, int zb, const cx<TB>* __restrict__ b,
+                                                  long long b_rstride, const cx<R>* __restrict__ w,
+                                                  R omega, cx<R>* __restrict__ out,
+                                                  const RhsState* st, int gate) {
+    const int r = blockIdx.z;
+    if (!gate_ok(st, r, gate)) return;
+    const Pos q = plane_pos(g.nx, g.plane);
+    if (!q.valid) return;
+    const int z0 = blockIdx.y * zb;
+    const int z1 = min(g.nz, z0 + zb);
+    const R ih2 = R(1.0 / (g.h * g.h));
+    const cx<TB>* br = b + (long long)r * b_rstride;
+    cx<R>* orr = out + (long long)r * g.n;
+    const long long col = (long long)q.j * g.nx + q.i;
+    // u1 = W b at a node (0 outside the Dirichlet unknowns)
+    auto u1 = [&](long long idx) -> cx<R> { return w[idx] * cvt<R>(br[idx]); };
+    auto u1z = [&](int z) -> cx<R> {
+        if (BC == BC_DIRICHLET && (z < 1 || z > g.nz - 2)) return czero<R>();
+        return u1((long long)z * g.plane + col);
+    };
+    const bool bnd_col = BC == BC_DIRICHLET &&
+                         (q.i == 0 || q.j == 0 || q.i == g.nx - 1 || q.j == g.ny - 1);
+    cx<R> um = z0 > 0 ? u1z(z0 - 1) : czero<R>();
+    cx<R> uc = u1z(z0);
+    for (int z = z0; z < z1; ++z) {
+        cx<R> up = z + 1 < g.nz ? u1z(z + 1) : czero<R>();
+        const long long idx = (long long)z * g.plane + col;
+        cx<R> res;
+        if (BC == BC_DIRICHLET && (bnd_col || z == 0 || z == g.nz - 1)) {
+            res = czero<R>();
+        } else {
+            const long long base = (long long)z * g.plane;
+            auto ld = [&](int ii, int jj) -> cx<R> {
+                if (BC == BC_DIRICHLET && (ii < 1 || jj < 1 || ii > g.nx - 2 || jj > g.ny - 2))
+                    return czero<R>();
+                return u1(base + (long long)jj * g.nx + ii);
+            };
+            cx<R> s = inplane_sum<BC, R>(ld, q.i, q.j, g.nx, g.ny);
+            cx<R> zm = um, zpv = up;
+            if (BC == BC_SOMMERFELD) {
+                if (z == 0) zm = up;
+                if (z == g.nz - 1) zpv = um;
+            }
+            s = s + zm;
+            s = s + zpv;
+            res = (R(1) - omega) * cvt<R>(br[idx]) + ih2 * s;
+        }
+        orr[idx] = res;
+        um = uc;
+        uc = up;
+    }
+}
+
+// Full-weighting restriction (section 3.4.2, eq. matrix-free restriction):
+// coarse node I = fine node 2I, weights 8/4/2/1 over 64; a fine node outside
+// the domain takes its mirror value (Sommerfeld); Dirichlet coarse boundary = 0.
+template <int BC, typename R>
+__global__ __launch_bounds__(512) void k_mg_restrict(Geo gf, Geo gc, int zb,
+                                                     const cx<R>* __restrict__ rf,
+                                                     cx<R>* __restrict__ bc_out, const RhsState* st,
+                                                     int gate) {
+    const int r = blockIdx.z;
+    if (!gate_ok(st, r, gate)) return;
+    const Pos q = plane_pos(gc.nx, gc.plane);
+    if (!q.valid) return;
+    const int z0 = blockIdx.y * zb;
+    const int z1 = min(gc.nz, z0 + zb);
+    const cx<R>* fr = rf + (long long)r * gf.n;
+    cx<R>* cr = bc_out + (long long)r * gc.n;
+    const long long ccol = (long long)q.j * gc.nx + q.i;
+    int xs[3], ys[3];
+#pragma unroll
+    for (int d = -1; d <= 1; ++d) {
+        int fx = 2 * q.i + d, fy = 2 * q.j + d;
+        if (fx < 0) fx = -fx;
+        if (fx > gf.nx - 1) fx = 2 * (gf.nx - 1) - fx;
+        if (fy < 0) fy = -fy;
+        if (fy > gf.ny - 1) fy = 2 * (gf.ny - 1) - fy;
+        xs[d + 1] = fx;
+        ys[d + 1] = fy;
+    }
+    const bool bnd_col = BC == BC_DIRICHLET &&
+                         (q.i == 0 || q.j == 0 || q.i == gc.nx - 1 || q.j == gc.ny - 1);
+    for (int Z = z0; Z < z1; ++Z) {
+        cx<R> acc = czero<R>();
+        if (!(BC == BC_DIRICHLET && (bnd_col || Z == 0 || Z == gc.nz - 1))) {
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz) {
+                int fz = 2 * Z + dz;
+                if (fz < 0) fz = -fz;
+                if (fz > gf.nz - 1) fz = 2 * (gf.nz - 1) - fz;
+                const cx<R>* pl = fr + (long long)fz * gf.plane;
+                cx<R> ps = czero<R>();
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const cx<R>* row = pl + (long long)ys[dy] * gf.nx;
+                    cx<R> rs = row[xs[0]] + row[xs[2]];
+                    rs = rs + R(2) * row[xs[1]];
+                    ps = ps + (dy == 1 ? R(2) : R(1)) * rs;
+                }
+                acc = acc + (dz == 0 ? R(2) : R(1)) * ps;
+            }
+            acc = R(1.0 / 64.0) * acc;
+        }
+        cr[(long long)Z * gc.plane + ccol] = acc;
+    }
+}
+
+// Trilinear prolongation (section 3.4.3, eq. matrix-free prolongation) of the
+// coarse error at fine node (i, j, z).
+template <typename R>
+__device__ __forceinline__ cx<R> prolong_at(const cx<R>* __restrict__ ec, const Geo& gc, int i,
+                                            int j, int z) {
+    const int ci = i >> 1, cj = j >> 1, cz = z >> 1;
+    const int oi = i & 1, oj = j & 1, oz = z & 1;
+    const cx<R>* p0 = ec + ((long long)cz * gc.plane + (long long)cj * gc.nx + ci);
+    cx<R> s = p0[0];
+    if (oi) s = s + p0[1];
+    if (oj) {
+        s = s + p0[gc.nx];
+        if (oi) s = s + p0[gc.nx + 1];
+    }
+    if (oz) {
+        const cx<R>* p1 = p0 + gc.plane;
+        s = s + p1[0];
+        if (oi) s = s + p1[1];
+        if (oj) {
+            s = s + p1[gc.nx];
+            if (oi) s = s + p1[gc.nx + 1];
+        }
+    }
+    const int cnt = oi + oj + oz;
+    const R wgt = cnt == 0 ? R(1) : cnt == 1 ? R(0.5) : cnt == 2 ? R(0.25) : R(0.125);
+    return wgt * s;
+}
+
+// Up pass, part 1: u2 = W b + P e  (recomputed pre-smoothed iterate + correction,
+// Algorithm 1 steps 5-6).
+template <int BC, typename TB, typename R>
+__global__ __launch_bounds__(512) void k_mg_correct(Geo g, Geo gc, int zb,
+                                                    const cx<TB>* __restrict__ b, long long b_rstride,
+                                                    const cx<R>* __restrict__ w,
+                                                    const cx<R>* __restrict__ ec,
+                                                    cx<R>* __restrict__ u2, const RhsState* st,
+                                                    int gate) {
+    const int r = blockIdx.z;
+    if (!gate_ok(st, r, gate)) return;
+    const Pos q = plane_pos(g.nx, g.plane);
+    if (!q.valid) return;
+    const int z0 = blockIdx.y * zb;
+    const int z1 = min(g.nz, z0 + zb);
+    const cx<TB>* br = b + (long long)r * b_rstride;
+    const cx<R>* er = ec + (long long)r * gc.n;
+    cx<R>* ur = u2 + (long long)r * g.n;
+    const long long col = (long long)q.j * g.nx + q.i;
+    const bool bnd_col = BC == BC_DIRICHLET &&
+                         (q.i == 0 || q.j == 0 || q.i == g.nx - 1 || q.j == g.ny - 1);
+    for (int z = z0; z < z1; ++z) {
+        const long long idx = (long long)z * g.plane + col;
+        cx<R> val;
+        if (BC == BC_DIRICHLET && (bnd_col || z == 0 || z == g.nz - 1)) {
+            val = czero<R>();
+        } else {
+            val = w[idx] * cvt<R>(br[idx]) + prolong_at(er, gc, q.i, q.j, z);
+        }
+        ur[idx] = val;
+    }
+}
+
+// Up pass, part 2: post-smoothing u3 = u2 + W (b - M u2)
+//   = (1 - omega) u2 + W_j (b_j + (1/h^2) sum'_nb u2_nb)        (Algorithm 1 step 7)
+template <int BC, typename TB, typename R, typename TO>
+__global__ __launch_bounds__(512) void k_mg_smooth(Geo g, int zb, const cx<R>* __restrict__ u2,
+                                                   const cx<TB>* __restrict__ b, long long b_rstride,
+                                                   const cx<R>* __restrict__ w, R omega,
+                                                   cx<TO>* __restrict__ out, long long o_rstride,
+                                                   const RhsState* st, int gate) {
+    const int r = blockIdx.z;
+    if (!gate_ok(st, r, gate)) return;
+    const Pos q = plane_pos(g.nx, g.plane);
+    if (!q.valid) return;
+    const int z0 = blockIdx.y * zb;
+    const int z1 = min(g.nz, z0 + zb);
+    const R ih2 = R(1.0 / (g.h * g.h));
+    const cx<R>* ur = u2 + (long long)r * g.n;
+    const cx<TB>* br = b + (long long)r * b_rstride;
+    cx<TO>* orr = out + (long long)r * o_rstride;
+    const long long col = (long long)q.j * g.nx + q.i;
+    auto uz = [&](int z) -> cx<R> {
+        if (BC == BC_DIRICHLET && (z < 1 || z > g.nz - 2)) return czero<R>();
+        return ur[(long long)z * g.plane + col];
+    };
+    const bool bnd_col = BC == BC_DIRICHLET &&
+                         (q.i == 0 || q.j == 0 || q.i == g.nx - 1 || q.j == g.ny - 1);
+    cx<R> um = z0 > 0 ? uz(z0 - 1) : czero<R>();
+    cx<R> uc = uz(z0);
+    for (int z = z0; z < z1; ++z) {
+        cx<R> up = z + 1 < g.nz ? uz(z + 1) : czero<R>();
+        const long long idx = (long long)z * g.plane + col;
+        cx<R> res;
+        if (BC == BC_DIRICHLET && (bnd_col || z == 0 || z == g.nz - 1)) {
+            res = czero<R>();
+        } else {
+            const cx<R>* pl = ur + (long long)z * g.plane;
+            auto ld = [&](int ii, int jj) -> cx<R> { return pl[(long long)jj * g.nx + ii]; };
+            cx<R> s = inplane_sum<BC, R>(ld, q.i, q.j, g.nx, g.ny);
+            cx<R> zm = um, zpv = up;
+            if (BC == BC_SOMMERFELD) {
+                if (z == 0) zm = up;
+                if (z == g.nz - 1) zpv = um;
+            }
+            s = s + zm;
+            s = s + zpv;
+            res = (R(1) - omega) * uc + w[idx] * (cvt<R>(br[idx]) + ih2 * s);
+        }
+        orr[idx] = cvt<TO>(res);
+        um = uc;
+        uc = up;
+    }
+}
+
+// Coarsest level: e = M_c^-1 b over the unknown nodes (dense inverse stored
+// column-major so that lanes read consecutive rows).  One workgroup per RHS.
+template <typename R>
+__global__ __launch_bounds__(256) void k_coarse(int n_nodes, int n_unk, const int* __restrict__ cidx,
+                                                const cx<R>* __restrict__ minv_cm,
+                                                const cx<R>* __restrict__ b, cx<R>* __restrict__ e,
+                                                const RhsState* st, int gate) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<R>* sb = reinterpret_cast<cx<R>*>(smem_raw);
+    const int r = blockIdx.x;
+    if (!gate_ok(st, r, gate)) return;
+    const cx<R>* br = b + (long long)r * n_nodes;
+    cx<R>* er = e + (long long)r * n_nodes;
+    for (int t = threadIdx.x; t < n_unk; t += blockDim.x) sb[t] = br[cidx[t]];
+    for (int t = threadIdx.x; t < n_nodes; t += blockDim.x) er[t] = czero<R>();
+    __syncthreads();
+    for (int row = threadIdx.x; row < n_unk; row += blockDim.x) {
+        cx<R> s = czero<R>();
+        for (int c = 0; c < n_unk; ++c) s = s + minv_cm[(long long)c * n_unk + row] * sb[c];
+        er[cidx[row]] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Krylov vector updates (complex128), flat over nodes: gridDim = (blocks, 1, nrhs).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void k_p_update(long long n, c128* __restrict__ p,
+                                                  const c128* __restrict__ rr,
+                                                  const c128* __restrict__ v, const RhsState* st) {
+    const int r = blockIdx.z;
+    if (st[r].status != ST_RUN) return;
+    const c128 beta = st[r].beta, om = st[r].omega;
+    const long long off = (long long)r * n;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        p[off + i] = rr[off + i] + beta * (p[off + i] - om * v[off + i]);
+    }
+}
+
+__global__ __launch_bounds__(512) void k_s_update(long long n, c128* __restrict__ s,
+                                                  const c128* __restrict__ rr,
+                                                  const c128* __restrict__ v, const RhsState* st,
+                                                  double* __restrict__ part, long long nblk_max) {
+    const int r = blockIdx.z;
+    if (st[r].status != ST_RUN) return;
+    const c128 al = st[r].alpha;
+    const long long off = (long long)r * n;
+    double acc[1] = {0.0};
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        c128 sv = rr[off + i] - al * v[off + i];
+        s[off + i] = sv;
+        acc[0] += abs2(sv);
+    }
+    block_sum_store<1>(acc, part + part_index(r, SLOT_S, 0, nblk_max) + blockIdx.x, nblk_max);
+}
+
+__global__ __launch_bounds__(512) void k_x_half(long long n, c128* __restrict__ x,
+                                                const c128* __restrict__ ph, const RhsState* st) {
+    const int r = blockIdx.z;
+    if (st[r].status != ST_HALF) return;
+    const c128 al = st[r].alpha;
+    const long long off = (long long)r * n;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        x[off + i] = x[off + i] + al * ph[off + i];
+    }
+}
+
+// x += alpha p_hat + omega s_hat; r = s - omega t; partials ||r||^2, r_hat^H r.
+__global__ __launch_bounds__(512) void k_update_xr(long long n, c128* __restrict__ x,
+                                                   c128* __restrict__ rr,
+                                                   const c128* __restrict__ ph,
+                                                   const c128* __restrict__ sh,
+                                                   const c128* __restrict__ s,
+                                                   const c128* __restrict__ t,
+                                                   const c128* __restrict__ rhat, const RhsState* st,
+                                                   double* __restrict__ part, long long nblk_max) {
+    const int r = blockIdx.z;
+    if (st[r].status != ST_RUN) return;
+    const c128 al = st[r].alpha, om = st[r].omega;
+    const long long off = (long long)r * n;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        x[off + i] = x[off + i] + al * ph[off + i] + om * sh[off + i];
+        c128 rv = s[off + i] - om * t[off + i];
+        rr[off + i] = rv;
+        acc[0] += abs2(rv);
+        c128 d = cdot(rhat[off + i], rv);
+        acc[1] += d.re;
+        acc[2] += d.im;
+    }
+    block_sum_store<3>(acc, part + part_index(r, SLOT_R, 0, nblk_max) + blockIdx.x, nblk_max);
+}
+
+// ---------------------------------------------------------------------------
+// Finalisation of the reductions and the Bi-CGSTAB scalar recurrences, one
+// workgroup per right-hand side; partial sums are added in a fixed order so a
+// solve is bitwise repeatable.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ void fixed_sum(const double* __restrict__ part, long long nblk, long long nblk_max,
+                          double (&out)[NT]) {
+    __shared__ double sm[NT][1024];
+    double v[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        double s = 0.0;
+        for (long long b = threadIdx.x; b < nblk; b += blockDim.x) s += part[t * nblk_max + b];
+        v[t] = s;
+        sm[t][threadIdx.x] = s;
+    }
+    __syncthreads();
+    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) sm[t][threadIdx.x] += sm[t][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) out[t] = sm[t][0];
+}
+
+__device__ __forceinline__ bool finite2(c128 a) { return isfinite(a.re) && isfinite(a.im); }
+
+__global__ __launch_bounds__(1024) void k_finalize(int mode, RhsState* st, const double* part,
+                                                   long long nblk, long long nblk_max, double tol) {
+    const int r = blockIdx.x;
+    RhsState& S = st[r];
+    const int status = S.status;
+    // which right-hand sides take part in this step
+    bool act;
+    switch (mode) {
+        case FIN_INIT: act = status == ST_RUN; break;
+        case FIN_TRUE: act = status != ST_RUN && status != ST_IDLE && status != ST_HALF; break;
+        case FIN_OMEGA: act = status == ST_RUN || status == ST_HALF; break;
+        default: act = status == ST_RUN; break;
+    }
+    if (!act) return;
+    const double tiny = 1e-300;
+    if (mode == FIN_INIT || mode == FIN_TRUE) {
+        double s[4];
+        fixed_sum<4>(part + part_index(r, SLOT_R, 0, nblk_max), nblk, nblk_max, s);
+        if (threadIdx.x != 0) return;
+        if (mode == FIN_INIT) {
+            S.bnorm2 = s[3];
+            S.rnorm2 = s[0];
+            S.rhat_norm2 = s[0];
+            S.tol2 = tol * tol * s[3];
+            S.rho = mk(1.0, 0.0);
+            S.alpha = mk(1.0, 0.0);
+            S.omega = mk(1.0, 0.0);
+            S.beta = mk(0.0, 0.0);
+            S.iters2 = 0;
+            S.matvecs = 1;
+            S.restarts = 0;
+            S.true_rnorm2 = 0.0;
+            if (!isfinite(s[0]) || !isfinite(s[3])) S.status = ST_NUMERIC;
+            else if (s[3] == 0.0 || s[0] <= S.tol2) S.status = ST_CONV;
+        } else {
+            S.true_rnorm2 = s[0];
+            if (!isfinite(s[0])) {
+                S.status = ST_NUMERIC;
+            } else if (status == ST_CONV && S.bnorm2 > 0.0 && s[0] > S.tol2 && S.iters2 < S.maxit2 &&
+                       S.restarts < 5) {
+                // the recursive residual drifted from the true one: restart from x
+                S.status = ST_RUN;
+                S.rnorm2 = s[0];
+                S.rhat_norm2 = s[0];
+                S.rho = mk(1.0, 0.0);
+                S.alpha = mk(1.0, 0.0);
+                S.omega = mk(1.0, 0.0);
+                S.matvecs += 1;
+                S.restarts += 1;
+            }
+        }
+        return;
+    }
+    if (mode == FIN_RHO) {
+        double s[3];
+        fixed_sum<3>(part + part_index(r, SLOT_R, 0, nblk_max), nblk, nblk_max, s);
+        if (threadIdx.x != 0) return;
+        const double rn2 = s[0];
+        const c128 rho_new = mk(s[1], s[2]);
+        if (!isfinite(rn2) || !finite2(rho_new)) { S.status = ST_NUMERIC; return; }
+        S.rnorm2 = rn2;
+        if (rn2 <= S.tol2) { S.status = ST_CONV; return; }
+        if (abs2(S.omega) <= tiny * tiny) { S.status = ST_BREAK; return; }
+        if (S.iters2 >= S.maxit2) { S.status = ST_MAXIT; return; }
+        if (sqrt(abs2(rho_new)) <= tiny * sqrt(S.rhat_norm2) * sqrt(rn2)) { S.status = ST_BREAK; return; }
+        S.beta = cdiv(rho_new, S.rho) * cdiv(S.alpha, S.omega);
+        S.rho = rho_new;
+        return;
+    }
+    if (mode == FIN_ALPHA) {
+        double s[2];
+        fixed_sum<2>(part + part_index(r, SLOT_V, 0, nblk_max), nblk, nblk_max, s);
+        if (threadIdx.x != 0) return;
+        const c128 rv = mk(s[0], s[1]);
+        S.matvecs += 1;
+        if (!finite2(rv)) { S.status = ST_NUMERIC; return; }
+        if (abs2(rv) == 0.0) { S.status = ST_BREAK; return; }
+        S.alpha = cdiv(S.rho, rv);
+        return;
+    }
+    if (mode == FIN_S) {
+        double s[1];
+        fixed_sum<1>(part + part_index(r, SLOT_S, 0, nblk_max), nblk, nblk_max, s);
+        if (threadIdx.x != 0) return;
+        if (!isfinite(s[0])) { S.status = ST_NUMERIC; return; }
+        S.snorm2 = s[0];
+        if (s[0] <= S.tol2) S.status = ST_HALF;
+        return;
+    }
+    if (mode == FIN_OMEGA) {
+        if (status == ST_HALF) {
+            if (threadIdx.x == 0) {
+                S.status = ST_CONV;
+                S.iters2 += 1;
+                S.rnorm2 = S.snorm2;
+            }
+            return;
+        }
+        double s[3];
+        fixed_sum<3>(part + part_index(r, SLOT_T, 0, nblk_max), nblk, nblk_max, s);
+        if (threadIdx.x != 0) return;
+        S.matvecs += 1;
+        const c128 ts = mk(s[0], s[1]);
+        const double tt = s[2];
+        if (!finite2(ts) || !isfinite(tt)) { S.status = ST_NUMERIC; return; }
+        if (tt == 0.0) { S.status = ST_BREAK; return; }
+        S.omega = mk(ts.re / tt, ts.im / tt);
+        S.iters2 += 2;
+        return;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up and auxiliary kernels
+// ---------------------------------------------------------------------------
+__global__ void k_model_check(long long n, const double* __restrict__ k, double* __restrict__ k2,
+                              double* __restrict__ kb, int* __restrict__ bad) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double v = k[i];
+        if (!isfinite(v) || v < 0.0) atomicAdd(bad, 1);
+        k2[i] = v * v;
+        kb[i] = v;
+    }
+}
+
+// k_{l+1}(I) = k_l(2I)  (injection)
+__global__ void k_inject(Geo gf, Geo gc, const double* __restrict__ kf, double* __restrict__ kc) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < gc.n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int z = (int)(i / gc.plane);
+        const int rem = (int)(i - (long long)z * gc.plane);
+        const int y = rem / gc.nx, x = rem - y * gc.nx;
+        kc[i] = kf[(long long)(2 * z) * gf.plane + (long long)(2 * y) * gf.nx + 2 * x];
+    }
+}
+
+// W = omega / D with D = 6/h^2 - (beta1 - beta2 i) k^2 - n_j 2 i k / h; computed in
+// double, stored in the level precision.  Dirichlet boundary nodes get W = 0.
+template <typename R>
+__global__ void k_make_w(Geo g, int bc, const double* __restrict__ k, double beta1, double beta2,
+                         double omega, cx<R>* __restrict__ w) {
+    const double ih2 = 1.0 / (g.h * g.h);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int z = (int)(i / g.plane);
+        const int rem = (int)(i - (long long)z * g.plane);
+        const int y = rem / g.nx, x = rem - y * g.nx;
+        const double kk = k[i];
+        c128 d = mk(6.0 * ih2 - beta1 * kk * kk, beta2 * kk * kk);
+        c128 wv;
+        if (bc == BC_SOMMERFELD) {
+            d.im -= faces(x, y, z, g.nx, g.ny, g.nz) * 2.0 * kk / g.h;
+            wv = cdiv(mk(omega, 0.0), d);
+        } else {
+            wv = on_boundary(x, y, z, g.nx, g.ny, g.nz) ? mk(0.0, 0.0) : cdiv(mk(omega, 0.0), d);
+        }
+        w[i] = cvt<R>(wv);
+    }
+}
+
+__global__ void k_copy_rhs(Geo g, int bc, int nrhs, const c128* __restrict__ src,
+                           c128* __restrict__ dst) {
+    const long long tot = (long long)nrhs * g.n;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long node = i % g.n;
+        const int z = (int)(node / g.plane);
+        const int rem = (int)(node - (long long)z * g.plane);
+        const int y = rem / g.nx, x = rem - y * g.nx;
+        c128 v = src[i];
+        if (bc == BC_DIRICHLET && on_boundary(x, y, z, g.nx, g.ny, g.nz)) v = mk(0.0, 0.0);
+        dst[i] = v;
+    }
+}
+
+// rhs = D^-1 conj(g), D_j = 2^(-n_j)  (Sommerfeld); Dirichlet: conj(g) inside, 0 on the boundary
+__global__ void k_adjoint_rhs(Geo g, int bc, int nrhs, const c128* __restrict__ gin,
+                              c128* __restrict__ out) {
+    const long long tot = (long long)nrhs * g.n;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long node = i % g.n;
+        const int z = (int)(node / g.plane);
+        const int rem = (int)(node - (long long)z * g.plane);
+        const int y = rem / g.nx, x = rem - y * g.nx;
+        c128 v = conj(gin[i]);
+        if (bc == BC_SOMMERFELD) {
+            v = double(1 << faces(x, y, z, g.nx, g.ny, g.nz)) * v;
+        } else if (on_boundary(x, y, z, g.nx, g.ny, g.nz)) {
+            v = mk(0.0, 0.0);
+        }
+        out[i] = v;
+    }
+}
+
+// grad_j = -sum_r Re(D_j w_rj a'_j u_rj), a'_j = -omega^2 - i n_j omega / (h sqrt(s_j))
+__global__ void k_grad_s(Geo g, int bc, int nrhs, const c128* __restrict__ u,
+                         const c128* __restrict__ w, const double* __restrict__ s, double omega,
+                         double* __restrict__ grad) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int z = (int)(i / g.plane);
+        const int rem = (int)(i - (long long)z * g.plane);
+        const int y = rem / g.nx, x = rem - y * g.nx;
+        int nf = 0;
+        double d = 1.0;
+        if (bc == BC_SOMMERFELD) {
+            nf = faces(x, y, z, g.nx, g.ny, g.nz);
+            d = 1.0 / double(1 << nf);
+        } else if (on_boundary(x, y, z, g.nx, g.ny, g.nz)) {
+            grad[i] = 0.0;
+            continue;
+        }
+        const c128 ap = mk(-omega * omega, -nf * omega / (g.h * sqrt(s[i])));
+        double acc = 0.0;
+        for (int r = 0; r < nrhs; ++r) {
+            const c128 t = (w[(long long)r * g.n + i] * ap) * u[(long long)r * g.n + i];
+            acc += t.re;
+        }
+        grad[i] = -d * acc;
+    }
+}
+
+__global__ void k_set_point(long long off, double val, c128* __restrict__ b) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) b[off] = mk(val, 0.0);
+}
+
+__global__ void k_fill_status(int n, RhsState* st, int status, int maxit2) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) {
+        st[r].status = status;
+        st[r].maxit2 = maxit2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+static inline dim3 grid_fine(const Geo& g, const Launch& L, int nrhs) {
+    return dim3((unsigned)((g.plane + L.block - 1) / L.block), (unsigned)((g.nz + L.zb - 1) / L.zb),
+                (unsigned)nrhs);
+}
+
+long long nblk_of(const Geo& g, const Launch& L) {
+    return (long long)((g.plane + L.block - 1) / L.block) * ((g.nz + L.zb - 1) / L.zb);
+}
+
+static inline unsigned flat_blocks(long long n, int block, int cap) {
+    long long b = (n + block - 1) / block;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+void launch_apply(hipStream_t s, int bc, int mode, const Geo& g, const Launch& L, int nrhs,
+                  const c128* x, c128* y, const double* k2, const double* kb, double sr, double si,
+                  const c128* aux, double* part, long long nblk_max, const RhsState* st, int gate) {
+    dim3 grid = grid_fine(g, L, nrhs);
+#define HH_APPLY(BCV, MV)                                                                         \
+    hipLaunchKernelGGL((k_apply<BCV, MV>), grid, dim3(L.block), 0, s, g, L.zb, x, y, k2, kb, sr, si, \
+                       aux, part, nblk_max, st, gate)
+    if (bc == BC_SOMMERFELD) {
+        if (mode == OP_PLAIN) HH_APPLY(BC_SOMMERFELD, OP_PLAIN);
+        else if (mode == OP_V) HH_APPLY(BC_SOMMERFELD, OP_V);
+        else HH_APPLY(BC_SOMMERFELD, OP_T);
+    } else {
+        if (mode == OP_PLAIN) HH_APPLY(BC_DIRICHLET, OP_PLAIN);
+        else if (mode == OP_V) HH_APPLY(BC_DIRICHLET, OP_V);
+        else HH_APPLY(BC_DIRICHLET, OP_T);
+    }
+#undef HH_APPLY
+}
+
+void launch_init(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs, const c128* b,
+                 c128* x, c128* r, c128* rhat, c128* p, c128* v, const double* k2, const double* kb,
+                 int use_x0, double* part, long long nblk_max, const RhsState* st, int gate) {
+    dim3 grid = grid_fine(g, L, nrhs);
+    if (bc == BC_SOMMERFELD)
+        hipLaunchKernelGGL((k_init<BC_SOMMERFELD>), grid, dim3(L.block), 0, s, g, L.zb, b, x, r, rhat,
+                           p, v, k2, kb, use_x0, part, nblk_max, st, gate);
+    else
+        hipLaunchKernelGGL((k_init<BC_DIRICHLET>), grid, dim3(L.block), 0, s, g, L.zb, b, x, r, rhat,
+                           p, v, k2, kb, use_x0, part, nblk_max, st, gate);
+}
+
+template <typename TB, typename R>
+void launch_mg_resid(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs,
+                     const cx<TB>* b, long long b_rstride, const cx<R>* w, double omega, cx<R>* out,
+                     const RhsState* st, int gate) {
+    dim3 grid = grid_fine(g, L, nrhs);
+    if (bc == BC_SOMMERFELD)
+        hipLaunchKernelGGL((k_mg_resid<BC_SOMMERFELD, TB, R>), grid, dim3(L.block), 0, s, g, L.zb, b,
+                           b_rstride, w, R(omega), out, st, gate);
+    else
+        hipLaunchKernelGGL((k_mg_resid<BC_DIRICHLET, TB, R>), grid, dim3(L.block), 0, s, g, L.zb, b,
+                           b_rstride, w, R(omega), out, st, gate);
+}
+
+template <typename R>
+void launch_mg_restrict(hipStream_t s, int bc, const Geo& gf, const Geo& gc, const Launch& L,
+                        int nrhs, const cx<R>* rf, cx<R>* bc_out, const RhsState* st, int gate) {
+    dim3 grid = grid_fine(gc, L, nrhs);
+    if (bc == BC_SOMMERFELD)
+        hipLaunchKernelGGL((k_mg_restrict<BC_SOMMERFELD, R>), grid, dim3(L.block), 0, s, gf, gc, L.zb,
+                           rf, bc_out, st, gate);
+    else
+        hipLaunchKernelGGL((k_mg_restrict<BC_DIRICHLET, R>), grid, dim3(L.block), 0, s, gf, gc, L.zb,
+                           rf, bc_out, st, gate);
+}
+
+template <typename TB, typename R>
+void launch_mg_correct(hipStream_t s, int bc, const Geo& g, const Geo& gc, const Launch& L, int nrhs,
+                       const cx<TB>* b, long long b_rstride, const cx<R>* w, const cx<R>* ec,
+                       cx<R>* u2, const RhsState* st, int gate) {
+    dim3 grid = grid_fine(g, L, nrhs);
+    if (bc == BC_SOMMERFELD)
+        hipLaunchKernelGGL((k_mg_correct<BC_SOMMERFELD, TB, R>), grid, dim3(L.block), 0, s, g, gc,
+                           L.zb, b, b_rstride, w, ec, u2, st, gate);
+    else
+        hipLaunchKernelGGL((k_mg_correct<BC_DIRICHLET, TB, R>), grid, dim3(L.block), 0, s, g, gc,
+                           L.zb, b, b_rstride, w, ec, u2, st, gate);
+}
+
+template <typename TB, typename R, typename TO>
+void launch_mg_smooth(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs,
+                      const cx<R>* u2, const cx<TB>* b, long long b_rstride, const cx<R>* w,
+                      double omega, cx<TO>* out, long long o_rstride, const RhsState* st, int gate) {
+    dim3 grid = grid_fine(g, L, nrhs);
+    if (bc == BC_SOMMERFELD)
+        hipLaunchKernelGGL((k_mg_smooth<BC_SOMMERFELD, TB, R, TO>), grid, dim3(L.block), 0, s, g, L.zb,
+                           u2, b, b_rstride, w, R(omega), out, o_rstride, st, gate);
+    else
+        hipLaunchKernelGGL((k_mg_smooth<BC_DIRICHLET, TB, R, TO>), grid, dim3(L.block), 0, s, g, L.zb,
+                           u2, b, b_rstride, w, R(omega), out, o_rstride, st, gate);
+}
+
+template <typename R>
+void launch_coarse(hipStream_t s, int nrhs, int n_nodes, int n_unk, const int* cidx,
+                   const cx<R>* minv, const cx<R>* b, cx<R>* e, const RhsState* st, int gate) {
+    hipLaunchKernelGGL((k_coarse<R>), dim3(nrhs), dim3(256), n_unk * sizeof(cx<R>), s, n_nodes, n_unk,
+                       cidx, minv, b, e, st, gate);
+}
+
+#define HH_INST(TB, R, TO)                                                                        \
+    template void launch_mg_resid<TB, R>(hipStream_t, int, const Geo&, const Launch&, int,         \
+                                         const cx<TB>*, long long, const cx<R>*, double, cx<R>*,  \
+                                         const RhsState*, int);                                    \
+    template void launch_mg_correct<TB, R>(hipStream_t, int, const Geo&, const Geo&, const Launch&, \
+                                           int, const cx<TB>*, long long, const cx<R>*,            \
+                                           const cx<R>*, cx<R>*, const RhsState*, int);            \
+    template void launch_mg_smooth<TB, R, TO>(hipStream_t, int, const Geo&, const Launch&, int,    \
+                                              const cx<R>*, const cx<TB>*, long long,              \
+                                              const cx<R>*, double, cx<TO>*, long long,            \
+                                              const RhsState*, int);
+HH_INST(double, double, double)
+HH_INST(double, float, double)
+HH_INST(float, float, float)
+#undef HH_INST
+template void launch_mg_restrict<double>(hipStream_t, int, const Geo&, const Geo&, const Launch&,
+                                         int, const c128*, c128*, const RhsState*, int);
+template void launch_mg_restrict<float>(hipStream_t, int, const Geo&, const Geo&, const Launch&, int,
+                                        const c64*, c64*, const RhsState*, int);
+template void launch_coarse<double>(hipStream_t, int, int, int, const int*, const c128*,
+                                    const c128*, c128*, const RhsState*, int);
+template void launch_coarse<float>(hipStream_t, int, int, int, const int*, const c64*, const c64*,
+                                   c64*, const RhsState*, int);
+
+void launch_p_update(hipStream_t s, long long n, int nrhs, c128* p, const c128* r, const c128* v,
+                     const RhsState* st, const Launch& L) {
+    hipLaunchKernelGGL(k_p_update, dim3(L.flat_cap, 1, nrhs), dim3(L.block),
+                       0, s, n, p, r, v, st);
+}
+void launch_s_update(hipStream_t s, long long n, int nrhs, c128* sv, const c128* r, const c128* v,
+                     const RhsState* st, double* part, long long nblk_max, const Launch& L) {
+    hipLaunchKernelGGL(k_s_update, dim3(L.flat_cap, 1, nrhs), dim3(L.block),
+                       0, s, n, sv, r, v, st, part, nblk_max);
+}
+void launch_x_half(hipStream_t s, long long n, int nrhs, c128* x, const c128* ph,
+                   const RhsState* st, const Launch& L) {
+    hipLaunchKernelGGL(k_x_half, dim3(L.flat_cap, 1, nrhs), dim3(L.block), 0,
+                       s, n, x, ph, st);
+}
+void launch_update_xr(hipStream_t s, long long n, int nrhs, c128* x, c128* r, const c128* ph,
+                      const c128* sh, const c128* sv, const c128* t, const c128* rhat,
+                      const RhsState* st, double* part, long long nblk_max, const Launch& L) {
+    hipLaunchKernelGGL(k_update_xr, dim3(L.flat_cap, 1, nrhs), dim3(L.block),
+                       0, s, n, x, r, ph, sh, sv, t, rhat, st, part, nblk_max);
+}
+
+void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const double* part,
+                     long long nblk, long long nblk_max, double tol) {
+    hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(1024), 0, s, mode, st, part, nblk, nblk_max, tol);
+}
+
+void launch_model_check(hipStream_t s, long long n, const double* k, double* k2, double* kb, int* bad) {
+    hipLaunchKernelGGL(k_model_check, dim3(flat_blocks(n, 256, 8192)), dim3(256), 0, s, n, k, k2, kb,
+                       bad);
+}
+void launch_inject(hipStream_t s, const Geo& gf, const Geo& gc, const double* kf, double* kc) {
+    hipLaunchKernelGGL(k_inject, dim3(flat_blocks(gc.n, 256, 8192)), dim3(256), 0, s, gf, gc, kf, kc);
+}
+template <typename R>
+void launch_make_w(hipStream_t s, const Geo& g, int bc, const double* k, double beta1, double beta2,
+                   double omega, cx<R>* w) {
+    hipLaunchKernelGGL((k_make_w<R>), dim3(flat_blocks(g.n, 256, 8192)), dim3(256), 0, s, g, bc, k,
+                       beta1, beta2, omega, w);
+}
+template void launch_make_w<double>(hipStream_t, const Geo&, int, const double*, double, double,
+                                    double, c128*);
+template void launch_make_w<float>(hipStream_t, const Geo&, int, const double*, double, double,
+                                   double, c64*);
+void launch_copy_rhs(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* src, c128* dst) {
+    hipLaunchKernelGGL(k_copy_rhs, dim3(flat_blocks((long long)nrhs * g.n, 256, 8192)), dim3(256), 0,
+                       s, g, bc, nrhs, src, dst);
+}
+void launch_adjoint_rhs(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* gin, c128* out) {
+    hipLaunchKernelGGL(k_adjoint_rhs, dim3(flat_blocks((long long)nrhs * g.n, 256, 8192)), dim3(256),
+                       0, s, g, bc, nrhs, gin, out);
+}
+void launch_grad_s(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* u, const c128* w,
+                   const double* sl, double omega, double* grad) {
+    hipLaunchKernelGGL(k_grad_s, dim3(flat_blocks(g.n, 256, 8192)), dim3(256), 0, s, g, bc, nrhs, u, w,
+                       sl, omega, grad);
+}
+void launch_set_point(hipStream_t s, long long off, double val, c128* b) {
+    hipLaunchKernelGGL(k_set_point, dim3(1), dim3(64), 0, s, off, val, b);
+}
+void launch_fill_status(hipStream_t s, int n, RhsState* st, int status, int maxit2) {
+    hipLaunchKernelGGL(k_fill_status, dim3(1), dim3(64), 0, s, n, st, status, maxit2);
+}
+
+}  // namespace hh

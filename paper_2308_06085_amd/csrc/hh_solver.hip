@@ -1,0 +1,867 @@
+// Host side of the gfx950 Helmholtz library: context, grid hierarchy set-up,
+// coarsest-grid factorisation, the Bi-CGSTAB driver and the C ABI of hh.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/hh.h"
+#include "hh_common.h"
+#include "hh_kernels.h"
+
+using namespace hh;
+
+namespace {
+
+constexpr int NRHS_LIMIT = 16;
+constexpr long long NBLK_CAP = 65536;   // workgroups of a reduction-producing launch
+constexpr int COARSE_UNK_CAP = 2048;    // unknowns of the dense coarsest solve
+constexpr int MAX_RESTARTS = 5;
+
+std::string g_create_error;
+
+struct LevelBuf {
+    Geo g;
+    Launch L;
+    double* k = nullptr;  // wavenumber at the nodes of this level
+    void* w = nullptr;    // omega D^-1 (complex, level precision)
+    void* tmp = nullptr;  // residual (down pass) / corrected iterate (up pass)
+    void* b = nullptr;    // right-hand side (levels >= 1)
+    void* e = nullptr;    // V-cycle result (levels >= 1)
+};
+
+}  // namespace
+
+struct hh_ctx {
+    hh_config cfg{};
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    int device = 0;
+    bool mixed = false;
+    size_t csize = 16;  // bytes per complex of the multigrid precision
+    std::vector<LevelBuf> lv;
+    Launch base;        // requested fine-grid launch shape
+    Launch L0;          // effective fine-level launch shape
+    long long nblk0 = 0;
+    // fine-level complex128 state
+    double* k2 = nullptr;
+    double* kb = nullptr;
+    c128 *bsrc = nullptr, *xk = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr,
+         *s = nullptr, *t = nullptr, *ph = nullptr, *sh = nullptr;
+    RhsState* st = nullptr;
+    RhsState* st_host = nullptr;  // pinned
+    double* part = nullptr;
+    int* bad = nullptr;
+    int* bad_host = nullptr;
+    // coarsest level
+    int* cidx = nullptr;
+    void* minv = nullptr;
+    int n_unk = 0;
+    // state
+    bool model_set = false;
+    int nrhs_cur = 0;
+    bool use_graph = true;
+    int check_every = 4;
+    std::map<int, hipGraphExec_t> graphs;
+    float last_ms = 0.f;
+    std::string err;
+};
+
+namespace {
+
+hh_status fail(hh_ctx* c, hh_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    else g_create_error = buf;
+    return st;
+}
+
+#define HIPCHK(ctx, call)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? HH_ERR_OOM : HH_ERR_HIP, "%s: %s (%s:%d)", \
+                        #call, hipGetErrorString(e_), __FILE__, __LINE__);                        \
+    } while (0)
+
+#define CHK(expr)                      \
+    do {                               \
+        hh_status s_ = (expr);         \
+        if (s_ != HH_OK) return s_;    \
+    } while (0)
+
+Geo make_geo(int nx, int ny, int nz, double h) {
+    Geo g;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.plane = nx * ny;
+    g.n = (long long)nx * ny * nz;
+    g.h = h;
+    return g;
+}
+
+// Workgroup shape of a level: `base` lanes (fewer on small planes) and enough
+// z-planes per workgroup to keep the reduction partials below NBLK_CAP while
+// leaving >= ~2048 workgroups where the grid allows it.
+Launch level_launch(const Geo& g, const Launch& base) {
+    Launch L = base;
+    while (L.block > 64 && L.block / 2 >= g.plane) L.block /= 2;
+    const long long pb = (g.plane + L.block - 1) / L.block;
+    int zb = base.zb > 0 ? base.zb : 8;
+    if (base.zb <= 0) {
+        // automatic: aim for ~4096 workgroups, at least 4 planes per workgroup when that still fills the chip
+        long long want = std::max<long long>(1, (pb * g.nz) / 4096);
+        zb = (int)std::min<long long>(std::max<long long>(want, 1), 32);
+    }
+    zb = std::max(1, std::min(zb, g.nz));
+    while (pb * ((g.nz + zb - 1) / zb) > NBLK_CAP) ++zb;
+    L.zb = zb;
+    return L;
+}
+
+template <typename T>
+hh_status dalloc(hh_ctx* c, T** p, size_t bytes) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, HH_ERR_OOM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    *p = (T*)q;
+    return HH_OK;
+}
+
+void free_all(hh_ctx* c) {
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    for (auto& L : c->lv) {
+        (void)hipFree(L.k);
+        (void)hipFree(L.w);
+        (void)hipFree(L.tmp);
+        (void)hipFree(L.b);
+        (void)hipFree(L.e);
+    }
+    c->lv.clear();
+    void* ptrs[] = {c->k2, c->kb, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->s, c->t,
+                    c->ph, c->sh, c->st, c->part, c->bad, c->cidx, c->minv};
+    for (void* q : ptrs) (void)hipFree(q);
+    if (c->st_host) (void)hipHostFree(c->st_host);
+    if (c->bad_host) (void)hipHostFree(c->bad_host);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+}
+
+void invalidate_graphs(hh_ctx* c) {
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+void apply_launch(hh_ctx* c) {
+    for (auto& L : c->lv) L.L = level_launch(L.g, c->base);
+    c->L0 = c->lv[0].L;
+    c->nblk0 = nblk_of(c->lv[0].g, c->L0);
+    invalidate_graphs(c);
+}
+
+// -------------------------------------------------------------------------
+// V-cycle enqueue: z = V(bin) on level 0 input/output of complex128.
+// -------------------------------------------------------------------------
+template <typename R>
+void enqueue_vcycle_t(hh_ctx* c, hipStream_t s, int nrhs, const c128* bin, c128* bout,
+                      const RhsState* st, int gate) {
+    const int L = (int)c->lv.size();
+    const int bc = c->cfg.bc;
+    const double om = c->cfg.omega;
+    auto C = [](void* p) { return reinterpret_cast<cx<R>*>(p); };
+    LevelBuf& f = c->lv[0];
+    // down
+    launch_mg_resid<double, R>(s, bc, f.g, f.L, nrhs, bin, f.g.n, C(f.w), om, C(f.tmp), st, gate);
+    launch_mg_restrict<R>(s, bc, f.g, c->lv[1].g, c->lv[1].L, nrhs, C(f.tmp), C(c->lv[1].b), st, gate);
+    for (int l = 1; l < L - 1; ++l) {
+        LevelBuf& a = c->lv[l];
+        LevelBuf& n = c->lv[l + 1];
+        launch_mg_resid<R, R>(s, bc, a.g, a.L, nrhs, C(a.b), a.g.n, C(a.w), om, C(a.tmp), st, gate);
+        launch_mg_restrict<R>(s, bc, a.g, n.g, n.L, nrhs, C(a.tmp), C(n.b), st, gate);
+    }
+    // coarsest
+    LevelBuf& cl = c->lv[L - 1];
+    launch_coarse<R>(s, nrhs, (int)cl.g.n, c->n_unk, c->cidx, C(c->minv), C(cl.b), C(cl.e), st, gate);
+    // up
+    for (int l = L - 2; l >= 1; --l) {
+        LevelBuf& a = c->lv[l];
+        LevelBuf& n = c->lv[l + 1];
+        launch_mg_correct<R, R>(s, bc, a.g, n.g, a.L, nrhs, C(a.b), a.g.n, C(a.w), C(n.e), C(a.tmp), st,
+                                gate);
+        launch_mg_smooth<R, R, R>(s, bc, a.g, a.L, nrhs, C(a.tmp), C(a.b), a.g.n, C(a.w), om, C(a.e),
+                                  a.g.n, st, gate);
+    }
+    launch_mg_correct<double, R>(s, bc, f.g, c->lv[1].g, f.L, nrhs, bin, f.g.n, C(f.w), C(c->lv[1].e),
+                                 C(f.tmp), st, gate);
+    launch_mg_smooth<double, R, double>(s, bc, f.g, f.L, nrhs, C(f.tmp), bin, f.g.n, C(f.w), om, bout,
+                                        f.g.n, st, gate);
+}
+
+void enqueue_vcycle(hh_ctx* c, hipStream_t s, int nrhs, const c128* bin, c128* bout,
+                    const RhsState* st, int gate) {
+    if (c->mixed) enqueue_vcycle_t<float>(c, s, nrhs, bin, bout, st, gate);
+    else enqueue_vcycle_t<double>(c, s, nrhs, bin, bout, st, gate);
+}
+
+// One Bi-CGSTAB step for all right-hand sides still iterating (device-side scalars).
+void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs) {
+    const Geo& g = c->lv[0].g;
+    const long long n = g.n;
+    const long long nb = c->nblk0;
+    const int bc = c->cfg.bc;
+    Launch F = c->L0;
+    F.flat_cap = (int)nb;  // flat kernels use exactly nblk0 workgroups: same partial count
+    launch_finalize(s, FIN_RHO, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
+    launch_p_update(s, n, nrhs, c->p, c->r, c->v, c->st, F);
+    enqueue_vcycle(c, s, nrhs, c->p, c->ph, c->st, ST_RUN);
+    launch_apply(s, bc, OP_V, g, c->L0, nrhs, c->ph, c->v, c->k2, c->kb, 1.0, 0.0, c->rhat, c->part,
+                 NBLK_CAP, c->st, ST_RUN);
+    launch_finalize(s, FIN_ALPHA, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
+    launch_s_update(s, n, nrhs, c->s, c->r, c->v, c->st, c->part, NBLK_CAP, F);
+    launch_finalize(s, FIN_S, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
+    launch_x_half(s, n, nrhs, c->xk, c->ph, c->st, F);
+    enqueue_vcycle(c, s, nrhs, c->s, c->sh, c->st, ST_RUN);
+    launch_apply(s, bc, OP_T, g, c->L0, nrhs, c->sh, c->t, c->k2, c->kb, 1.0, 0.0, c->s, c->part,
+                 NBLK_CAP, c->st, ST_RUN);
+    launch_finalize(s, FIN_OMEGA, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
+    launch_update_xr(s, n, nrhs, c->xk, c->r, c->ph, c->sh, c->s, c->t, c->rhat, c->st, c->part,
+                     NBLK_CAP, F);
+}
+
+hh_status get_graph(hh_ctx* c, int nrhs, hipGraphExec_t* out) {
+    auto it = c->graphs.find(nrhs);
+    if (it != c->graphs.end()) {
+        *out = it->second;
+        return HH_OK;
+    }
+    hipGraph_t graph = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+    enqueue_iteration(c, c->cap, nrhs);
+    hipError_t le = hipGetLastError();
+    hipError_t ee = hipStreamEndCapture(c->cap, &graph);
+    if (le != hipSuccess) return fail(c, HH_ERR_HIP, "launch during capture: %s", hipGetErrorString(le));
+    if (ee != hipSuccess) return fail(c, HH_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(c, HH_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    c->graphs[nrhs] = exec;
+    *out = exec;
+    return HH_OK;
+}
+
+hh_status read_states(hh_ctx* c, int nrhs) {
+    HIPCHK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HH_OK;
+}
+
+// Dense inverse of the coarsest rediscretised M over its unknowns (Gauss-Jordan
+// with partial pivoting in complex double), stored column-major.
+hh_status build_coarse(hh_ctx* c) {
+    LevelBuf& cl = c->lv.back();
+    const Geo& g = cl.g;
+    std::vector<double> k(g.n);
+    HIPCHK(c, hipMemcpy(k.data(), cl.k, sizeof(double) * g.n, hipMemcpyDeviceToHost));
+    const bool som = c->cfg.bc == HH_BC_SOMMERFELD;
+    std::vector<int> node_of, unk_of(g.n, -1);
+    for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y)
+            for (int x = 0; x < g.nx; ++x) {
+                const bool bnd = x == 0 || y == 0 || z == 0 || x == g.nx - 1 || y == g.ny - 1 || z == g.nz - 1;
+                if (som || !bnd) {
+                    const int id = (z * g.ny + y) * g.nx + x;
+                    unk_of[id] = (int)node_of.size();
+                    node_of.push_back(id);
+                }
+            }
+    const int n = (int)node_of.size();
+    if (n > COARSE_UNK_CAP)
+        return fail(c, HH_ERR_ARG, "coarsest grid has %d unknowns (> %d); use more levels", n, COARSE_UNK_CAP);
+    typedef std::complex<double> C;
+    std::vector<C> a((size_t)n * n, C(0, 0)), inv((size_t)n * n, C(0, 0));
+    const double ih2 = 1.0 / (g.h * g.h);
+    const C sigma(c->cfg.beta1, -c->cfg.beta2);
+    for (int u = 0; u < n; ++u) {
+        const int id = node_of[u];
+        const int x = id % g.nx, y = (id / g.nx) % g.ny, z = id / g.plane;
+        const int pos[3] = {x, y, z};
+        const int ext[3] = {g.nx, g.ny, g.nz};
+        const int str[3] = {1, g.nx, g.plane};
+        C d = 6.0 * ih2 - sigma * (k[id] * k[id]);
+        for (int ax = 0; ax < 3; ++ax)
+            for (int dir = -1; dir <= 1; dir += 2) {
+                const int q = pos[ax] + dir;
+                int nb;
+                if (q >= 0 && q < ext[ax]) {
+                    nb = id + dir * str[ax];
+                } else {
+                    // eliminated ghost: mirror neighbour, diagonal -2ik/h
+                    nb = id - dir * str[ax];
+                    d -= C(0.0, 2.0 * k[id] / g.h);
+                }
+                const int col = unk_of[nb];
+                if (col >= 0) a[(size_t)u * n + col] -= ih2;
+            }
+        a[(size_t)u * n + u] += d;
+    }
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        double best = std::abs(a[(size_t)col * n + col]);
+        for (int r = col + 1; r < n; ++r) {
+            double v = std::abs(a[(size_t)r * n + col]);
+            if (v > best) best = v, piv = r;
+        }
+        if (best == 0.0 || !std::isfinite(best)) return fail(c, HH_ERR_NUMERIC, "coarsest M is singular");
+        if (piv != col)
+            for (int j = 0; j < n; ++j) {
+                std::swap(a[(size_t)piv * n + j], a[(size_t)col * n + j]);
+                std::swap(inv[(size_t)piv * n + j], inv[(size_t)col * n + j]);
+            }
+        const C dinv = 1.0 / a[(size_t)col * n + col];
+        for (int j = 0; j < n; ++j) {
+            a[(size_t)col * n + j] *= dinv;
+            inv[(size_t)col * n + j] *= dinv;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            const C f = a[(size_t)r * n + col];
+            if (f == C(0, 0)) continue;
+            for (int j = 0; j < n; ++j) {
+                a[(size_t)r * n + j] -= f * a[(size_t)col * n + j];
+                inv[(size_t)r * n + j] -= f * inv[(size_t)col * n + j];
+            }
+        }
+    }
+    c->n_unk = n;
+    (void)hipFree(c->cidx);
+    (void)hipFree(c->minv);
+    c->cidx = nullptr;
+    c->minv = nullptr;
+    CHK(dalloc(c, &c->cidx, sizeof(int) * n));
+    HIPCHK(c, hipMemcpy(c->cidx, node_of.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+    if (c->mixed) {
+        std::vector<c64> cm((size_t)n * n);
+        for (int r = 0; r < n; ++r)
+            for (int j = 0; j < n; ++j)
+                cm[(size_t)j * n + r] = c64{(float)inv[(size_t)r * n + j].real(), (float)inv[(size_t)r * n + j].imag()};
+        CHK(dalloc(c, (c64**)&c->minv, sizeof(c64) * cm.size()));
+        HIPCHK(c, hipMemcpy(c->minv, cm.data(), sizeof(c64) * cm.size(), hipMemcpyHostToDevice));
+    } else {
+        std::vector<c128> cm((size_t)n * n);
+        for (int r = 0; r < n; ++r)
+            for (int j = 0; j < n; ++j)
+                cm[(size_t)j * n + r] = c128{inv[(size_t)r * n + j].real(), inv[(size_t)r * n + j].imag()};
+        CHK(dalloc(c, (c128**)&c->minv, sizeof(c128) * cm.size()));
+        HIPCHK(c, hipMemcpy(c->minv, cm.data(), sizeof(c128) * cm.size(), hipMemcpyHostToDevice));
+    }
+    return HH_OK;
+}
+
+hh_status check_ready(hh_ctx* c, int nrhs) {
+    if (!c) return HH_ERR_ARG;
+    if (!c->model_set) return fail(c, HH_ERR_STATE, "hh_set_model has not been called");
+    if (nrhs < 1 || nrhs > c->cfg.nrhs_max)
+        return fail(c, HH_ERR_ARG, "nrhs=%d outside 1..%d", nrhs, c->cfg.nrhs_max);
+    return HH_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void hh_default_config(hh_config* cfg, int nx, int ny, int nz, double h) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->nx = nx;
+    cfg->ny = ny;
+    cfg->nz = nz;
+    cfg->h = h;
+    cfg->bc = HH_BC_SOMMERFELD;
+    cfg->beta1 = 1.0;
+    cfg->beta2 = -0.5;
+    cfg->omega = 0.8;
+    cfg->n_levels = 0;
+    cfg->prec = HH_PREC_FP64;
+    cfg->nrhs_max = 1;
+}
+
+const char* hh_last_error(const hh_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
+    if (!cfg || !out) return fail(nullptr, HH_ERR_ARG, "null argument");
+    *out = nullptr;
+    const int dims[3] = {cfg->nx, cfg->ny, cfg->nz};
+    for (int d : dims)
+        if (d < 3 || d % 2 == 0) return fail(nullptr, HH_ERR_ARG, "every axis needs an odd node count >= 3 (got %d)", d);
+    if (!(cfg->h > 0.0) || !std::isfinite(cfg->h)) return fail(nullptr, HH_ERR_ARG, "h must be > 0");
+    if (cfg->bc != HH_BC_DIRICHLET && cfg->bc != HH_BC_SOMMERFELD) return fail(nullptr, HH_ERR_ARG, "bad bc");
+    if (cfg->prec != HH_PREC_FP64 && cfg->prec != HH_PREC_MIXED) return fail(nullptr, HH_ERR_ARG, "bad prec");
+    if (cfg->nrhs_max < 1 || cfg->nrhs_max > NRHS_LIMIT)
+        return fail(nullptr, HH_ERR_ARG, "nrhs_max must be in 1..%d", NRHS_LIMIT);
+    if (!(cfg->omega > 0.0 && cfg->omega <= 1.0)) return fail(nullptr, HH_ERR_ARG, "omega must be in (0, 1]");
+    // level shapes
+    std::vector<Geo> shapes;
+    shapes.push_back(make_geo(cfg->nx, cfg->ny, cfg->nz, cfg->h));
+    if (cfg->n_levels > 0) {
+        for (int l = 1; l < cfg->n_levels; ++l) {
+            const Geo& g = shapes.back();
+            if ((g.nx - 1) % 2 || (g.ny - 1) % 2 || (g.nz - 1) % 2 || std::min({g.nx, g.ny, g.nz}) < 5)
+                return fail(nullptr, HH_ERR_ARG, "cannot coarsen %dx%dx%d to %d levels", cfg->nx, cfg->ny,
+                            cfg->nz, cfg->n_levels);
+            shapes.push_back(make_geo((g.nx - 1) / 2 + 1, (g.ny - 1) / 2 + 1, (g.nz - 1) / 2 + 1, g.h * 2));
+        }
+    } else {
+        while (true) {
+            const Geo& g = shapes.back();
+            if ((g.nx - 1) % 2 || (g.ny - 1) % 2 || (g.nz - 1) % 2) break;
+            if (std::min({(g.nx - 1) / 2 + 1, (g.ny - 1) / 2 + 1, (g.nz - 1) / 2 + 1}) < 3) break;
+            shapes.push_back(make_geo((g.nx - 1) / 2 + 1, (g.ny - 1) / 2 + 1, (g.nz - 1) / 2 + 1, g.h * 2));
+        }
+    }
+    if (shapes.size() < 2) return fail(nullptr, HH_ERR_ARG, "grid cannot be coarsened (need at least 2 levels)");
+
+    hh_ctx* c = new hh_ctx();
+    c->cfg = *cfg;
+    c->cfg.n_levels = (int)shapes.size();
+    c->stream = (hipStream_t)hip_stream;
+    c->mixed = cfg->prec == HH_PREC_MIXED;
+    c->csize = c->mixed ? sizeof(c64) : sizeof(c128);
+    (void)hipGetDevice(&c->device);
+    auto bail = [&](hh_status s) {
+        g_create_error = c->err;
+        free_all(c);
+        delete c;
+        return s;
+    };
+    if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(c, HH_ERR_HIP, "hipStreamCreateWithFlags failed"));
+    const int R = cfg->nrhs_max;
+    const int L = (int)shapes.size();
+    c->lv.resize(L);
+    for (int l = 0; l < L; ++l) {
+        LevelBuf& B = c->lv[l];
+        B.g = shapes[l];
+        const size_t nn = (size_t)B.g.n;
+        hh_status s;
+        if ((s = dalloc(c, &B.k, sizeof(double) * nn)) != HH_OK) return bail(s);
+        if ((s = dalloc(c, (char**)&B.w, c->csize * nn)) != HH_OK) return bail(s);
+        if (l < L - 1)
+            if ((s = dalloc(c, (char**)&B.tmp, c->csize * nn * R)) != HH_OK) return bail(s);
+        if (l >= 1) {
+            if ((s = dalloc(c, (char**)&B.b, c->csize * nn * R)) != HH_OK) return bail(s);
+            if ((s = dalloc(c, (char**)&B.e, c->csize * nn * R)) != HH_OK) return bail(s);
+        }
+    }
+    const size_t n0 = (size_t)shapes[0].n;
+    c128** vecs[] = {&c->bsrc, &c->xk, &c->r, &c->rhat, &c->p, &c->v, &c->s, &c->t, &c->ph, &c->sh};
+    for (c128** q : vecs) {
+        hh_status s = dalloc(c, q, sizeof(c128) * n0 * R);
+        if (s != HH_OK) return bail(s);
+    }
+    hh_status s;
+    if ((s = dalloc(c, &c->k2, sizeof(double) * n0)) != HH_OK) return bail(s);
+    if ((s = dalloc(c, &c->kb, sizeof(double) * n0)) != HH_OK) return bail(s);
+    if ((s = dalloc(c, &c->st, sizeof(RhsState) * R)) != HH_OK) return bail(s);
+    if ((s = dalloc(c, &c->part, sizeof(double) * (size_t)R * NSLOT * MAX_TERMS * NBLK_CAP)) != HH_OK)
+        return bail(s);
+    if ((s = dalloc(c, &c->bad, sizeof(int))) != HH_OK) return bail(s);
+    if (hipHostMalloc((void**)&c->st_host, sizeof(RhsState) * R, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->bad_host, sizeof(int), hipHostMallocDefault) != hipSuccess)
+        return bail(fail(c, HH_ERR_OOM, "hipHostMalloc failed"));
+    // zero everything once so no kernel ever reads uninitialised memory
+    hipError_t ze = hipSuccess;
+    auto zero = [&](void* q, size_t bytes) {
+        if (q && ze == hipSuccess) ze = hipMemsetAsync(q, 0, bytes, c->stream);
+    };
+    for (auto& B : c->lv) {
+        zero(B.k, sizeof(double) * B.g.n);
+        zero(B.w, c->csize * B.g.n);
+        zero(B.tmp, c->csize * B.g.n * R);
+        zero(B.b, c->csize * B.g.n * R);
+        zero(B.e, c->csize * B.g.n * R);
+    }
+    for (c128** q : vecs) zero(*q, sizeof(c128) * n0 * R);
+    zero(c->k2, sizeof(double) * n0);
+    zero(c->kb, sizeof(double) * n0);
+    zero(c->st, sizeof(RhsState) * R);
+    zero(c->part, sizeof(double) * (size_t)R * NSLOT * MAX_TERMS * NBLK_CAP);
+    launch_fill_status(c->stream, R, c->st, ST_IDLE, 0);
+    if (ze != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess)
+        return bail(fail(c, HH_ERR_HIP, "initialisation failed"));
+    c->base.block = 256;
+    c->base.zb = 0;
+    apply_launch(c);
+    *out = c;
+    return HH_OK;
+}
+
+hh_status hh_destroy(hh_ctx* ctx) {
+    if (!ctx) return HH_OK;
+    (void)hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+    return HH_OK;
+}
+
+hh_status hh_level_shape(const hh_ctx* ctx, int l, int* nx, int* ny, int* nz, int* n_levels) {
+    if (!ctx) return HH_ERR_ARG;
+    if (n_levels) *n_levels = (int)ctx->lv.size();
+    if (l < 0 || l >= (int)ctx->lv.size()) return HH_ERR_ARG;
+    if (nx) *nx = ctx->lv[l].g.nx;
+    if (ny) *ny = ctx->lv[l].g.ny;
+    if (nz) *nz = ctx->lv[l].g.nz;
+    return HH_OK;
+}
+
+hh_status hh_set_model(hh_ctx* c, const double* k) {
+    if (!c || !k) return c ? fail(c, HH_ERR_ARG, "null k") : HH_ERR_ARG;
+    c->model_set = false;
+    LevelBuf& f = c->lv[0];
+    HIPCHK(c, hipMemsetAsync(c->bad, 0, sizeof(int), c->stream));
+    launch_model_check(c->stream, f.g.n, k, c->k2, c->kb, c->bad);
+    HIPCHK(c, hipMemcpyAsync(f.k, k, sizeof(double) * f.g.n, hipMemcpyDeviceToDevice, c->stream));
+    for (size_t l = 1; l < c->lv.size(); ++l)
+        launch_inject(c->stream, c->lv[l - 1].g, c->lv[l].g, c->lv[l - 1].k, c->lv[l].k);
+    for (auto& B : c->lv) {
+        if (c->mixed)
+            launch_make_w<float>(c->stream, B.g, c->cfg.bc, B.k, c->cfg.beta1, c->cfg.beta2, c->cfg.omega,
+                                 (c64*)B.w);
+        else
+            launch_make_w<double>(c->stream, B.g, c->cfg.bc, B.k, c->cfg.beta1, c->cfg.beta2, c->cfg.omega,
+                                  (c128*)B.w);
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->bad_host, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (*c->bad_host) return fail(c, HH_ERR_NUMERIC, "k holds %d NaN/Inf or negative values", *c->bad_host);
+    CHK(build_coarse(c));
+    c->model_set = true;
+    return HH_OK;
+}
+
+hh_status hh_set_sources(hh_ctx* c, const void* b, int nrhs) {
+    if (!c || !b) return c ? fail(c, HH_ERR_ARG, "null b") : HH_ERR_ARG;
+    if (nrhs < 1 || nrhs > c->cfg.nrhs_max) return fail(c, HH_ERR_ARG, "nrhs=%d outside 1..%d", nrhs, c->cfg.nrhs_max);
+    launch_copy_rhs(c->stream, c->lv[0].g, c->cfg.bc, nrhs, (const c128*)b, c->bsrc);
+    HIPCHK(c, hipGetLastError());
+    c->nrhs_cur = nrhs;
+    return HH_OK;
+}
+
+hh_status hh_set_point_sources(hh_ctx* c, const int* ijk, int nrhs) {
+    if (!c || !ijk) return c ? fail(c, HH_ERR_ARG, "null ijk") : HH_ERR_ARG;
+    if (nrhs < 1 || nrhs > c->cfg.nrhs_max) return fail(c, HH_ERR_ARG, "nrhs=%d outside 1..%d", nrhs, c->cfg.nrhs_max);
+    const Geo& g = c->lv[0].g;
+    for (int r = 0; r < nrhs; ++r) {
+        const int iz = ijk[3 * r], iy = ijk[3 * r + 1], ix = ijk[3 * r + 2];
+        if (iz < 0 || iy < 0 || ix < 0 || iz >= g.nz || iy >= g.ny || ix >= g.nx)
+            return fail(c, HH_ERR_ARG, "source %d at (%d,%d,%d) outside the grid", r, iz, iy, ix);
+        if (c->cfg.bc == HH_BC_DIRICHLET &&
+            (iz == 0 || iy == 0 || ix == 0 || iz == g.nz - 1 || iy == g.ny - 1 || ix == g.nx - 1))
+            return fail(c, HH_ERR_ARG, "source %d lies on the Dirichlet boundary", r);
+    }
+    HIPCHK(c, hipMemsetAsync(c->bsrc, 0, sizeof(c128) * g.n * nrhs, c->stream));
+    const double val = 1.0 / (g.h * g.h * g.h);
+    for (int r = 0; r < nrhs; ++r) {
+        const long long off = (long long)r * g.n + (long long)ijk[3 * r] * g.plane +
+                              (long long)ijk[3 * r + 1] * g.nx + ijk[3 * r + 2];
+        launch_set_point(c->stream, off, val, c->bsrc);
+    }
+    HIPCHK(c, hipGetLastError());
+    c->nrhs_cur = nrhs;
+    return HH_OK;
+}
+
+hh_status hh_apply_operator(hh_ctx* c, const void* x, void* y, int nrhs) {
+    CHK(check_ready(c, nrhs));
+    if (!x || !y) return fail(c, HH_ERR_ARG, "null pointer");
+    launch_apply(c->stream, c->cfg.bc, OP_PLAIN, c->lv[0].g, c->L0, nrhs, (const c128*)x, (c128*)y, c->k2,
+                 c->kb, 1.0, 0.0, nullptr, nullptr, NBLK_CAP, nullptr, GATE_ALL);
+    HIPCHK(c, hipGetLastError());
+    return HH_OK;
+}
+
+hh_status hh_apply_shifted(hh_ctx* c, const void* x, void* y, int nrhs) {
+    CHK(check_ready(c, nrhs));
+    if (!x || !y) return fail(c, HH_ERR_ARG, "null pointer");
+    launch_apply(c->stream, c->cfg.bc, OP_PLAIN, c->lv[0].g, c->L0, nrhs, (const c128*)x, (c128*)y, c->k2,
+                 c->kb, c->cfg.beta1, -c->cfg.beta2, nullptr, nullptr, NBLK_CAP, nullptr, GATE_ALL);
+    HIPCHK(c, hipGetLastError());
+    return HH_OK;
+}
+
+hh_status hh_apply_vcycle(hh_ctx* c, const void* r, void* z, int nrhs) {
+    CHK(check_ready(c, nrhs));
+    if (!r || !z) return fail(c, HH_ERR_ARG, "null pointer");
+    enqueue_vcycle(c, c->stream, nrhs, (const c128*)r, (c128*)z, nullptr, GATE_ALL);
+    HIPCHK(c, hipGetLastError());
+    return HH_OK;
+}
+
+hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_stats* stats) {
+    if (!c) return HH_ERR_ARG;
+    if (c->nrhs_cur < 1) return fail(c, HH_ERR_STATE, "no right-hand side set");
+    const int nrhs = c->nrhs_cur;
+    CHK(check_ready(c, nrhs));
+    if (!x) return fail(c, HH_ERR_ARG, "null x");
+    if (!(rtol > 0.0) || maxit < 1) return fail(c, HH_ERR_ARG, "need rtol > 0 and maxit >= 1");
+    const Geo& g = c->lv[0].g;
+    const size_t bytes = sizeof(c128) * g.n * nrhs;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    if (use_x0) HIPCHK(c, hipMemcpyAsync(c->xk, x, bytes, hipMemcpyDeviceToDevice, c->stream));
+    launch_fill_status(c->stream, nrhs, c->st, ST_RUN, 2 * maxit);
+    launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->k2,
+                c->kb, use_x0, c->part, NBLK_CAP, c->st, ST_RUN);
+    launch_finalize(c->stream, FIN_INIT, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, rtol);
+    HIPCHK(c, hipGetLastError());
+    CHK(read_states(c, nrhs));
+    // b = 0: the solution is x = 0
+    for (int r = 0; r < nrhs; ++r)
+        if (c->st_host[r].bnorm2 == 0.0)
+            HIPCHK(c, hipMemsetAsync(c->xk + (size_t)r * g.n, 0, sizeof(c128) * g.n, c->stream));
+    hipGraphExec_t exec = nullptr;
+    if (c->use_graph) CHK(get_graph(c, nrhs, &exec));
+    int guard = 0;
+    while (true) {
+        bool any_run = false;
+        for (int r = 0; r < nrhs; ++r) any_run |= c->st_host[r].status == ST_RUN;
+        if (any_run) {
+            for (int k = 0; k < c->check_every; ++k) {
+                if (exec) HIPCHK(c, hipGraphLaunch(exec, c->stream));
+                else enqueue_iteration(c, c->stream, nrhs);
+            }
+            HIPCHK(c, hipGetLastError());
+            CHK(read_states(c, nrhs));
+            if (++guard > 4 * (maxit + 8) * (MAX_RESTARTS + 1)) return fail(c, HH_ERR_STATE, "driver did not terminate");
+            continue;
+        }
+        // every right-hand side stopped: recompute the true residual b - A x;
+        // a converged one whose true residual misses rtol restarts from x
+        launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->k2,
+                    c->kb, 1, c->part, NBLK_CAP, c->st, GATE_FINISHED);
+        launch_finalize(c->stream, FIN_TRUE, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, rtol);
+        HIPCHK(c, hipGetLastError());
+        CHK(read_states(c, nrhs));
+        bool restarted = false;
+        for (int r = 0; r < nrhs; ++r) restarted |= c->st_host[r].status == ST_RUN;
+        if (!restarted) break;
+    }
+    HIPCHK(c, hipMemcpyAsync(x, c->xk, bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    hh_status worst = HH_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        const RhsState& S = c->st_host[r];
+        hh_status sr;
+        switch (S.status) {
+            case ST_CONV: sr = HH_OK; break;
+            case ST_BREAK: sr = HH_ERR_BREAKDOWN; break;
+            case ST_MAXIT: sr = HH_ERR_NOT_CONVERGED; break;
+            case ST_NUMERIC: sr = HH_ERR_NUMERIC; break;
+            default: sr = HH_ERR_STATE; break;
+        }
+        if (S.status == ST_CONV && S.bnorm2 > 0.0 && S.true_rnorm2 > S.tol2) sr = HH_ERR_NOT_CONVERGED;
+        if (stats) {
+            hh_stats& o = stats[r];
+            o.iterations = 0.5 * S.iters2;
+            o.matvecs = S.matvecs;
+            o.relres = S.bnorm2 > 0.0 ? std::sqrt(S.rnorm2 / S.bnorm2) : 0.0;
+            o.relres_true = S.bnorm2 > 0.0 ? std::sqrt(S.true_rnorm2 / S.bnorm2) : 0.0;
+            o.status = sr;
+            o.restarts = S.restarts;
+        }
+        if (worst == HH_OK && sr != HH_OK) worst = sr;
+    }
+    c->last_ms = ms;
+    c->err = worst == HH_OK ? std::string() : std::string("not every right-hand side converged");
+    return worst;
+}
+
+hh_status hh_adjoint_rhs(hh_ctx* c, const void* g, void* rhs, int nrhs) {
+    CHK(check_ready(c, nrhs));
+    if (!g || !rhs) return fail(c, HH_ERR_ARG, "null pointer");
+    launch_adjoint_rhs(c->stream, c->lv[0].g, c->cfg.bc, nrhs, (const c128*)g, (c128*)rhs);
+    HIPCHK(c, hipGetLastError());
+    return HH_OK;
+}
+
+hh_status hh_grad_slowness2(hh_ctx* c, const void* u, const void* w, const double* s, double omega,
+                            double* grad, int nrhs) {
+    CHK(check_ready(c, nrhs));
+    if (!u || !w || !s || !grad) return fail(c, HH_ERR_ARG, "null pointer");
+    launch_grad_s(c->stream, c->lv[0].g, c->cfg.bc, nrhs, (const c128*)u, (const c128*)w, s, omega, grad);
+    HIPCHK(c, hipGetLastError());
+    return HH_OK;
+}
+
+hh_status hh_set_option(hh_ctx* c, const char* name, long long value) {
+    if (!c || !name) return HH_ERR_ARG;
+    std::string n(name);
+    if (n == "graph") {
+        c->use_graph = value != 0;
+    } else if (n == "check_every") {
+        if (value < 1 || value > 1000) return fail(c, HH_ERR_ARG, "check_every must be in 1..1000");
+        c->check_every = (int)value;
+    } else if (n == "block") {
+        if (value != 64 && value != 128 && value != 256 && value != 512)
+            return fail(c, HH_ERR_ARG, "block must be 64, 128, 256 or 512");
+        c->base.block = (int)value;
+        apply_launch(c);
+    } else if (n == "zb") {
+        if (value < 0 || value > 1024) return fail(c, HH_ERR_ARG, "zb must be in 0..1024");
+        c->base.zb = (int)value;
+        apply_launch(c);
+    } else {
+        return fail(c, HH_ERR_ARG, "unknown option '%s'", name);
+    }
+    return HH_OK;
+}
+
+hh_status hh_get_option(const hh_ctx* c, const char* name, long long* value) {
+    if (!c || !name || !value) return HH_ERR_ARG;
+    std::string n(name);
+    if (n == "graph") *value = c->use_graph;
+    else if (n == "check_every") *value = c->check_every;
+    else if (n == "block") *value = c->L0.block;
+    else if (n == "zb") *value = c->L0.zb;
+    else if (n == "n_levels") *value = (long long)c->lv.size();
+    else if (n == "coarse_unknowns") *value = c->n_unk;
+    else return HH_ERR_ARG;
+    return HH_OK;
+}
+
+hh_status hh_time_kernel(hh_ctx* c, int which, int nrhs, int reps, float* ms_avg) {
+    CHK(check_ready(c, nrhs));
+    if (reps < 1 || !ms_avg) return fail(c, HH_ERR_ARG, "reps >= 1 and ms_avg required");
+    const Geo& g = c->lv[0].g;
+    const int bc = c->cfg.bc;
+    Launch F = c->L0;
+    F.flat_cap = (int)c->nblk0;
+    launch_fill_status(c->stream, nrhs, c->st, ST_RUN, 2);
+    auto one = [&]() {
+        switch (which) {
+            case 0:
+                launch_apply(c->stream, bc, OP_T, g, c->L0, nrhs, c->sh, c->t, c->k2, c->kb, 1.0, 0.0, c->s,
+                             c->part, NBLK_CAP, c->st, ST_RUN);
+                break;
+            case 1:
+                launch_update_xr(c->stream, g.n, nrhs, c->xk, c->r, c->ph, c->sh, c->s, c->t, c->rhat, c->st,
+                                 c->part, NBLK_CAP, F);
+                break;
+            case 2:
+                if (c->mixed)
+                    launch_mg_resid<double, float>(c->stream, bc, g, c->L0, nrhs, c->p, g.n, (c64*)c->lv[0].w,
+                                                   c->cfg.omega, (c64*)c->lv[0].tmp, c->st, ST_RUN);
+                else
+                    launch_mg_resid<double, double>(c->stream, bc, g, c->L0, nrhs, c->p, g.n, (c128*)c->lv[0].w,
+                                                    c->cfg.omega, (c128*)c->lv[0].tmp, c->st, ST_RUN);
+                break;
+            case 3:
+                if (c->mixed)
+                    launch_mg_restrict<float>(c->stream, bc, g, c->lv[1].g, c->lv[1].L, nrhs, (c64*)c->lv[0].tmp,
+                                              (c64*)c->lv[1].b, c->st, ST_RUN);
+                else
+                    launch_mg_restrict<double>(c->stream, bc, g, c->lv[1].g, c->lv[1].L, nrhs, (c128*)c->lv[0].tmp,
+                                               (c128*)c->lv[1].b, c->st, ST_RUN);
+                break;
+            case 4:
+                if (c->mixed)
+                    launch_mg_correct<double, float>(c->stream, bc, g, c->lv[1].g, c->L0, nrhs, c->p, g.n,
+                                                     (c64*)c->lv[0].w, (c64*)c->lv[1].e, (c64*)c->lv[0].tmp,
+                                                     c->st, ST_RUN);
+                else
+                    launch_mg_correct<double, double>(c->stream, bc, g, c->lv[1].g, c->L0, nrhs, c->p, g.n,
+                                                      (c128*)c->lv[0].w, (c128*)c->lv[1].e,
+                                                      (c128*)c->lv[0].tmp, c->st, ST_RUN);
+                break;
+            default:
+                if (c->mixed)
+                    launch_mg_smooth<double, float, double>(c->stream, bc, g, c->L0, nrhs, (c64*)c->lv[0].tmp,
+                                                            c->p, g.n, (c64*)c->lv[0].w, c->cfg.omega, c->ph,
+                                                            g.n, c->st, ST_RUN);
+                else
+                    launch_mg_smooth<double, double, double>(c->stream, bc, g, c->L0, nrhs,
+                                                             (c128*)c->lv[0].tmp, c->p, g.n,
+                                                             (c128*)c->lv[0].w, c->cfg.omega, c->ph, g.n,
+                                                             c->st, ST_RUN);
+                break;
+        }
+    };
+    if (which < 0 || which > 5) return fail(c, HH_ERR_ARG, "unknown kernel id %d", which);
+    one();  // warm-up
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int i = 0; i < reps; ++i) one();
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    HIPCHK(c, hipGetLastError());
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_avg = ms / reps;
+    launch_fill_status(c->stream, c->cfg.nrhs_max, c->st, ST_IDLE, 0);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HH_OK;
+}
+
+hh_status hh_autotune(hh_ctx* c, int nrhs) {
+    CHK(check_ready(c, nrhs));
+    const int blocks[] = {64, 128, 256, 512};
+    const int zbs[] = {2, 4, 8, 16, 32};
+    Launch best = c->base;
+    float best_ms = 1e30f;
+    for (int b : blocks)
+        for (int z : zbs) {
+            c->base.block = b;
+            c->base.zb = z;
+            apply_launch(c);
+            float tot = 0.f;
+            for (int which : {0, 2, 4, 5}) {
+                float ms = 0.f;
+                CHK(hh_time_kernel(c, which, nrhs, 5, &ms));
+                tot += ms;
+            }
+            if (tot < best_ms) {
+                best_ms = tot;
+                best = c->base;
+            }
+        }
+    c->base = best;
+    apply_launch(c);
+    return HH_OK;
+}
+
+}  // extern "C"
