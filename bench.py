@@ -44,10 +44,10 @@ METRIC = "DoF-iterations/s of CSLP-Bi-CGSTAB, mixed vs FP64 at 1e-6 rel residual
 KERNELS = {
     0: ("apply_A+dots", 2, (16 + 8 + 16 + 16, 16 + 8 + 16 + 16)),
     1: ("update_xr+dots", 1, (6 * 16 + 2 * 16, 6 * 16 + 2 * 16)),
-    2: ("mg_resid_L0", 2, (16 + 16 + 16, 16 + 8 + 8)),
-    3: ("mg_restrict_L0", 2, (16 + 2, 8 + 1)),
-    4: ("mg_correct_L0", 2, (16 + 16 + 2 + 16, 16 + 8 + 1 + 8)),
-    5: ("mg_smooth_L0", 2, (16 + 16 + 16 + 16, 8 + 16 + 8 + 16)),
+    2: ("mg_down_L0", 2, (16 + 16 + 16 / 8, 16 + 8 + 8 / 8)),
+    3: ("mg_up_L0", 2, (16 + 16 + 16 / 8 + 16, 16 + 8 + 8 / 8 + 16)),
+    4: ("p_update", 1, (4 * 16, 4 * 16)),
+    5: ("s_update+dot", 1, (3 * 16, 3 * 16)),
 }
 
 # HBM traffic per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
@@ -121,7 +121,8 @@ def kernel_roofline(solver, nrhs, prec_idx, n_nodes, reps=20):
     for kid, (name, per_iter, nbytes) in KERNELS.items():
         ms = solver.time_kernel(kid, nrhs=nrhs, reps=reps)
         algo = nbytes[prec_idx] * n_nodes * nrhs
-        rows[name] = {"ms": ms, "per_iter": per_iter, "bytes": algo, "GBs": algo / (ms * 1e-3) / 1e9}
+        rows[name] = {"ms": ms, "per_iter": per_iter, "bytes": int(algo),
+                      "GBs": algo / (ms * 1e-3) / 1e9}
     dom = max(rows, key=lambda k: rows[k]["ms"] * rows[k]["per_iter"])
     return dom, rows
 

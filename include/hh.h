@@ -158,8 +158,9 @@ hh_status hh_grad_slowness2(hh_ctx* ctx, const void* u, const void* w, const dou
 
 /* Options: "graph" (1 = replay each Bi-CGSTAB step as a captured hipGraph,
  * default 1), "check_every" (steps between host convergence checks, default 4),
- * "block" (threads per workgroup of the fine-grid kernels: 64, 128, 256, 512),
- * "zb" (z-planes per workgroup, 0 = automatic). */
+ * "block" (threads per workgroup of the stencil kernels: 64, 128, 256, 512),
+ * "zb" (z-planes per workgroup of the stencil kernels, 0 = automatic).
+ * hh_get_option also reports "n_levels", "coarse_unknowns", "zb_down", "zb_up". */
 hh_status hh_set_option(hh_ctx* ctx, const char* name, long long value);
 hh_status hh_get_option(const hh_ctx* ctx, const char* name, long long* value);
 
@@ -167,9 +168,11 @@ hh_status hh_get_option(const hh_ctx* ctx, const char* name, long long* value);
  * on the context stream, exactly as hh_solve launches it (same grid, same
  * workgroup shape), on the context's scratch vectors, and return the average
  * duration in milliseconds measured with HIP events on that stream.
- * which: 0 = y = A x with fused partial dot products, 1 = the Krylov x/r update,
- * 2 = fine-level smoother + residual, 3 = fine-level restriction,
- * 4 = fine-level prolongation + correction, 5 = fine-level post-smoother.
+ * which: 0 = t = A s_hat with the fused partial dot products, 1 = the Krylov
+ * x / r update with its dot products, 2 = fused multigrid down pass on the
+ * finest level (smoother + residual + restriction), 3 = fused up pass on the
+ * finest level (prolongation + correction + post-smoother), 4 = p update,
+ * 5 = s update with ||s||^2.
  * Requires hh_set_model.  Overwrites internal scratch only. */
 hh_status hh_time_kernel(hh_ctx* ctx, int which, int nrhs, int reps, float* ms_avg_host);
 

@@ -1,0 +1,73 @@
+// Device helpers shared by the kernel translation units.
+#pragma once
+#include "hh_common.h"
+#include "hh_kernels.h"
+
+namespace hh {
+
+__device__ __forceinline__ bool gate_ok(const RhsState* st, int r, int gate) {
+    if (st == nullptr || gate == GATE_ALL) return true;
+    int s = st[r].status;
+    if (gate == GATE_FINISHED) return s != ST_RUN && s != ST_IDLE && s != ST_HALF;
+    return s == gate;
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> czero() { return cx<R>{R(0), R(0)}; }
+
+// Deterministic block reduction of NT doubles: butterfly within each 64-lane
+// wavefront, then wavefront partials summed by thread 0 in wave order.  The
+// result goes to out[t * stride] for t < NT.
+template <int NT>
+__device__ __forceinline__ void block_sum_store(double (&v)[NT], double* out, long long stride) {
+    __shared__ double sm[NT][16];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) v[t] += __shfl_xor(v[t], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) sm[t][wid] = v[t];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += sm[t][w];
+            out[t * stride] = s;
+        }
+    }
+}
+
+__device__ __forceinline__ long long part_index(int r, int slot, int term, long long nblk_max) {
+    return ((long long)(r * NSLOT + slot) * MAX_TERMS + term) * nblk_max;
+}
+
+
+// Workgroup -> tile map that keeps neighbouring tiles on one XCD.  The
+// dispatcher hands workgroup i to XCD i % 8 (round robin over the 8 XCDs of
+// the MI355X); this permutation gives XCD x a contiguous range of tiles, so
+// the halo rows two neighbouring tiles share stay in that XCD's L2.  It is a
+// bijection of [0, N) whatever the dispatch order.
+__device__ __forceinline__ int xcd_tile_id(int id, int N) {
+    constexpr int NX = 8;
+    const int per = N / NX, rem = N % NX;
+    const int x = id % NX, k = id / NX;
+    return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+}
+
+// Index of a fine-grid node reached through the boundary: a position outside
+// [0, n) is replaced by its mirror image (the eliminated ghost point of a
+// Sommerfeld boundary, or the even extension of the full-weighting stencil),
+// then clamped so that lanes past the end of a tile stay in bounds.
+__device__ __forceinline__ int mirror_clamp(int g, int n) {
+    if (g < 0) g = -g;
+    if (g > n - 1) g = 2 * (n - 1) - g;
+    return g < 0 ? 0 : (g > n - 1 ? n - 1 : g);
+}
+
+}  // namespace hh

@@ -29,21 +29,21 @@ void launch_init(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs,
                  c128* x, c128* r, c128* rhat, c128* p, c128* v, const double* k2, const double* kb,
                  int use_x0, double* part, long long nblk_max, const RhsState* st, int gate);
 
+// CSLP parameters of the multigrid kernels: M = -Laplace - (beta1 - beta2 i) k^2,
+// damped-Jacobi weight omega.
+struct MgParams {
+    double beta1, beta2, omega;
+};
 template <typename TB, typename R>
-void launch_mg_resid(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs,
-                     const cx<TB>* b, long long b_rstride, const cx<R>* w, double omega, cx<R>* out,
-                     const RhsState* st, int gate);
-template <typename R>
-void launch_mg_restrict(hipStream_t s, int bc, const Geo& gf, const Geo& gc, const Launch& L,
-                        int nrhs, const cx<R>* rf, cx<R>* bc_out, const RhsState* st, int gate);
-template <typename TB, typename R>
-void launch_mg_correct(hipStream_t s, int bc, const Geo& g, const Geo& gc, const Launch& L, int nrhs,
-                       const cx<TB>* b, long long b_rstride, const cx<R>* w, const cx<R>* ec,
-                       cx<R>* u2, const RhsState* st, int gate);
+void launch_mg_down(hipStream_t s, int bc, const Geo& gf, const Geo& gc, int zbc, int nrhs,
+                    const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
+                    cx<R>* bc_out, const RhsState* st, int gate);
 template <typename TB, typename R, typename TO>
-void launch_mg_smooth(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs,
-                      const cx<R>* u2, const cx<TB>* b, long long b_rstride, const cx<R>* w,
-                      double omega, cx<TO>* out, long long o_rstride, const RhsState* st, int gate);
+void launch_mg_up(hipStream_t s, int bc, const Geo& g, const Geo& gc, int zb, int nrhs,
+                  const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
+                  const cx<R>* ec, cx<TO>* out, long long o_rstride, const RhsState* st, int gate);
+int mg_down_blocks(const Geo& gc, int zbc);
+int mg_up_blocks(const Geo& g, int zb);
 template <typename R>
 void launch_coarse(hipStream_t s, int nrhs, int n_nodes, int n_unk, const int* cidx,
                    const cx<R>* minv, const cx<R>* b, cx<R>* e, const RhsState* st, int gate);
@@ -63,8 +63,7 @@ void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const doub
 void launch_model_check(hipStream_t s, long long n, const double* k, double* k2, double* kb, int* bad);
 void launch_inject(hipStream_t s, const Geo& gf, const Geo& gc, const double* kf, double* kc);
 template <typename R>
-void launch_make_w(hipStream_t s, const Geo& g, int bc, const double* k, double beta1, double beta2,
-                   double omega, cx<R>* w);
+void launch_level_k2(hipStream_t s, long long n, const double* k, R* k2);
 void launch_copy_rhs(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* src, c128* dst);
 void launch_adjoint_rhs(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* gin, c128* out);
 void launch_grad_s(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* u, const c128* w,

@@ -16,61 +16,14 @@
 // (Sommerfeld only) and sigma = 1 for A, beta1 - beta2 i for the CSLP M
 // (section 3.3).
 //
-// Damped Jacobi with zero initial guess (section 3.4.1), u1 = W b with
-// W = omega D^-1 (precomputed per level), and the residual then reads
-//   b - M u1 = (1 - omega) b + (1/h^2) sum'_nb (W b)_nb
-// because D_j W_j = omega; the post-smoother similarly reads
-//   u + W (b - M u) = (1 - omega) u + W_j (b_j + (1/h^2) sum'_nb u_nb).
-// No division is done in the multigrid kernels.
+// The multigrid passes are in hh_mg_fused.hip; this file holds the operator
+// apply, the coarsest-grid solve, the Krylov vector updates, the reductions and
+// the set-up kernels.
 #include "hh_common.h"
+#include "hh_device.h"
 #include "hh_kernels.h"
 
 namespace hh {
-
-// ---------------------------------------------------------------------------
-// helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ bool gate_ok(const RhsState* st, int r, int gate) {
-    if (st == nullptr || gate == GATE_ALL) return true;
-    int s = st[r].status;
-    if (gate == GATE_FINISHED) return s != ST_RUN && s != ST_IDLE && s != ST_HALF;
-    return s == gate;
-}
-
-template <typename R>
-__device__ __forceinline__ cx<R> czero() { return cx<R>{R(0), R(0)}; }
-
-// Deterministic block reduction of NT doubles: butterfly within each 64-lane
-// wavefront, then wavefront partials summed by thread 0 in wave order.  The
-// result goes to out[t * stride] for t < NT.
-template <int NT>
-__device__ __forceinline__ void block_sum_store(double (&v)[NT], double* out, long long stride) {
-    __shared__ double sm[NT][16];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t) v[t] += __shfl_xor(v[t], off, 64);
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t) sm[t][wid] = v[t];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + 63) >> 6;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            double s = 0.0;
-            for (int w = 0; w < nw; ++w) s += sm[t][w];
-            out[t * stride] = s;
-        }
-    }
-}
-
-__device__ __forceinline__ long long part_index(int r, int slot, int term, long long nblk_max) {
-    return ((long long)(r * NSLOT + slot) * MAX_TERMS + term) * nblk_max;
-}
 
 struct Pos {
     int i, j;        // x, y of this lane's column
@@ -285,232 +238,6 @@ __global__ __launch_bounds__(512) void k_init(Geo g, int zb, const c128* __restr
     }
     const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
     block_sum_store<4>(acc, part + part_index(r, SLOT_R, 0, nblk_max) + blk, nblk_max);
-}
-
-// ---------------------------------------------------------------------------
-// Multigrid, down pass of level l: r = b - M (W b) = (1 - omega) b + (1/h^2) sum'_nb (W b)_nb
-// (pre-smoothing from zero + residual, Algorithm 1 steps 1-2).
-// ---------------------------------------------------------------------------
-template <int BC, typename TB, typename R>
-__global__ __launch_bounds__(512) void k_mg_resid(Geo g, int zb, const cx<TB>* __restrict__ b,
-                                                  long long b_rstride, const cx<R>* __restrict__ w,
-                                                  R omega, cx<R>* __restrict__ out,
-                                                  const RhsState* st, int gate) {
-    const int r = blockIdx.z;
-    if (!gate_ok(st, r, gate)) return;
-    const Pos q = plane_pos(g.nx, g.plane);
-    if (!q.valid) return;
-    const int z0 = blockIdx.y * zb;
-    const int z1 = min(g.nz, z0 + zb);
-    const R ih2 = R(1.0 / (g.h * g.h));
-    const cx<TB>* br = b + (long long)r * b_rstride;
-    cx<R>* orr = out + (long long)r * g.n;
-    const long long col = (long long)q.j * g.nx + q.i;
-    // u1 = W b at a node (0 outside the Dirichlet unknowns)
-    auto u1 = [&](long long idx) -> cx<R> { return w[idx] * cvt<R>(br[idx]); };
-    auto u1z = [&](int z) -> cx<R> {
-        if (BC == BC_DIRICHLET && (z < 1 || z > g.nz - 2)) return czero<R>();
-        return u1((long long)z * g.plane + col);
-    };
-    const bool bnd_col = BC == BC_DIRICHLET &&
-                         (q.i == 0 || q.j == 0 || q.i == g.nx - 1 || q.j == g.ny - 1);
-    cx<R> um = z0 > 0 ? u1z(z0 - 1) : czero<R>();
-    cx<R> uc = u1z(z0);
-    for (int z = z0; z < z1; ++z) {
-        cx<R> up = z + 1 < g.nz ? u1z(z + 1) : czero<R>();
-        const long long idx = (long long)z * g.plane + col;
-        cx<R> res;
-        if (BC == BC_DIRICHLET && (bnd_col || z == 0 || z == g.nz - 1)) {
-            res = czero<R>();
-        } else {
-            const long long base = (long long)z * g.plane;
-            auto ld = [&](int ii, int jj) -> cx<R> {
-                if (BC == BC_DIRICHLET && (ii < 1 || jj < 1 || ii > g.nx - 2 || jj > g.ny - 2))
-                    return czero<R>();
-                return u1(base + (long long)jj * g.nx + ii);
-            };
-            cx<R> s = inplane_sum<BC, R>(ld, q.i, q.j, g.nx, g.ny);
-            cx<R> zm = um, zpv = up;
-            if (BC == BC_SOMMERFELD) {
-                if (z == 0) zm = up;
-                if (z == g.nz - 1) zpv = um;
-            }
-            s = s + zm;
-            s = s + zpv;
-            res = (R(1) - omega) * cvt<R>(br[idx]) + ih2 * s;
-        }
-        orr[idx] = res;
-        um = uc;
-        uc = up;
-    }
-}
-
-// Full-weighting restriction (section 3.4.2, eq. matrix-free restriction):
-// coarse node I = fine node 2I, weights 8/4/2/1 over 64; a fine node outside
-// the domain takes its mirror value (Sommerfeld); Dirichlet coarse boundary = 0.
-template <int BC, typename R>
-__global__ __launch_bounds__(512) void k_mg_restrict(Geo gf, Geo gc, int zb,
-                                                     const cx<R>* __restrict__ rf,
-                                                     cx<R>* __restrict__ bc_out, const RhsState* st,
-                                                     int gate) {
-    const int r = blockIdx.z;
-    if (!gate_ok(st, r, gate)) return;
-    const Pos q = plane_pos(gc.nx, gc.plane);
-    if (!q.valid) return;
-    const int z0 = blockIdx.y * zb;
-    const int z1 = min(gc.nz, z0 + zb);
-    const cx<R>* fr = rf + (long long)r * gf.n;
-    cx<R>* cr = bc_out + (long long)r * gc.n;
-    const long long ccol = (long long)q.j * gc.nx + q.i;
-    int xs[3], ys[3];
-#pragma unroll
-    for (int d = -1; d <= 1; ++d) {
-        int fx = 2 * q.i + d, fy = 2 * q.j + d;
-        if (fx < 0) fx = -fx;
-        if (fx > gf.nx - 1) fx = 2 * (gf.nx - 1) - fx;
-        if (fy < 0) fy = -fy;
-        if (fy > gf.ny - 1) fy = 2 * (gf.ny - 1) - fy;
-        xs[d + 1] = fx;
-        ys[d + 1] = fy;
-    }
-    const bool bnd_col = BC == BC_DIRICHLET &&
-                         (q.i == 0 || q.j == 0 || q.i == gc.nx - 1 || q.j == gc.ny - 1);
-    for (int Z = z0; Z < z1; ++Z) {
-        cx<R> acc = czero<R>();
-        if (!(BC == BC_DIRICHLET && (bnd_col || Z == 0 || Z == gc.nz - 1))) {
-#pragma unroll
-            for (int dz = -1; dz <= 1; ++dz) {
-                int fz = 2 * Z + dz;
-                if (fz < 0) fz = -fz;
-                if (fz > gf.nz - 1) fz = 2 * (gf.nz - 1) - fz;
-                const cx<R>* pl = fr + (long long)fz * gf.plane;
-                cx<R> ps = czero<R>();
-#pragma unroll
-                for (int dy = 0; dy < 3; ++dy) {
-                    const cx<R>* row = pl + (long long)ys[dy] * gf.nx;
-                    cx<R> rs = row[xs[0]] + row[xs[2]];
-                    rs = rs + R(2) * row[xs[1]];
-                    ps = ps + (dy == 1 ? R(2) : R(1)) * rs;
-                }
-                acc = acc + (dz == 0 ? R(2) : R(1)) * ps;
-            }
-            acc = R(1.0 / 64.0) * acc;
-        }
-        cr[(long long)Z * gc.plane + ccol] = acc;
-    }
-}
-
-// Trilinear prolongation (section 3.4.3, eq. matrix-free prolongation) of the
-// coarse error at fine node (i, j, z).
-template <typename R>
-__device__ __forceinline__ cx<R> prolong_at(const cx<R>* __restrict__ ec, const Geo& gc, int i,
-                                            int j, int z) {
-    const int ci = i >> 1, cj = j >> 1, cz = z >> 1;
-    const int oi = i & 1, oj = j & 1, oz = z & 1;
-    const cx<R>* p0 = ec + ((long long)cz * gc.plane + (long long)cj * gc.nx + ci);
-    cx<R> s = p0[0];
-    if (oi) s = s + p0[1];
-    if (oj) {
-        s = s + p0[gc.nx];
-        if (oi) s = s + p0[gc.nx + 1];
-    }
-    if (oz) {
-        const cx<R>* p1 = p0 + gc.plane;
-        s = s + p1[0];
-        if (oi) s = s + p1[1];
-        if (oj) {
-            s = s + p1[gc.nx];
-            if (oi) s = s + p1[gc.nx + 1];
-        }
-    }
-    const int cnt = oi + oj + oz;
-    const R wgt = cnt == 0 ? R(1) : cnt == 1 ? R(0.5) : cnt == 2 ? R(0.25) : R(0.125);
-    return wgt * s;
-}
-
-// Up pass, part 1: u2 = W b + P e  (recomputed pre-smoothed iterate + correction,
-// Algorithm 1 steps 5-6).
-template <int BC, typename TB, typename R>
-__global__ __launch_bounds__(512) void k_mg_correct(Geo g, Geo gc, int zb,
-                                                    const cx<TB>* __restrict__ b, long long b_rstride,
-                                                    const cx<R>* __restrict__ w,
-                                                    const cx<R>* __restrict__ ec,
-                                                    cx<R>* __restrict__ u2, const RhsState* st,
-                                                    int gate) {
-    const int r = blockIdx.z;
-    if (!gate_ok(st, r, gate)) return;
-    const Pos q = plane_pos(g.nx, g.plane);
-    if (!q.valid) return;
-    const int z0 = blockIdx.y * zb;
-    const int z1 = min(g.nz, z0 + zb);
-    const cx<TB>* br = b + (long long)r * b_rstride;
-    const cx<R>* er = ec + (long long)r * gc.n;
-    cx<R>* ur = u2 + (long long)r * g.n;
-    const long long col = (long long)q.j * g.nx + q.i;
-    const bool bnd_col = BC == BC_DIRICHLET &&
-                         (q.i == 0 || q.j == 0 || q.i == g.nx - 1 || q.j == g.ny - 1);
-    for (int z = z0; z < z1; ++z) {
-        const long long idx = (long long)z * g.plane + col;
-        cx<R> val;
-        if (BC == BC_DIRICHLET && (bnd_col || z == 0 || z == g.nz - 1)) {
-            val = czero<R>();
-        } else {
-            val = w[idx] * cvt<R>(br[idx]) + prolong_at(er, gc, q.i, q.j, z);
-        }
-        ur[idx] = val;
-    }
-}
-
-// Up pass, part 2: post-smoothing u3 = u2 + W (b - M u2)
-//   = (1 - omega) u2 + W_j (b_j + (1/h^2) sum'_nb u2_nb)        (Algorithm 1 step 7)
-template <int BC, typename TB, typename R, typename TO>
-__global__ __launch_bounds__(512) void k_mg_smooth(Geo g, int zb, const cx<R>* __restrict__ u2,
-                                                   const cx<TB>* __restrict__ b, long long b_rstride,
-                                                   const cx<R>* __restrict__ w, R omega,
-                                                   cx<TO>* __restrict__ out, long long o_rstride,
-                                                   const RhsState* st, int gate) {
-    const int r = blockIdx.z;
-    if (!gate_ok(st, r, gate)) return;
-    const Pos q = plane_pos(g.nx, g.plane);
-    if (!q.valid) return;
-    const int z0 = blockIdx.y * zb;
-    const int z1 = min(g.nz, z0 + zb);
-    const R ih2 = R(1.0 / (g.h * g.h));
-    const cx<R>* ur = u2 + (long long)r * g.n;
-    const cx<TB>* br = b + (long long)r * b_rstride;
-    cx<TO>* orr = out + (long long)r * o_rstride;
-    const long long col = (long long)q.j * g.nx + q.i;
-    auto uz = [&](int z) -> cx<R> {
-        if (BC == BC_DIRICHLET && (z < 1 || z > g.nz - 2)) return czero<R>();
-        return ur[(long long)z * g.plane + col];
-    };
-    const bool bnd_col = BC == BC_DIRICHLET &&
-                         (q.i == 0 || q.j == 0 || q.i == g.nx - 1 || q.j == g.ny - 1);
-    cx<R> um = z0 > 0 ? uz(z0 - 1) : czero<R>();
-    cx<R> uc = uz(z0);
-    for (int z = z0; z < z1; ++z) {
-        cx<R> up = z + 1 < g.nz ? uz(z + 1) : czero<R>();
-        const long long idx = (long long)z * g.plane + col;
-        cx<R> res;
-        if (BC == BC_DIRICHLET && (bnd_col || z == 0 || z == g.nz - 1)) {
-            res = czero<R>();
-        } else {
-            const cx<R>* pl = ur + (long long)z * g.plane;
-            auto ld = [&](int ii, int jj) -> cx<R> { return pl[(long long)jj * g.nx + ii]; };
-            cx<R> s = inplane_sum<BC, R>(ld, q.i, q.j, g.nx, g.ny);
-            cx<R> zm = um, zpv = up;
-            if (BC == BC_SOMMERFELD) {
-                if (z == 0) zm = up;
-                if (z == g.nz - 1) zpv = um;
-            }
-            s = s + zm;
-            s = s + zpv;
-            res = (R(1) - omega) * uc + w[idx] * (cvt<R>(br[idx]) + ih2 * s);
-        }
-        orr[idx] = cvt<TO>(res);
-        um = uc;
-        uc = up;
-    }
 }
 
 // Coarsest level: e = M_c^-1 b over the unknown nodes (dense inverse stored
@@ -777,27 +504,13 @@ __global__ void k_inject(Geo gf, Geo gc, const double* __restrict__ kf, double* 
     }
 }
 
-// W = omega / D with D = 6/h^2 - (beta1 - beta2 i) k^2 - n_j 2 i k / h; computed in
-// double, stored in the level precision.  Dirichlet boundary nodes get W = 0.
+// k^2 of a level in the multigrid precision.
 template <typename R>
-__global__ void k_make_w(Geo g, int bc, const double* __restrict__ k, double beta1, double beta2,
-                         double omega, cx<R>* __restrict__ w) {
-    const double ih2 = 1.0 / (g.h * g.h);
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.n;
+__global__ void k_level_k2(long long n, const double* __restrict__ k, R* __restrict__ k2) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        const int z = (int)(i / g.plane);
-        const int rem = (int)(i - (long long)z * g.plane);
-        const int y = rem / g.nx, x = rem - y * g.nx;
-        const double kk = k[i];
-        c128 d = mk(6.0 * ih2 - beta1 * kk * kk, beta2 * kk * kk);
-        c128 wv;
-        if (bc == BC_SOMMERFELD) {
-            d.im -= faces(x, y, z, g.nx, g.ny, g.nz) * 2.0 * kk / g.h;
-            wv = cdiv(mk(omega, 0.0), d);
-        } else {
-            wv = on_boundary(x, y, z, g.nx, g.ny, g.nz) ? mk(0.0, 0.0) : cdiv(mk(omega, 0.0), d);
-        }
-        w[i] = cvt<R>(wv);
+        const double v = k[i];
+        k2[i] = R(v * v);
     }
 }
 
@@ -926,57 +639,6 @@ void launch_init(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs,
                            p, v, k2, kb, use_x0, part, nblk_max, st, gate);
 }
 
-template <typename TB, typename R>
-void launch_mg_resid(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs,
-                     const cx<TB>* b, long long b_rstride, const cx<R>* w, double omega, cx<R>* out,
-                     const RhsState* st, int gate) {
-    dim3 grid = grid_fine(g, L, nrhs);
-    if (bc == BC_SOMMERFELD)
-        hipLaunchKernelGGL((k_mg_resid<BC_SOMMERFELD, TB, R>), grid, dim3(L.block), 0, s, g, L.zb, b,
-                           b_rstride, w, R(omega), out, st, gate);
-    else
-        hipLaunchKernelGGL((k_mg_resid<BC_DIRICHLET, TB, R>), grid, dim3(L.block), 0, s, g, L.zb, b,
-                           b_rstride, w, R(omega), out, st, gate);
-}
-
-template <typename R>
-void launch_mg_restrict(hipStream_t s, int bc, const Geo& gf, const Geo& gc, const Launch& L,
-                        int nrhs, const cx<R>* rf, cx<R>* bc_out, const RhsState* st, int gate) {
-    dim3 grid = grid_fine(gc, L, nrhs);
-    if (bc == BC_SOMMERFELD)
-        hipLaunchKernelGGL((k_mg_restrict<BC_SOMMERFELD, R>), grid, dim3(L.block), 0, s, gf, gc, L.zb,
-                           rf, bc_out, st, gate);
-    else
-        hipLaunchKernelGGL((k_mg_restrict<BC_DIRICHLET, R>), grid, dim3(L.block), 0, s, gf, gc, L.zb,
-                           rf, bc_out, st, gate);
-}
-
-template <typename TB, typename R>
-void launch_mg_correct(hipStream_t s, int bc, const Geo& g, const Geo& gc, const Launch& L, int nrhs,
-                       const cx<TB>* b, long long b_rstride, const cx<R>* w, const cx<R>* ec,
-                       cx<R>* u2, const RhsState* st, int gate) {
-    dim3 grid = grid_fine(g, L, nrhs);
-    if (bc == BC_SOMMERFELD)
-        hipLaunchKernelGGL((k_mg_correct<BC_SOMMERFELD, TB, R>), grid, dim3(L.block), 0, s, g, gc,
-                           L.zb, b, b_rstride, w, ec, u2, st, gate);
-    else
-        hipLaunchKernelGGL((k_mg_correct<BC_DIRICHLET, TB, R>), grid, dim3(L.block), 0, s, g, gc,
-                           L.zb, b, b_rstride, w, ec, u2, st, gate);
-}
-
-template <typename TB, typename R, typename TO>
-void launch_mg_smooth(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs,
-                      const cx<R>* u2, const cx<TB>* b, long long b_rstride, const cx<R>* w,
-                      double omega, cx<TO>* out, long long o_rstride, const RhsState* st, int gate) {
-    dim3 grid = grid_fine(g, L, nrhs);
-    if (bc == BC_SOMMERFELD)
-        hipLaunchKernelGGL((k_mg_smooth<BC_SOMMERFELD, TB, R, TO>), grid, dim3(L.block), 0, s, g, L.zb,
-                           u2, b, b_rstride, w, R(omega), out, o_rstride, st, gate);
-    else
-        hipLaunchKernelGGL((k_mg_smooth<BC_DIRICHLET, TB, R, TO>), grid, dim3(L.block), 0, s, g, L.zb,
-                           u2, b, b_rstride, w, R(omega), out, o_rstride, st, gate);
-}
-
 template <typename R>
 void launch_coarse(hipStream_t s, int nrhs, int n_nodes, int n_unk, const int* cidx,
                    const cx<R>* minv, const cx<R>* b, cx<R>* e, const RhsState* st, int gate) {
@@ -984,25 +646,6 @@ void launch_coarse(hipStream_t s, int nrhs, int n_nodes, int n_unk, const int* c
                        cidx, minv, b, e, st, gate);
 }
 
-#define HH_INST(TB, R, TO)                                                                        \
-    template void launch_mg_resid<TB, R>(hipStream_t, int, const Geo&, const Launch&, int,         \
-                                         const cx<TB>*, long long, const cx<R>*, double, cx<R>*,  \
-                                         const RhsState*, int);                                    \
-    template void launch_mg_correct<TB, R>(hipStream_t, int, const Geo&, const Geo&, const Launch&, \
-                                           int, const cx<TB>*, long long, const cx<R>*,            \
-                                           const cx<R>*, cx<R>*, const RhsState*, int);            \
-    template void launch_mg_smooth<TB, R, TO>(hipStream_t, int, const Geo&, const Launch&, int,    \
-                                              const cx<R>*, const cx<TB>*, long long,              \
-                                              const cx<R>*, double, cx<TO>*, long long,            \
-                                              const RhsState*, int);
-HH_INST(double, double, double)
-HH_INST(double, float, double)
-HH_INST(float, float, float)
-#undef HH_INST
-template void launch_mg_restrict<double>(hipStream_t, int, const Geo&, const Geo&, const Launch&,
-                                         int, const c128*, c128*, const RhsState*, int);
-template void launch_mg_restrict<float>(hipStream_t, int, const Geo&, const Geo&, const Launch&, int,
-                                        const c64*, c64*, const RhsState*, int);
 template void launch_coarse<double>(hipStream_t, int, int, int, const int*, const c128*,
                                     const c128*, c128*, const RhsState*, int);
 template void launch_coarse<float>(hipStream_t, int, int, int, const int*, const c64*, const c64*,
@@ -1043,15 +686,11 @@ void launch_inject(hipStream_t s, const Geo& gf, const Geo& gc, const double* kf
     hipLaunchKernelGGL(k_inject, dim3(flat_blocks(gc.n, 256, 8192)), dim3(256), 0, s, gf, gc, kf, kc);
 }
 template <typename R>
-void launch_make_w(hipStream_t s, const Geo& g, int bc, const double* k, double beta1, double beta2,
-                   double omega, cx<R>* w) {
-    hipLaunchKernelGGL((k_make_w<R>), dim3(flat_blocks(g.n, 256, 8192)), dim3(256), 0, s, g, bc, k,
-                       beta1, beta2, omega, w);
+void launch_level_k2(hipStream_t s, long long n, const double* k, R* k2) {
+    hipLaunchKernelGGL((k_level_k2<R>), dim3(flat_blocks(n, 256, 8192)), dim3(256), 0, s, n, k, k2);
 }
-template void launch_make_w<double>(hipStream_t, const Geo&, int, const double*, double, double,
-                                    double, c128*);
-template void launch_make_w<float>(hipStream_t, const Geo&, int, const double*, double, double,
-                                   double, c64*);
+template void launch_level_k2<double>(hipStream_t, long long, const double*, double*);
+template void launch_level_k2<float>(hipStream_t, long long, const double*, float*);
 void launch_copy_rhs(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* src, c128* dst) {
     hipLaunchKernelGGL(k_copy_rhs, dim3(flat_blocks((long long)nrhs * g.n, 256, 8192)), dim3(256), 0,
                        s, g, bc, nrhs, src, dst);

@@ -1,0 +1,461 @@
+// Multigrid kernels for gfx950: one fused pass down and one fused pass up per level.
+//
+// With M u = (1/h^2) lap(u) - c u,  lap(u)_j = sum_nb (u_j - u_nb),
+//      c_j = (beta1 - beta2 i) k_j^2 + n_j 2 i k_j / h,   D_j = 6/h^2 - c_j,
+// (paper section 3.3 and Algorithm 2: the 7-point stencil with its Sommerfeld
+// ghost points eliminated; n_j = faces node j lies on) and W = omega D^-1:
+//
+// Down (Algorithm 1 steps 1-3: zero initial guess, one damped-Jacobi sweep,
+// residual, full-weighting restriction of section 3.4.2):
+//   u1 = W b,   r = b - (1/h^2) lap(u1) + c u1,   b_H = R r.
+// Up (Algorithm 1 steps 5-7: trilinear prolongation of section 3.4.3,
+// correction, one damped-Jacobi sweep):
+//   u2 = W b + P e_H,   u3 = u2 + W (b - (1/h^2) lap(u2) + c u2).
+//
+// The Laplacian is summed as differences u_j - u_nb: for the smooth part of u
+// each difference is exact in floating point, so the correction keeps its
+// relative accuracy in single precision instead of losing a factor of about
+// 6 / (k h)^2 to cancellation in 6 u_j - sum u_nb.
+//
+// Only the level's k^2 is stored; c, D and W are recomputed per node.  Both
+// kernels stage x-y planes of a tile and its halo in LDS and march along z with
+// a ring of three planes; the global loads of the next plane are issued into
+// registers before the current plane is computed.  Halo positions outside the
+// domain are read from their mirror image: for Sommerfeld levels that is the
+// eliminated ghost point (its 2hik part is in c) and the even extension of the
+// full-weighting stencil; for Dirichlet levels the boundary values are zero and
+// boundary outputs are forced to zero.
+#include "hh_common.h"
+#include "hh_device.h"
+#include "hh_kernels.h"
+
+namespace hh {
+
+__device__ __forceinline__ int ring3(int f) { return ((f % 3) + 3) % 3; }
+
+// Runtime tile shape of a level: width = ceil(n / ceil(n / maxw)) so a row of
+// 2^k + 1 nodes splits into nearly equal tiles, height = as many rows as the
+// workgroup's lanes allow (at most maxh).
+struct TileShape {
+    int tw, th, ntx, nty;
+};
+__host__ __device__ inline TileShape tile_shape(int nx, int ny, int maxw, int lanes, int maxh) {
+    TileShape T;
+    T.ntx = (nx + maxw - 1) / maxw;
+    T.tw = (nx + T.ntx - 1) / T.ntx;
+    T.th = lanes / T.tw;
+    if (T.th > maxh) T.th = maxh;
+    if (T.th > ny) T.th = ny;
+    T.nty = (ny + T.th - 1) / T.th;
+    return T;
+}
+
+constexpr int DN_LANES = 256, DN_MAXW = 32, DN_MAXH = 16;
+constexpr int DN_REGION = 1280;  // >= (2 tw + 3)(2 th + 3) for every shape tile_shape() returns
+constexpr int DN_RES = 1152;     // >= (2 tw + 1)(2 th + 1)
+constexpr int UP_LANES = 512, UP_MAXW = 64, UP_MAXH = 16;
+constexpr int UP_REGION = 704;   // >= (tw + 2)(th + 2)
+
+// Level constants of the CSLP operator in the compute precision.
+template <typename R>
+struct LevelCoef {
+    R ih2, six_ih2, two_over_h, sr, si, omega;
+};
+template <typename R>
+__device__ __forceinline__ LevelCoef<R> level_coef(const Geo& g, double beta1, double beta2,
+                                                   double omega) {
+    LevelCoef<R> L;
+    L.ih2 = R(1.0 / (g.h * g.h));
+    L.six_ih2 = R(6.0 / (g.h * g.h));
+    L.two_over_h = R(2.0 / g.h);
+    L.sr = R(beta1);
+    L.si = R(-beta2);
+    L.omega = R(omega);
+    return L;
+}
+
+// c_j = (beta1 - beta2 i) k^2 + n_j 2 i k / h
+template <typename R>
+__device__ __forceinline__ cx<R> shift_c(const LevelCoef<R>& L, R k2, int nf) {
+    cx<R> c = {L.sr * k2, L.si * k2};
+    if (nf) c.im += R(nf) * L.two_over_h * sqrt(k2);
+    return c;
+}
+// W = omega / (6/h^2 - c)
+template <typename R>
+__device__ __forceinline__ cx<R> jacobi_w(const LevelCoef<R>& L, cx<R> c) {
+    const R dr = L.six_ih2 - c.re, di = -c.im;
+    const R s = L.omega / (dr * dr + di * di);
+    return {dr * s, -di * s};
+}
+
+__device__ __forceinline__ int faces_of(int x, int y, int z, const Geo& g) {
+    return (x == 0) + (x == g.nx - 1) + (y == 0) + (y == g.ny - 1) + (z == 0) + (z == g.nz - 1);
+}
+
+// ---------------------------------------------------------------------------
+// Down: b_H = R (b - M W b).  One lane per coarse column of a tw x th tile,
+// marching over `zbc` coarse planes (2 zbc + 1 fine residual planes).
+// ---------------------------------------------------------------------------
+template <int BC, typename TB, typename R>
+__global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
+                                                      const cx<TB>* __restrict__ b,
+                                                      long long b_rstride,
+                                                      const R* __restrict__ k2l, double beta1,
+                                                      double beta2, double omega,
+                                                      cx<R>* __restrict__ bc_out,
+                                                      const RhsState* st, int gate) {
+    constexpr int NU = (DN_REGION + DN_LANES - 1) / DN_LANES;
+    constexpr int NR = (DN_RES + DN_LANES - 1) / DN_LANES;
+    __shared__ cx<R> u1s[3][DN_REGION];
+    __shared__ cx<R> rs[DN_RES];
+
+    const int r = blockIdx.z;
+    if (!gate_ok(st, r, gate)) return;
+    const int t = threadIdx.x;
+    const TileShape T = tile_shape(gc.nx, gc.ny, DN_MAXW, DN_LANES, DN_MAXH);
+    const int RW = 2 * T.tw + 3, RH = 2 * T.th + 3;
+    const int IW = 2 * T.tw + 1, IH = 2 * T.th + 1;
+    const int id = xcd_tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int tz = id / gridDim.x;
+    const int txy = id - tz * gridDim.x;
+    const int tyi = txy / T.ntx, txi = txy - tyi * T.ntx;
+    const int X0 = txi * T.tw, Y0 = tyi * T.th;
+    const int Z0 = tz * zbc, Z1 = min(gc.nz, Z0 + zbc);
+    const int gx0 = 2 * X0 - 2, gy0 = 2 * Y0 - 2;
+    const cx<TB>* br = b + (long long)r * b_rstride;
+    const LevelCoef<R> L = level_coef<R>(gf, beta1, beta2, omega);
+
+    // region nodes of this lane: in-plane offset and face count within the x-y plane
+    int uoff[NU], unf[NU];
+    bool ubnd[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+        const int idx = t + k * DN_LANES;
+        const int ly = idx / RW, lx = idx - ly * RW;
+        const int gx = mirror_clamp(gx0 + lx, gf.nx), gy = mirror_clamp(gy0 + ly, gf.ny);
+        uoff[k] = gy * gf.nx + gx;
+        unf[k] = (gx == 0) + (gx == gf.nx - 1) + (gy == 0) + (gy == gf.ny - 1);
+        ubnd[k] = unf[k] != 0;
+    }
+    int roff[NR], rl[NR], rnf[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int idx = t + k * DN_LANES;
+        const int iy = idx / IW, ix = idx - iy * IW;
+        const int gx = mirror_clamp(gx0 + 1 + ix, gf.nx), gy = mirror_clamp(gy0 + 1 + iy, gf.ny);
+        roff[k] = gy * gf.nx + gx;
+        rnf[k] = (gx == 0) + (gx == gf.nx - 1) + (gy == 0) + (gy == gf.ny - 1);
+        rl[k] = (iy + 1) * RW + ix + 1;
+    }
+
+    // raw loads in flight: region plane for u1, inner plane for the residual
+    cx<TB> ub[NU];
+    R uk[NU];
+    cx<TB> rb[NR];
+    R rk[NR];
+    auto fetch_u1 = [&](int f) {
+        const long long base = (long long)mirror_clamp(f, gf.nz) * gf.plane;
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+            if (t + k * DN_LANES < RW * RH) {
+                ub[k] = br[base + uoff[k]];
+                uk[k] = k2l[base + uoff[k]];
+            }
+        }
+    };
+    auto commit_u1 = [&](int f) {
+        const int fz = mirror_clamp(f, gf.nz);
+        const int zf = (fz == 0) + (fz == gf.nz - 1);
+        cx<R>* dst = u1s[ring3(f)];
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+            const int idx = t + k * DN_LANES;
+            if (idx < RW * RH) {
+                const int nf = BC == BC_SOMMERFELD ? unf[k] + zf : 0;
+                cx<R> v = jacobi_w(L, shift_c(L, uk[k], nf)) * cvt<R>(ub[k]);
+                if (BC == BC_DIRICHLET && (ubnd[k] || zf)) v = czero<R>();
+                dst[idx] = v;
+            }
+        }
+    };
+    auto fetch_res = [&](int f) {
+        const long long base = (long long)mirror_clamp(f, gf.nz) * gf.plane;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            if (t + k * DN_LANES < IW * IH) {
+                rb[k] = br[base + roff[k]];
+                rk[k] = k2l[base + roff[k]];
+            }
+        }
+    };
+    auto residual = [&](int f) {
+        const int fz = mirror_clamp(f, gf.nz);
+        const int zf = (fz == 0) + (fz == gf.nz - 1);
+        const cx<R>* um = u1s[ring3(f - 1)];
+        const cx<R>* uc = u1s[ring3(f)];
+        const cx<R>* up = u1s[ring3(f + 1)];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int idx = t + k * DN_LANES;
+            if (idx < IW * IH) {
+                const int c = rl[k];
+                const cx<R> u = uc[c];
+                cx<R> lap = (u - uc[c - 1]) + (u - uc[c + 1]);
+                lap = lap + (u - uc[c - RW]);
+                lap = lap + (u - uc[c + RW]);
+                lap = lap + (u - um[c]);
+                lap = lap + (u - up[c]);
+                const int nf = BC == BC_SOMMERFELD ? rnf[k] + zf : 0;
+                rs[idx] = (cvt<R>(rb[k]) - L.ih2 * lap) + shift_c(L, rk[k], nf) * u;
+            }
+        }
+    };
+
+    const int cxl = t % T.tw, cyl = t / T.tw;
+    const int X = X0 + cxl, Y = Y0 + cyl;
+    const bool mine = cyl < T.th && X < gc.nx && Y < gc.ny;
+    const int ic = mine ? (2 * cyl + 1) * IW + 2 * cxl + 1 : IW + 1;
+    cx<R> acc = czero<R>();
+    fetch_u1(2 * Z0 - 2);
+    commit_u1(2 * Z0 - 2);
+    fetch_u1(2 * Z0 - 1);
+    commit_u1(2 * Z0 - 1);
+    fetch_u1(2 * Z0);
+    fetch_res(2 * Z0 - 1);
+    for (int f = 2 * Z0 - 1; f <= 2 * Z1 - 1; ++f) {
+        commit_u1(f + 1);
+        if (f + 2 <= 2 * Z1) fetch_u1(f + 2);
+        __syncthreads();
+        residual(f);
+        if (f + 1 <= 2 * Z1 - 1) fetch_res(f + 1);
+        __syncthreads();
+        // 2D full weighting of the residual plane at the lane's coarse column
+        cx<R> q = R(4) * rs[ic];
+        cx<R> e = rs[ic - 1] + rs[ic + 1];
+        e = e + rs[ic - IW];
+        e = e + rs[ic + IW];
+        cx<R> c4 = rs[ic - IW - 1] + rs[ic - IW + 1];
+        c4 = c4 + rs[ic + IW - 1];
+        c4 = c4 + rs[ic + IW + 1];
+        q = q + R(2) * e;
+        q = q + c4;
+        // z weights 1, 2, 1 over the fine planes 2Z - 1, 2Z, 2Z + 1
+        if (f == 2 * Z0 - 1) {
+            acc = q;
+        } else if ((f & 1) == 0) {
+            acc = acc + R(2) * q;
+        } else {
+            const int Z = (f - 1) >> 1;
+            if (mine) {
+                cx<R> v = R(1.0 / 64.0) * (acc + q);
+                if (BC == BC_DIRICHLET &&
+                    (X == 0 || Y == 0 || Z == 0 || X == gc.nx - 1 || Y == gc.ny - 1 || Z == gc.nz - 1))
+                    v = czero<R>();
+                bc_out[(long long)r * gc.n + (long long)Z * gc.plane + (long long)Y * gc.nx + X] = v;
+            }
+            acc = q;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Up: u3 = u2 + W (b - (1/h^2) lap(u2) + c u2), u2 = W b + P e_H.  One lane
+// per fine column of a tw x th tile, marching over `zb` planes.
+// ---------------------------------------------------------------------------
+template <int BC, typename TB, typename R, typename TO>
+__global__ __launch_bounds__(UP_LANES) void k_mg_up(Geo g, Geo gc, int zb,
+                                                    const cx<TB>* __restrict__ b, long long b_rstride,
+                                                    const R* __restrict__ k2l, double beta1,
+                                                    double beta2, double omega,
+                                                    const cx<R>* __restrict__ ec,
+                                                    cx<TO>* __restrict__ out, long long o_rstride,
+                                                    const RhsState* st, int gate) {
+    constexpr int NU = (UP_REGION + UP_LANES - 1) / UP_LANES;
+    __shared__ cx<R> us[3][UP_REGION];
+
+    const int r = blockIdx.z;
+    if (!gate_ok(st, r, gate)) return;
+    const int t = threadIdx.x;
+    const TileShape T = tile_shape(g.nx, g.ny, UP_MAXW, UP_LANES, UP_MAXH);
+    const int RW = T.tw + 2, RH = T.th + 2;
+    const int id = xcd_tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int tz = id / gridDim.x;
+    const int txy = id - tz * gridDim.x;
+    const int tyi = txy / T.ntx, txi = txy - tyi * T.ntx;
+    const int X0 = txi * T.tw, Y0 = tyi * T.th;
+    const int z0 = tz * zb, z1 = min(g.nz, z0 + zb);
+    const cx<TB>* br = b + (long long)r * b_rstride;
+    const cx<R>* er = ec + (long long)r * gc.n;
+    const LevelCoef<R> L = level_coef<R>(g, beta1, beta2, omega);
+
+    // region nodes: fine in-plane offset, face count in the plane, and the two
+    // coarse in-plane offsets per axis with their interpolation weights
+    int uoff[NU], unf[NU], cx0[NU], cx1[NU], cy0[NU], cy1[NU];
+    R wx[NU], wy[NU];
+    bool ubnd[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+        const int idx = t + k * UP_LANES;
+        const int ly = idx / RW, lx = idx - ly * RW;
+        const int gx = mirror_clamp(X0 - 1 + lx, g.nx), gy = mirror_clamp(Y0 - 1 + ly, g.ny);
+        uoff[k] = gy * g.nx + gx;
+        unf[k] = (gx == 0) + (gx == g.nx - 1) + (gy == 0) + (gy == g.ny - 1);
+        ubnd[k] = unf[k] != 0;
+        cx0[k] = gx >> 1;
+        cx1[k] = min((gx >> 1) + (gx & 1), gc.nx - 1);
+        cy0[k] = (gy >> 1) * gc.nx;
+        cy1[k] = min((gy >> 1) + (gy & 1), gc.ny - 1) * gc.nx;
+        wx[k] = (gx & 1) ? R(0.5) : R(1);
+        wy[k] = (gy & 1) ? R(0.5) : R(1);
+    }
+
+    cx<TB> ub[NU];
+    R uk[NU];
+    cx<R> ue[NU][8];
+    auto fetch_u2 = [&](int f) {
+        const int fz = mirror_clamp(f, g.nz);
+        const long long base = (long long)fz * g.plane;
+        const cx<R>* e0 = er + (long long)(fz >> 1) * gc.plane;
+        const cx<R>* e1 = er + (long long)min((fz >> 1) + (fz & 1), gc.nz - 1) * gc.plane;
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+            if (t + k * UP_LANES < RW * RH) {
+                ub[k] = br[base + uoff[k]];
+                uk[k] = k2l[base + uoff[k]];
+                ue[k][0] = e0[cy0[k] + cx0[k]];
+                ue[k][1] = e0[cy0[k] + cx1[k]];
+                ue[k][2] = e0[cy1[k] + cx0[k]];
+                ue[k][3] = e0[cy1[k] + cx1[k]];
+                ue[k][4] = e1[cy0[k] + cx0[k]];
+                ue[k][5] = e1[cy0[k] + cx1[k]];
+                ue[k][6] = e1[cy1[k] + cx0[k]];
+                ue[k][7] = e1[cy1[k] + cx1[k]];
+            }
+        }
+    };
+    auto commit_u2 = [&](int f) {
+        const int fz = mirror_clamp(f, g.nz);
+        const int zf = (fz == 0) + (fz == g.nz - 1);
+        const R wz = (fz & 1) ? R(0.5) : R(1);
+        cx<R>* dst = us[ring3(f)];
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+            const int idx = t + k * UP_LANES;
+            if (idx < RW * RH) {
+                // trilinear interpolation; an even index takes its own coarse node only
+                const R ax = wx[k], ay = wy[k];
+                const R bx = R(1) - ax, by = R(1) - ay, bz = R(1) - wz;
+                cx<R> p0 = (ax * ue[k][0] + bx * ue[k][1]);
+                cx<R> p1 = (ax * ue[k][2] + bx * ue[k][3]);
+                cx<R> p2 = (ax * ue[k][4] + bx * ue[k][5]);
+                cx<R> p3 = (ax * ue[k][6] + bx * ue[k][7]);
+                cx<R> pe = wz * (ay * p0 + by * p1) + bz * (ay * p2 + by * p3);
+                const int nf = BC == BC_SOMMERFELD ? unf[k] + zf : 0;
+                cx<R> v = jacobi_w(L, shift_c(L, uk[k], nf)) * cvt<R>(ub[k]) + pe;
+                if (BC == BC_DIRICHLET && (ubnd[k] || zf)) v = czero<R>();
+                dst[idx] = v;
+            }
+        }
+    };
+
+    const int tx = t % T.tw, ty = t / T.tw;
+    const int gx = X0 + tx, gy = Y0 + ty;
+    const bool own = ty < T.th && gx < g.nx && gy < g.ny;
+    const int c = own ? (ty + 1) * RW + tx + 1 : RW + 1;
+    const long long ooff = own ? (long long)gy * g.nx + gx : 0;
+    const int onf = (gx == 0) + (gx == g.nx - 1) + (gy == 0) + (gy == g.ny - 1);
+    cx<TO>* orr = out + (long long)r * o_rstride;
+    cx<TB> ob = {};
+    R ok = R(0);
+    auto fetch_own = [&](int z) {
+        if (own) {
+            ob = br[(long long)z * g.plane + ooff];
+            ok = k2l[(long long)z * g.plane + ooff];
+        }
+    };
+    fetch_u2(z0 - 1);
+    commit_u2(z0 - 1);
+    fetch_u2(z0);
+    commit_u2(z0);
+    fetch_u2(z0 + 1);
+    fetch_own(z0);
+    for (int z = z0; z < z1; ++z) {
+        commit_u2(z + 1);
+        if (z + 2 <= z1) fetch_u2(z + 2);
+        __syncthreads();
+        if (own) {
+            const cx<R>* um = us[ring3(z - 1)];
+            const cx<R>* uc = us[ring3(z)];
+            const cx<R>* up = us[ring3(z + 1)];
+            const cx<R> u = uc[c];
+            cx<R> lap = (u - uc[c - 1]) + (u - uc[c + 1]);
+            lap = lap + (u - uc[c - RW]);
+            lap = lap + (u - uc[c + RW]);
+            lap = lap + (u - um[c]);
+            lap = lap + (u - up[c]);
+            const int nf = BC == BC_SOMMERFELD ? onf + (z == 0) + (z == g.nz - 1) : 0;
+            const cx<R> cc = shift_c(L, ok, nf);
+            cx<R> v = u + jacobi_w(L, cc) * ((cvt<R>(ob) - L.ih2 * lap) + cc * u);
+            if (BC == BC_DIRICHLET && (onf || z == 0 || z == g.nz - 1)) v = czero<R>();
+            const long long gi = (long long)z * g.plane + ooff;
+            if (z + 1 < z1) fetch_own(z + 1);
+            orr[gi] = cvt<TO>(v);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+int mg_down_blocks(const Geo& gc, int zbc) {
+    const TileShape T = tile_shape(gc.nx, gc.ny, DN_MAXW, DN_LANES, DN_MAXH);
+    return T.ntx * T.nty * ((gc.nz + zbc - 1) / zbc);
+}
+int mg_up_blocks(const Geo& g, int zb) {
+    const TileShape T = tile_shape(g.nx, g.ny, UP_MAXW, UP_LANES, UP_MAXH);
+    return T.ntx * T.nty * ((g.nz + zb - 1) / zb);
+}
+
+template <typename TB, typename R>
+void launch_mg_down(hipStream_t s, int bc, const Geo& gf, const Geo& gc, int zbc, int nrhs,
+                    const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
+                    cx<R>* bc_out, const RhsState* st, int gate) {
+    const TileShape T = tile_shape(gc.nx, gc.ny, DN_MAXW, DN_LANES, DN_MAXH);
+    dim3 grid(T.ntx * T.nty, (gc.nz + zbc - 1) / zbc, nrhs);
+    if (bc == BC_SOMMERFELD)
+        hipLaunchKernelGGL((k_mg_down<BC_SOMMERFELD, TB, R>), grid, dim3(DN_LANES), 0, s, gf, gc, zbc, b,
+                           b_rstride, k2l, P.beta1, P.beta2, P.omega, bc_out, st, gate);
+    else
+        hipLaunchKernelGGL((k_mg_down<BC_DIRICHLET, TB, R>), grid, dim3(DN_LANES), 0, s, gf, gc, zbc, b,
+                           b_rstride, k2l, P.beta1, P.beta2, P.omega, bc_out, st, gate);
+}
+
+template <typename TB, typename R, typename TO>
+void launch_mg_up(hipStream_t s, int bc, const Geo& g, const Geo& gc, int zb, int nrhs,
+                  const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
+                  const cx<R>* ec, cx<TO>* out, long long o_rstride, const RhsState* st, int gate) {
+    const TileShape T = tile_shape(g.nx, g.ny, UP_MAXW, UP_LANES, UP_MAXH);
+    dim3 grid(T.ntx * T.nty, (g.nz + zb - 1) / zb, nrhs);
+    if (bc == BC_SOMMERFELD)
+        hipLaunchKernelGGL((k_mg_up<BC_SOMMERFELD, TB, R, TO>), grid, dim3(UP_LANES), 0, s, g, gc, zb, b,
+                           b_rstride, k2l, P.beta1, P.beta2, P.omega, ec, out, o_rstride, st, gate);
+    else
+        hipLaunchKernelGGL((k_mg_up<BC_DIRICHLET, TB, R, TO>), grid, dim3(UP_LANES), 0, s, g, gc, zb, b,
+                           b_rstride, k2l, P.beta1, P.beta2, P.omega, ec, out, o_rstride, st, gate);
+}
+
+#define HH_INST_F(TB, R, TO)                                                                           \
+    template void launch_mg_down<TB, R>(hipStream_t, int, const Geo&, const Geo&, int, int, const cx<TB>*, \
+                                        long long, const R*, const MgParams&, cx<R>*, const RhsState*,   \
+                                        int);                                                             \
+    template void launch_mg_up<TB, R, TO>(hipStream_t, int, const Geo&, const Geo&, int, int,              \
+                                          const cx<TB>*, long long, const R*, const MgParams&,            \
+                                          const cx<R>*, cx<TO>*, long long, const RhsState*, int);
+HH_INST_F(double, double, double)
+HH_INST_F(double, float, double)
+HH_INST_F(float, float, float)
+#undef HH_INST_F
+
+}  // namespace hh

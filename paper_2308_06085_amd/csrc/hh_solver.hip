@@ -30,9 +30,10 @@ std::string g_create_error;
 struct LevelBuf {
     Geo g;
     Launch L;
+    int zb_down = 4;      // coarse planes per workgroup of the fused down kernel into this level's child
+    int zb_up = 8;        // fine planes per workgroup of the fused up kernel on this level
     double* k = nullptr;  // wavenumber at the nodes of this level
-    void* w = nullptr;    // omega D^-1 (complex, level precision)
-    void* tmp = nullptr;  // residual (down pass) / corrected iterate (up pass)
+    void* k2l = nullptr;  // k^2 in the multigrid precision
     void* b = nullptr;    // right-hand side (levels >= 1)
     void* e = nullptr;    // V-cycle result (levels >= 1)
 };
@@ -46,6 +47,7 @@ struct hh_ctx {
     int device = 0;
     bool mixed = false;
     size_t csize = 16;  // bytes per complex of the multigrid precision
+    size_t rsize = 8;   // bytes per real of the multigrid precision
     std::vector<LevelBuf> lv;
     Launch base;        // requested fine-grid launch shape
     Launch L0;          // effective fine-level launch shape
@@ -148,8 +150,7 @@ void free_all(hh_ctx* c) {
     c->graphs.clear();
     for (auto& L : c->lv) {
         (void)hipFree(L.k);
-        (void)hipFree(L.w);
-        (void)hipFree(L.tmp);
+        (void)hipFree(L.k2l);
         (void)hipFree(L.b);
         (void)hipFree(L.e);
     }
@@ -167,8 +168,27 @@ void invalidate_graphs(hh_ctx* c) {
     c->graphs.clear();
 }
 
+// z-planes per workgroup of a multigrid pass: long z-marches amortise the two
+// halo planes each workgroup loads, but the grid must still fill the chip.
+// Take the longest of 16, 8, 4 planes that leaves >= 1024 workgroups, else the
+// longest of 4, 2, 1 that leaves >= 256.
+template <typename F>
+int pick_zb(F blocks) {
+    for (int zb : {16, 8, 4})
+        if (blocks(zb) >= 1024) return zb;
+    for (int zb : {4, 2})
+        if (blocks(zb) >= 256) return zb;
+    return 1;
+}
+
 void apply_launch(hh_ctx* c) {
     for (auto& L : c->lv) L.L = level_launch(L.g, c->base);
+    for (size_t l = 0; l + 1 < c->lv.size(); ++l) {
+        const Geo gc = c->lv[l + 1].g;
+        const Geo g = c->lv[l].g;
+        c->lv[l].zb_down = pick_zb([&](int z) { return mg_down_blocks(gc, z); });
+        c->lv[l].zb_up = pick_zb([&](int z) { return mg_up_blocks(g, z); });
+    }
     c->L0 = c->lv[0].L;
     c->nblk0 = nblk_of(c->lv[0].g, c->L0);
     invalidate_graphs(c);
@@ -182,34 +202,29 @@ void enqueue_vcycle_t(hh_ctx* c, hipStream_t s, int nrhs, const c128* bin, c128*
                       const RhsState* st, int gate) {
     const int L = (int)c->lv.size();
     const int bc = c->cfg.bc;
-    const double om = c->cfg.omega;
+    const MgParams P{c->cfg.beta1, c->cfg.beta2, c->cfg.omega};
     auto C = [](void* p) { return reinterpret_cast<cx<R>*>(p); };
+    auto K = [](void* p) { return reinterpret_cast<const R*>(p); };
     LevelBuf& f = c->lv[0];
-    // down
-    launch_mg_resid<double, R>(s, bc, f.g, f.L, nrhs, bin, f.g.n, C(f.w), om, C(f.tmp), st, gate);
-    launch_mg_restrict<R>(s, bc, f.g, c->lv[1].g, c->lv[1].L, nrhs, C(f.tmp), C(c->lv[1].b), st, gate);
+    LevelBuf& cl = c->lv[L - 1];
+    // down: one pass per level writes the next level's right-hand side
+    launch_mg_down<double, R>(s, bc, f.g, c->lv[1].g, f.zb_down, nrhs, bin, f.g.n, K(f.k2l), P,
+                              C(c->lv[1].b), st, gate);
     for (int l = 1; l < L - 1; ++l) {
         LevelBuf& a = c->lv[l];
         LevelBuf& n = c->lv[l + 1];
-        launch_mg_resid<R, R>(s, bc, a.g, a.L, nrhs, C(a.b), a.g.n, C(a.w), om, C(a.tmp), st, gate);
-        launch_mg_restrict<R>(s, bc, a.g, n.g, n.L, nrhs, C(a.tmp), C(n.b), st, gate);
+        launch_mg_down<R, R>(s, bc, a.g, n.g, a.zb_down, nrhs, C(a.b), a.g.n, K(a.k2l), P, C(n.b), st, gate);
     }
-    // coarsest
-    LevelBuf& cl = c->lv[L - 1];
     launch_coarse<R>(s, nrhs, (int)cl.g.n, c->n_unk, c->cidx, C(c->minv), C(cl.b), C(cl.e), st, gate);
-    // up
+    // up: one pass per level writes the level's V-cycle result
     for (int l = L - 2; l >= 1; --l) {
         LevelBuf& a = c->lv[l];
         LevelBuf& n = c->lv[l + 1];
-        launch_mg_correct<R, R>(s, bc, a.g, n.g, a.L, nrhs, C(a.b), a.g.n, C(a.w), C(n.e), C(a.tmp), st,
-                                gate);
-        launch_mg_smooth<R, R, R>(s, bc, a.g, a.L, nrhs, C(a.tmp), C(a.b), a.g.n, C(a.w), om, C(a.e),
-                                  a.g.n, st, gate);
+        launch_mg_up<R, R, R>(s, bc, a.g, n.g, a.zb_up, nrhs, C(a.b), a.g.n, K(a.k2l), P, C(n.e), C(a.e),
+                              a.g.n, st, gate);
     }
-    launch_mg_correct<double, R>(s, bc, f.g, c->lv[1].g, f.L, nrhs, bin, f.g.n, C(f.w), C(c->lv[1].e),
-                                 C(f.tmp), st, gate);
-    launch_mg_smooth<double, R, double>(s, bc, f.g, f.L, nrhs, C(f.tmp), bin, f.g.n, C(f.w), om, bout,
-                                        f.g.n, st, gate);
+    launch_mg_up<double, R, double>(s, bc, f.g, c->lv[1].g, f.zb_up, nrhs, bin, f.g.n, K(f.k2l), P,
+                                    C(c->lv[1].e), bout, f.g.n, st, gate);
 }
 
 void enqueue_vcycle(hh_ctx* c, hipStream_t s, int nrhs, const c128* bin, c128* bout,
@@ -449,6 +464,7 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
     c->stream = (hipStream_t)hip_stream;
     c->mixed = cfg->prec == HH_PREC_MIXED;
     c->csize = c->mixed ? sizeof(c64) : sizeof(c128);
+    c->rsize = c->mixed ? sizeof(float) : sizeof(double);
     (void)hipGetDevice(&c->device);
     auto bail = [&](hh_status s) {
         g_create_error = c->err;
@@ -467,9 +483,7 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
         const size_t nn = (size_t)B.g.n;
         hh_status s;
         if ((s = dalloc(c, &B.k, sizeof(double) * nn)) != HH_OK) return bail(s);
-        if ((s = dalloc(c, (char**)&B.w, c->csize * nn)) != HH_OK) return bail(s);
-        if (l < L - 1)
-            if ((s = dalloc(c, (char**)&B.tmp, c->csize * nn * R)) != HH_OK) return bail(s);
+        if ((s = dalloc(c, (char**)&B.k2l, c->rsize * nn)) != HH_OK) return bail(s);
         if (l >= 1) {
             if ((s = dalloc(c, (char**)&B.b, c->csize * nn * R)) != HH_OK) return bail(s);
             if ((s = dalloc(c, (char**)&B.e, c->csize * nn * R)) != HH_OK) return bail(s);
@@ -498,8 +512,7 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
     };
     for (auto& B : c->lv) {
         zero(B.k, sizeof(double) * B.g.n);
-        zero(B.w, c->csize * B.g.n);
-        zero(B.tmp, c->csize * B.g.n * R);
+        zero(B.k2l, c->rsize * B.g.n);
         zero(B.b, c->csize * B.g.n * R);
         zero(B.e, c->csize * B.g.n * R);
     }
@@ -546,12 +559,8 @@ hh_status hh_set_model(hh_ctx* c, const double* k) {
     for (size_t l = 1; l < c->lv.size(); ++l)
         launch_inject(c->stream, c->lv[l - 1].g, c->lv[l].g, c->lv[l - 1].k, c->lv[l].k);
     for (auto& B : c->lv) {
-        if (c->mixed)
-            launch_make_w<float>(c->stream, B.g, c->cfg.bc, B.k, c->cfg.beta1, c->cfg.beta2, c->cfg.omega,
-                                 (c64*)B.w);
-        else
-            launch_make_w<double>(c->stream, B.g, c->cfg.bc, B.k, c->cfg.beta1, c->cfg.beta2, c->cfg.omega,
-                                  (c128*)B.w);
+        if (c->mixed) launch_level_k2<float>(c->stream, B.g.n, B.k, (float*)B.k2l);
+        else launch_level_k2<double>(c->stream, B.g.n, B.k, (double*)B.k2l);
     }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->bad_host, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -751,6 +760,8 @@ hh_status hh_get_option(const hh_ctx* c, const char* name, long long* value) {
     if (!c || !name || !value) return HH_ERR_ARG;
     std::string n(name);
     if (n == "graph") *value = c->use_graph;
+    else if (n == "zb_down") *value = c->lv[0].zb_down;
+    else if (n == "zb_up") *value = c->lv[0].zb_up;
     else if (n == "check_every") *value = c->check_every;
     else if (n == "block") *value = c->L0.block;
     else if (n == "zb") *value = c->L0.zb;
@@ -760,64 +771,63 @@ hh_status hh_get_option(const hh_ctx* c, const char* name, long long* value) {
     return HH_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One launch of fine-level kernel `which` exactly as the solve issues it.
+template <typename R>
+void launch_one_fine(hh_ctx* c, int which, int nrhs) {
+    const Geo& g = c->lv[0].g;
+    const Geo& g1 = c->lv[1].g;
+    LevelBuf& f = c->lv[0];
+    const int bc = c->cfg.bc;
+    const MgParams P{c->cfg.beta1, c->cfg.beta2, c->cfg.omega};
+    hipStream_t s = c->stream;
+    Launch F = c->L0;
+    F.flat_cap = (int)c->nblk0;
+    auto C = [](void* p) { return reinterpret_cast<cx<R>*>(p); };
+    const R* k2l = reinterpret_cast<const R*>(f.k2l);
+    switch (which) {
+        case 0:
+            launch_apply(s, bc, OP_T, g, c->L0, nrhs, c->sh, c->t, c->k2, c->kb, 1.0, 0.0, c->s, c->part,
+                         NBLK_CAP, c->st, ST_RUN);
+            break;
+        case 1:
+            launch_update_xr(s, g.n, nrhs, c->xk, c->r, c->ph, c->sh, c->s, c->t, c->rhat, c->st, c->part,
+                             NBLK_CAP, F);
+            break;
+        case 2:
+            launch_mg_down<double, R>(s, bc, g, g1, f.zb_down, nrhs, c->p, g.n, k2l, P, C(c->lv[1].b), c->st,
+                                      ST_RUN);
+            break;
+        case 3:
+            launch_mg_up<double, R, double>(s, bc, g, g1, f.zb_up, nrhs, c->p, g.n, k2l, P, C(c->lv[1].e),
+                                            c->ph, g.n, c->st, ST_RUN);
+            break;
+        case 4:
+            launch_p_update(s, g.n, nrhs, c->p, c->r, c->v, c->st, F);
+            break;
+        default:
+            launch_s_update(s, g.n, nrhs, c->s, c->r, c->v, c->st, c->part, NBLK_CAP, F);
+            break;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
 hh_status hh_time_kernel(hh_ctx* c, int which, int nrhs, int reps, float* ms_avg) {
     CHK(check_ready(c, nrhs));
     if (reps < 1 || !ms_avg) return fail(c, HH_ERR_ARG, "reps >= 1 and ms_avg required");
-    const Geo& g = c->lv[0].g;
-    const int bc = c->cfg.bc;
-    Launch F = c->L0;
-    F.flat_cap = (int)c->nblk0;
+    if (which < 0 || which > 5) return fail(c, HH_ERR_ARG, "unknown kernel id %d", which);
+    // the gated kernels act on right-hand sides marked as iterating
     launch_fill_status(c->stream, nrhs, c->st, ST_RUN, 2);
     auto one = [&]() {
-        switch (which) {
-            case 0:
-                launch_apply(c->stream, bc, OP_T, g, c->L0, nrhs, c->sh, c->t, c->k2, c->kb, 1.0, 0.0, c->s,
-                             c->part, NBLK_CAP, c->st, ST_RUN);
-                break;
-            case 1:
-                launch_update_xr(c->stream, g.n, nrhs, c->xk, c->r, c->ph, c->sh, c->s, c->t, c->rhat, c->st,
-                                 c->part, NBLK_CAP, F);
-                break;
-            case 2:
-                if (c->mixed)
-                    launch_mg_resid<double, float>(c->stream, bc, g, c->L0, nrhs, c->p, g.n, (c64*)c->lv[0].w,
-                                                   c->cfg.omega, (c64*)c->lv[0].tmp, c->st, ST_RUN);
-                else
-                    launch_mg_resid<double, double>(c->stream, bc, g, c->L0, nrhs, c->p, g.n, (c128*)c->lv[0].w,
-                                                    c->cfg.omega, (c128*)c->lv[0].tmp, c->st, ST_RUN);
-                break;
-            case 3:
-                if (c->mixed)
-                    launch_mg_restrict<float>(c->stream, bc, g, c->lv[1].g, c->lv[1].L, nrhs, (c64*)c->lv[0].tmp,
-                                              (c64*)c->lv[1].b, c->st, ST_RUN);
-                else
-                    launch_mg_restrict<double>(c->stream, bc, g, c->lv[1].g, c->lv[1].L, nrhs, (c128*)c->lv[0].tmp,
-                                               (c128*)c->lv[1].b, c->st, ST_RUN);
-                break;
-            case 4:
-                if (c->mixed)
-                    launch_mg_correct<double, float>(c->stream, bc, g, c->lv[1].g, c->L0, nrhs, c->p, g.n,
-                                                     (c64*)c->lv[0].w, (c64*)c->lv[1].e, (c64*)c->lv[0].tmp,
-                                                     c->st, ST_RUN);
-                else
-                    launch_mg_correct<double, double>(c->stream, bc, g, c->lv[1].g, c->L0, nrhs, c->p, g.n,
-                                                      (c128*)c->lv[0].w, (c128*)c->lv[1].e,
-                                                      (c128*)c->lv[0].tmp, c->st, ST_RUN);
-                break;
-            default:
-                if (c->mixed)
-                    launch_mg_smooth<double, float, double>(c->stream, bc, g, c->L0, nrhs, (c64*)c->lv[0].tmp,
-                                                            c->p, g.n, (c64*)c->lv[0].w, c->cfg.omega, c->ph,
-                                                            g.n, c->st, ST_RUN);
-                else
-                    launch_mg_smooth<double, double, double>(c->stream, bc, g, c->L0, nrhs,
-                                                             (c128*)c->lv[0].tmp, c->p, g.n,
-                                                             (c128*)c->lv[0].w, c->cfg.omega, c->ph, g.n,
-                                                             c->st, ST_RUN);
-                break;
-        }
+        if (c->mixed) launch_one_fine<float>(c, which, nrhs);
+        else launch_one_fine<double>(c, which, nrhs);
     };
-    if (which < 0 || which > 5) return fail(c, HH_ERR_ARG, "unknown kernel id %d", which);
     one();  // warm-up
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
@@ -849,7 +859,7 @@ hh_status hh_autotune(hh_ctx* c, int nrhs) {
             c->base.zb = z;
             apply_launch(c);
             float tot = 0.f;
-            for (int which : {0, 2, 4, 5}) {
+            for (int which : {0, 2, 3}) {
                 float ms = 0.f;
                 CHK(hh_time_kernel(c, which, nrhs, 5, &ms));
                 tot += ms;

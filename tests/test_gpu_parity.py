@@ -49,7 +49,7 @@ def hetero_k(shape, seed, lo=4.0, hi=12.0):
 
 # shapes: several workgroups per plane, ragged last workgroup, non-cubic, and
 # level counts from 2 to 5
-SHAPES = [(9, 9, 9), (17, 9, 33), (33, 17, 17), (5, 9, 65)]
+SHAPES = [(9, 9, 9), (17, 9, 33), (33, 17, 17), (5, 9, 65), (9, 65, 129), (33, 97, 41)]
 
 
 @pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
