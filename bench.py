@@ -154,6 +154,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=4)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy a 1 GiB device buffer 3 times (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver keeps the whole grid on one device "
@@ -165,6 +167,13 @@ def main():
     from paper_2308_06085_amd import Solver
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        bbuf = torch.empty_like(a)
+        for _ in range(3):
+            bbuf.copy_(a)
+        torch.cuda.synchronize()
+        del a, bbuf
     wl, nodes, desc = make_workload(args.workload)
     nrhs = len(nodes)
     n_nodes = int(np.prod(wl.shape))

@@ -53,8 +53,18 @@ __host__ __device__ inline TileShape tile_shape(int nx, int ny, int maxw, int la
 constexpr int DN_LANES = 256, DN_MAXW = 32, DN_MAXH = 16;
 constexpr int DN_REGION = 1280;  // >= (2 tw + 3)(2 th + 3) for every shape tile_shape() returns
 constexpr int DN_RES = 1152;     // >= (2 tw + 1)(2 th + 1)
-constexpr int UP_LANES = 512, UP_MAXW = 64, UP_MAXH = 16;
-constexpr int UP_REGION = 704;   // >= (tw + 2)(th + 2)
+constexpr int UP_LANES = 512, UP_MAXW = 32;  // up pass: one lane per region node
+// Tile of the up pass: the tile plus a one-node halo must fit the lanes,
+// (tw + 2)(th + 2) <= lanes.
+__host__ __device__ inline TileShape up_tile_shape(int nx, int ny) {
+    TileShape T;
+    T.ntx = (nx + UP_MAXW - 1) / UP_MAXW;
+    T.tw = (nx + T.ntx - 1) / T.ntx;
+    T.th = UP_LANES / (T.tw + 2) - 2;
+    if (T.th > ny) T.th = ny;
+    T.nty = (ny + T.th - 1) / T.th;
+    return T;
+}
 
 // Level constants of the CSLP operator in the compute precision.
 template <typename R>
@@ -74,18 +84,26 @@ __device__ __forceinline__ LevelCoef<R> level_coef(const Geo& g, double beta1, d
     return L;
 }
 
+// Square root and reciprocal: correctly rounded in double; in single precision
+// the hardware v_sqrt_f32 / v_rcp_f32 (about 1 ulp), far inside the accuracy a
+// complex64 V-cycle is held to.
+__device__ __forceinline__ double mg_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float mg_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double mg_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float mg_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // c_j = (beta1 - beta2 i) k^2 + n_j 2 i k / h
 template <typename R>
 __device__ __forceinline__ cx<R> shift_c(const LevelCoef<R>& L, R k2, int nf) {
     cx<R> c = {L.sr * k2, L.si * k2};
-    if (nf) c.im += R(nf) * L.two_over_h * sqrt(k2);
+    if (nf) c.im += R(nf) * L.two_over_h * mg_sqrt(k2);
     return c;
 }
 // W = omega / (6/h^2 - c)
 template <typename R>
 __device__ __forceinline__ cx<R> jacobi_w(const LevelCoef<R>& L, cx<R> c) {
     const R dr = L.six_ih2 - c.re, di = -c.im;
-    const R s = L.omega / (dr * dr + di * di);
+    const R s = L.omega * mg_rcp(dr * dr + di * di);
     return {dr * s, -di * s};
 }
 
@@ -154,14 +172,14 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
     R uk[NU];
     cx<TB> rb[NR];
     R rk[NR];
+    // Loads are issued unconditionally (every offset is a valid node) so the
+    // compiler can count them precisely and keep the next plane in flight.
     auto fetch_u1 = [&](int f) {
         const long long base = (long long)mirror_clamp(f, gf.nz) * gf.plane;
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
-            if (t + k * DN_LANES < RW * RH) {
-                ub[k] = br[base + uoff[k]];
-                uk[k] = k2l[base + uoff[k]];
-            }
+            ub[k] = br[base + uoff[k]];
+            uk[k] = k2l[base + uoff[k]];
         }
     };
     auto commit_u1 = [&](int f) {
@@ -183,10 +201,8 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
         const long long base = (long long)mirror_clamp(f, gf.nz) * gf.plane;
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
-            if (t + k * DN_LANES < IW * IH) {
-                rb[k] = br[base + roff[k]];
-                rk[k] = k2l[base + roff[k]];
-            }
+            rb[k] = br[base + roff[k]];
+            rk[k] = k2l[base + roff[k]];
         }
     };
     auto residual = [&](int f) {
@@ -225,10 +241,10 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
     fetch_res(2 * Z0 - 1);
     for (int f = 2 * Z0 - 1; f <= 2 * Z1 - 1; ++f) {
         commit_u1(f + 1);
-        if (f + 2 <= 2 * Z1) fetch_u1(f + 2);
+        fetch_u1(f + 2);  // past the chunk's end this reads a valid (unused) plane
         __syncthreads();
         residual(f);
-        if (f + 1 <= 2 * Z1 - 1) fetch_res(f + 1);
+        fetch_res(f + 1);
         __syncthreads();
         // 2D full weighting of the residual plane at the lane's coarse column
         cx<R> q = R(4) * rs[ic];
@@ -260,8 +276,9 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
 }
 
 // ---------------------------------------------------------------------------
-// Up: u3 = u2 + W (b - (1/h^2) lap(u2) + c u2), u2 = W b + P e_H.  One lane
-// per fine column of a tw x th tile, marching over `zb` planes.
+// Up: u3 = u2 + W (b - (1/h^2) lap(u2) + c u2), u2 = W b + P e_H.  Each lane
+// owns one node of the tile-plus-halo region; the lanes inside the halo
+// compute the output.  The workgroup marches over `zb` planes.
 // ---------------------------------------------------------------------------
 template <int BC, typename TB, typename R, typename TO>
 __global__ __launch_bounds__(UP_LANES) void k_mg_up(Geo g, Geo gc, int zb,
@@ -271,13 +288,12 @@ __global__ __launch_bounds__(UP_LANES) void k_mg_up(Geo g, Geo gc, int zb,
                                                     const cx<R>* __restrict__ ec,
                                                     cx<TO>* __restrict__ out, long long o_rstride,
                                                     const RhsState* st, int gate) {
-    constexpr int NU = (UP_REGION + UP_LANES - 1) / UP_LANES;
-    __shared__ cx<R> us[3][UP_REGION];
+    __shared__ cx<R> us[3][UP_LANES];
 
     const int r = blockIdx.z;
     if (!gate_ok(st, r, gate)) return;
     const int t = threadIdx.x;
-    const TileShape T = tile_shape(g.nx, g.ny, UP_MAXW, UP_LANES, UP_MAXH);
+    const TileShape T = up_tile_shape(g.nx, g.ny);
     const int RW = T.tw + 2, RH = T.th + 2;
     const int id = xcd_tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int tz = id / gridDim.x;
@@ -289,119 +305,101 @@ __global__ __launch_bounds__(UP_LANES) void k_mg_up(Geo g, Geo gc, int zb,
     const cx<R>* er = ec + (long long)r * gc.n;
     const LevelCoef<R> L = level_coef<R>(g, beta1, beta2, omega);
 
-    // region nodes: fine in-plane offset, face count in the plane, and the two
-    // coarse in-plane offsets per axis with their interpolation weights
-    int uoff[NU], unf[NU], cx0[NU], cx1[NU], cy0[NU], cy1[NU];
-    R wx[NU], wy[NU];
-    bool ubnd[NU];
-#pragma unroll
-    for (int k = 0; k < NU; ++k) {
-        const int idx = t + k * UP_LANES;
-        const int ly = idx / RW, lx = idx - ly * RW;
-        const int gx = mirror_clamp(X0 - 1 + lx, g.nx), gy = mirror_clamp(Y0 - 1 + ly, g.ny);
-        uoff[k] = gy * g.nx + gx;
-        unf[k] = (gx == 0) + (gx == g.nx - 1) + (gy == 0) + (gy == g.ny - 1);
-        ubnd[k] = unf[k] != 0;
-        cx0[k] = gx >> 1;
-        cx1[k] = min((gx >> 1) + (gx & 1), gc.nx - 1);
-        cy0[k] = (gy >> 1) * gc.nx;
-        cy1[k] = min((gy >> 1) + (gy & 1), gc.ny - 1) * gc.nx;
-        wx[k] = (gx & 1) ? R(0.5) : R(1);
-        wy[k] = (gy & 1) ? R(0.5) : R(1);
-    }
+    // this lane's region node: fine in-plane offset (mirrored into the grid),
+    // face count in the plane, the coarse corners and weights of its interpolation
+    const bool in_region = t < RW * RH;
+    const int ly = t / RW, lx = t - ly * RW;
+    const int gxr = X0 - 1 + lx, gyr = Y0 - 1 + ly;
+    const int gx = mirror_clamp(gxr, g.nx), gy = mirror_clamp(gyr, g.ny);
+    const int uoff = gy * g.nx + gx;
+    const int unf = (gx == 0) + (gx == g.nx - 1) + (gy == 0) + (gy == g.ny - 1);
+    const int cx0 = gx >> 1, cx1 = min((gx >> 1) + (gx & 1), gc.nx - 1);
+    const int cy0 = (gy >> 1) * gc.nx, cy1 = min((gy >> 1) + (gy & 1), gc.ny - 1) * gc.nx;
+    const R ax = (gx & 1) ? R(0.5) : R(1), ay = (gy & 1) ? R(0.5) : R(1);
+    const R bx = R(1) - ax, by = R(1) - ay;
+    // output lanes: inside the halo and on the grid
+    const bool own = in_region && lx >= 1 && lx <= T.tw && ly >= 1 && ly <= T.th && gxr < g.nx &&
+                     gyr < g.ny;
 
-    cx<TB> ub[NU];
-    R uk[NU];
-    cx<R> ue[NU][8];
+    // raw loads in flight (issued unconditionally: every offset is a valid node)
+    cx<TB> ub;
+    R uk;
+    cx<R> ue[8];
     auto fetch_u2 = [&](int f) {
         const int fz = mirror_clamp(f, g.nz);
         const long long base = (long long)fz * g.plane;
         const cx<R>* e0 = er + (long long)(fz >> 1) * gc.plane;
         const cx<R>* e1 = er + (long long)min((fz >> 1) + (fz & 1), gc.nz - 1) * gc.plane;
-#pragma unroll
-        for (int k = 0; k < NU; ++k) {
-            if (t + k * UP_LANES < RW * RH) {
-                ub[k] = br[base + uoff[k]];
-                uk[k] = k2l[base + uoff[k]];
-                ue[k][0] = e0[cy0[k] + cx0[k]];
-                ue[k][1] = e0[cy0[k] + cx1[k]];
-                ue[k][2] = e0[cy1[k] + cx0[k]];
-                ue[k][3] = e0[cy1[k] + cx1[k]];
-                ue[k][4] = e1[cy0[k] + cx0[k]];
-                ue[k][5] = e1[cy0[k] + cx1[k]];
-                ue[k][6] = e1[cy1[k] + cx0[k]];
-                ue[k][7] = e1[cy1[k] + cx1[k]];
-            }
-        }
+        ub = br[base + uoff];
+        uk = k2l[base + uoff];
+        ue[0] = e0[cy0 + cx0];
+        ue[1] = e0[cy0 + cx1];
+        ue[2] = e0[cy1 + cx0];
+        ue[3] = e0[cy1 + cx1];
+        ue[4] = e1[cy0 + cx0];
+        ue[5] = e1[cy0 + cx1];
+        ue[6] = e1[cy1 + cx0];
+        ue[7] = e1[cy1 + cx1];
     };
-    auto commit_u2 = [&](int f) {
+    // u2 at this lane's node; the stencil of the output lanes needs it in LDS
+    auto make_u2 = [&](int f, cx<R>& kk_c, R& kk) -> cx<R> {
         const int fz = mirror_clamp(f, g.nz);
         const int zf = (fz == 0) + (fz == g.nz - 1);
-        const R wz = (fz & 1) ? R(0.5) : R(1);
-        cx<R>* dst = us[ring3(f)];
-#pragma unroll
-        for (int k = 0; k < NU; ++k) {
-            const int idx = t + k * UP_LANES;
-            if (idx < RW * RH) {
-                // trilinear interpolation; an even index takes its own coarse node only
-                const R ax = wx[k], ay = wy[k];
-                const R bx = R(1) - ax, by = R(1) - ay, bz = R(1) - wz;
-                cx<R> p0 = (ax * ue[k][0] + bx * ue[k][1]);
-                cx<R> p1 = (ax * ue[k][2] + bx * ue[k][3]);
-                cx<R> p2 = (ax * ue[k][4] + bx * ue[k][5]);
-                cx<R> p3 = (ax * ue[k][6] + bx * ue[k][7]);
-                cx<R> pe = wz * (ay * p0 + by * p1) + bz * (ay * p2 + by * p3);
-                const int nf = BC == BC_SOMMERFELD ? unf[k] + zf : 0;
-                cx<R> v = jacobi_w(L, shift_c(L, uk[k], nf)) * cvt<R>(ub[k]) + pe;
-                if (BC == BC_DIRICHLET && (ubnd[k] || zf)) v = czero<R>();
-                dst[idx] = v;
-            }
-        }
+        const R wz = (fz & 1) ? R(0.5) : R(1), bz = R(1) - wz;
+        // trilinear interpolation; an even index takes its own coarse node only
+        const cx<R> p0 = ax * ue[0] + bx * ue[1];
+        const cx<R> p1 = ax * ue[2] + bx * ue[3];
+        const cx<R> p2 = ax * ue[4] + bx * ue[5];
+        const cx<R> p3 = ax * ue[6] + bx * ue[7];
+        const cx<R> pe = wz * (ay * p0 + by * p1) + bz * (ay * p2 + by * p3);
+        const int nf = BC == BC_SOMMERFELD ? unf + zf : 0;
+        kk = uk;
+        kk_c = shift_c(L, uk, nf);
+        cx<R> v = jacobi_w(L, kk_c) * cvt<R>(ub) + pe;
+        if (BC == BC_DIRICHLET && (unf || zf)) v = czero<R>();
+        return v;
     };
 
-    const int tx = t % T.tw, ty = t / T.tw;
-    const int gx = X0 + tx, gy = Y0 + ty;
-    const bool own = ty < T.th && gx < g.nx && gy < g.ny;
-    const int c = own ? (ty + 1) * RW + tx + 1 : RW + 1;
-    const long long ooff = own ? (long long)gy * g.nx + gx : 0;
-    const int onf = (gx == 0) + (gx == g.nx - 1) + (gy == 0) + (gy == g.ny - 1);
     cx<TO>* orr = out + (long long)r * o_rstride;
-    cx<TB> ob = {};
-    R ok = R(0);
-    auto fetch_own = [&](int z) {
-        if (own) {
-            ob = br[(long long)z * g.plane + ooff];
-            ok = k2l[(long long)z * g.plane + ooff];
-        }
-    };
+    const long long ooff = own ? (long long)gyr * g.nx + gxr : 0;
+    // per plane this lane keeps its own u2, b, c for the output step
+    cx<R> u_cur, c_cur, c_nxt;
+    R k_unused;
+    cx<TB> b_cur, b_nxt;
     fetch_u2(z0 - 1);
-    commit_u2(z0 - 1);
+    {
+        cx<R> cc;
+        cx<R> v = make_u2(z0 - 1, cc, k_unused);
+        if (in_region) us[ring3(z0 - 1)][t] = v;
+    }
     fetch_u2(z0);
-    commit_u2(z0);
+    b_cur = ub;
+    u_cur = make_u2(z0, c_cur, k_unused);
+    if (in_region) us[ring3(z0)][t] = u_cur;
     fetch_u2(z0 + 1);
-    fetch_own(z0);
     for (int z = z0; z < z1; ++z) {
-        commit_u2(z + 1);
-        if (z + 2 <= z1) fetch_u2(z + 2);
+        b_nxt = ub;
+        const cx<R> u_nxt = make_u2(z + 1, c_nxt, k_unused);
+        if (in_region) us[ring3(z + 1)][t] = u_nxt;
+        fetch_u2(z + 2);  // past the chunk's end this reads a valid (unused) plane
         __syncthreads();
         if (own) {
             const cx<R>* um = us[ring3(z - 1)];
             const cx<R>* uc = us[ring3(z)];
             const cx<R>* up = us[ring3(z + 1)];
-            const cx<R> u = uc[c];
-            cx<R> lap = (u - uc[c - 1]) + (u - uc[c + 1]);
-            lap = lap + (u - uc[c - RW]);
-            lap = lap + (u - uc[c + RW]);
-            lap = lap + (u - um[c]);
-            lap = lap + (u - up[c]);
-            const int nf = BC == BC_SOMMERFELD ? onf + (z == 0) + (z == g.nz - 1) : 0;
-            const cx<R> cc = shift_c(L, ok, nf);
-            cx<R> v = u + jacobi_w(L, cc) * ((cvt<R>(ob) - L.ih2 * lap) + cc * u);
-            if (BC == BC_DIRICHLET && (onf || z == 0 || z == g.nz - 1)) v = czero<R>();
-            const long long gi = (long long)z * g.plane + ooff;
-            if (z + 1 < z1) fetch_own(z + 1);
-            orr[gi] = cvt<TO>(v);
+            const cx<R> u = u_cur;
+            cx<R> lap = (u - uc[t - 1]) + (u - uc[t + 1]);
+            lap = lap + (u - uc[t - RW]);
+            lap = lap + (u - uc[t + RW]);
+            lap = lap + (u - um[t]);
+            lap = lap + (u - up[t]);
+            cx<R> v = u + jacobi_w(L, c_cur) * ((cvt<R>(b_cur) - L.ih2 * lap) + c_cur * u);
+            if (BC == BC_DIRICHLET && (unf || z == 0 || z == g.nz - 1)) v = czero<R>();
+            orr[(long long)z * g.plane + ooff] = cvt<TO>(v);
         }
+        u_cur = u_nxt;
+        c_cur = c_nxt;
+        b_cur = b_nxt;
         __syncthreads();
     }
 }
@@ -414,7 +412,7 @@ int mg_down_blocks(const Geo& gc, int zbc) {
     return T.ntx * T.nty * ((gc.nz + zbc - 1) / zbc);
 }
 int mg_up_blocks(const Geo& g, int zb) {
-    const TileShape T = tile_shape(g.nx, g.ny, UP_MAXW, UP_LANES, UP_MAXH);
+    const TileShape T = up_tile_shape(g.nx, g.ny);
     return T.ntx * T.nty * ((g.nz + zb - 1) / zb);
 }
 
@@ -436,7 +434,7 @@ template <typename TB, typename R, typename TO>
 void launch_mg_up(hipStream_t s, int bc, const Geo& g, const Geo& gc, int zb, int nrhs,
                   const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
                   const cx<R>* ec, cx<TO>* out, long long o_rstride, const RhsState* st, int gate) {
-    const TileShape T = tile_shape(g.nx, g.ny, UP_MAXW, UP_LANES, UP_MAXH);
+    const TileShape T = up_tile_shape(g.nx, g.ny);
     dim3 grid(T.ntx * T.nty, (g.nz + zb - 1) / zb, nrhs);
     if (bc == BC_SOMMERFELD)
         hipLaunchKernelGGL((k_mg_up<BC_SOMMERFELD, TB, R, TO>), grid, dim3(UP_LANES), 0, s, g, gc, zb, b,
