@@ -16,7 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhh.so")
-SOURCES = ["hh_kernels.hip", "hh_mg_fused.hip", "hh_solver.hip"]
+SOURCES = ["hh_kernels.hip", "hh_mg_fused.hip", "hh_mg_tail.hip", "hh_solver.hip"]
 ARCH = os.environ.get("HH_OFFLOAD_ARCH", "gfx950")
 
 

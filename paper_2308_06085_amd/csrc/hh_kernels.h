@@ -44,6 +44,29 @@ void launch_mg_up(hipStream_t s, int bc, const Geo& g, const Geo& gc, int zb, in
                   const cx<R>* ec, cx<TO>* out, long long o_rstride, const RhsState* st, int gate);
 int mg_down_blocks(const Geo& gc, int zbc);
 int mg_up_blocks(const Geo& g, int zb);
+
+// The trailing (smallest) levels of the hierarchy, run by one workgroup per
+// right-hand side with every array in LDS.  off = offset of the level's nodes
+// in the LDS arrays, total = sum of the levels' node counts.
+constexpr int MAX_TAIL = 8;
+struct TailLevel {
+    int nx, ny, nz, n, off;
+    double h;
+    const void* k2;  // level k^2 in the multigrid precision (device)
+};
+struct TailDesc {
+    int nlev, total, n_unk;
+    double beta1, beta2, omega;
+    const int* cidx;   // coarsest unknown -> node
+    const void* minv;  // dense inverse of the coarsest M, column-major
+    TailLevel lv[MAX_TAIL];
+};
+size_t mg_tail_lds_bytes(const TailDesc& D, bool single);
+// Raise the kernel's dynamic-LDS limit to `bytes`; returns false if refused.
+bool mg_tail_allow_lds(size_t bytes);
+template <typename R>
+void launch_mg_tail(hipStream_t s, int bc, const TailDesc& D, int nrhs, const cx<R>* b_first,
+                    cx<R>* e_first, const RhsState* st, int gate);
 template <typename R>
 void launch_coarse(hipStream_t s, int nrhs, int n_nodes, int n_unk, const int* cidx,
                    const cx<R>* minv, const cx<R>* b, cx<R>* e, const RhsState* st, int gate);

@@ -1,0 +1,262 @@
+// The smallest multigrid levels in one workgroup, with every array in LDS.
+//
+// Below a few thousand nodes a level's passes are pure latency: a separate
+// kernel per pass costs a launch and a memory round trip for microseconds of
+// work.  This kernel runs the whole rest of the V-cycle from level `first`
+// down to the coarsest level and back up (Algorithm 1 applied recursively:
+// damped-Jacobi pre-smoothing from zero, residual, full weighting, exact
+// coarsest solve with the dense inverse, trilinear prolongation, correction,
+// damped-Jacobi post-smoothing) with one workgroup per right-hand side; the
+// passes are separated by workgroup barriers instead of kernel boundaries.
+// Operators and boundary rules are those of the fused passes:
+//   M u = (1/h^2) lap(u) - c u,  lap(u)_j = sum_nb (u_j - u_nb) with the
+//   Sommerfeld ghost point replaced by its mirror image (its 2hik part is in c),
+//   W = omega / (6/h^2 - c).
+#include "hh_common.h"
+#include "hh_device.h"
+#include "hh_kernels.h"
+
+namespace hh {
+
+namespace {
+
+__device__ __forceinline__ double t_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float t_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double t_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float t_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <typename R>
+struct TailCoef {
+    R ih2, six_ih2, two_over_h, sr, si, omega;
+};
+
+// node index -> (x, y, z)
+__device__ __forceinline__ void unflat(int i, const TailLevel& L, int& x, int& y, int& z) {
+    const int plane = L.nx * L.ny;
+    z = i / plane;
+    const int rem = i - z * plane;
+    y = rem / L.nx;
+    x = rem - y * L.nx;
+}
+
+__device__ __forceinline__ int mirror_in(int g, int n) { return g < 0 ? -g : (g > n - 1 ? 2 * (n - 1) - g : g); }
+
+template <int BC, typename R>
+__device__ __forceinline__ cx<R> shift_c_t(const TailCoef<R>& C, R k2, int nf) {
+    cx<R> c = {C.sr * k2, C.si * k2};
+    if (BC == BC_SOMMERFELD && nf) c.im += R(nf) * C.two_over_h * t_sqrt(k2);
+    return c;
+}
+template <typename R>
+__device__ __forceinline__ cx<R> jacobi_w_t(const TailCoef<R>& C, cx<R> c) {
+    const R dr = C.six_ih2 - c.re, di = -c.im;
+    const R s = C.omega * t_rcp(dr * dr + di * di);
+    return {dr * s, -di * s};
+}
+
+// lap(u) at (x, y, z) of level L from the LDS array u
+template <typename R>
+__device__ __forceinline__ cx<R> lap_at(const cx<R>* u, const TailLevel& L, int x, int y, int z) {
+    const int plane = L.nx * L.ny;
+    const int i = (z * L.ny + y) * L.nx + x;
+    const cx<R> c = u[i];
+    const int xm = mirror_in(x - 1, L.nx), xp = mirror_in(x + 1, L.nx);
+    const int ym = mirror_in(y - 1, L.ny), yp = mirror_in(y + 1, L.ny);
+    const int zm = mirror_in(z - 1, L.nz), zp = mirror_in(z + 1, L.nz);
+    cx<R> s = (c - u[i - x + xm]) + (c - u[i - x + xp]);
+    s = s + (c - u[i + (ym - y) * L.nx]);
+    s = s + (c - u[i + (yp - y) * L.nx]);
+    s = s + (c - u[i + (zm - z) * plane]);
+    s = s + (c - u[i + (zp - z) * plane]);
+    return s;
+}
+
+}  // namespace
+
+template <int BC, typename R>
+__global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, const cx<R>* __restrict__ b_first,
+                                                  cx<R>* __restrict__ e_first,
+                                                  const RhsState* st, int gate) {
+    extern __shared__ unsigned char tail_smem[];
+    const int r = blockIdx.x;
+    if (!gate_ok(st, r, gate)) return;
+    const int t = threadIdx.x, nt = blockDim.x;
+    // LDS layout per level: b, u (the level's V-cycle result), w (scratch), k^2
+    cx<R>* base = reinterpret_cast<cx<R>*>(tail_smem);
+    auto B = [&](int l) { return base + 3 * D.lv[l].off; };
+    auto U = [&](int l) { return base + 3 * D.lv[l].off + D.lv[l].n; };
+    auto T = [&](int l) { return base + 3 * D.lv[l].off + 2 * D.lv[l].n; };
+    R* kbase = reinterpret_cast<R*>(base + 3 * D.total);
+    auto K = [&](int l) { return kbase + D.lv[l].off; };
+    auto coef = [&](int l) {
+        TailCoef<R> C;
+        const double h = D.lv[l].h;
+        C.ih2 = R(1.0 / (h * h));
+        C.six_ih2 = R(6.0 / (h * h));
+        C.two_over_h = R(2.0 / h);
+        C.sr = R(D.beta1);
+        C.si = R(-D.beta2);
+        C.omega = R(D.omega);
+        return C;
+    };
+    auto faces = [&](const TailLevel& L, int x, int y, int z) {
+        return (x == 0) + (x == L.nx - 1) + (y == 0) + (y == L.ny - 1) + (z == 0) + (z == L.nz - 1);
+    };
+    const int nl = D.nlev;
+    // stage the right-hand side of the first level and every level's k^2
+    const cx<R>* bsrc = b_first + (long long)r * D.lv[0].n;
+    for (int i = t; i < D.lv[0].n; i += nt) B(0)[i] = bsrc[i];
+    for (int l = 0; l < nl; ++l) {
+        const R* kg = reinterpret_cast<const R*>(D.lv[l].k2);
+        for (int i = t; i < D.lv[l].n; i += nt) K(l)[i] = kg[i];
+    }
+    __syncthreads();
+    // ---- down
+    for (int l = 0; l < nl - 1; ++l) {
+        const TailLevel& L = D.lv[l];
+        const TailLevel& Lc = D.lv[l + 1];
+        const TailCoef<R> C = coef(l);
+        cx<R>* b = B(l);
+        cx<R>* u = U(l);
+        cx<R>* w = T(l);
+        const R* k2 = K(l);
+        // pre-smoothing from zero: u1 = W b
+        for (int i = t; i < L.n; i += nt) {
+            int x, y, z;
+            unflat(i, L, x, y, z);
+            const int nf = faces(L, x, y, z);
+            cx<R> v = jacobi_w_t(C, shift_c_t<BC>(C, k2[i], nf)) * b[i];
+            if (BC == BC_DIRICHLET && nf) v = czero<R>();
+            u[i] = v;
+        }
+        __syncthreads();
+        // residual r = b - (1/h^2) lap(u1) + c u1
+        for (int i = t; i < L.n; i += nt) {
+            int x, y, z;
+            unflat(i, L, x, y, z);
+            const int nf = faces(L, x, y, z);
+            cx<R> v = (b[i] - C.ih2 * lap_at(u, L, x, y, z)) + shift_c_t<BC>(C, k2[i], nf) * u[i];
+            if (BC == BC_DIRICHLET && nf) v = czero<R>();
+            w[i] = v;
+        }
+        __syncthreads();
+        // full weighting onto the next level (mirror extension at the boundary)
+        cx<R>* bc = B(l + 1);
+        for (int i = t; i < Lc.n; i += nt) {
+            int X, Y, Z;
+            unflat(i, Lc, X, Y, Z);
+            cx<R> acc = czero<R>();
+            if (!(BC == BC_DIRICHLET && faces(Lc, X, Y, Z))) {
+                for (int dz = -1; dz <= 1; ++dz) {
+                    const int fz = mirror_in(2 * Z + dz, L.nz);
+                    for (int dy = -1; dy <= 1; ++dy) {
+                        const int fy = mirror_in(2 * Y + dy, L.ny);
+                        const cx<R>* row = w + (fz * L.ny + fy) * L.nx;
+                        const int fx0 = mirror_in(2 * X - 1, L.nx), fx2 = mirror_in(2 * X + 1, L.nx);
+                        cx<R> rs = row[fx0] + row[fx2];
+                        rs = rs + R(2) * row[2 * X];
+                        const R wyz = (dy == 0 ? R(2) : R(1)) * (dz == 0 ? R(2) : R(1));
+                        acc = acc + wyz * rs;
+                    }
+                }
+                acc = R(1.0 / 64.0) * acc;
+            }
+            bc[i] = acc;
+        }
+        __syncthreads();
+    }
+    // ---- coarsest: e = M_c^-1 b over the unknown nodes (inverse stored column-major)
+    {
+        const TailLevel& L = D.lv[nl - 1];
+        cx<R>* b = B(nl - 1);
+        cx<R>* u = U(nl - 1);
+        const cx<R>* minv = reinterpret_cast<const cx<R>*>(D.minv);
+        for (int i = t; i < L.n; i += nt) u[i] = czero<R>();
+        __syncthreads();
+        for (int row = t; row < D.n_unk; row += nt) {
+            cx<R> s = czero<R>();
+            for (int c = 0; c < D.n_unk; ++c) s = s + minv[(long long)c * D.n_unk + row] * b[D.cidx[c]];
+            u[D.cidx[row]] = s;
+        }
+        __syncthreads();
+    }
+    // ---- up
+    for (int l = nl - 2; l >= 0; --l) {
+        const TailLevel& L = D.lv[l];
+        const TailLevel& Lc = D.lv[l + 1];
+        const TailCoef<R> C = coef(l);
+        cx<R>* b = B(l);
+        cx<R>* u = U(l);
+        cx<R>* w = T(l);
+        const cx<R>* ec = U(l + 1);
+        const R* k2 = K(l);
+        // u2 = W b + P e (trilinear interpolation)
+        for (int i = t; i < L.n; i += nt) {
+            int x, y, z;
+            unflat(i, L, x, y, z);
+            const int nf = faces(L, x, y, z);
+            const int cxi = x >> 1, cyi = y >> 1, czi = z >> 1;
+            const int ox = x & 1, oy = y & 1, oz = z & 1;
+            cx<R> pe = czero<R>();
+            for (int a = 0; a <= oz; ++a)
+                for (int bb = 0; bb <= oy; ++bb)
+                    for (int c = 0; c <= ox; ++c)
+                        pe = pe + ec[((czi + a) * Lc.ny + cyi + bb) * Lc.nx + cxi + c];
+            const R wt = R(1) / R(1 << (ox + oy + oz));
+            cx<R> v = jacobi_w_t(C, shift_c_t<BC>(C, k2[i], nf)) * b[i] + wt * pe;
+            if (BC == BC_DIRICHLET && nf) v = czero<R>();
+            w[i] = v;
+        }
+        __syncthreads();
+        // post-smoothing: u3 = u2 + W (b - (1/h^2) lap(u2) + c u2)
+        for (int i = t; i < L.n; i += nt) {
+            int x, y, z;
+            unflat(i, L, x, y, z);
+            const int nf = faces(L, x, y, z);
+            const cx<R> cc = shift_c_t<BC>(C, k2[i], nf);
+            const cx<R> u2 = w[i];
+            cx<R> v = u2 + jacobi_w_t(C, cc) * ((b[i] - C.ih2 * lap_at(w, L, x, y, z)) + cc * u2);
+            if (BC == BC_DIRICHLET && nf) v = czero<R>();
+            u[i] = v;
+        }
+        __syncthreads();
+    }
+    cx<R>* edst = e_first + (long long)r * D.lv[0].n;
+    for (int i = t; i < D.lv[0].n; i += nt) edst[i] = U(0)[i];
+}
+
+size_t mg_tail_lds_bytes(const TailDesc& D, bool single) {
+    const size_t cs = single ? sizeof(c64) : sizeof(c128);
+    const size_t rs = single ? sizeof(float) : sizeof(double);
+    return (size_t)D.total * (3 * cs + rs);
+}
+
+bool mg_tail_allow_lds(size_t bytes) {
+    const int v = (int)bytes;
+    return hipFuncSetAttribute((const void*)k_mg_tail<BC_SOMMERFELD, double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess &&
+           hipFuncSetAttribute((const void*)k_mg_tail<BC_DIRICHLET, double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess &&
+           hipFuncSetAttribute((const void*)k_mg_tail<BC_SOMMERFELD, float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess &&
+           hipFuncSetAttribute((const void*)k_mg_tail<BC_DIRICHLET, float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess;
+}
+
+template <typename R>
+void launch_mg_tail(hipStream_t s, int bc, const TailDesc& D, int nrhs, const cx<R>* b_first,
+                    cx<R>* e_first, const RhsState* st, int gate) {
+    const size_t lds = mg_tail_lds_bytes(D, sizeof(R) == sizeof(float));
+    if (bc == BC_SOMMERFELD)
+        hipLaunchKernelGGL((k_mg_tail<BC_SOMMERFELD, R>), dim3(nrhs), dim3(1024), lds, s, D, b_first, e_first,
+                           st, gate);
+    else
+        hipLaunchKernelGGL((k_mg_tail<BC_DIRICHLET, R>), dim3(nrhs), dim3(1024), lds, s, D, b_first, e_first,
+                           st, gate);
+}
+template void launch_mg_tail<double>(hipStream_t, int, const TailDesc&, int, const c128*, c128*,
+                                     const RhsState*, int);
+template void launch_mg_tail<float>(hipStream_t, int, const TailDesc&, int, const c64*, c64*,
+                                    const RhsState*, int);
+
+}  // namespace hh

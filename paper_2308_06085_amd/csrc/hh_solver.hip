@@ -72,6 +72,8 @@ struct hh_ctx {
     bool use_graph = true;
     int check_every = 4;
     std::map<int, hipGraphExec_t> graphs;
+    int tail_first = 0;   // first level run by the single-workgroup tail kernel
+    size_t tail_lds_cap = 65536;
     float last_ms = 0.f;
     std::string err;
 };
@@ -181,6 +183,48 @@ int pick_zb(F blocks) {
     return 1;
 }
 
+// Trailing levels for the tail kernel: from the coarsest upwards while the
+// levels' LDS arrays fit the budget; level 0 always stays with the fused passes.
+void choose_tail(hh_ctx* c) {
+    const int L = (int)c->lv.size();
+    const size_t per_node = c->mixed ? 3 * sizeof(c64) + sizeof(float) : 3 * sizeof(c128) + sizeof(double);
+    long long total = 0;
+    int first = L - 1;
+    total = c->lv[L - 1].g.n;
+    while (first - 1 >= 1 && first - 1 >= L - MAX_TAIL &&
+           (size_t)(total + c->lv[first - 1].g.n) * per_node <= c->tail_lds_cap) {
+        --first;
+        total += c->lv[first].g.n;
+    }
+    c->tail_first = first;
+}
+
+TailDesc tail_desc(hh_ctx* c) {
+    TailDesc D{};
+    const int L = (int)c->lv.size();
+    D.nlev = L - c->tail_first;
+    D.n_unk = c->n_unk;
+    D.beta1 = c->cfg.beta1;
+    D.beta2 = c->cfg.beta2;
+    D.omega = c->cfg.omega;
+    D.cidx = c->cidx;
+    D.minv = c->minv;
+    int off = 0;
+    for (int i = 0; i < D.nlev; ++i) {
+        const LevelBuf& B = c->lv[c->tail_first + i];
+        D.lv[i].nx = B.g.nx;
+        D.lv[i].ny = B.g.ny;
+        D.lv[i].nz = B.g.nz;
+        D.lv[i].n = (int)B.g.n;
+        D.lv[i].off = off;
+        D.lv[i].h = B.g.h;
+        D.lv[i].k2 = B.k2l;
+        off += (int)B.g.n;
+    }
+    D.total = off;
+    return D;
+}
+
 void apply_launch(hh_ctx* c) {
     for (auto& L : c->lv) L.L = level_launch(L.g, c->base);
     for (size_t l = 0; l + 1 < c->lv.size(); ++l) {
@@ -200,24 +244,24 @@ void apply_launch(hh_ctx* c) {
 template <typename R>
 void enqueue_vcycle_t(hh_ctx* c, hipStream_t s, int nrhs, const c128* bin, c128* bout,
                       const RhsState* st, int gate) {
-    const int L = (int)c->lv.size();
     const int bc = c->cfg.bc;
+    const int T = c->tail_first;
     const MgParams P{c->cfg.beta1, c->cfg.beta2, c->cfg.omega};
     auto C = [](void* p) { return reinterpret_cast<cx<R>*>(p); };
     auto K = [](void* p) { return reinterpret_cast<const R*>(p); };
     LevelBuf& f = c->lv[0];
-    LevelBuf& cl = c->lv[L - 1];
-    // down: one pass per level writes the next level's right-hand side
+    // down: one fused pass per level writes the next level's right-hand side
     launch_mg_down<double, R>(s, bc, f.g, c->lv[1].g, f.zb_down, nrhs, bin, f.g.n, K(f.k2l), P,
                               C(c->lv[1].b), st, gate);
-    for (int l = 1; l < L - 1; ++l) {
+    for (int l = 1; l < T; ++l) {
         LevelBuf& a = c->lv[l];
         LevelBuf& n = c->lv[l + 1];
         launch_mg_down<R, R>(s, bc, a.g, n.g, a.zb_down, nrhs, C(a.b), a.g.n, K(a.k2l), P, C(n.b), st, gate);
     }
-    launch_coarse<R>(s, nrhs, (int)cl.g.n, c->n_unk, c->cidx, C(c->minv), C(cl.b), C(cl.e), st, gate);
-    // up: one pass per level writes the level's V-cycle result
-    for (int l = L - 2; l >= 1; --l) {
+    // the smallest levels and the coarsest solve in one workgroup per right-hand side
+    launch_mg_tail<R>(s, bc, tail_desc(c), nrhs, C(c->lv[T].b), C(c->lv[T].e), st, gate);
+    // up: one fused pass per level writes the level's V-cycle result
+    for (int l = T - 1; l >= 1; --l) {
         LevelBuf& a = c->lv[l];
         LevelBuf& n = c->lv[l + 1];
         launch_mg_up<R, R, R>(s, bc, a.g, n.g, a.zb_up, nrhs, C(a.b), a.g.n, K(a.k2l), P, C(n.e), C(a.e),
@@ -307,8 +351,6 @@ hh_status build_coarse(hh_ctx* c) {
                 }
             }
     const int n = (int)node_of.size();
-    if (n > COARSE_UNK_CAP)
-        return fail(c, HH_ERR_ARG, "coarsest grid has %d unknowns (> %d); use more levels", n, COARSE_UNK_CAP);
     typedef std::complex<double> C;
     std::vector<C> a((size_t)n * n, C(0, 0)), inv((size_t)n * n, C(0, 0));
     const double ih2 = 1.0 / (g.h * g.h);
@@ -365,26 +407,20 @@ hh_status build_coarse(hh_ctx* c) {
             }
         }
     }
-    c->n_unk = n;
-    (void)hipFree(c->cidx);
-    (void)hipFree(c->minv);
-    c->cidx = nullptr;
-    c->minv = nullptr;
-    CHK(dalloc(c, &c->cidx, sizeof(int) * n));
+    // cidx / minv were sized in hh_create for this level, so captured graphs keep valid pointers
+    if (n != c->n_unk) return fail(c, HH_ERR_STATE, "coarsest unknown count changed");
     HIPCHK(c, hipMemcpy(c->cidx, node_of.data(), sizeof(int) * n, hipMemcpyHostToDevice));
     if (c->mixed) {
         std::vector<c64> cm((size_t)n * n);
         for (int r = 0; r < n; ++r)
             for (int j = 0; j < n; ++j)
                 cm[(size_t)j * n + r] = c64{(float)inv[(size_t)r * n + j].real(), (float)inv[(size_t)r * n + j].imag()};
-        CHK(dalloc(c, (c64**)&c->minv, sizeof(c64) * cm.size()));
         HIPCHK(c, hipMemcpy(c->minv, cm.data(), sizeof(c64) * cm.size(), hipMemcpyHostToDevice));
     } else {
         std::vector<c128> cm((size_t)n * n);
         for (int r = 0; r < n; ++r)
             for (int j = 0; j < n; ++j)
                 cm[(size_t)j * n + r] = c128{inv[(size_t)r * n + j].real(), inv[(size_t)r * n + j].imag()};
-        CHK(dalloc(c, (c128**)&c->minv, sizeof(c128) * cm.size()));
         HIPCHK(c, hipMemcpy(c->minv, cm.data(), sizeof(c128) * cm.size(), hipMemcpyHostToDevice));
     }
     return HH_OK;
@@ -502,6 +538,18 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
     if ((s = dalloc(c, &c->part, sizeof(double) * (size_t)R * NSLOT * MAX_TERMS * NBLK_CAP)) != HH_OK)
         return bail(s);
     if ((s = dalloc(c, &c->bad, sizeof(int))) != HH_OK) return bail(s);
+    {
+        const Geo& gcst = shapes.back();
+        const long long nu = cfg->bc == HH_BC_SOMMERFELD
+                                 ? gcst.n
+                                 : (long long)(gcst.nx - 2) * (gcst.ny - 2) * (gcst.nz - 2);
+        if (nu > COARSE_UNK_CAP)
+            return bail(fail(c, HH_ERR_ARG, "coarsest grid has %lld unknowns (> %d); use more levels", nu,
+                             COARSE_UNK_CAP));
+        c->n_unk = (int)nu;
+        if ((s = dalloc(c, &c->cidx, sizeof(int) * nu)) != HH_OK) return bail(s);
+        if ((s = dalloc(c, (char**)&c->minv, c->csize * nu * nu)) != HH_OK) return bail(s);
+    }
     if (hipHostMalloc((void**)&c->st_host, sizeof(RhsState) * R, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->bad_host, sizeof(int), hipHostMallocDefault) != hipSuccess)
         return bail(fail(c, HH_ERR_OOM, "hipHostMalloc failed"));
@@ -526,6 +574,10 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
         return bail(fail(c, HH_ERR_HIP, "initialisation failed"));
     c->base.block = 256;
     c->base.zb = 0;
+    // the tail kernel may use up to 128 KB of LDS where the device allows it
+    c->tail_lds_cap = mg_tail_allow_lds(131072) ? 131072 : 65536;
+    (void)hipGetLastError();
+    choose_tail(c);
     apply_launch(c);
     *out = c;
     return HH_OK;
@@ -552,6 +604,7 @@ hh_status hh_level_shape(const hh_ctx* ctx, int l, int* nx, int* ny, int* nz, in
 hh_status hh_set_model(hh_ctx* c, const double* k) {
     if (!c || !k) return c ? fail(c, HH_ERR_ARG, "null k") : HH_ERR_ARG;
     c->model_set = false;
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // no pending solve still reads the old model
     LevelBuf& f = c->lv[0];
     HIPCHK(c, hipMemsetAsync(c->bad, 0, sizeof(int), c->stream));
     launch_model_check(c->stream, f.g.n, k, c->k2, c->kb, c->bad);
@@ -761,6 +814,7 @@ hh_status hh_get_option(const hh_ctx* c, const char* name, long long* value) {
     std::string n(name);
     if (n == "graph") *value = c->use_graph;
     else if (n == "zb_down") *value = c->lv[0].zb_down;
+    else if (n == "tail_first") *value = c->tail_first;
     else if (n == "zb_up") *value = c->lv[0].zb_up;
     else if (n == "check_every") *value = c->check_every;
     else if (n == "block") *value = c->L0.block;
