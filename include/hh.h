@@ -173,6 +173,7 @@ hh_status hh_get_option(const hh_ctx* ctx, const char* name, long long* value);
  * finest level (smoother + residual + restriction), 3 = fused up pass on the
  * finest level (prolongation + correction + post-smoother), 4 = p update,
  * 5 = s update with ||s||^2.
+ * The context's Krylov vectors are first filled with finite nonzero data.
  * Requires hh_set_model.  Overwrites internal scratch only. */
 hh_status hh_time_kernel(hh_ctx* ctx, int which, int nrhs, int reps, float* ms_avg_host);
 

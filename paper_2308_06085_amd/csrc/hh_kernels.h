@@ -67,16 +67,10 @@ bool mg_tail_allow_lds(size_t bytes);
 template <typename R>
 void launch_mg_tail(hipStream_t s, int bc, const TailDesc& D, int nrhs, const cx<R>* b_first,
                     cx<R>* e_first, const RhsState* st, int gate);
-template <typename R>
-void launch_coarse(hipStream_t s, int nrhs, int n_nodes, int n_unk, const int* cidx,
-                   const cx<R>* minv, const cx<R>* b, cx<R>* e, const RhsState* st, int gate);
-
 void launch_p_update(hipStream_t s, long long n, int nrhs, c128* p, const c128* r, const c128* v,
                      const RhsState* st, const Launch& L);
 void launch_s_update(hipStream_t s, long long n, int nrhs, c128* sv, const c128* r, const c128* v,
                      const RhsState* st, double* part, long long nblk_max, const Launch& L);
-void launch_x_half(hipStream_t s, long long n, int nrhs, c128* x, const c128* ph,
-                   const RhsState* st, const Launch& L);
 void launch_update_xr(hipStream_t s, long long n, int nrhs, c128* x, c128* r, const c128* ph,
                       const c128* sh, const c128* sv, const c128* t, const c128* rhat,
                       const RhsState* st, double* part, long long nblk_max, const Launch& L);
@@ -92,6 +86,8 @@ void launch_adjoint_rhs(hipStream_t s, const Geo& g, int bc, int nrhs, const c12
 void launch_grad_s(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* u, const c128* w,
                    const double* sl, double omega, double* grad);
 void launch_set_point(hipStream_t s, long long off, double val, c128* b);
-void launch_fill_status(hipStream_t s, int n, RhsState* st, int status, int maxit2);
+// status and iteration limit of the first n right-hand sides; tol2 < 0 also
+// replaces the squared stopping threshold (no reduction then meets it)
+void launch_fill_status(hipStream_t s, int n, RhsState* st, int status, int maxit2, double tol2 = 0.0);
 
 }  // namespace hh

@@ -73,6 +73,172 @@ __device__ __forceinline__ bool on_boundary(int i, int j, int z, int nx, int ny,
 }
 
 // ---------------------------------------------------------------------------
+// Reductions and the Bi-CGSTAB scalar recurrences.
+//
+// Every reduction-producing kernel writes one partial sum per workgroup.  The
+// partials of a slot are added in a fixed order (lane t takes partials t,
+// t + blockDim, ...; then a fixed butterfly) by the one-workgroup-per-RHS
+// kernel k_finalize, which then does the scalar update, so a solve is bitwise
+// repeatable.  (Finishing the sum in the last workgroup of the producing kernel
+// would need a device-scope fence per workgroup, which on a multi-XCD device
+// writes back the XCD's L2 and costs more than the extra launch.)
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ void block_fixed_sum(const double* __restrict__ part, long long nblk, long long nblk_max,
+                                double (&out)[NT]) {
+    __shared__ double sm[NT][16];
+    double v[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        double s = 0.0;
+        for (long long b = threadIdx.x; b < nblk; b += blockDim.x) s += part[t * nblk_max + b];
+        v[t] = s;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) v[t] += __shfl_xor(v[t], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) sm[t][wid] = v[t];
+    }
+    __syncthreads();
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += sm[t][w];
+        out[t] = s;
+    }
+}
+
+__device__ __forceinline__ bool finite2(c128 a) { return isfinite(a.re) && isfinite(a.im); }
+
+// Scalar update of one right-hand side from the slot sums (one thread).
+__device__ void fin_update(int mode, RhsState& S, const double* s, double tol) {
+    const double tiny = 1e-300;
+    const int status = S.status;
+    switch (mode) {
+        case FIN_INIT:
+            S.bnorm2 = s[3];
+            S.rnorm2 = s[0];
+            S.rhat_norm2 = s[0];
+            S.tol2 = tol * tol * s[3];
+            S.rho = mk(1.0, 0.0);
+            S.alpha = mk(1.0, 0.0);
+            S.omega = mk(1.0, 0.0);
+            S.beta = mk(0.0, 0.0);
+            S.iters2 = 0;
+            S.matvecs = 1;
+            S.restarts = 0;
+            S.true_rnorm2 = 0.0;
+            if (!isfinite(s[0]) || !isfinite(s[3])) S.status = ST_NUMERIC;
+            else if (s[3] == 0.0 || s[0] <= S.tol2) S.status = ST_CONV;
+            return;
+        case FIN_TRUE:
+            S.true_rnorm2 = s[0];
+            if (!isfinite(s[0])) {
+                S.status = ST_NUMERIC;
+            } else if (status == ST_CONV && S.bnorm2 > 0.0 && s[0] > S.tol2 && S.iters2 < S.maxit2 &&
+                       S.restarts < 5) {
+                // the recursive residual drifted from the true one: restart from x
+                S.status = ST_RUN;
+                S.rnorm2 = s[0];
+                S.rhat_norm2 = s[0];
+                S.rho = mk(1.0, 0.0);
+                S.alpha = mk(1.0, 0.0);
+                S.omega = mk(1.0, 0.0);
+                S.matvecs += 1;
+                S.restarts += 1;
+            }
+            return;
+        case FIN_RHO: {
+            if (status == ST_HALF) {
+                // the half step has added alpha p_hat to x: this right-hand side is done
+                S.status = ST_CONV;
+                S.iters2 += 1;
+                S.rnorm2 = S.snorm2;
+                return;
+            }
+            const double rn2 = s[0];
+            const c128 rho_new = mk(s[1], s[2]);
+            if (!isfinite(rn2) || !finite2(rho_new)) { S.status = ST_NUMERIC; return; }
+            S.rnorm2 = rn2;
+            if (rn2 <= S.tol2) { S.status = ST_CONV; return; }
+            if (abs2(S.omega) <= tiny * tiny) { S.status = ST_BREAK; return; }
+            if (S.iters2 >= S.maxit2) { S.status = ST_MAXIT; return; }
+            if (sqrt(abs2(rho_new)) <= tiny * sqrt(S.rhat_norm2) * sqrt(rn2)) { S.status = ST_BREAK; return; }
+            S.beta = cdiv(rho_new, S.rho) * cdiv(S.alpha, S.omega);
+            S.rho = rho_new;
+            return;
+        }
+        case FIN_ALPHA: {
+            const c128 rv = mk(s[0], s[1]);
+            S.matvecs += 1;
+            if (!finite2(rv)) { S.status = ST_NUMERIC; return; }
+            if (abs2(rv) == 0.0) { S.status = ST_BREAK; return; }
+            S.alpha = cdiv(S.rho, rv);
+            return;
+        }
+        case FIN_S:
+            if (!isfinite(s[0])) { S.status = ST_NUMERIC; return; }
+            S.snorm2 = s[0];
+            if (s[0] <= S.tol2) S.status = ST_HALF;
+            return;
+        case FIN_OMEGA: {
+            S.matvecs += 1;
+            const c128 ts = mk(s[0], s[1]);
+            const double tt = s[2];
+            if (!finite2(ts) || !isfinite(tt)) { S.status = ST_NUMERIC; return; }
+            if (tt == 0.0) { S.status = ST_BREAK; return; }
+            S.omega = mk(ts.re / tt, ts.im / tt);
+            S.iters2 += 2;
+            return;
+        }
+        default:
+            return;
+    }
+}
+
+__device__ __forceinline__ int fin_slot(int mode) {
+    switch (mode) {
+        case FIN_ALPHA: return SLOT_V;
+        case FIN_S: return SLOT_S;
+        case FIN_OMEGA: return SLOT_T;
+        default: return SLOT_R;
+    }
+}
+__device__ __forceinline__ int fin_terms(int mode) {
+    switch (mode) {
+        case FIN_ALPHA: return 2;
+        case FIN_S: return 1;
+        case FIN_OMEGA: return 3;
+        case FIN_RHO: return 3;
+        default: return 4;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_finalize(int mode, RhsState* st, const double* part,
+                                                   long long nblk, long long nblk_max, double tol) {
+    const int r = blockIdx.x;
+    RhsState& S = st[r];
+    const int status = S.status;
+    bool act;
+    switch (mode) {
+        case FIN_TRUE: act = status != ST_RUN && status != ST_IDLE && status != ST_HALF; break;
+        case FIN_RHO: act = status == ST_RUN || status == ST_HALF; break;
+        default: act = status == ST_RUN; break;
+    }
+    if (!act) return;
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};
+    if (status != ST_HALF)
+        block_fixed_sum<4>(part + part_index(r, fin_slot(mode), 0, nblk_max), nblk, nblk_max, sums);
+    if (threadIdx.x == 0) fin_update(mode, S, sums, tol);
+}
+
+// ---------------------------------------------------------------------------
 // Operator apply, complex128.  MODE selects the fused epilogue:
 //   OP_PLAIN : y = Op x
 //   OP_V     : y = A x, partials Re/Im sum conj(rhat) y          (slot V)
@@ -240,31 +406,9 @@ __global__ __launch_bounds__(512) void k_init(Geo g, int zb, const c128* __restr
     block_sum_store<4>(acc, part + part_index(r, SLOT_R, 0, nblk_max) + blk, nblk_max);
 }
 
-// Coarsest level: e = M_c^-1 b over the unknown nodes (dense inverse stored
-// column-major so that lanes read consecutive rows).  One workgroup per RHS.
-template <typename R>
-__global__ __launch_bounds__(256) void k_coarse(int n_nodes, int n_unk, const int* __restrict__ cidx,
-                                                const cx<R>* __restrict__ minv_cm,
-                                                const cx<R>* __restrict__ b, cx<R>* __restrict__ e,
-                                                const RhsState* st, int gate) {
-    extern __shared__ unsigned char smem_raw[];
-    cx<R>* sb = reinterpret_cast<cx<R>*>(smem_raw);
-    const int r = blockIdx.x;
-    if (!gate_ok(st, r, gate)) return;
-    const cx<R>* br = b + (long long)r * n_nodes;
-    cx<R>* er = e + (long long)r * n_nodes;
-    for (int t = threadIdx.x; t < n_unk; t += blockDim.x) sb[t] = br[cidx[t]];
-    for (int t = threadIdx.x; t < n_nodes; t += blockDim.x) er[t] = czero<R>();
-    __syncthreads();
-    for (int row = threadIdx.x; row < n_unk; row += blockDim.x) {
-        cx<R> s = czero<R>();
-        for (int c = 0; c < n_unk; ++c) s = s + minv_cm[(long long)c * n_unk + row] * sb[c];
-        er[cidx[row]] = s;
-    }
-}
-
 // ---------------------------------------------------------------------------
-// Krylov vector updates (complex128), flat over nodes: gridDim = (blocks, 1, nrhs).
+// Krylov vector updates (complex128), grid-stride over nodes with exactly the
+// fine-grid kernels' workgroup count per right-hand side: gridDim = (nblk, 1, nrhs).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(512) void k_p_update(long long n, c128* __restrict__ p,
                                                   const c128* __restrict__ rr,
@@ -279,6 +423,7 @@ __global__ __launch_bounds__(512) void k_p_update(long long n, c128* __restrict_
     }
 }
 
+// s = r - alpha v, partial ||s||^2, then (last workgroup) the half-step test.
 __global__ __launch_bounds__(512) void k_s_update(long long n, c128* __restrict__ s,
                                                   const c128* __restrict__ rr,
                                                   const c128* __restrict__ v, const RhsState* st,
@@ -297,19 +442,9 @@ __global__ __launch_bounds__(512) void k_s_update(long long n, c128* __restrict_
     block_sum_store<1>(acc, part + part_index(r, SLOT_S, 0, nblk_max) + blockIdx.x, nblk_max);
 }
 
-__global__ __launch_bounds__(512) void k_x_half(long long n, c128* __restrict__ x,
-                                                const c128* __restrict__ ph, const RhsState* st) {
-    const int r = blockIdx.z;
-    if (st[r].status != ST_HALF) return;
-    const c128 al = st[r].alpha;
-    const long long off = (long long)r * n;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        x[off + i] = x[off + i] + al * ph[off + i];
-    }
-}
-
-// x += alpha p_hat + omega s_hat; r = s - omega t; partials ||r||^2, r_hat^H r.
+// Iterating right-hand sides: x += alpha p_hat + omega s_hat; r = s - omega t;
+// partials ||r||^2, r_hat^H r.  Right-hand sides that stopped at the half step:
+// x += alpha p_hat (the next FIN_RHO marks them converged).
 __global__ __launch_bounds__(512) void k_update_xr(long long n, c128* __restrict__ x,
                                                    c128* __restrict__ rr,
                                                    const c128* __restrict__ ph,
@@ -319,9 +454,16 @@ __global__ __launch_bounds__(512) void k_update_xr(long long n, c128* __restrict
                                                    const c128* __restrict__ rhat, const RhsState* st,
                                                    double* __restrict__ part, long long nblk_max) {
     const int r = blockIdx.z;
-    if (st[r].status != ST_RUN) return;
+    const int status = st[r].status;
+    if (status != ST_RUN && status != ST_HALF) return;
     const c128 al = st[r].alpha, om = st[r].omega;
     const long long off = (long long)r * n;
+    if (status == ST_HALF) {
+        for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+             i += (long long)gridDim.x * blockDim.x)
+            x[off + i] = x[off + i] + al * ph[off + i];
+        return;
+    }
     double acc[3] = {0.0, 0.0, 0.0};
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
@@ -334,149 +476,6 @@ __global__ __launch_bounds__(512) void k_update_xr(long long n, c128* __restrict
         acc[2] += d.im;
     }
     block_sum_store<3>(acc, part + part_index(r, SLOT_R, 0, nblk_max) + blockIdx.x, nblk_max);
-}
-
-// ---------------------------------------------------------------------------
-// Finalisation of the reductions and the Bi-CGSTAB scalar recurrences, one
-// workgroup per right-hand side; partial sums are added in a fixed order so a
-// solve is bitwise repeatable.
-// ---------------------------------------------------------------------------
-template <int NT>
-__device__ void fixed_sum(const double* __restrict__ part, long long nblk, long long nblk_max,
-                          double (&out)[NT]) {
-    __shared__ double sm[NT][1024];
-    double v[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        double s = 0.0;
-        for (long long b = threadIdx.x; b < nblk; b += blockDim.x) s += part[t * nblk_max + b];
-        v[t] = s;
-        sm[t][threadIdx.x] = s;
-    }
-    __syncthreads();
-    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) sm[t][threadIdx.x] += sm[t][threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int t = 0; t < NT; ++t) out[t] = sm[t][0];
-}
-
-__device__ __forceinline__ bool finite2(c128 a) { return isfinite(a.re) && isfinite(a.im); }
-
-__global__ __launch_bounds__(1024) void k_finalize(int mode, RhsState* st, const double* part,
-                                                   long long nblk, long long nblk_max, double tol) {
-    const int r = blockIdx.x;
-    RhsState& S = st[r];
-    const int status = S.status;
-    // which right-hand sides take part in this step
-    bool act;
-    switch (mode) {
-        case FIN_INIT: act = status == ST_RUN; break;
-        case FIN_TRUE: act = status != ST_RUN && status != ST_IDLE && status != ST_HALF; break;
-        case FIN_OMEGA: act = status == ST_RUN || status == ST_HALF; break;
-        default: act = status == ST_RUN; break;
-    }
-    if (!act) return;
-    const double tiny = 1e-300;
-    if (mode == FIN_INIT || mode == FIN_TRUE) {
-        double s[4];
-        fixed_sum<4>(part + part_index(r, SLOT_R, 0, nblk_max), nblk, nblk_max, s);
-        if (threadIdx.x != 0) return;
-        if (mode == FIN_INIT) {
-            S.bnorm2 = s[3];
-            S.rnorm2 = s[0];
-            S.rhat_norm2 = s[0];
-            S.tol2 = tol * tol * s[3];
-            S.rho = mk(1.0, 0.0);
-            S.alpha = mk(1.0, 0.0);
-            S.omega = mk(1.0, 0.0);
-            S.beta = mk(0.0, 0.0);
-            S.iters2 = 0;
-            S.matvecs = 1;
-            S.restarts = 0;
-            S.true_rnorm2 = 0.0;
-            if (!isfinite(s[0]) || !isfinite(s[3])) S.status = ST_NUMERIC;
-            else if (s[3] == 0.0 || s[0] <= S.tol2) S.status = ST_CONV;
-        } else {
-            S.true_rnorm2 = s[0];
-            if (!isfinite(s[0])) {
-                S.status = ST_NUMERIC;
-            } else if (status == ST_CONV && S.bnorm2 > 0.0 && s[0] > S.tol2 && S.iters2 < S.maxit2 &&
-                       S.restarts < 5) {
-                // the recursive residual drifted from the true one: restart from x
-                S.status = ST_RUN;
-                S.rnorm2 = s[0];
-                S.rhat_norm2 = s[0];
-                S.rho = mk(1.0, 0.0);
-                S.alpha = mk(1.0, 0.0);
-                S.omega = mk(1.0, 0.0);
-                S.matvecs += 1;
-                S.restarts += 1;
-            }
-        }
-        return;
-    }
-    if (mode == FIN_RHO) {
-        double s[3];
-        fixed_sum<3>(part + part_index(r, SLOT_R, 0, nblk_max), nblk, nblk_max, s);
-        if (threadIdx.x != 0) return;
-        const double rn2 = s[0];
-        const c128 rho_new = mk(s[1], s[2]);
-        if (!isfinite(rn2) || !finite2(rho_new)) { S.status = ST_NUMERIC; return; }
-        S.rnorm2 = rn2;
-        if (rn2 <= S.tol2) { S.status = ST_CONV; return; }
-        if (abs2(S.omega) <= tiny * tiny) { S.status = ST_BREAK; return; }
-        if (S.iters2 >= S.maxit2) { S.status = ST_MAXIT; return; }
-        if (sqrt(abs2(rho_new)) <= tiny * sqrt(S.rhat_norm2) * sqrt(rn2)) { S.status = ST_BREAK; return; }
-        S.beta = cdiv(rho_new, S.rho) * cdiv(S.alpha, S.omega);
-        S.rho = rho_new;
-        return;
-    }
-    if (mode == FIN_ALPHA) {
-        double s[2];
-        fixed_sum<2>(part + part_index(r, SLOT_V, 0, nblk_max), nblk, nblk_max, s);
-        if (threadIdx.x != 0) return;
-        const c128 rv = mk(s[0], s[1]);
-        S.matvecs += 1;
-        if (!finite2(rv)) { S.status = ST_NUMERIC; return; }
-        if (abs2(rv) == 0.0) { S.status = ST_BREAK; return; }
-        S.alpha = cdiv(S.rho, rv);
-        return;
-    }
-    if (mode == FIN_S) {
-        double s[1];
-        fixed_sum<1>(part + part_index(r, SLOT_S, 0, nblk_max), nblk, nblk_max, s);
-        if (threadIdx.x != 0) return;
-        if (!isfinite(s[0])) { S.status = ST_NUMERIC; return; }
-        S.snorm2 = s[0];
-        if (s[0] <= S.tol2) S.status = ST_HALF;
-        return;
-    }
-    if (mode == FIN_OMEGA) {
-        if (status == ST_HALF) {
-            if (threadIdx.x == 0) {
-                S.status = ST_CONV;
-                S.iters2 += 1;
-                S.rnorm2 = S.snorm2;
-            }
-            return;
-        }
-        double s[3];
-        fixed_sum<3>(part + part_index(r, SLOT_T, 0, nblk_max), nblk, nblk_max, s);
-        if (threadIdx.x != 0) return;
-        S.matvecs += 1;
-        const c128 ts = mk(s[0], s[1]);
-        const double tt = s[2];
-        if (!finite2(ts) || !isfinite(tt)) { S.status = ST_NUMERIC; return; }
-        if (tt == 0.0) { S.status = ST_BREAK; return; }
-        S.omega = mk(ts.re / tt, ts.im / tt);
-        S.iters2 += 2;
-        return;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -581,11 +580,12 @@ __global__ void k_set_point(long long off, double val, c128* __restrict__ b) {
     if (threadIdx.x == 0 && blockIdx.x == 0) b[off] = mk(val, 0.0);
 }
 
-__global__ void k_fill_status(int n, RhsState* st, int status, int maxit2) {
+__global__ void k_fill_status(int n, RhsState* st, int status, int maxit2, double tol2) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < n) {
         st[r].status = status;
         st[r].maxit2 = maxit2;
+        if (tol2 < 0.0) st[r].tol2 = tol2;
     }
 }
 
@@ -639,18 +639,6 @@ void launch_init(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs,
                            p, v, k2, kb, use_x0, part, nblk_max, st, gate);
 }
 
-template <typename R>
-void launch_coarse(hipStream_t s, int nrhs, int n_nodes, int n_unk, const int* cidx,
-                   const cx<R>* minv, const cx<R>* b, cx<R>* e, const RhsState* st, int gate) {
-    hipLaunchKernelGGL((k_coarse<R>), dim3(nrhs), dim3(256), n_unk * sizeof(cx<R>), s, n_nodes, n_unk,
-                       cidx, minv, b, e, st, gate);
-}
-
-template void launch_coarse<double>(hipStream_t, int, int, int, const int*, const c128*,
-                                    const c128*, c128*, const RhsState*, int);
-template void launch_coarse<float>(hipStream_t, int, int, int, const int*, const c64*, const c64*,
-                                   c64*, const RhsState*, int);
-
 void launch_p_update(hipStream_t s, long long n, int nrhs, c128* p, const c128* r, const c128* v,
                      const RhsState* st, const Launch& L) {
     hipLaunchKernelGGL(k_p_update, dim3(L.flat_cap, 1, nrhs), dim3(L.block),
@@ -658,21 +646,15 @@ void launch_p_update(hipStream_t s, long long n, int nrhs, c128* p, const c128* 
 }
 void launch_s_update(hipStream_t s, long long n, int nrhs, c128* sv, const c128* r, const c128* v,
                      const RhsState* st, double* part, long long nblk_max, const Launch& L) {
-    hipLaunchKernelGGL(k_s_update, dim3(L.flat_cap, 1, nrhs), dim3(L.block),
-                       0, s, n, sv, r, v, st, part, nblk_max);
-}
-void launch_x_half(hipStream_t s, long long n, int nrhs, c128* x, const c128* ph,
-                   const RhsState* st, const Launch& L) {
-    hipLaunchKernelGGL(k_x_half, dim3(L.flat_cap, 1, nrhs), dim3(L.block), 0,
-                       s, n, x, ph, st);
+    hipLaunchKernelGGL(k_s_update, dim3(L.flat_cap, 1, nrhs), dim3(L.block), 0, s, n, sv, r, v, st, part,
+                       nblk_max);
 }
 void launch_update_xr(hipStream_t s, long long n, int nrhs, c128* x, c128* r, const c128* ph,
                       const c128* sh, const c128* sv, const c128* t, const c128* rhat,
                       const RhsState* st, double* part, long long nblk_max, const Launch& L) {
-    hipLaunchKernelGGL(k_update_xr, dim3(L.flat_cap, 1, nrhs), dim3(L.block),
-                       0, s, n, x, r, ph, sh, sv, t, rhat, st, part, nblk_max);
+    hipLaunchKernelGGL(k_update_xr, dim3(L.flat_cap, 1, nrhs), dim3(L.block), 0, s, n, x, r, ph, sh, sv, t,
+                       rhat, st, part, nblk_max);
 }
-
 void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const double* part,
                      long long nblk, long long nblk_max, double tol) {
     hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(1024), 0, s, mode, st, part, nblk, nblk_max, tol);
@@ -707,8 +689,8 @@ void launch_grad_s(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* u,
 void launch_set_point(hipStream_t s, long long off, double val, c128* b) {
     hipLaunchKernelGGL(k_set_point, dim3(1), dim3(64), 0, s, off, val, b);
 }
-void launch_fill_status(hipStream_t s, int n, RhsState* st, int status, int maxit2) {
-    hipLaunchKernelGGL(k_fill_status, dim3(1), dim3(64), 0, s, n, st, status, maxit2);
+void launch_fill_status(hipStream_t s, int n, RhsState* st, int status, int maxit2, double tol2) {
+    hipLaunchKernelGGL(k_fill_status, dim3(1), dim3(64), 0, s, n, st, status, maxit2, tol2);
 }
 
 }  // namespace hh

@@ -173,10 +173,23 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, const cx<R>* __res
         const cx<R>* minv = reinterpret_cast<const cx<R>*>(D.minv);
         for (int i = t; i < L.n; i += nt) u[i] = czero<R>();
         __syncthreads();
-        for (int row = t; row < D.n_unk; row += nt) {
+        // G lanes per row (a power of two <= 64, so a group stays inside one
+        // wavefront): lane j of a group sums the columns c = j, j + G, ..., then
+        // the group adds its partial sums with a fixed butterfly.
+        int G = 1;
+        while (G < 64 && 2 * G * D.n_unk <= nt) G *= 2;
+        const int sub = t & (G - 1);
+        for (int row0 = 0; row0 < D.n_unk; row0 += nt / G) {
+            const int row = row0 + t / G;
             cx<R> s = czero<R>();
-            for (int c = 0; c < D.n_unk; ++c) s = s + minv[(long long)c * D.n_unk + row] * b[D.cidx[c]];
-            u[D.cidx[row]] = s;
+            if (row < D.n_unk)
+                for (int c = sub; c < D.n_unk; c += G)
+                    s = s + minv[(long long)c * D.n_unk + row] * b[D.cidx[c]];
+            for (int off = G >> 1; off > 0; off >>= 1) {
+                s.re += __shfl_xor(s.re, off, 64);
+                s.im += __shfl_xor(s.im, off, 64);
+            }
+            if (row < D.n_unk && sub == 0) u[D.cidx[row]] = s;
         }
         __syncthreads();
     }

@@ -277,7 +277,9 @@ void enqueue_vcycle(hh_ctx* c, hipStream_t s, int nrhs, const c128* bin, c128* b
     else enqueue_vcycle_t<double>(c, s, nrhs, bin, bout, st, gate);
 }
 
-// One Bi-CGSTAB step for all right-hand sides still iterating (device-side scalars).
+// One Bi-CGSTAB step for all right-hand sides still iterating (device-side
+// scalars).  A right-hand side that meets the tolerance at the half step gets
+// x += alpha p_hat in the x / r update and is marked converged by the next FIN_RHO.
 void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs) {
     const Geo& g = c->lv[0].g;
     const long long n = g.n;
@@ -293,7 +295,6 @@ void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs) {
     launch_finalize(s, FIN_ALPHA, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
     launch_s_update(s, n, nrhs, c->s, c->r, c->v, c->st, c->part, NBLK_CAP, F);
     launch_finalize(s, FIN_S, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
-    launch_x_half(s, n, nrhs, c->xk, c->ph, c->st, F);
     enqueue_vcycle(c, s, nrhs, c->s, c->sh, c->st, ST_RUN);
     launch_apply(s, bc, OP_T, g, c->L0, nrhs, c->sh, c->t, c->k2, c->kb, 1.0, 0.0, c->s, c->part,
                  NBLK_CAP, c->st, ST_RUN);
@@ -711,8 +712,11 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
     if (c->use_graph) CHK(get_graph(c, nrhs, &exec));
     int guard = 0;
     while (true) {
-        bool any_run = false;
-        for (int r = 0; r < nrhs; ++r) any_run |= c->st_host[r].status == ST_RUN;
+        bool any_run = false, any_half = false;
+        for (int r = 0; r < nrhs; ++r) {
+            any_run |= c->st_host[r].status == ST_RUN;
+            any_half |= c->st_host[r].status == ST_HALF;
+        }
         if (any_run) {
             for (int k = 0; k < c->check_every; ++k) {
                 if (exec) HIPCHK(c, hipGraphLaunch(exec, c->stream));
@@ -725,6 +729,7 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
         }
         // every right-hand side stopped: recompute the true residual b - A x;
         // a converged one whose true residual misses rtol restarts from x
+        if (any_half) launch_finalize(c->stream, FIN_RHO, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, rtol);
         launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->k2,
                     c->kb, 1, c->part, NBLK_CAP, c->st, GATE_FINISHED);
         launch_finalize(c->stream, FIN_TRUE, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, rtol);
@@ -876,8 +881,14 @@ hh_status hh_time_kernel(hh_ctx* c, int which, int nrhs, int reps, float* ms_avg
     CHK(check_ready(c, nrhs));
     if (reps < 1 || !ms_avg) return fail(c, HH_ERR_ARG, "reps >= 1 and ms_avg required");
     if (which < 0 || which > 5) return fail(c, HH_ERR_ARG, "unknown kernel id %d", which);
-    // the gated kernels act on right-hand sides marked as iterating
-    launch_fill_status(c->stream, nrhs, c->st, ST_RUN, 2);
+    const Geo& g = c->lv[0].g;
+    // Inputs: finite, nonzero scratch data (every double 0x3F3F...: about 4.8e-4),
+    // right-hand sides marked as iterating with an unreachable tolerance, so
+    // the fused scalar updates never stop an iteration between repetitions.
+    const size_t vb = sizeof(c128) * (size_t)g.n * nrhs;
+    for (c128* q : {c->xk, c->r, c->rhat, c->p, c->v, c->s, c->t, c->ph, c->sh})
+        HIPCHK(c, hipMemsetAsync(q, 0x3f, vb, c->stream));
+    launch_fill_status(c->stream, nrhs, c->st, ST_RUN, 1 << 30, -1.0);
     auto one = [&]() {
         if (c->mixed) launch_one_fine<float>(c, which, nrhs);
         else launch_one_fine<double>(c, which, nrhs);
