@@ -1,0 +1,201 @@
+"""GPU parity at the full workload sizes, in the launch configuration bench.py uses.
+
+* wedge 129 x 129 x 257 (4,276,737 unknowns, Sommerfeld, 10 Hz): operator and
+  one V-cycle against the oracle element by element on the whole grid; FP64 and
+  mixed solves checked by the true residual under the oracle's operator; the
+  mixed solution against a tight FP64 solve.
+* the same wedge with 16 seeded top-face sources, one batched mixed solve:
+  every right-hand side's true residual under the oracle's operator.
+* 513^3 cube, k = 160, 8 levels: the operator on z-slabs against the oracle,
+  and the solve's true residual accumulated slab by slab with the oracle's operator.
+* adjoint workload, 65^3 smoothed-noise model: the autograd gradient against
+  the oracle's adjoint gradient and central finite differences on 20 directions.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle.discretization import Level
+from oracle.multigrid import build_hierarchy, vcycle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.fixture(scope="module")
+def wedge():
+    return W.wedge(10.0)
+
+
+def _solver(wl, **kw):
+    from paper_2308_06085_amd import Solver
+
+    return Solver(wl.shape, wl.h, bc=wl.bc, n_levels=wl.n_levels, **kw)
+
+
+def test_wedge_operator_and_vcycle_full_grid(wedge):
+    wl = wedge
+    lvl = Level(wl.shape, wl.h, wl.k, wl.bc)
+    x = W.random_complex(wl.shape, seed=21)
+    for prec, tol in (("fp64", 1e-12), ("mixed", 1e-5)):
+        s = _solver(wl, prec=prec)
+        s.set_model(dev(wl.k))
+        if prec == "fp64":
+            y = host(s.apply_operator(dev(x)))[0]
+            assert relerr(y, O.apply_A(x, lvl)) <= 1e-13
+        z = host(s.apply_vcycle(dev(x)))[0]
+        ref = vcycle(x, build_hierarchy(wl.k, wl.h, wl.bc))
+        assert relerr(z, ref) <= tol, prec
+        s.close()
+
+
+def _true_relres(wl, x, nodes):
+    lvl = Level(wl.shape, wl.h, wl.k, wl.bc)
+    b = O.point_source_rhs(wl.shape, wl.h, nodes)
+    return [float(np.linalg.norm(b[r] - O.apply_A(x[r], lvl)) / np.linalg.norm(b[r]))
+            for r in range(len(nodes))]
+
+
+def test_wedge_solves_fp64_and_mixed(wedge):
+    wl = wedge
+    sols = {}
+    for prec in ("fp64", "mixed"):
+        s = _solver(wl, prec=prec)
+        s.set_model(dev(wl.k))
+        s.set_point_sources(wl.sources)
+        x, st = s.solve(rtol=1e-6)
+        x = host(x)
+        rel = _true_relres(wl, x, wl.sources)[0]
+        assert st[0].status == "HH_OK" and rel <= 1e-6, (prec, rel, st[0])
+        assert abs(st[0].relres_true - rel) <= 1e-9
+        sols[prec] = x[0]
+        if prec == "fp64":
+            xt, stt = s.solve(rtol=1e-10)
+            sols["tight"] = host(xt)[0]
+        s.close()
+    err = {p: np.linalg.norm(sols[p] - sols["tight"]) / np.linalg.norm(sols["tight"])
+           for p in ("fp64", "mixed")}
+    # both stop at the same residual; their errors are of the same size
+    assert err["mixed"] <= 10 * err["fp64"] + 1e-7, err
+
+
+def test_wedge_batched_sixteen_sources(wedge):
+    wl = wedge
+    nodes = W.batched_wedge_sources(16, seed=4)
+    s = _solver(wl, prec="mixed", nrhs_max=16)
+    s.set_model(dev(wl.k))
+    s.set_point_sources(nodes)
+    x, st = s.solve(rtol=1e-6)
+    x = host(x)
+    rel = _true_relres(wl, x, nodes)
+    assert all(t.status == "HH_OK" for t in st), [t.status for t in st]
+    assert max(rel) <= 1e-6, rel
+    # a batched right-hand side equals the same source solved alone
+    s1 = _solver(wl, prec="mixed", nrhs_max=1)
+    s1.set_model(dev(wl.k))
+    s1.set_point_sources([nodes[5]])
+    x1, st1 = s1.solve(rtol=1e-6)
+    assert np.array_equal(host(x1)[0], x[5]) and st1[0].iterations == st[5].iterations
+
+
+def _slab_apply(x, k, h, z0, z1):
+    """Oracle A x on planes z0..z1-1, computed on the slab z0-1..z1 (clipped):
+    only the slab's interior planes are exact, and those are the ones returned."""
+    nz = x.shape[0]
+    a, b = max(z0 - 1, 0), min(z1 + 1, nz)
+    lvl = Level(x[a:b].shape, h, k[a:b], "sommerfeld")
+    y = O.apply_A(x[a:b], lvl)
+    return y[z0 - a: z0 - a + (z1 - z0)]
+
+
+@pytest.mark.timeout(600)
+def test_cube513_operator_slabs_and_solve_residual():
+    wl = W.big_cube()
+    assert wl.shape == (513, 513, 513)
+    s = _solver(wl, prec="mixed")
+    assert len(s.level_shapes()) == 8 and s.level_shapes()[-1] == (5, 5, 5)
+    s.set_model(dev(wl.k))
+    # operator on three slabs (bottom boundary, middle, top boundary), FP64 apply
+    rng = np.random.default_rng(31)
+    for z0, z1 in ((0, 3), (255, 258), (510, 513)):
+        xs = np.zeros(wl.shape, dtype=np.complex128)
+        a, b = max(z0 - 1, 0), min(z1 + 1, 513)
+        xs[a:b] = rng.standard_normal((b - a, 513, 513)) + 1j * rng.standard_normal((b - a, 513, 513))
+        y = s.apply_operator(dev(xs))
+        yz = host(y[0, z0:z1])
+        ref = _slab_apply(xs, wl.k, wl.h, z0, z1)
+        assert relerr(yz, ref) <= 1e-13, (z0, z1)
+        del y
+    torch.cuda.empty_cache()
+    s.set_point_sources(wl.sources)
+    x, st = s.solve(rtol=1e-6, maxit=2000)
+    assert st[0].status == "HH_OK", st[0]
+    xh = host(x)[0]
+    del x
+    torch.cuda.empty_cache()
+    b = np.zeros(wl.shape, dtype=np.complex128)
+    iz, iy, ix = wl.sources[0]
+    b[iz, iy, ix] = 1.0 / wl.h**3
+    num = 0.0
+    for z0 in range(0, 513, 64):
+        z1 = min(z0 + 64, 513)
+        num += float(np.sum(np.abs(b[z0:z1] - _slab_apply(xh, wl.k, wl.h, z0, z1)) ** 2))
+    rel = np.sqrt(num) / np.linalg.norm(b)
+    assert rel <= 1e-6, rel
+    assert abs(rel - st[0].relres_true) <= 1e-8
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_workload_gradient():
+    """65^3 smoothed-noise model, omega with max kh = 0.5, centre-top source, 8 x 8
+    receivers: dL/ds by one adjoint solve through torch.autograd vs the oracle's
+    adjoint gradient (cosine >= 0.9999) and central differences on 20 directions
+    (cosine >= 0.999), all solves at rtol 1e-10 in complex128."""
+    from oracle.adjoint import misfit_and_gradient, sample, solve_forward
+    from paper_2308_06085_amd import HelmholtzSolve, Solver
+
+    aw = W.adjoint_workload(65, ndir=20)
+    shape = aw.s_true.shape
+    b = O.point_source_rhs(shape, aw.h, [aw.source])
+    d = sample(solve_forward(aw.s_true, aw.omega, aw.h, b[0]).x, aw.receivers)
+    s = Solver(shape, aw.h, bc="sommerfeld")
+    rec = torch.tensor(aw.receivers, device="cuda")
+    d_t = dev(d)
+    b_t = dev(b)
+
+    def loss_fn(s_t):
+        u = HelmholtzSolve.apply(s_t, b_t, aw.omega, s, 1e-10)
+        ur = u[0][rec[:, 0], rec[:, 1], rec[:, 2]]
+        return 0.5 * torch.sum(torch.abs(ur - d_t) ** 2)
+
+    s_t = dev(aw.s_model).requires_grad_(True)
+    loss = loss_fn(s_t)
+    loss.backward()
+    g_gpu = host(s_t.grad)
+    _, g_ref, _ = misfit_and_gradient(aw.s_model, aw.omega, aw.h, aw.source, aw.receivers, d)
+    cos = float(np.sum(g_gpu * g_ref) / (np.linalg.norm(g_gpu) * np.linalg.norm(g_ref)))
+    assert cos >= 0.9999, cos
+    fd, ad = [], []
+    with torch.no_grad():
+        for v in aw.directions:
+            lp = float(loss_fn(dev(aw.s_model + aw.eps * v)))
+            lm = float(loss_fn(dev(aw.s_model - aw.eps * v)))
+            fd.append((lp - lm) / (2 * aw.eps))
+            ad.append(float(np.sum(g_gpu * v)))
+    fd, ad = np.array(fd), np.array(ad)
+    cos_fd = fd @ ad / (np.linalg.norm(fd) * np.linalg.norm(ad))
+    assert cos_fd >= 0.999, (cos_fd, fd, ad)
