@@ -158,8 +158,10 @@ hh_status hh_grad_slowness2(hh_ctx* ctx, const void* u, const void* w, const dou
 
 /* Options: "graph" (1 = replay each Bi-CGSTAB step as a captured hipGraph,
  * default 1), "check_every" (steps between host convergence checks, default 4),
- * "block" (threads per workgroup of the stencil kernels: 64, 128, 256, 512),
- * "zb" (z-planes per workgroup of the stencil kernels, 0 = automatic).
+ * "block" (threads per workgroup of the stencil kernels: 64, 128, 256, 512;
+ * default 512), "zb" (z-planes per workgroup of the stencil kernels, default 2,
+ * 0 = automatic), "zb_down" / "zb_up" (z-planes per workgroup of the finest
+ * level's multigrid down / up pass, 0 = automatic).
  * hh_get_option also reports "n_levels", "coarse_unknowns", "zb_down", "zb_up". */
 hh_status hh_set_option(hh_ctx* ctx, const char* name, long long value);
 hh_status hh_get_option(const hh_ctx* ctx, const char* name, long long* value);

@@ -73,6 +73,7 @@ struct hh_ctx {
     int check_every = 4;
     std::map<int, hipGraphExec_t> graphs;
     int tail_first = 0;   // first level run by the single-workgroup tail kernel
+    int zb_down0 = 0, zb_up0 = 0;  // finest-level z-planes of the multigrid passes (0 = automatic)
     size_t tail_lds_cap = 65536;
     float last_ms = 0.f;
     std::string err;
@@ -172,12 +173,14 @@ void invalidate_graphs(hh_ctx* c) {
 
 // z-planes per workgroup of a multigrid pass: long z-marches amortise the two
 // halo planes each workgroup loads, but the grid must still fill the chip.
-// Take the longest of 16, 8, 4 planes that leaves >= 1024 workgroups, else the
-// longest of 4, 2, 1 that leaves >= 256.
+// Take the longest of 16, 8, 4 planes that leaves >= `want` workgroups, else
+// the longest of 4, 2 that leaves >= 256, else 1.  (Measured on the wedge and
+// the 513^3 cube: the down pass wants >= 1024 workgroups, the up pass, with
+// 512 lanes per workgroup, >= 512.)
 template <typename F>
-int pick_zb(F blocks) {
+int pick_zb(F blocks, int want) {
     for (int zb : {16, 8, 4})
-        if (blocks(zb) >= 1024) return zb;
+        if (blocks(zb) >= want) return zb;
     for (int zb : {4, 2})
         if (blocks(zb) >= 256) return zb;
     return 1;
@@ -230,9 +233,11 @@ void apply_launch(hh_ctx* c) {
     for (size_t l = 0; l + 1 < c->lv.size(); ++l) {
         const Geo gc = c->lv[l + 1].g;
         const Geo g = c->lv[l].g;
-        c->lv[l].zb_down = pick_zb([&](int z) { return mg_down_blocks(gc, z); });
-        c->lv[l].zb_up = pick_zb([&](int z) { return mg_up_blocks(g, z); });
+        c->lv[l].zb_down = pick_zb([&](int z) { return mg_down_blocks(gc, z); }, 1024);
+        c->lv[l].zb_up = pick_zb([&](int z) { return mg_up_blocks(g, z); }, 512);
     }
+    if (c->zb_down0 > 0) c->lv[0].zb_down = std::min(c->zb_down0, c->lv[1].g.nz);
+    if (c->zb_up0 > 0) c->lv[0].zb_up = std::min(c->zb_up0, c->lv[0].g.nz);
     c->L0 = c->lv[0].L;
     c->nblk0 = nblk_of(c->lv[0].g, c->L0);
     invalidate_graphs(c);
@@ -573,8 +578,8 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
     launch_fill_status(c->stream, R, c->st, ST_IDLE, 0);
     if (ze != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess)
         return bail(fail(c, HH_ERR_HIP, "initialisation failed"));
-    c->base.block = 256;
-    c->base.zb = 0;
+    c->base.block = 512;
+    c->base.zb = 2;
     // the tail kernel may use up to 128 KB of LDS where the device allows it
     c->tail_lds_cap = mg_tail_allow_lds(131072) ? 131072 : 65536;
     (void)hipGetLastError();
@@ -807,6 +812,10 @@ hh_status hh_set_option(hh_ctx* c, const char* name, long long value) {
     } else if (n == "zb") {
         if (value < 0 || value > 1024) return fail(c, HH_ERR_ARG, "zb must be in 0..1024");
         c->base.zb = (int)value;
+        apply_launch(c);
+    } else if (n == "zb_down" || n == "zb_up") {
+        if (value < 0 || value > 1024) return fail(c, HH_ERR_ARG, "%s must be in 0..1024", name);
+        (n == "zb_down" ? c->zb_down0 : c->zb_up0) = (int)value;
         apply_launch(c);
     } else {
         return fail(c, HH_ERR_ARG, "unknown option '%s'", name);
