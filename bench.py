@@ -40,26 +40,41 @@ METRIC = "DoF-iterations/s of CSLP-Bi-CGSTAB, mixed vs FP64 at 1e-6 rel residual
 # Kernel ids of hh_time_kernel, launches per Bi-CGSTAB step and algorithmic
 # bytes per fine-grid node per right-hand side for (fp64, mixed) precision:
 # every array the kernel must read or write once (complex128 16 B, complex64
-# 8 B, real k^2 8 B, Jacobi factor W complex in the multigrid precision).
+# 8 B, real k^2 8 B for the operator, k^2 in the multigrid precision for the
+# multigrid passes, coarse-grid arrays 1/8 of a fine one).
 KERNELS = {
     0: ("apply_A+dots", 2, (16 + 8 + 16 + 16, 16 + 8 + 16 + 16)),
     1: ("update_xr+dots", 1, (6 * 16 + 2 * 16, 6 * 16 + 2 * 16)),
-    2: ("mg_down_L0", 2, (16 + 16 + 16 / 8, 16 + 8 + 8 / 8)),
-    3: ("mg_up_L0", 2, (16 + 16 + 16 / 8 + 16, 16 + 8 + 8 / 8 + 16)),
+    2: ("mg_down_L0", 2, (16 + 8 + 16 / 8, 16 + 4 + 8 / 8)),
+    3: ("mg_up_L0", 2, (16 + 8 + 16 / 8 + 16, 16 + 4 + 8 / 8 + 16)),
     4: ("p_update", 1, (4 * 16, 4 * 16)),
     5: ("s_update+dot", 1, (3 * 16, 3 * 16)),
 }
 
-# HBM traffic per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
-# (profiles/*_pmc.md), keyed by kernel name and workload; valid only for the
-# kernel source it was measured on (sha256 of hh_kernels.hip).
-TRAFFIC = {}
+# HBM traffic per launch, FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scale factors
+# from a 1 GiB reference copy) from two rocprofv3 --pmc runs of
+# `bench.py --steps 1 --warmup 0 --no-cpu --no-fp64 --copy-calibration`
+# (profiles/wedge_129x129x257_solve.md).  Valid only for the kernel sources it
+# was measured on (kernel_source_sha); otherwise reported as null.
+TRAFFIC = {
+    ("apply_A+dots", "wedge", "mixed"): (337.3e6, "64634005d9b6fa79"),
+    ("update_xr+dots", "wedge", "mixed"): (547.9e6, "64634005d9b6fa79"),
+    ("mg_down_L0", "wedge", "mixed"): (168.8e6, "64634005d9b6fa79"),
+    ("mg_up_L0", "wedge", "mixed"): (181.1e6, "64634005d9b6fa79"),
+    ("p_update", "wedge", "mixed"): (273.7e6, "64634005d9b6fa79"),
+    ("s_update+dot", "wedge", "mixed"): (205.5e6, "64634005d9b6fa79"),
+}
 
 
 def kernel_source_sha() -> str:
-    p = os.path.join(ROOT, "paper_2308_06085_amd", "csrc", "hh_kernels.hip")
-    with open(p, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256 (16 hex digits) of every HIP source and header of the library."""
+    csrc = os.path.join(ROOT, "paper_2308_06085_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def make_workload(name):
@@ -216,8 +231,8 @@ def main():
     row = head["kernels"][dom]
     traffic = None
     key = (dom, args.workload, "mixed")
-    if key in TRAFFIC and TRAFFIC[key][2] == kernel_source_sha():
-        traffic = TRAFFIC[key][0] + TRAFFIC[key][1]
+    if key in TRAFFIC and TRAFFIC[key][1] == kernel_source_sha():
+        traffic = TRAFFIC[key][0]
     line = {
         "metric": METRIC,
         "value": head["value"],
