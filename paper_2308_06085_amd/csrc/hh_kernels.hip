@@ -88,11 +88,27 @@ __device__ void block_fixed_sum(const double* __restrict__ part, long long nblk,
                                 double (&out)[NT]) {
     __shared__ double sm[NT][16];
     double v[NT];
+    // lane t adds partials t, t + blockDim, t + 2 blockDim, ... in that order; the
+    // loads of eight consecutive terms of that sequence are issued before their
+    // adds (out-of-range slots read a valid partial and add exactly zero)
+    constexpr int U = 8;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        double s = 0.0;
-        for (long long b = threadIdx.x; b < nblk; b += blockDim.x) s += part[t * nblk_max + b];
-        v[t] = s;
+    for (int t = 0; t < NT; ++t) v[t] = 0.0;
+    for (long long b0 = threadIdx.x; b0 < nblk; b0 += (long long)U * blockDim.x) {
+        double ld[NT][U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long b = b0 + (long long)u * blockDim.x;
+            const long long bc = b < nblk ? b : nblk - 1;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) ld[t][u] = part[t * nblk_max + bc];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool in = b0 + (long long)u * blockDim.x < nblk;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) v[t] += in ? ld[t][u] : 0.0;
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
