@@ -19,8 +19,8 @@
 //
 // Only the level's k^2 is stored; c, D and W are recomputed per node.  Both
 // kernels stage x-y planes of a tile and its halo in LDS and march along z with
-// a ring of three planes; the global loads of the next plane are issued into
-// registers before the current plane is computed.  Halo positions outside the
+// a ring of three planes; the global loads of the next two planes are issued
+// into registers before the current plane is computed.  Halo positions outside the
 // domain are read from their mirror image: for Sommerfeld levels that is the
 // eliminated ghost point (its 2hik part is in c) and the even extension of the
 // full-weighting stencil; for Dirichlet levels the boundary values are zero and
@@ -52,7 +52,6 @@ __host__ __device__ inline TileShape tile_shape(int nx, int ny, int maxw, int la
 
 constexpr int DN_LANES = 256, DN_MAXW = 32, DN_MAXH = 16;
 constexpr int DN_REGION = 1280;  // >= (2 tw + 3)(2 th + 3) for every shape tile_shape() returns
-constexpr int DN_RES = 1152;     // >= (2 tw + 1)(2 th + 1)
 constexpr int UP_LANES = 512, UP_MAXW = 32;  // up pass: one lane per region node
 // Tile of the up pass: the tile plus a one-node halo must fit the lanes,
 // (tw + 2)(th + 2) <= lanes.
@@ -112,9 +111,24 @@ __device__ __forceinline__ int faces_of(int x, int y, int z, const Geo& g) {
 }
 
 // ---------------------------------------------------------------------------
-// Down: b_H = R (b - M W b).  One lane per coarse column of a tw x th tile,
-// marching over `zbc` coarse planes (2 zbc + 1 fine residual planes).
+// Down: b_H = R (b - M W b).  The workgroup owns a tw x th tile of coarse
+// columns and marches over `zbc` coarse planes (2 zbc + 1 fine residual
+// planes).  Each lane owns NU nodes of the fine region (tile plus a two-node
+// halo): it loads their b and k^2, writes u1 = W b to the LDS ring, and keeps
+// b and c in registers for the residual of the same nodes one plane later, so
+// every input is read once per plane.  Two planes of loads are in flight.
 // ---------------------------------------------------------------------------
+template <typename TB, typename R, int NU>
+struct DownRaw {
+    cx<TB> b[NU];
+    R k[NU];
+};
+template <typename R, int NU>
+struct DownKeep {
+    cx<R> b[NU];
+    cx<R> c[NU];
+};
+
 template <int BC, typename TB, typename R>
 __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
                                                       const cx<TB>* __restrict__ b,
@@ -124,16 +138,14 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
                                                       cx<R>* __restrict__ bc_out,
                                                       const RhsState* st, int gate) {
     constexpr int NU = (DN_REGION + DN_LANES - 1) / DN_LANES;
-    constexpr int NR = (DN_RES + DN_LANES - 1) / DN_LANES;
     __shared__ cx<R> u1s[3][DN_REGION];
-    __shared__ cx<R> rs[DN_RES];
+    __shared__ cx<R> rs[DN_REGION];
 
     const int r = blockIdx.z;
     if (!gate_ok(st, r, gate)) return;
     const int t = threadIdx.x;
     const TileShape T = tile_shape(gc.nx, gc.ny, DN_MAXW, DN_LANES, DN_MAXH);
     const int RW = 2 * T.tw + 3, RH = 2 * T.th + 3;
-    const int IW = 2 * T.tw + 1, IH = 2 * T.th + 1;
     const int id = xcd_tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int tz = id / gridDim.x;
     const int txy = id - tz * gridDim.x;
@@ -144,9 +156,10 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
     const cx<TB>* br = b + (long long)r * b_rstride;
     const LevelCoef<R> L = level_coef<R>(gf, beta1, beta2, omega);
 
-    // region nodes of this lane: in-plane offset and face count within the x-y plane
+    // region nodes of this lane: in-plane offset, face count within the x-y
+    // plane, and whether the residual is needed there (region minus its rim)
     int uoff[NU], unf[NU];
-    bool ubnd[NU];
+    bool ubnd[NU], uin[NU];
 #pragma unroll
     for (int k = 0; k < NU; ++k) {
         const int idx = t + k * DN_LANES;
@@ -155,75 +168,55 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
         uoff[k] = gy * gf.nx + gx;
         unf[k] = (gx == 0) + (gx == gf.nx - 1) + (gy == 0) + (gy == gf.ny - 1);
         ubnd[k] = unf[k] != 0;
-    }
-    int roff[NR], rl[NR], rnf[NR];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        const int idx = t + k * DN_LANES;
-        const int iy = idx / IW, ix = idx - iy * IW;
-        const int gx = mirror_clamp(gx0 + 1 + ix, gf.nx), gy = mirror_clamp(gy0 + 1 + iy, gf.ny);
-        roff[k] = gy * gf.nx + gx;
-        rnf[k] = (gx == 0) + (gx == gf.nx - 1) + (gy == 0) + (gy == gf.ny - 1);
-        rl[k] = (iy + 1) * RW + ix + 1;
+        uin[k] = idx < RW * RH && lx >= 1 && lx <= RW - 2 && ly >= 1 && ly <= RH - 2;
     }
 
-    // raw loads in flight: region plane for u1, inner plane for the residual
-    cx<TB> ub[NU];
-    R uk[NU];
-    cx<TB> rb[NR];
-    R rk[NR];
     // Loads are issued unconditionally (every offset is a valid node) so the
-    // compiler can count them precisely and keep the next plane in flight.
-    auto fetch_u1 = [&](int f) {
-        const long long base = (long long)mirror_clamp(f, gf.nz) * gf.plane;
+    // compiler can count them and keep later planes in flight.  Planes past
+    // the chunk's last one re-read that plane instead (an L2 hit).
+    const int flast = 2 * Z1;
+    auto fetch = [&](int f, DownRaw<TB, R, NU>& w) {
+        const long long base = (long long)mirror_clamp(min(f, flast), gf.nz) * gf.plane;
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
-            ub[k] = br[base + uoff[k]];
-            uk[k] = k2l[base + uoff[k]];
+            w.b[k] = br[base + uoff[k]];
+            w.k[k] = k2l[base + uoff[k]];
         }
     };
-    auto commit_u1 = [&](int f) {
+    // u1 = W b to the ring; b and c kept for this plane's residual
+    auto commit = [&](int f, const DownRaw<TB, R, NU>& w, DownKeep<R, NU>& kp) {
         const int fz = mirror_clamp(f, gf.nz);
         const int zf = (fz == 0) + (fz == gf.nz - 1);
         cx<R>* dst = u1s[ring3(f)];
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
             const int idx = t + k * DN_LANES;
-            if (idx < RW * RH) {
-                const int nf = BC == BC_SOMMERFELD ? unf[k] + zf : 0;
-                cx<R> v = jacobi_w(L, shift_c(L, uk[k], nf)) * cvt<R>(ub[k]);
-                if (BC == BC_DIRICHLET && (ubnd[k] || zf)) v = czero<R>();
-                dst[idx] = v;
-            }
+            const int nf = BC == BC_SOMMERFELD ? unf[k] + zf : 0;
+            const cx<R> c = shift_c(L, w.k[k], nf);
+            const cx<R> bb = cvt<R>(w.b[k]);
+            cx<R> v = jacobi_w(L, c) * bb;
+            if (BC == BC_DIRICHLET && (ubnd[k] || zf)) v = czero<R>();
+            if (idx < RW * RH) dst[idx] = v;
+            kp.b[k] = bb;
+            kp.c[k] = c;
         }
     };
-    auto fetch_res = [&](int f) {
-        const long long base = (long long)mirror_clamp(f, gf.nz) * gf.plane;
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            rb[k] = br[base + roff[k]];
-            rk[k] = k2l[base + roff[k]];
-        }
-    };
-    auto residual = [&](int f) {
-        const int fz = mirror_clamp(f, gf.nz);
-        const int zf = (fz == 0) + (fz == gf.nz - 1);
+    // r = b - (1/h^2) lap(u1) + c u1 on the region's inner nodes
+    auto residual = [&](int f, const DownKeep<R, NU>& kp) {
         const cx<R>* um = u1s[ring3(f - 1)];
         const cx<R>* uc = u1s[ring3(f)];
         const cx<R>* up = u1s[ring3(f + 1)];
 #pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            const int idx = t + k * DN_LANES;
-            if (idx < IW * IH) {
-                const int c = rl[k];
+        for (int k = 0; k < NU; ++k) {
+            if (uin[k]) {
+                const int c = t + k * DN_LANES;
                 const cx<R> u = uc[c];
                 cx<R> lap = (u - uc[c - 1]) + (u - uc[c + 1]);
                 lap = lap + (u - uc[c - RW]);
                 lap = lap + (u - uc[c + RW]);
                 lap = lap + (u - um[c]);
                 lap = lap + (u - up[c]);
-                const int nf = BC == BC_SOMMERFELD ? rnf[k] + zf : 0;
-                rs[idx] = (cvt<R>(rb[k]) - L.ih2 * lap) + shift_c(L, rk[k], nf) * u;
+                rs[c] = (kp.b[k] - L.ih2 * lap) + kp.c[k] * u;
             }
         }
     };
@@ -231,32 +224,25 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
     const int cxl = t % T.tw, cyl = t / T.tw;
     const int X = X0 + cxl, Y = Y0 + cyl;
     const bool mine = cyl < T.th && X < gc.nx && Y < gc.ny;
-    const int ic = mine ? (2 * cyl + 1) * IW + 2 * cxl + 1 : IW + 1;
+    const int ic = mine ? (2 * cyl + 2) * RW + 2 * cxl + 2 : RW + 1;
     cx<R> acc = czero<R>();
-    fetch_u1(2 * Z0 - 2);
-    commit_u1(2 * Z0 - 2);
-    fetch_u1(2 * Z0 - 1);
-    commit_u1(2 * Z0 - 1);
-    fetch_u1(2 * Z0);
-    fetch_res(2 * Z0 - 1);
-    for (int f = 2 * Z0 - 1; f <= 2 * Z1 - 1; ++f) {
-        commit_u1(f + 1);
-        fetch_u1(f + 2);  // past the chunk's end this reads a valid (unused) plane
+    // one step: u1 of plane f + 1, residual of plane f, its 2D full weighting
+    // accumulated with z weights 1, 2, 1 over fine planes 2Z - 1, 2Z, 2Z + 1
+    auto step = [&](int f, DownRaw<TB, R, NU>& w, DownKeep<R, NU>& cur, DownKeep<R, NU>& nxt) {
+        commit(f + 1, w, nxt);
+        fetch(f + 3, w);
         __syncthreads();
-        residual(f);
-        fetch_res(f + 1);
+        residual(f, cur);
         __syncthreads();
-        // 2D full weighting of the residual plane at the lane's coarse column
         cx<R> q = R(4) * rs[ic];
         cx<R> e = rs[ic - 1] + rs[ic + 1];
-        e = e + rs[ic - IW];
-        e = e + rs[ic + IW];
-        cx<R> c4 = rs[ic - IW - 1] + rs[ic - IW + 1];
-        c4 = c4 + rs[ic + IW - 1];
-        c4 = c4 + rs[ic + IW + 1];
+        e = e + rs[ic - RW];
+        e = e + rs[ic + RW];
+        cx<R> c4 = rs[ic - RW - 1] + rs[ic - RW + 1];
+        c4 = c4 + rs[ic + RW - 1];
+        c4 = c4 + rs[ic + RW + 1];
         q = q + R(2) * e;
         q = q + c4;
-        // z weights 1, 2, 1 over the fine planes 2Z - 1, 2Z, 2Z + 1
         if (f == 2 * Z0 - 1) {
             acc = q;
         } else if ((f & 1) == 0) {
@@ -272,6 +258,23 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
             }
             acc = q;
         }
+    };
+
+    // u1 planes 2 Z0 - 2 .. 2 Z1, residual planes 2 Z0 - 1 .. 2 Z1 - 1.
+    // Set A holds the planes 2 Z0 - 2 + even, set B the odd ones.
+    DownRaw<TB, R, NU> A, B;
+    DownKeep<R, NU> K0, K1;
+    const int F0 = 2 * Z0 - 2;
+    fetch(F0, A);
+    fetch(F0 + 1, B);
+    commit(F0, A, K1);  // plane F0 only feeds the residual stencil; K1 is overwritten below
+    fetch(F0 + 2, A);
+    commit(F0 + 1, B, K0);
+    fetch(F0 + 3, B);
+    for (int f = F0 + 1; f <= 2 * Z1 - 1; f += 2) {
+        step(f, A, K0, K1);
+        if (f + 1 > 2 * Z1 - 1) break;
+        step(f + 1, B, K1, K0);
     }
 }
 
@@ -321,67 +324,67 @@ __global__ __launch_bounds__(UP_LANES) void k_mg_up(Geo g, Geo gc, int zb,
     const bool own = in_region && lx >= 1 && lx <= T.tw && ly >= 1 && ly <= T.th && gxr < g.nx &&
                      gyr < g.ny;
 
-    // raw loads in flight (issued unconditionally: every offset is a valid node)
-    cx<TB> ub;
-    R uk;
-    cx<R> ue[8];
-    auto fetch_u2 = [&](int f) {
-        const int fz = mirror_clamp(f, g.nz);
+    // raw loads of one plane: b, k^2 and the eight coarse corners.  Loads are
+    // issued unconditionally (every offset is a valid node); a plane past the
+    // chunk's last one re-reads that plane instead (an L2 hit).
+    struct Raw {
+        cx<TB> b;
+        R k;
+        cx<R> e[8];
+    };
+    auto fetch = [&](int f, Raw& w) {
+        const int fz = mirror_clamp(min(f, z1), g.nz);
         const long long base = (long long)fz * g.plane;
         const cx<R>* e0 = er + (long long)(fz >> 1) * gc.plane;
         const cx<R>* e1 = er + (long long)min((fz >> 1) + (fz & 1), gc.nz - 1) * gc.plane;
-        ub = br[base + uoff];
-        uk = k2l[base + uoff];
-        ue[0] = e0[cy0 + cx0];
-        ue[1] = e0[cy0 + cx1];
-        ue[2] = e0[cy1 + cx0];
-        ue[3] = e0[cy1 + cx1];
-        ue[4] = e1[cy0 + cx0];
-        ue[5] = e1[cy0 + cx1];
-        ue[6] = e1[cy1 + cx0];
-        ue[7] = e1[cy1 + cx1];
+        w.b = br[base + uoff];
+        w.k = k2l[base + uoff];
+        w.e[0] = e0[cy0 + cx0];
+        w.e[1] = e0[cy0 + cx1];
+        w.e[2] = e0[cy1 + cx0];
+        w.e[3] = e0[cy1 + cx1];
+        w.e[4] = e1[cy0 + cx0];
+        w.e[5] = e1[cy0 + cx1];
+        w.e[6] = e1[cy1 + cx0];
+        w.e[7] = e1[cy1 + cx1];
     };
-    // u2 at this lane's node; the stencil of the output lanes needs it in LDS
-    auto make_u2 = [&](int f, cx<R>& kk_c, R& kk) -> cx<R> {
+    // u2 at this lane's node of plane f, also written to the ring for the
+    // stencil of the output lanes; c is returned for the output step
+    auto make_u2 = [&](int f, const Raw& w, cx<R>& c_out) -> cx<R> {
         const int fz = mirror_clamp(f, g.nz);
         const int zf = (fz == 0) + (fz == g.nz - 1);
         const R wz = (fz & 1) ? R(0.5) : R(1), bz = R(1) - wz;
         // trilinear interpolation; an even index takes its own coarse node only
-        const cx<R> p0 = ax * ue[0] + bx * ue[1];
-        const cx<R> p1 = ax * ue[2] + bx * ue[3];
-        const cx<R> p2 = ax * ue[4] + bx * ue[5];
-        const cx<R> p3 = ax * ue[6] + bx * ue[7];
+        const cx<R> p0 = ax * w.e[0] + bx * w.e[1];
+        const cx<R> p1 = ax * w.e[2] + bx * w.e[3];
+        const cx<R> p2 = ax * w.e[4] + bx * w.e[5];
+        const cx<R> p3 = ax * w.e[6] + bx * w.e[7];
         const cx<R> pe = wz * (ay * p0 + by * p1) + bz * (ay * p2 + by * p3);
         const int nf = BC == BC_SOMMERFELD ? unf + zf : 0;
-        kk = uk;
-        kk_c = shift_c(L, uk, nf);
-        cx<R> v = jacobi_w(L, kk_c) * cvt<R>(ub) + pe;
+        c_out = shift_c(L, w.k, nf);
+        cx<R> v = jacobi_w(L, c_out) * cvt<R>(w.b) + pe;
         if (BC == BC_DIRICHLET && (unf || zf)) v = czero<R>();
+        if (in_region) us[ring3(f)][t] = v;
         return v;
     };
 
     cx<TO>* orr = out + (long long)r * o_rstride;
     const long long ooff = own ? (long long)gyr * g.nx + gxr : 0;
-    // per plane this lane keeps its own u2, b, c for the output step
-    cx<R> u_cur, c_cur, c_nxt;
-    R k_unused;
+    // per plane this lane keeps its own u2, b, c for the output step.  The
+    // first two planes are loaded together; in the march one plane is in flight.
+    Raw w, w2;
+    cx<R> u_cur, c_cur, c_nxt, c_unused;
     cx<TB> b_cur, b_nxt;
-    fetch_u2(z0 - 1);
-    {
-        cx<R> cc;
-        cx<R> v = make_u2(z0 - 1, cc, k_unused);
-        if (in_region) us[ring3(z0 - 1)][t] = v;
-    }
-    fetch_u2(z0);
-    b_cur = ub;
-    u_cur = make_u2(z0, c_cur, k_unused);
-    if (in_region) us[ring3(z0)][t] = u_cur;
-    fetch_u2(z0 + 1);
+    fetch(z0 - 1, w);
+    fetch(z0, w2);
+    (void)make_u2(z0 - 1, w, c_unused);
+    fetch(z0 + 1, w);
+    b_cur = w2.b;
+    u_cur = make_u2(z0, w2, c_cur);
     for (int z = z0; z < z1; ++z) {
-        b_nxt = ub;
-        const cx<R> u_nxt = make_u2(z + 1, c_nxt, k_unused);
-        if (in_region) us[ring3(z + 1)][t] = u_nxt;
-        fetch_u2(z + 2);  // past the chunk's end this reads a valid (unused) plane
+        b_nxt = w.b;
+        const cx<R> u_nxt = make_u2(z + 1, w, c_nxt);
+        fetch(z + 2, w);
         __syncthreads();
         if (own) {
             const cx<R>* um = us[ring3(z - 1)];
