@@ -161,8 +161,11 @@ hh_status hh_grad_slowness2(hh_ctx* ctx, const void* u, const void* w, const dou
  * "block" (threads per workgroup of the stencil kernels: 64, 128, 256, 512;
  * default 512), "zb" (z-planes per workgroup of the stencil kernels, default 2,
  * 0 = automatic), "zb_down" / "zb_up" (z-planes per workgroup of the finest
- * level's multigrid down / up pass, 0 = automatic).
- * hh_get_option also reports "n_levels", "coarse_unknowns", "zb_down", "zb_up". */
+ * level's multigrid down / up pass, 0 = automatic), "zb_down:<l>" / "zb_up:<l>"
+ * (the same for level l, 0 <= l < n_levels - 1; levels run by the single-workgroup
+ * tail kernel ignore it).  A level outside that range is HH_ERR_ARG.
+ * hh_get_option also reports "n_levels", "coarse_unknowns", "tail_first" (first
+ * level run by the tail kernel) and the z-planes in use under the same names. */
 hh_status hh_set_option(hh_ctx* ctx, const char* name, long long value);
 hh_status hh_get_option(const hh_ctx* ctx, const char* name, long long* value);
 

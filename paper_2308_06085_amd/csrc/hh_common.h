@@ -80,9 +80,8 @@ struct RhsState {
 enum Slot : int {
     SLOT_R = 0,   // ||r||^2, Re/Im r_hat^H r, ||b||^2
     SLOT_V = 1,   // Re/Im r_hat^H v
-    SLOT_S = 2,   // ||s||^2
-    SLOT_T = 3,   // Re/Im t^H s, ||t||^2
-    NSLOT = 4
+    SLOT_T = 2,   // Re/Im t^H s, ||t||^2 (from t = A s_hat), ||s||^2 (from the s update)
+    NSLOT = 3
 };
 constexpr int MAX_TERMS = 4;
 

@@ -16,7 +16,9 @@ struct Launch {
 };
 
 enum OpMode : int { OP_PLAIN = 0, OP_V = 1, OP_T = 2 };
-enum FinMode : int { FIN_INIT = 0, FIN_RHO = 1, FIN_ALPHA = 2, FIN_S = 3, FIN_OMEGA = 4, FIN_TRUE = 5 };
+// FIN_OMEGA also takes the half-step test on ||s||: the s update writes its
+// partial sums beside those of t = A s_hat, so one finalize serves both.
+enum FinMode : int { FIN_INIT = 0, FIN_RHO = 1, FIN_ALPHA = 2, FIN_OMEGA = 4, FIN_TRUE = 5 };
 constexpr int GATE_ALL = -1;       // act on every right-hand side
 constexpr int GATE_FINISHED = -2;  // act on right-hand sides that stopped iterating
 

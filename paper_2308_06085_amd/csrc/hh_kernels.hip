@@ -30,14 +30,26 @@ struct Pos {
     bool valid;      // lane owns a node of the plane
 };
 
-__device__ __forceinline__ Pos plane_pos(int nx, int plane) {
+// Column of this lane in plane chunk `bx` (blockDim.x nodes of the flattened plane).
+__device__ __forceinline__ Pos plane_pos(int nx, int plane, int bx) {
     Pos q;
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    int p = bx * blockDim.x + threadIdx.x;
     q.valid = p < plane;
     if (!q.valid) p = 0;
     q.j = p / nx;
     q.i = p - q.j * nx;
     return q;
+}
+
+// (plane chunk, z chunk) of this workgroup of a stencil kernel whose grid is
+// (chunks per plane, z chunks).  The XCD-aware map keeps z-neighbouring chunks,
+// which share their boundary planes, on one XCD and so in one L2.
+struct StencilTile {
+    int bx, bz;
+};
+__device__ __forceinline__ StencilTile stencil_tile() {
+    const int id = xcd_tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    return {id % (int)gridDim.x, id / (int)gridDim.x};
 }
 
 // Neighbour sum with the boundary rule of the level.  `ld(i, j)` returns the
@@ -198,12 +210,12 @@ __device__ void fin_update(int mode, RhsState& S, const double* s, double tol) {
             S.alpha = cdiv(S.rho, rv);
             return;
         }
-        case FIN_S:
-            if (!isfinite(s[0])) { S.status = ST_NUMERIC; return; }
-            S.snorm2 = s[0];
-            if (s[0] <= S.tol2) S.status = ST_HALF;
-            return;
         case FIN_OMEGA: {
+            // half step first: ||s|| small means x += alpha p_hat ends this
+            // right-hand side, and t = A s_hat (already formed) is not used
+            if (!isfinite(s[3])) { S.status = ST_NUMERIC; return; }
+            S.snorm2 = s[3];
+            if (s[3] <= S.tol2) { S.status = ST_HALF; return; }
             S.matvecs += 1;
             const c128 ts = mk(s[0], s[1]);
             const double tt = s[2];
@@ -221,7 +233,6 @@ __device__ void fin_update(int mode, RhsState& S, const double* s, double tol) {
 __device__ __forceinline__ int fin_slot(int mode) {
     switch (mode) {
         case FIN_ALPHA: return SLOT_V;
-        case FIN_S: return SLOT_S;
         case FIN_OMEGA: return SLOT_T;
         default: return SLOT_R;
     }
@@ -229,11 +240,21 @@ __device__ __forceinline__ int fin_slot(int mode) {
 __device__ __forceinline__ int fin_terms(int mode) {
     switch (mode) {
         case FIN_ALPHA: return 2;
-        case FIN_S: return 1;
-        case FIN_OMEGA: return 3;
+        case FIN_OMEGA: return 4;
         case FIN_RHO: return 3;
+        case FIN_TRUE: return 1;
         default: return 4;
     }
+}
+
+// the first NT terms of a slot into sums[0 .. NT)
+template <int NT>
+__device__ __forceinline__ void fixed_sum_into(const double* __restrict__ part, long long nblk,
+                                               long long nblk_max, double* sums) {
+    double o[NT];
+    block_fixed_sum<NT>(part, nblk, nblk_max, o);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) sums[t] = o[t];
 }
 
 __global__ __launch_bounds__(1024) void k_finalize(int mode, RhsState* st, const double* part,
@@ -249,8 +270,16 @@ __global__ __launch_bounds__(1024) void k_finalize(int mode, RhsState* st, const
     }
     if (!act) return;
     double sums[4] = {0.0, 0.0, 0.0, 0.0};
-    if (status != ST_HALF)
-        block_fixed_sum<4>(part + part_index(r, fin_slot(mode), 0, nblk_max), nblk, nblk_max, sums);
+    if (status != ST_HALF) {
+        // only the terms the mode reads are loaded
+        const double* base = part + part_index(r, fin_slot(mode), 0, nblk_max);
+        switch (fin_terms(mode)) {
+            case 1: fixed_sum_into<1>(base, nblk, nblk_max, sums); break;
+            case 2: fixed_sum_into<2>(base, nblk, nblk_max, sums); break;
+            case 3: fixed_sum_into<3>(base, nblk, nblk_max, sums); break;
+            default: fixed_sum_into<4>(base, nblk, nblk_max, sums); break;
+        }
+    }
     if (threadIdx.x == 0) fin_update(mode, S, sums, tol);
 }
 
@@ -268,8 +297,9 @@ __global__ __launch_bounds__(512) void k_apply(Geo g, int zb, const c128* __rest
                                                long long nblk_max, const RhsState* st, int gate) {
     const int r = blockIdx.z;
     if (!gate_ok(st, r, gate)) return;
-    const Pos q = plane_pos(g.nx, g.plane);
-    const int z0 = blockIdx.y * zb;
+    const StencilTile tl = stencil_tile();
+    const Pos q = plane_pos(g.nx, g.plane, tl.bx);
+    const int z0 = tl.bz * zb;
     const int z1 = min(g.nz, z0 + zb);
     const double ih2 = 1.0 / (g.h * g.h);
     const double two_over_h = 2.0 / g.h;
@@ -355,8 +385,9 @@ __global__ __launch_bounds__(512) void k_init(Geo g, int zb, const c128* __restr
                                               const RhsState* st, int gate) {
     const int r = blockIdx.z;
     if (!gate_ok(st, r, gate)) return;
-    const Pos q = plane_pos(g.nx, g.plane);
-    const int z0 = blockIdx.y * zb;
+    const StencilTile tl = stencil_tile();
+    const Pos q = plane_pos(g.nx, g.plane, tl.bx);
+    const int z0 = tl.bz * zb;
     const int z1 = min(g.nz, z0 + zb);
     const double ih2 = 1.0 / (g.h * g.h);
     const double two_over_h = 2.0 / g.h;
@@ -439,7 +470,8 @@ __global__ __launch_bounds__(512) void k_p_update(long long n, c128* __restrict_
     }
 }
 
-// s = r - alpha v, partial ||s||^2, then (last workgroup) the half-step test.
+// s = r - alpha v and the partial sums of ||s||^2 (slot T, term 3) for the
+// half-step test.
 __global__ __launch_bounds__(512) void k_s_update(long long n, c128* __restrict__ s,
                                                   const c128* __restrict__ rr,
                                                   const c128* __restrict__ v, const RhsState* st,
@@ -455,7 +487,7 @@ __global__ __launch_bounds__(512) void k_s_update(long long n, c128* __restrict_
         s[off + i] = sv;
         acc[0] += abs2(sv);
     }
-    block_sum_store<1>(acc, part + part_index(r, SLOT_S, 0, nblk_max) + blockIdx.x, nblk_max);
+    block_sum_store<1>(acc, part + part_index(r, SLOT_T, 3, nblk_max) + blockIdx.x, nblk_max);
 }
 
 // Iterating right-hand sides: x += alpha p_hat + omega s_hat; r = s - omega t;

@@ -52,6 +52,7 @@ __host__ __device__ inline TileShape tile_shape(int nx, int ny, int maxw, int la
 
 constexpr int DN_LANES = 256, DN_MAXW = 32, DN_MAXH = 16;
 constexpr int DN_REGION = 1280;  // >= (2 tw + 3)(2 th + 3) for every shape tile_shape() returns
+static_assert(DN_REGION % DN_LANES == 0, "every lane's region slots must lie inside the LDS arrays");
 constexpr int UP_LANES = 512, UP_MAXW = 32;  // up pass: one lane per region node
 // Tile of the up pass: the tile plus a one-node halo must fit the lanes,
 // (tw + 2)(th + 2) <= lanes.
@@ -129,7 +130,7 @@ struct DownKeep {
     cx<R> c[NU];
 };
 
-template <int BC, typename TB, typename R>
+template <int BC, typename TB, typename R, bool ONE>
 __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
                                                       const cx<TB>* __restrict__ b,
                                                       long long b_rstride,
@@ -182,6 +183,9 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
             w.b[k] = br[base + uoff[k]];
             w.k[k] = k2l[base + uoff[k]];
         }
+        // keep the scheduler from moving these loads past later ones: loads
+        // complete in issue order, so a plane must be issued as one group
+        __builtin_amdgcn_sched_barrier(0);
     };
     // u1 = W b to the ring; b and c kept for this plane's residual
     auto commit = [&](int f, const DownRaw<TB, R, NU>& w, DownKeep<R, NU>& kp) {
@@ -196,7 +200,9 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
             const cx<R> bb = cvt<R>(w.b[k]);
             cx<R> v = jacobi_w(L, c) * bb;
             if (BC == BC_DIRICHLET && (ubnd[k] || zf)) v = czero<R>();
-            if (idx < RW * RH) dst[idx] = v;
+            // unguarded: idx < NU * DN_LANES = DN_REGION, and slots past the
+            // region are never read (a guard would sink the loads into it)
+            dst[idx] = v;
             kp.b[k] = bb;
             kp.c[k] = c;
         }
@@ -228,9 +234,10 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
     cx<R> acc = czero<R>();
     // one step: u1 of plane f + 1, residual of plane f, its 2D full weighting
     // accumulated with z weights 1, 2, 1 over fine planes 2Z - 1, 2Z, 2Z + 1
-    auto step = [&](int f, DownRaw<TB, R, NU>& w, DownKeep<R, NU>& cur, DownKeep<R, NU>& nxt) {
+    auto step = [&](int f, DownRaw<TB, R, NU>& w, DownKeep<R, NU>& cur, DownKeep<R, NU>& nxt,
+                    bool refill) {
         commit(f + 1, w, nxt);
-        fetch(f + 3, w);
+        if (refill) fetch(f + 3, w);
         __syncthreads();
         residual(f, cur);
         __syncthreads();
@@ -261,20 +268,37 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
     };
 
     // u1 planes 2 Z0 - 2 .. 2 Z1, residual planes 2 Z0 - 1 .. 2 Z1 - 1.
-    // Set A holds the planes 2 Z0 - 2 + even, set B the odd ones.
-    DownRaw<TB, R, NU> A, B;
-    DownKeep<R, NU> K0, K1;
     const int F0 = 2 * Z0 - 2;
-    fetch(F0, A);
-    fetch(F0 + 1, B);
-    commit(F0, A, K1);  // plane F0 only feeds the residual stencil; K1 is overwritten below
-    fetch(F0 + 2, A);
-    commit(F0 + 1, B, K0);
-    fetch(F0 + 3, B);
-    for (int f = F0 + 1; f <= 2 * Z1 - 1; f += 2) {
-        step(f, A, K0, K1);
-        if (f + 1 > 2 * Z1 - 1) break;
-        step(f + 1, B, K1, K0);
+    if constexpr (ONE) {
+        // one coarse plane per workgroup (the small levels, where latency
+        // rules): all five fine planes are loaded in one round
+        DownRaw<TB, R, NU> S0, S1, S2, S3, S4;
+        DownKeep<R, NU> K0, K1;
+        fetch(F0, S0);
+        fetch(F0 + 1, S1);
+        fetch(F0 + 2, S2);
+        fetch(F0 + 3, S3);
+        fetch(F0 + 4, S4);
+        commit(F0, S0, K1);  // plane F0 only feeds the residual stencil; K1 is overwritten below
+        commit(F0 + 1, S1, K0);
+        step(F0 + 1, S2, K0, K1, false);
+        step(F0 + 2, S3, K1, K0, false);
+        step(F0 + 3, S4, K0, K1, false);
+    } else {
+        // set A holds the planes F0 + even, set B the odd ones
+        DownRaw<TB, R, NU> A, B;
+        DownKeep<R, NU> K0, K1;
+        fetch(F0, A);
+        fetch(F0 + 1, B);
+        commit(F0, A, K1);  // plane F0 only feeds the residual stencil; K1 is overwritten below
+        fetch(F0 + 2, A);
+        commit(F0 + 1, B, K0);
+        fetch(F0 + 3, B);
+        for (int f = F0 + 1; f <= 2 * Z1 - 1; f += 2) {
+            step(f, A, K0, K1, true);
+            if (f + 1 > 2 * Z1 - 1) break;
+            step(f + 1, B, K1, K0, true);
+        }
     }
 }
 
@@ -283,7 +307,7 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
 // owns one node of the tile-plus-halo region; the lanes inside the halo
 // compute the output.  The workgroup marches over `zb` planes.
 // ---------------------------------------------------------------------------
-template <int BC, typename TB, typename R, typename TO>
+template <int BC, typename TB, typename R, typename TO, bool ONE>
 __global__ __launch_bounds__(UP_LANES) void k_mg_up(Geo g, Geo gc, int zb,
                                                     const cx<TB>* __restrict__ b, long long b_rstride,
                                                     const R* __restrict__ k2l, double beta1,
@@ -364,46 +388,63 @@ __global__ __launch_bounds__(UP_LANES) void k_mg_up(Geo g, Geo gc, int zb,
         c_out = shift_c(L, w.k, nf);
         cx<R> v = jacobi_w(L, c_out) * cvt<R>(w.b) + pe;
         if (BC == BC_DIRICHLET && (unf || zf)) v = czero<R>();
-        if (in_region) us[ring3(f)][t] = v;
+        us[ring3(f)][t] = v;  // unguarded: lanes past the region write slots never read
         return v;
     };
 
     cx<TO>* orr = out + (long long)r * o_rstride;
     const long long ooff = own ? (long long)gyr * g.nx + gxr : 0;
-    // per plane this lane keeps its own u2, b, c for the output step.  The
-    // first two planes are loaded together; in the march one plane is in flight.
-    Raw w, w2;
-    cx<R> u_cur, c_cur, c_nxt, c_unused;
-    cx<TB> b_cur, b_nxt;
-    fetch(z0 - 1, w);
-    fetch(z0, w2);
-    (void)make_u2(z0 - 1, w, c_unused);
-    fetch(z0 + 1, w);
-    b_cur = w2.b;
-    u_cur = make_u2(z0, w2, c_cur);
-    for (int z = z0; z < z1; ++z) {
-        b_nxt = w.b;
-        const cx<R> u_nxt = make_u2(z + 1, w, c_nxt);
-        fetch(z + 2, w);
-        __syncthreads();
+    // u3 of plane z at the output lanes, from the u2 ring and this lane's u2, b, c
+    auto emit = [&](int z, const cx<R>& u, const cx<R>& c, const cx<TB>& bz) {
         if (own) {
             const cx<R>* um = us[ring3(z - 1)];
             const cx<R>* uc = us[ring3(z)];
             const cx<R>* up = us[ring3(z + 1)];
-            const cx<R> u = u_cur;
             cx<R> lap = (u - uc[t - 1]) + (u - uc[t + 1]);
             lap = lap + (u - uc[t - RW]);
             lap = lap + (u - uc[t + RW]);
             lap = lap + (u - um[t]);
             lap = lap + (u - up[t]);
-            cx<R> v = u + jacobi_w(L, c_cur) * ((cvt<R>(b_cur) - L.ih2 * lap) + c_cur * u);
+            cx<R> v = u + jacobi_w(L, c) * ((cvt<R>(bz) - L.ih2 * lap) + c * u);
             if (BC == BC_DIRICHLET && (unf || z == 0 || z == g.nz - 1)) v = czero<R>();
             orr[(long long)z * g.plane + ooff] = cvt<TO>(v);
         }
-        u_cur = u_nxt;
-        c_cur = c_nxt;
-        b_cur = b_nxt;
+    };
+    // per plane this lane keeps its own u2, b, c for the output step
+    Raw w, w2;
+    cx<R> u_cur, c_cur, c_nxt, c_unused;
+    cx<TB> b_cur, b_nxt;
+    if constexpr (ONE) {
+        // one plane per workgroup (the small levels, where latency rules):
+        // its three planes are loaded in one round
+        Raw w3;
+        fetch(z0 - 1, w);
+        fetch(z0, w2);
+        fetch(z0 + 1, w3);
+        (void)make_u2(z0 - 1, w, c_unused);
+        u_cur = make_u2(z0, w2, c_cur);
+        (void)make_u2(z0 + 1, w3, c_unused);
         __syncthreads();
+        emit(z0, u_cur, c_cur, w2.b);
+    } else {
+        // the first two planes are loaded together; in the march one plane is in flight
+        fetch(z0 - 1, w);
+        fetch(z0, w2);
+        (void)make_u2(z0 - 1, w, c_unused);
+        fetch(z0 + 1, w);
+        b_cur = w2.b;
+        u_cur = make_u2(z0, w2, c_cur);
+        for (int z = z0; z < z1; ++z) {
+            b_nxt = w.b;
+            const cx<R> u_nxt = make_u2(z + 1, w, c_nxt);
+            fetch(z + 2, w);
+            __syncthreads();
+            emit(z, u_cur, c_cur, b_cur);
+            u_cur = u_nxt;
+            c_cur = c_nxt;
+            b_cur = b_nxt;
+            __syncthreads();
+        }
     }
 }
 
@@ -425,12 +466,17 @@ void launch_mg_down(hipStream_t s, int bc, const Geo& gf, const Geo& gc, int zbc
                     cx<R>* bc_out, const RhsState* st, int gate) {
     const TileShape T = tile_shape(gc.nx, gc.ny, DN_MAXW, DN_LANES, DN_MAXH);
     dim3 grid(T.ntx * T.nty, (gc.nz + zbc - 1) / zbc, nrhs);
-    if (bc == BC_SOMMERFELD)
-        hipLaunchKernelGGL((k_mg_down<BC_SOMMERFELD, TB, R>), grid, dim3(DN_LANES), 0, s, gf, gc, zbc, b,
-                           b_rstride, k2l, P.beta1, P.beta2, P.omega, bc_out, st, gate);
-    else
-        hipLaunchKernelGGL((k_mg_down<BC_DIRICHLET, TB, R>), grid, dim3(DN_LANES), 0, s, gf, gc, zbc, b,
-                           b_rstride, k2l, P.beta1, P.beta2, P.omega, bc_out, st, gate);
+#define HH_DOWN(BCV, ONEV)                                                                                \
+    hipLaunchKernelGGL((k_mg_down<BCV, TB, R, ONEV>), grid, dim3(DN_LANES), 0, s, gf, gc, zbc, b, b_rstride, \
+                       k2l, P.beta1, P.beta2, P.omega, bc_out, st, gate)
+    if (bc == BC_SOMMERFELD) {
+        if (zbc == 1) HH_DOWN(BC_SOMMERFELD, true);
+        else HH_DOWN(BC_SOMMERFELD, false);
+    } else {
+        if (zbc == 1) HH_DOWN(BC_DIRICHLET, true);
+        else HH_DOWN(BC_DIRICHLET, false);
+    }
+#undef HH_DOWN
 }
 
 template <typename TB, typename R, typename TO>
@@ -439,12 +485,17 @@ void launch_mg_up(hipStream_t s, int bc, const Geo& g, const Geo& gc, int zb, in
                   const cx<R>* ec, cx<TO>* out, long long o_rstride, const RhsState* st, int gate) {
     const TileShape T = up_tile_shape(g.nx, g.ny);
     dim3 grid(T.ntx * T.nty, (g.nz + zb - 1) / zb, nrhs);
-    if (bc == BC_SOMMERFELD)
-        hipLaunchKernelGGL((k_mg_up<BC_SOMMERFELD, TB, R, TO>), grid, dim3(UP_LANES), 0, s, g, gc, zb, b,
-                           b_rstride, k2l, P.beta1, P.beta2, P.omega, ec, out, o_rstride, st, gate);
-    else
-        hipLaunchKernelGGL((k_mg_up<BC_DIRICHLET, TB, R, TO>), grid, dim3(UP_LANES), 0, s, g, gc, zb, b,
-                           b_rstride, k2l, P.beta1, P.beta2, P.omega, ec, out, o_rstride, st, gate);
+#define HH_UP(BCV, ONEV)                                                                                \
+    hipLaunchKernelGGL((k_mg_up<BCV, TB, R, TO, ONEV>), grid, dim3(UP_LANES), 0, s, g, gc, zb, b, b_rstride, \
+                       k2l, P.beta1, P.beta2, P.omega, ec, out, o_rstride, st, gate)
+    if (bc == BC_SOMMERFELD) {
+        if (zb == 1) HH_UP(BC_SOMMERFELD, true);
+        else HH_UP(BC_SOMMERFELD, false);
+    } else {
+        if (zb == 1) HH_UP(BC_DIRICHLET, true);
+        else HH_UP(BC_DIRICHLET, false);
+    }
+#undef HH_UP
 }
 
 #define HH_INST_F(TB, R, TO)                                                                           \

@@ -7,6 +7,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -73,7 +74,9 @@ struct hh_ctx {
     int check_every = 4;
     std::map<int, hipGraphExec_t> graphs;
     int tail_first = 0;   // first level run by the single-workgroup tail kernel
-    int zb_down0 = 0, zb_up0 = 0;  // finest-level z-planes of the multigrid passes (0 = automatic)
+    // z-planes per workgroup of each level's multigrid passes set by the caller
+    // (0 = automatic); indexed by level, grown on demand
+    std::vector<int> zb_down_set, zb_up_set;
     size_t tail_lds_cap = 65536;
     float last_ms = 0.f;
     std::string err;
@@ -236,8 +239,12 @@ void apply_launch(hh_ctx* c) {
         c->lv[l].zb_down = pick_zb([&](int z) { return mg_down_blocks(gc, z); }, 1024);
         c->lv[l].zb_up = pick_zb([&](int z) { return mg_up_blocks(g, z); }, 512);
     }
-    if (c->zb_down0 > 0) c->lv[0].zb_down = std::min(c->zb_down0, c->lv[1].g.nz);
-    if (c->zb_up0 > 0) c->lv[0].zb_up = std::min(c->zb_up0, c->lv[0].g.nz);
+    for (size_t l = 0; l + 1 < c->lv.size(); ++l) {
+        if (l < c->zb_down_set.size() && c->zb_down_set[l] > 0)
+            c->lv[l].zb_down = std::min(c->zb_down_set[l], c->lv[l + 1].g.nz);
+        if (l < c->zb_up_set.size() && c->zb_up_set[l] > 0)
+            c->lv[l].zb_up = std::min(c->zb_up_set[l], c->lv[l].g.nz);
+    }
     c->L0 = c->lv[0].L;
     c->nblk0 = nblk_of(c->lv[0].g, c->L0);
     invalidate_graphs(c);
@@ -299,7 +306,6 @@ void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs) {
                  NBLK_CAP, c->st, ST_RUN);
     launch_finalize(s, FIN_ALPHA, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
     launch_s_update(s, n, nrhs, c->s, c->r, c->v, c->st, c->part, NBLK_CAP, F);
-    launch_finalize(s, FIN_S, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
     enqueue_vcycle(c, s, nrhs, c->s, c->sh, c->st, ST_RUN);
     launch_apply(s, bc, OP_T, g, c->L0, nrhs, c->sh, c->t, c->k2, c->kb, 1.0, 0.0, c->s, c->part,
                  NBLK_CAP, c->st, ST_RUN);
@@ -813,9 +819,24 @@ hh_status hh_set_option(hh_ctx* c, const char* name, long long value) {
         if (value < 0 || value > 1024) return fail(c, HH_ERR_ARG, "zb must be in 0..1024");
         c->base.zb = (int)value;
         apply_launch(c);
-    } else if (n == "zb_down" || n == "zb_up") {
+    } else if (n.rfind("zb_down", 0) == 0 || n.rfind("zb_up", 0) == 0) {
+        // "zb_down" / "zb_up" (finest level) or "zb_down:<level>" / "zb_up:<level>"
+        const bool down = n.rfind("zb_down", 0) == 0;
+        const std::string rest = n.substr(down ? 7 : 5);
+        int level = 0;
+        if (!rest.empty()) {
+            if (rest[0] != ':' || rest.size() < 2 || rest.size() > 4 ||
+                rest.find_first_not_of("0123456789", 1) != std::string::npos)
+                return fail(c, HH_ERR_ARG, "unknown option '%s'", name);
+            level = std::atoi(rest.c_str() + 1);
+        }
+        if (level >= (int)c->lv.size() - 1)
+            return fail(c, HH_ERR_ARG, "%s: level %d has no multigrid pass (levels 0..%d)", name, level,
+                        (int)c->lv.size() - 2);
         if (value < 0 || value > 1024) return fail(c, HH_ERR_ARG, "%s must be in 0..1024", name);
-        (n == "zb_down" ? c->zb_down0 : c->zb_up0) = (int)value;
+        std::vector<int>& v = down ? c->zb_down_set : c->zb_up_set;
+        if ((int)v.size() <= level) v.resize(level + 1, 0);
+        v[level] = (int)value;
         apply_launch(c);
     } else {
         return fail(c, HH_ERR_ARG, "unknown option '%s'", name);
@@ -827,9 +848,20 @@ hh_status hh_get_option(const hh_ctx* c, const char* name, long long* value) {
     if (!c || !name || !value) return HH_ERR_ARG;
     std::string n(name);
     if (n == "graph") *value = c->use_graph;
-    else if (n == "zb_down") *value = c->lv[0].zb_down;
+    else if (n.rfind("zb_down", 0) == 0 || n.rfind("zb_up", 0) == 0) {
+        const bool down = n.rfind("zb_down", 0) == 0;
+        const std::string rest = n.substr(down ? 7 : 5);
+        int level = 0;
+        if (!rest.empty()) {
+            if (rest[0] != ':' || rest.size() < 2 || rest.size() > 4 ||
+                rest.find_first_not_of("0123456789", 1) != std::string::npos)
+                return HH_ERR_ARG;
+            level = std::atoi(rest.c_str() + 1);
+        }
+        if (level >= (int)c->lv.size() - 1) return HH_ERR_ARG;
+        *value = down ? c->lv[level].zb_down : c->lv[level].zb_up;
+    }
     else if (n == "tail_first") *value = c->tail_first;
-    else if (n == "zb_up") *value = c->lv[0].zb_up;
     else if (n == "check_every") *value = c->check_every;
     else if (n == "block") *value = c->L0.block;
     else if (n == "zb") *value = c->L0.zb;
