@@ -41,14 +41,16 @@ METRIC = "DoF-iterations/s of CSLP-Bi-CGSTAB, mixed vs FP64 at 1e-6 rel residual
 # bytes per fine-grid node per right-hand side for (fp64, mixed) precision:
 # every array the kernel must read or write once (complex128 16 B, complex64
 # 8 B, real k^2 8 B for the operator, k^2 in the multigrid precision for the
-# multigrid passes, coarse-grid arrays 1/8 of a fine one).
+# multigrid passes, coarse-grid arrays 1/8 of a fine one).  In the mixed solve
+# the preconditioner's inputs (complex64 copies of p and s, written by the p
+# and s updates) and outputs p_hat, s_hat are complex64.
 KERNELS = {
-    0: ("apply_A+dots", 2, (16 + 8 + 16 + 16, 16 + 8 + 16 + 16)),
-    1: ("update_xr+dots", 1, (6 * 16 + 2 * 16, 6 * 16 + 2 * 16)),
-    2: ("mg_down_L0", 2, (16 + 8 + 16 / 8, 16 + 4 + 8 / 8)),
-    3: ("mg_up_L0", 2, (16 + 8 + 16 / 8 + 16, 16 + 4 + 8 / 8 + 16)),
-    4: ("p_update", 1, (4 * 16, 4 * 16)),
-    5: ("s_update+dot", 1, (3 * 16, 3 * 16)),
+    0: ("apply_A+dots", 2, (16 + 8 + 16 + 16, 8 + 8 + 16 + 16)),
+    1: ("update_xr+dots", 1, (6 * 16 + 2 * 16, 4 * 16 + 2 * 8 + 2 * 16)),
+    2: ("mg_down_L0", 2, (16 + 8 + 16 / 8, 8 + 4 + 8 / 8)),
+    3: ("mg_up_L0", 2, (16 + 8 + 16 / 8 + 16, 8 + 4 + 8 / 8 + 8)),
+    4: ("p_update", 1, (4 * 16, 4 * 16 + 8)),
+    5: ("s_update+dot", 1, (3 * 16, 3 * 16 + 8)),
 }
 
 # HBM traffic per launch, FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scale factors

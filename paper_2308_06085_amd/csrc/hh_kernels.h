@@ -24,8 +24,10 @@ constexpr int GATE_FINISHED = -2;  // act on right-hand sides that stopped itera
 
 long long nblk_of(const Geo& g, const Launch& L);
 
+// x: complex128, or complex64 (double / float); y and the arithmetic are complex128
+template <typename TX>
 void launch_apply(hipStream_t s, int bc, int mode, const Geo& g, const Launch& L, int nrhs,
-                  const c128* x, c128* y, const double* k2, const double* kb, double sr, double si,
+                  const cx<TX>* x, c128* y, const double* k2, const double* kb, double sr, double si,
                   const c128* aux, double* part, long long nblk_max, const RhsState* st, int gate);
 void launch_init(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs, const c128* b,
                  c128* x, c128* r, c128* rhat, c128* p, c128* v, const double* k2, const double* kb,
@@ -69,12 +71,16 @@ bool mg_tail_allow_lds(size_t bytes);
 template <typename R>
 void launch_mg_tail(hipStream_t s, int bc, const TailDesc& D, int nrhs, const cx<R>* b_first,
                     cx<R>* e_first, const RhsState* st, int gate);
+// p_low / s_low (may be null): a complex64 copy of the new p / s for a
+// single-precision preconditioner
 void launch_p_update(hipStream_t s, long long n, int nrhs, c128* p, const c128* r, const c128* v,
-                     const RhsState* st, const Launch& L);
+                     c64* p_low, const RhsState* st, const Launch& L);
 void launch_s_update(hipStream_t s, long long n, int nrhs, c128* sv, const c128* r, const c128* v,
-                     const RhsState* st, double* part, long long nblk_max, const Launch& L);
-void launch_update_xr(hipStream_t s, long long n, int nrhs, c128* x, c128* r, const c128* ph,
-                      const c128* sh, const c128* sv, const c128* t, const c128* rhat,
+                     c64* s_low, const RhsState* st, double* part, long long nblk_max, const Launch& L);
+// p_hat, s_hat: complex128, or complex64 from a single-precision preconditioner
+template <typename TH>
+void launch_update_xr(hipStream_t s, long long n, int nrhs, c128* x, c128* r, const cx<TH>* ph,
+                      const cx<TH>* sh, const c128* sv, const c128* t, const c128* rhat,
                       const RhsState* st, double* part, long long nblk_max, const Launch& L);
 void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const double* part,
                      long long nblk, long long nblk_max, double tol);

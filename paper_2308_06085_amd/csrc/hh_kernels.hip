@@ -284,13 +284,15 @@ __global__ __launch_bounds__(1024) void k_finalize(int mode, RhsState* st, const
 }
 
 // ---------------------------------------------------------------------------
-// Operator apply, complex128.  MODE selects the fused epilogue:
+// Operator apply in complex128 arithmetic; the input x is complex128 or, for
+// the single-precision preconditioner's outputs, complex64 (converted exactly
+// on load).  MODE selects the fused epilogue:
 //   OP_PLAIN : y = Op x
 //   OP_V     : y = A x, partials Re/Im sum conj(rhat) y          (slot V)
 //   OP_T     : y = A x, partials Re/Im sum conj(y) s, sum |y|^2   (slot T)
 // ---------------------------------------------------------------------------
-template <int BC, int MODE>
-__global__ __launch_bounds__(512) void k_apply(Geo g, int zb, const c128* __restrict__ x,
+template <int BC, int MODE, typename TX>
+__global__ __launch_bounds__(512) void k_apply(Geo g, int zb, const cx<TX>* __restrict__ x,
                                                c128* __restrict__ y, const double* __restrict__ k2,
                                                const double* __restrict__ kb, double sr, double si,
                                                const c128* __restrict__ aux, double* __restrict__ part,
@@ -304,14 +306,14 @@ __global__ __launch_bounds__(512) void k_apply(Geo g, int zb, const c128* __rest
     const double ih2 = 1.0 / (g.h * g.h);
     const double two_over_h = 2.0 / g.h;
     const long long roff = (long long)r * g.n;
-    const c128* xr = x + roff;
+    const cx<TX>* xr = x + roff;
     c128* yr = y + roff;
     const long long col = (long long)q.j * g.nx + q.i;
     double acc[3] = {0.0, 0.0, 0.0};
     if (q.valid) {
         auto ldz = [&](int z) -> c128 {
             if (BC == BC_DIRICHLET && (z < 1 || z > g.nz - 2)) return czero<double>();
-            return xr[(long long)z * g.plane + col];
+            return cvt<double>(xr[(long long)z * g.plane + col]);
         };
         const bool bnd_col = BC == BC_DIRICHLET &&
                              (q.i == 0 || q.j == 0 || q.i == g.nx - 1 || q.j == g.ny - 1);
@@ -324,8 +326,8 @@ __global__ __launch_bounds__(512) void k_apply(Geo g, int zb, const c128* __rest
             if (BC == BC_DIRICHLET && (bnd_col || z == 0 || z == g.nz - 1)) {
                 out = czero<double>();
             } else {
-                const c128* pl = xr + (long long)z * g.plane;
-                auto ld = [&](int ii, int jj) -> c128 { return pl[(long long)jj * g.nx + ii]; };
+                const cx<TX>* pl = xr + (long long)z * g.plane;
+                auto ld = [&](int ii, int jj) -> c128 { return cvt<double>(pl[(long long)jj * g.nx + ii]); };
                 c128 s = inplane_sum<BC, double>(ld, q.i, q.j, g.nx, g.ny);
                 c128 zm = xm, zpv = xp;
                 if (BC == BC_SOMMERFELD) {
@@ -457,25 +459,31 @@ __global__ __launch_bounds__(512) void k_init(Geo g, int zb, const c128* __restr
 // Krylov vector updates (complex128), grid-stride over nodes with exactly the
 // fine-grid kernels' workgroup count per right-hand side: gridDim = (nblk, 1, nrhs).
 // ---------------------------------------------------------------------------
+template <bool LOW>
 __global__ __launch_bounds__(512) void k_p_update(long long n, c128* __restrict__ p,
                                                   const c128* __restrict__ rr,
-                                                  const c128* __restrict__ v, const RhsState* st) {
+                                                  const c128* __restrict__ v, c64* __restrict__ p_low,
+                                                  const RhsState* st) {
     const int r = blockIdx.z;
     if (st[r].status != ST_RUN) return;
     const c128 beta = st[r].beta, om = st[r].omega;
     const long long off = (long long)r * n;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        p[off + i] = rr[off + i] + beta * (p[off + i] - om * v[off + i]);
+        const c128 pv = rr[off + i] + beta * (p[off + i] - om * v[off + i]);
+        p[off + i] = pv;
+        if (LOW) p_low[off + i] = cvt<float>(pv);
     }
 }
 
 // s = r - alpha v and the partial sums of ||s||^2 (slot T, term 3) for the
 // half-step test.
+template <bool LOW>
 __global__ __launch_bounds__(512) void k_s_update(long long n, c128* __restrict__ s,
                                                   const c128* __restrict__ rr,
-                                                  const c128* __restrict__ v, const RhsState* st,
-                                                  double* __restrict__ part, long long nblk_max) {
+                                                  const c128* __restrict__ v, c64* __restrict__ s_low,
+                                                  const RhsState* st, double* __restrict__ part,
+                                                  long long nblk_max) {
     const int r = blockIdx.z;
     if (st[r].status != ST_RUN) return;
     const c128 al = st[r].alpha;
@@ -485,6 +493,7 @@ __global__ __launch_bounds__(512) void k_s_update(long long n, c128* __restrict_
          i += (long long)gridDim.x * blockDim.x) {
         c128 sv = rr[off + i] - al * v[off + i];
         s[off + i] = sv;
+        if (LOW) s_low[off + i] = cvt<float>(sv);
         acc[0] += abs2(sv);
     }
     block_sum_store<1>(acc, part + part_index(r, SLOT_T, 3, nblk_max) + blockIdx.x, nblk_max);
@@ -493,10 +502,11 @@ __global__ __launch_bounds__(512) void k_s_update(long long n, c128* __restrict_
 // Iterating right-hand sides: x += alpha p_hat + omega s_hat; r = s - omega t;
 // partials ||r||^2, r_hat^H r.  Right-hand sides that stopped at the half step:
 // x += alpha p_hat (the next FIN_RHO marks them converged).
+template <typename TH>
 __global__ __launch_bounds__(512) void k_update_xr(long long n, c128* __restrict__ x,
                                                    c128* __restrict__ rr,
-                                                   const c128* __restrict__ ph,
-                                                   const c128* __restrict__ sh,
+                                                   const cx<TH>* __restrict__ ph,
+                                                   const cx<TH>* __restrict__ sh,
                                                    const c128* __restrict__ s,
                                                    const c128* __restrict__ t,
                                                    const c128* __restrict__ rhat, const RhsState* st,
@@ -509,13 +519,13 @@ __global__ __launch_bounds__(512) void k_update_xr(long long n, c128* __restrict
     if (status == ST_HALF) {
         for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
              i += (long long)gridDim.x * blockDim.x)
-            x[off + i] = x[off + i] + al * ph[off + i];
+            x[off + i] = x[off + i] + al * cvt<double>(ph[off + i]);
         return;
     }
     double acc[3] = {0.0, 0.0, 0.0};
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        x[off + i] = x[off + i] + al * ph[off + i] + om * sh[off + i];
+        x[off + i] = x[off + i] + al * cvt<double>(ph[off + i]) + om * cvt<double>(sh[off + i]);
         c128 rv = s[off + i] - om * t[off + i];
         rr[off + i] = rv;
         acc[0] += abs2(rv);
@@ -656,12 +666,13 @@ static inline unsigned flat_blocks(long long n, int block, int cap) {
     return (unsigned)b;
 }
 
+template <typename TX>
 void launch_apply(hipStream_t s, int bc, int mode, const Geo& g, const Launch& L, int nrhs,
-                  const c128* x, c128* y, const double* k2, const double* kb, double sr, double si,
+                  const cx<TX>* x, c128* y, const double* k2, const double* kb, double sr, double si,
                   const c128* aux, double* part, long long nblk_max, const RhsState* st, int gate) {
     dim3 grid = grid_fine(g, L, nrhs);
-#define HH_APPLY(BCV, MV)                                                                         \
-    hipLaunchKernelGGL((k_apply<BCV, MV>), grid, dim3(L.block), 0, s, g, L.zb, x, y, k2, kb, sr, si, \
+#define HH_APPLY(BCV, MV)                                                                             \
+    hipLaunchKernelGGL((k_apply<BCV, MV, TX>), grid, dim3(L.block), 0, s, g, L.zb, x, y, k2, kb, sr, si, \
                        aux, part, nblk_max, st, gate)
     if (bc == BC_SOMMERFELD) {
         if (mode == OP_PLAIN) HH_APPLY(BC_SOMMERFELD, OP_PLAIN);
@@ -674,6 +685,12 @@ void launch_apply(hipStream_t s, int bc, int mode, const Geo& g, const Launch& L
     }
 #undef HH_APPLY
 }
+template void launch_apply<double>(hipStream_t, int, int, const Geo&, const Launch&, int, const c128*,
+                                   c128*, const double*, const double*, double, double, const c128*,
+                                   double*, long long, const RhsState*, int);
+template void launch_apply<float>(hipStream_t, int, int, const Geo&, const Launch&, int, const c64*,
+                                  c128*, const double*, const double*, double, double, const c128*,
+                                  double*, long long, const RhsState*, int);
 
 void launch_init(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs, const c128* b,
                  c128* x, c128* r, c128* rhat, c128* p, c128* v, const double* k2, const double* kb,
@@ -688,21 +705,33 @@ void launch_init(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs,
 }
 
 void launch_p_update(hipStream_t s, long long n, int nrhs, c128* p, const c128* r, const c128* v,
-                     const RhsState* st, const Launch& L) {
-    hipLaunchKernelGGL(k_p_update, dim3(L.flat_cap, 1, nrhs), dim3(L.block),
-                       0, s, n, p, r, v, st);
+                     c64* p_low, const RhsState* st, const Launch& L) {
+    const dim3 grid(L.flat_cap, 1, nrhs);
+    if (p_low) hipLaunchKernelGGL(k_p_update<true>, grid, dim3(L.block), 0, s, n, p, r, v, p_low, st);
+    else hipLaunchKernelGGL(k_p_update<false>, grid, dim3(L.block), 0, s, n, p, r, v, p_low, st);
 }
 void launch_s_update(hipStream_t s, long long n, int nrhs, c128* sv, const c128* r, const c128* v,
-                     const RhsState* st, double* part, long long nblk_max, const Launch& L) {
-    hipLaunchKernelGGL(k_s_update, dim3(L.flat_cap, 1, nrhs), dim3(L.block), 0, s, n, sv, r, v, st, part,
-                       nblk_max);
+                     c64* s_low, const RhsState* st, double* part, long long nblk_max, const Launch& L) {
+    const dim3 grid(L.flat_cap, 1, nrhs);
+    if (s_low)
+        hipLaunchKernelGGL(k_s_update<true>, grid, dim3(L.block), 0, s, n, sv, r, v, s_low, st, part, nblk_max);
+    else
+        hipLaunchKernelGGL(k_s_update<false>, grid, dim3(L.block), 0, s, n, sv, r, v, s_low, st, part,
+                           nblk_max);
 }
-void launch_update_xr(hipStream_t s, long long n, int nrhs, c128* x, c128* r, const c128* ph,
-                      const c128* sh, const c128* sv, const c128* t, const c128* rhat,
+template <typename TH>
+void launch_update_xr(hipStream_t s, long long n, int nrhs, c128* x, c128* r, const cx<TH>* ph,
+                      const cx<TH>* sh, const c128* sv, const c128* t, const c128* rhat,
                       const RhsState* st, double* part, long long nblk_max, const Launch& L) {
-    hipLaunchKernelGGL(k_update_xr, dim3(L.flat_cap, 1, nrhs), dim3(L.block), 0, s, n, x, r, ph, sh, sv, t,
-                       rhat, st, part, nblk_max);
+    hipLaunchKernelGGL(k_update_xr<TH>, dim3(L.flat_cap, 1, nrhs), dim3(L.block), 0, s, n, x, r, ph, sh, sv,
+                       t, rhat, st, part, nblk_max);
 }
+template void launch_update_xr<double>(hipStream_t, long long, int, c128*, c128*, const c128*, const c128*,
+                                       const c128*, const c128*, const c128*, const RhsState*, double*,
+                                       long long, const Launch&);
+template void launch_update_xr<float>(hipStream_t, long long, int, c128*, c128*, const c64*, const c64*,
+                                      const c128*, const c128*, const c128*, const RhsState*, double*,
+                                      long long, const Launch&);
 void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const double* part,
                      long long nblk, long long nblk_max, double tol) {
     hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(1024), 0, s, mode, st, part, nblk, nblk_max, tol);

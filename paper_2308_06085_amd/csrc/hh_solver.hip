@@ -58,6 +58,9 @@ struct hh_ctx {
     double* kb = nullptr;
     c128 *bsrc = nullptr, *xk = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr,
          *s = nullptr, *t = nullptr, *ph = nullptr, *sh = nullptr;
+    // single-precision preconditioner: complex64 copies of p and s (its inputs);
+    // ph / sh then hold its complex64 outputs
+    c64 *p_low = nullptr, *s_low = nullptr;
     RhsState* st = nullptr;
     RhsState* st_host = nullptr;  // pinned
     double* part = nullptr;
@@ -162,7 +165,7 @@ void free_all(hh_ctx* c) {
     }
     c->lv.clear();
     void* ptrs[] = {c->k2, c->kb, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->s, c->t,
-                    c->ph, c->sh, c->st, c->part, c->bad, c->cidx, c->minv};
+                    c->ph, c->sh, c->p_low, c->s_low, c->st, c->part, c->bad, c->cidx, c->minv};
     for (void* q : ptrs) (void)hipFree(q);
     if (c->st_host) (void)hipHostFree(c->st_host);
     if (c->bad_host) (void)hipHostFree(c->bad_host);
@@ -251,10 +254,11 @@ void apply_launch(hh_ctx* c) {
 }
 
 // -------------------------------------------------------------------------
-// V-cycle enqueue: z = V(bin) on level 0 input/output of complex128.
+// V-cycle enqueue: z = V(bin) in precision R; level-0 input of type TB and
+// output of type TO (complex128, or complex64 inside the mixed solve).
 // -------------------------------------------------------------------------
-template <typename R>
-void enqueue_vcycle_t(hh_ctx* c, hipStream_t s, int nrhs, const c128* bin, c128* bout,
+template <typename R, typename TB, typename TO>
+void enqueue_vcycle_t(hh_ctx* c, hipStream_t s, int nrhs, const cx<TB>* bin, cx<TO>* bout,
                       const RhsState* st, int gate) {
     const int bc = c->cfg.bc;
     const int T = c->tail_first;
@@ -263,8 +267,8 @@ void enqueue_vcycle_t(hh_ctx* c, hipStream_t s, int nrhs, const c128* bin, c128*
     auto K = [](void* p) { return reinterpret_cast<const R*>(p); };
     LevelBuf& f = c->lv[0];
     // down: one fused pass per level writes the next level's right-hand side
-    launch_mg_down<double, R>(s, bc, f.g, c->lv[1].g, f.zb_down, nrhs, bin, f.g.n, K(f.k2l), P,
-                              C(c->lv[1].b), st, gate);
+    launch_mg_down<TB, R>(s, bc, f.g, c->lv[1].g, f.zb_down, nrhs, bin, f.g.n, K(f.k2l), P,
+                          C(c->lv[1].b), st, gate);
     for (int l = 1; l < T; ++l) {
         LevelBuf& a = c->lv[l];
         LevelBuf& n = c->lv[l + 1];
@@ -279,20 +283,24 @@ void enqueue_vcycle_t(hh_ctx* c, hipStream_t s, int nrhs, const c128* bin, c128*
         launch_mg_up<R, R, R>(s, bc, a.g, n.g, a.zb_up, nrhs, C(a.b), a.g.n, K(a.k2l), P, C(n.e), C(a.e),
                               a.g.n, st, gate);
     }
-    launch_mg_up<double, R, double>(s, bc, f.g, c->lv[1].g, f.zb_up, nrhs, bin, f.g.n, K(f.k2l), P,
-                                    C(c->lv[1].e), bout, f.g.n, st, gate);
+    launch_mg_up<TB, R, TO>(s, bc, f.g, c->lv[1].g, f.zb_up, nrhs, bin, f.g.n, K(f.k2l), P,
+                            C(c->lv[1].e), bout, f.g.n, st, gate);
 }
 
+// complex128 in and out (the standalone V-cycle and the FP64 solve)
 void enqueue_vcycle(hh_ctx* c, hipStream_t s, int nrhs, const c128* bin, c128* bout,
                     const RhsState* st, int gate) {
-    if (c->mixed) enqueue_vcycle_t<float>(c, s, nrhs, bin, bout, st, gate);
-    else enqueue_vcycle_t<double>(c, s, nrhs, bin, bout, st, gate);
+    if (c->mixed) enqueue_vcycle_t<float, double, double>(c, s, nrhs, bin, bout, st, gate);
+    else enqueue_vcycle_t<double, double, double>(c, s, nrhs, bin, bout, st, gate);
 }
 
-// One Bi-CGSTAB step for all right-hand sides still iterating (device-side
-// scalars).  A right-hand side that meets the tolerance at the half step gets
-// x += alpha p_hat in the x / r update and is marked converged by the next FIN_RHO.
-void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs) {
+// One step of the iteration; the mixed solve keeps the preconditioner's inputs
+// and outputs in complex64.  Its results are those of complex128 inputs and
+// outputs bit for bit: the preconditioner rounds its input to complex64 on
+// entry, and its output is a complex64 value either way.
+template <typename TH>
+void enqueue_iteration_t(hh_ctx* c, hipStream_t s, int nrhs, cx<TH>* ph, cx<TH>* sh, c64* p_low,
+                         c64* s_low) {
     const Geo& g = c->lv[0].g;
     const long long n = g.n;
     const long long nb = c->nblk0;
@@ -300,18 +308,31 @@ void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs) {
     Launch F = c->L0;
     F.flat_cap = (int)nb;  // flat kernels use exactly nblk0 workgroups: same partial count
     launch_finalize(s, FIN_RHO, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
-    launch_p_update(s, n, nrhs, c->p, c->r, c->v, c->st, F);
-    enqueue_vcycle(c, s, nrhs, c->p, c->ph, c->st, ST_RUN);
-    launch_apply(s, bc, OP_V, g, c->L0, nrhs, c->ph, c->v, c->k2, c->kb, 1.0, 0.0, c->rhat, c->part,
-                 NBLK_CAP, c->st, ST_RUN);
+    constexpr bool low = sizeof(TH) == sizeof(float);
+    launch_p_update(s, n, nrhs, c->p, c->r, c->v, p_low, c->st, F);
+    if constexpr (low) enqueue_vcycle_t<float, float, float>(c, s, nrhs, p_low, ph, c->st, ST_RUN);
+    else enqueue_vcycle(c, s, nrhs, c->p, ph, c->st, ST_RUN);
+    launch_apply(s, bc, OP_V, g, c->L0, nrhs, ph, c->v, c->k2, c->kb, 1.0, 0.0, c->rhat, c->part, NBLK_CAP,
+                 c->st, ST_RUN);
     launch_finalize(s, FIN_ALPHA, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
-    launch_s_update(s, n, nrhs, c->s, c->r, c->v, c->st, c->part, NBLK_CAP, F);
-    enqueue_vcycle(c, s, nrhs, c->s, c->sh, c->st, ST_RUN);
-    launch_apply(s, bc, OP_T, g, c->L0, nrhs, c->sh, c->t, c->k2, c->kb, 1.0, 0.0, c->s, c->part,
-                 NBLK_CAP, c->st, ST_RUN);
+    launch_s_update(s, n, nrhs, c->s, c->r, c->v, s_low, c->st, c->part, NBLK_CAP, F);
+    if constexpr (low) enqueue_vcycle_t<float, float, float>(c, s, nrhs, s_low, sh, c->st, ST_RUN);
+    else enqueue_vcycle(c, s, nrhs, c->s, sh, c->st, ST_RUN);
+    launch_apply(s, bc, OP_T, g, c->L0, nrhs, sh, c->t, c->k2, c->kb, 1.0, 0.0, c->s, c->part, NBLK_CAP,
+                 c->st, ST_RUN);
     launch_finalize(s, FIN_OMEGA, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
-    launch_update_xr(s, n, nrhs, c->xk, c->r, c->ph, c->sh, c->s, c->t, c->rhat, c->st, c->part,
-                     NBLK_CAP, F);
+    launch_update_xr<TH>(s, n, nrhs, c->xk, c->r, ph, sh, c->s, c->t, c->rhat, c->st, c->part, NBLK_CAP, F);
+}
+
+// One Bi-CGSTAB step for all right-hand sides still iterating (device-side
+// scalars).  A right-hand side that meets the tolerance at the half step gets
+// x += alpha p_hat in the x / r update and is marked converged by the next FIN_RHO.
+void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs) {
+    if (c->mixed)
+        enqueue_iteration_t<float>(c, s, nrhs, reinterpret_cast<c64*>(c->ph), reinterpret_cast<c64*>(c->sh),
+                                   c->p_low, c->s_low);
+    else
+        enqueue_iteration_t<double>(c, s, nrhs, c->ph, c->sh, nullptr, nullptr);
 }
 
 hh_status get_graph(hh_ctx* c, int nrhs, hipGraphExec_t* out) {
@@ -544,6 +565,10 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
         if (s != HH_OK) return bail(s);
     }
     hh_status s;
+    if (c->mixed) {
+        if ((s = dalloc(c, &c->p_low, sizeof(c64) * n0 * R)) != HH_OK) return bail(s);
+        if ((s = dalloc(c, &c->s_low, sizeof(c64) * n0 * R)) != HH_OK) return bail(s);
+    }
     if ((s = dalloc(c, &c->k2, sizeof(double) * n0)) != HH_OK) return bail(s);
     if ((s = dalloc(c, &c->kb, sizeof(double) * n0)) != HH_OK) return bail(s);
     if ((s = dalloc(c, &c->st, sizeof(RhsState) * R)) != HH_OK) return bail(s);
@@ -888,28 +913,34 @@ void launch_one_fine(hh_ctx* c, int which, int nrhs) {
     F.flat_cap = (int)c->nblk0;
     auto C = [](void* p) { return reinterpret_cast<cx<R>*>(p); };
     const R* k2l = reinterpret_cast<const R*>(f.k2l);
+    // the preconditioner's fine-level inputs and outputs: complex64 in the mixed solve
+    const cx<R>* pin =
+        c->mixed ? reinterpret_cast<const cx<R>*>(c->p_low) : reinterpret_cast<const cx<R>*>(c->p);
+    cx<R>* phat = reinterpret_cast<cx<R>*>(c->ph);
+    const cx<R>* shat = reinterpret_cast<const cx<R>*>(c->sh);
+    c64* p_low = c->mixed ? c->p_low : nullptr;
+    c64* s_low = c->mixed ? c->s_low : nullptr;
     switch (which) {
         case 0:
-            launch_apply(s, bc, OP_T, g, c->L0, nrhs, c->sh, c->t, c->k2, c->kb, 1.0, 0.0, c->s, c->part,
+            launch_apply(s, bc, OP_T, g, c->L0, nrhs, shat, c->t, c->k2, c->kb, 1.0, 0.0, c->s, c->part,
                          NBLK_CAP, c->st, ST_RUN);
             break;
         case 1:
-            launch_update_xr(s, g.n, nrhs, c->xk, c->r, c->ph, c->sh, c->s, c->t, c->rhat, c->st, c->part,
-                             NBLK_CAP, F);
+            launch_update_xr<R>(s, g.n, nrhs, c->xk, c->r, phat, shat, c->s, c->t, c->rhat, c->st, c->part,
+                                NBLK_CAP, F);
             break;
         case 2:
-            launch_mg_down<double, R>(s, bc, g, g1, f.zb_down, nrhs, c->p, g.n, k2l, P, C(c->lv[1].b), c->st,
-                                      ST_RUN);
+            launch_mg_down<R, R>(s, bc, g, g1, f.zb_down, nrhs, pin, g.n, k2l, P, C(c->lv[1].b), c->st, ST_RUN);
             break;
         case 3:
-            launch_mg_up<double, R, double>(s, bc, g, g1, f.zb_up, nrhs, c->p, g.n, k2l, P, C(c->lv[1].e),
-                                            c->ph, g.n, c->st, ST_RUN);
+            launch_mg_up<R, R, R>(s, bc, g, g1, f.zb_up, nrhs, pin, g.n, k2l, P, C(c->lv[1].e), phat, g.n,
+                                  c->st, ST_RUN);
             break;
         case 4:
-            launch_p_update(s, g.n, nrhs, c->p, c->r, c->v, c->st, F);
+            launch_p_update(s, g.n, nrhs, c->p, c->r, c->v, p_low, c->st, F);
             break;
         default:
-            launch_s_update(s, g.n, nrhs, c->s, c->r, c->v, c->st, c->part, NBLK_CAP, F);
+            launch_s_update(s, g.n, nrhs, c->s, c->r, c->v, s_low, c->st, c->part, NBLK_CAP, F);
             break;
     }
 }
@@ -929,6 +960,8 @@ hh_status hh_time_kernel(hh_ctx* c, int which, int nrhs, int reps, float* ms_avg
     const size_t vb = sizeof(c128) * (size_t)g.n * nrhs;
     for (c128* q : {c->xk, c->r, c->rhat, c->p, c->v, c->s, c->t, c->ph, c->sh})
         HIPCHK(c, hipMemsetAsync(q, 0x3f, vb, c->stream));
+    for (c64* q : {c->p_low, c->s_low})
+        if (q) HIPCHK(c, hipMemsetAsync(q, 0x3f, vb / 2, c->stream));
     launch_fill_status(c->stream, nrhs, c->st, ST_RUN, 1 << 30, -1.0);
     auto one = [&]() {
         if (c->mixed) launch_one_fine<float>(c, which, nrhs);
