@@ -307,8 +307,13 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
 // owns one node of the tile-plus-halo region; the lanes inside the halo
 // compute the output.  The workgroup marches over `zb` planes.
 // ---------------------------------------------------------------------------
+// Waves per SIMD the up pass is compiled for: three 512-lane workgroups per CU
+// in single precision (<= 80 VGPRs), two in double (<= 128 VGPRs).
+template <typename R>
+constexpr int UP_WAVES_PER_SIMD = sizeof(R) == sizeof(float) ? 6 : 4;
+
 template <int BC, typename TB, typename R, typename TO, bool ONE>
-__global__ __launch_bounds__(UP_LANES) void k_mg_up(Geo g, Geo gc, int zb,
+__global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g, Geo gc, int zb,
                                                     const cx<TB>* __restrict__ b, long long b_rstride,
                                                     const R* __restrict__ k2l, double beta1,
                                                     double beta2, double omega,
@@ -394,12 +399,14 @@ __global__ __launch_bounds__(UP_LANES) void k_mg_up(Geo g, Geo gc, int zb,
 
     cx<TO>* orr = out + (long long)r * o_rstride;
     const long long ooff = own ? (long long)gyr * g.nx + gxr : 0;
-    // u3 of plane z at the output lanes, from the u2 ring and this lane's u2, b, c
+    // u3 of plane z at the output lanes, from the u2 ring and this lane's u2, b, c.
+    // Past the bottom / top plane the stencil reads the mirror image, plane 1 /
+    // nz - 2 (the eliminated ghost point), whose u2 is already in the ring.
     auto emit = [&](int z, const cx<R>& u, const cx<R>& c, const cx<TB>& bz) {
         if (own) {
-            const cx<R>* um = us[ring3(z - 1)];
+            const cx<R>* um = us[ring3(z == 0 ? 1 : z - 1)];
             const cx<R>* uc = us[ring3(z)];
-            const cx<R>* up = us[ring3(z + 1)];
+            const cx<R>* up = us[ring3(z == g.nz - 1 ? g.nz - 2 : z + 1)];
             cx<R> lap = (u - uc[t - 1]) + (u - uc[t + 1]);
             lap = lap + (u - uc[t - RW]);
             lap = lap + (u - uc[t + RW]);
@@ -427,23 +434,81 @@ __global__ __launch_bounds__(UP_LANES) void k_mg_up(Geo g, Geo gc, int zb,
         __syncthreads();
         emit(z0, u_cur, c_cur, w2.b);
     } else {
-        // the first two planes are loaded together; in the march one plane is in flight
-        fetch(z0 - 1, w);
-        fetch(z0, w2);
-        (void)make_u2(z0 - 1, w, c_unused);
-        fetch(z0 + 1, w);
-        b_cur = w2.b;
-        u_cur = make_u2(z0, w2, c_cur);
-        for (int z = z0; z < z1; ++z) {
-            b_nxt = w.b;
-            const cx<R> u_nxt = make_u2(z + 1, w, c_nxt);
-            fetch(z + 2, w);
+        // March over the u2 planes z0 - 1 .. z1 clamped into the grid (the
+        // output step reads a mirrored plane's image instead), two planes of
+        // loads in flight.  Plane f interpolates between coarse planes
+        // c0 = f >> 1 and c1 = c0 + (f & 1): only c1 is loaded, the in-plane
+        // interpolation on c0 is the previous plane's (the same plane for even f).
+        const int plo = max(z0 - 1, 0), phi = min(z1, g.nz - 1);
+        struct RawC {
+            cx<TB> b;
+            R k;
+            cx<R> e[4];
+        };
+        auto fetch_c = [&](int f, RawC& v) {
+            const int fc = min(max(f, plo), phi);
+            const long long base = (long long)fc * g.plane;
+            const cx<R>* e1 = er + (long long)((fc >> 1) + (fc & 1)) * gc.plane;
+            v.b = br[base + uoff];
+            v.k = k2l[base + uoff];
+            v.e[0] = e1[cy0 + cx0];
+            v.e[1] = e1[cy0 + cx1];
+            v.e[2] = e1[cy1 + cx0];
+            v.e[3] = e1[cy1 + cx1];
+        };
+        auto interp = [&](const cx<R>(&e)[4]) -> cx<R> {
+            const cx<R> p0 = ax * e[0] + bx * e[1];
+            const cx<R> p1 = ax * e[2] + bx * e[3];
+            return ay * p0 + by * p1;
+        };
+        cx<R> carry;  // in-plane interpolation on the previous plane's c1
+        auto make_c = [&](int f, const RawC& v, cx<R>& c_out) -> cx<R> {
+            const int fc = min(max(f, plo), phi);
+            const int zf = (fc == 0) + (fc == g.nz - 1);
+            const R wz = (fc & 1) ? R(0.5) : R(1), bz = R(1) - wz;
+            const cx<R> pn = interp(v.e);
+            const cx<R> pe = wz * ((fc & 1) ? carry : pn) + bz * pn;
+            carry = pn;
+            const int nf = BC == BC_SOMMERFELD ? unf + zf : 0;
+            c_out = shift_c(L, v.k, nf);
+            cx<R> u = jacobi_w(L, c_out) * cvt<R>(v.b) + pe;
+            if (BC == BC_DIRICHLET && (unf || zf)) u = czero<R>();
+            us[ring3(f)][t] = u;  // unguarded: lanes past the region write slots never read
+            return u;
+        };
+        auto step = [&](int z, RawC& v) {
+            b_nxt = v.b;
+            const cx<R> u_nxt = make_c(z + 1, v, c_nxt);
+            fetch_c(z + 3, v);
             __syncthreads();
             emit(z, u_cur, c_cur, b_cur);
             u_cur = u_nxt;
             c_cur = c_nxt;
             b_cur = b_nxt;
             __syncthreads();
+        };
+        // set A holds the planes z0 - 1 + even, set B the odd ones
+        RawC A, B;
+        cx<R> e_first[4];  // coarse plane c0 of the first plane
+        {
+            const cx<R>* e0 = er + (long long)(plo >> 1) * gc.plane;
+            e_first[0] = e0[cy0 + cx0];
+            e_first[1] = e0[cy0 + cx1];
+            e_first[2] = e0[cy1 + cx0];
+            e_first[3] = e0[cy1 + cx1];
+        }
+        fetch_c(z0 - 1, A);
+        fetch_c(z0, B);
+        carry = interp(e_first);
+        (void)make_c(z0 - 1, A, c_unused);
+        fetch_c(z0 + 1, A);
+        b_cur = B.b;
+        u_cur = make_c(z0, B, c_cur);
+        fetch_c(z0 + 2, B);
+        for (int z = z0; z < z1; z += 2) {
+            step(z, A);
+            if (z + 1 >= z1) break;
+            step(z + 1, B);
         }
     }
 }
