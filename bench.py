@@ -13,10 +13,14 @@ solve is timed the same way and reported under ``fp64``.
 DoF-iterations/s = unknowns x Bi-CGSTAB iterations (half step = 0.5, summed
 over right-hand sides) / solve time.
 
-``roofline`` reports the kernel with the largest share of an iteration,
-timed with HIP events on the solver's stream by ``hh_time_kernel`` (the same
-launch shape as inside the solve); ``achieved`` = its algorithmic bytes per
-launch / its average duration, against 8 TB/s HBM3E peak.
+``roofline`` reports the kernel with the largest share of an iteration.  After
+the timed solves the same number of solves of the same workload run with the
+library's event tracing on: HIP events on the solver's stream around every
+fine-level launch of every step (the steps launched directly instead of
+replayed as a graph; only check windows in which every right-hand side kept
+iterating count).  ``achieved`` = the kernel's algorithmic bytes per launch /
+its average launch duration there, against 8 TB/s HBM3E peak; ``avg_ms`` and
+``launches`` are that average and the number of launches behind it.
 ``cpu_baseline`` times the CPU oracle on a bounded sample (a few Bi-CGSTAB
 steps of the same workload) on the host.
 """
@@ -133,13 +137,21 @@ def true_relres(wl, x, nodes):
     return out
 
 
-def kernel_roofline(solver, nrhs, prec_idx, n_nodes, reps=20):
+def kernel_roofline(solver, nrhs, prec_idx, n_nodes, x, solves):
+    """Per-kernel average launch duration inside real solves of the workload:
+    `solves` solves with the library's event tracing on (HIP events on the
+    solver's stream around every fine-level launch, steps launched directly
+    instead of replayed as a graph), then algorithmic bytes / duration."""
+    solver.set_option("trace", 1)
+    for _ in range(solves):
+        solver.solve(rtol=1e-6, out=x)
+    ms, cnt = solver.kernel_times()
+    solver.set_option("trace", 0)
     rows = {}
     for kid, (name, per_iter, nbytes) in KERNELS.items():
-        ms = solver.time_kernel(kid, nrhs=nrhs, reps=reps)
         algo = nbytes[prec_idx] * n_nodes * nrhs
-        rows[name] = {"ms": ms, "per_iter": per_iter, "bytes": int(algo),
-                      "GBs": algo / (ms * 1e-3) / 1e9}
+        rows[name] = {"ms": ms[kid], "launches": cnt[kid], "per_iter": per_iter, "bytes": int(algo),
+                      "GBs": algo / (ms[kid] * 1e-3) / 1e9 if ms[kid] > 0 else None}
     dom = max(rows, key=lambda k: rows[k]["ms"] * rows[k]["per_iter"])
     return dom, rows
 
@@ -206,13 +218,14 @@ def main():
 
     log = (lambda *a: print(*a, file=sys.stderr, flush=True)) if args.verbose else (lambda *a: None)
     results = {}
+    solutions = {}
     for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
         s = make(prec)
         x, stats, times, iters = run_solves(s, args.steps, args.warmup)
         t = float(np.sum(times))
         it = float(np.mean(iters))
         rel = true_relres(wl, x, nodes) if args.workload != "cube513" else [s_.relres_true for s_ in stats]
-        dom, rows = kernel_roofline(s, nrhs, 0 if prec == "fp64" else 1, n_nodes)
+        dom, rows = kernel_roofline(s, nrhs, 0 if prec == "fp64" else 1, n_nodes, x, max(1, args.steps))
         results[prec] = {
             "value": dof(wl) * float(np.sum(iters)) / t,
             "ms_per_step": 1e3 * t / args.steps,
@@ -225,8 +238,24 @@ def main():
         }
         log(prec, json.dumps(results[prec]))
         s.close()
+        solutions[prec] = x
         del x
         torch.cuda.empty_cache()
+    # error of each solution against a tight FP64 solve (relative 2-norm, worst
+    # right-hand side), outside the timed region
+    ref_err = None
+    if not args.no_fp64:
+        s = make("fp64")
+        xr, _ = s.solve(rtol=1e-10, maxit=20000)
+        ref_err = {"ref_rtol": 1e-10}
+        for prec, xs in solutions.items():
+            e = [float(torch.linalg.vector_norm(xs[i] - xr[i]) / torch.linalg.vector_norm(xr[i]))
+                 for i in range(nrhs)]
+            ref_err[prec] = max(e)
+        s.close()
+        del xr
+    solutions.clear()
+    torch.cuda.empty_cache()
 
     head = results["mixed"]
     dom = head["dominant"]
@@ -254,15 +283,22 @@ def main():
         "relres_true_max": head["relres_true_max"],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": row["GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": row["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": row["bytes"], "avg_ms": row["ms"]},
-        "kernels_mixed": {k_: {"ms": v["ms"], "GBs": round(v["GBs"], 1)} for k_, v in head["kernels"].items()},
+                     "algorithmic_bytes_per_launch": row["bytes"], "avg_ms": row["ms"],
+                     "launches": row["launches"]},
+        "kernels_mixed": {k_: {"ms": v["ms"], "GBs": v["GBs"] and round(v["GBs"], 1)}
+                          for k_, v in head["kernels"].items()},
     }
     if "fp64" in results:
         f = results["fp64"]
         line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "iterations": f["iterations"],
                         "relres_true_max": f["relres_true_max"], "dominant": f["dominant"],
-                        "kernels": {k_: {"ms": v["ms"], "GBs": round(v["GBs"], 1)} for k_, v in f["kernels"].items()}}
+                        "kernels": {k_: {"ms": v["ms"], "GBs": v["GBs"] and round(v["GBs"], 1)}
+                                    for k_, v in f["kernels"].items()}}
         line["mixed_speedup_time_to_solution"] = f["ms_per_step"] / head["ms_per_step"]
+        line["mixed_speedup_per_iteration"] = ((f["ms_per_step"] / f["iterations"])
+                                               / (head["ms_per_step"] / head["iterations"]))
+    if ref_err is not None:
+        line["error_vs_fp64_reference"] = ref_err
     if not args.no_cpu and args.workload != "cube513":
         line["cpu_baseline"] = cpu_baseline(wl, nodes, args.cpu_iters)
     print(json.dumps(line), flush=True)

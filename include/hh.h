@@ -160,7 +160,8 @@ hh_status hh_grad_slowness2(hh_ctx* ctx, const void* u, const void* w, const dou
  * default 1), "check_every" (steps between host convergence checks, default 4),
  * "block" (threads per workgroup of the stencil kernels: 64, 128, 256, 512;
  * default 512), "zb" (z-planes per workgroup of the stencil kernels, default 2,
- * 0 = automatic), "zb_down" / "zb_up" (z-planes per workgroup of the finest
+ * 0 = automatic), "trace" (1 = time the fine-level kernels of every solve with
+ * HIP events, see hh_kernel_times), "zb_down" / "zb_up" (z-planes per workgroup of the finest
  * level's multigrid down / up pass, 0 = automatic), "zb_down:<l>" / "zb_up:<l>"
  * (the same for level l, 0 <= l < n_levels - 1; levels run by the single-workgroup
  * tail kernel ignore it).  A level outside that range is HH_ERR_ARG.
@@ -181,6 +182,21 @@ hh_status hh_get_option(const hh_ctx* ctx, const char* name, long long* value);
  * The context's Krylov vectors are first filled with finite nonzero data.
  * Requires hh_set_model.  Overwrites internal scratch only. */
 hh_status hh_time_kernel(hh_ctx* ctx, int which, int nrhs, int reps, float* ms_avg_host);
+
+/* In-solve kernel timing.  With hh_set_option(ctx, "trace", 1) (which also
+ * resets the sums) every following hh_solve launches its steps directly
+ * (no graph replay) with HIP events on the context stream around the
+ * fine-level kernels of each step that runs; "trace" 0 returns to graph
+ * replay.  Only check windows (check_every steps) through which every
+ * right-hand side kept iterating are counted, so each counted launch did the
+ * full work of all right-hand sides.  hh_kernel_times returns, per kernel id
+ * of hh_time_kernel (0 = the
+ * operator apply with its dot products, both launches of a step; 1 = x / r
+ * update; 2 / 3 = finest-level multigrid down / up pass, both V-cycles;
+ * 4 = p update; 5 = s update), the average duration in milliseconds of the
+ * traced launches since tracing was enabled and their number.  ms_avg and
+ * launches are host arrays of 6 entries. */
+hh_status hh_kernel_times(const hh_ctx* ctx, double* ms_avg, long long* launches);
 
 /* Sweep workgroup shapes of the fine-grid kernels for the current grid and
  * keep the fastest (by HIP-event timing on the context stream). */

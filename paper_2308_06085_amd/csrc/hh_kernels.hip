@@ -308,57 +308,79 @@ __global__ __launch_bounds__(512) void k_apply(Geo g, int zb, const cx<TX>* __re
     const long long roff = (long long)r * g.n;
     const cx<TX>* xr = x + roff;
     c128* yr = y + roff;
-    const long long col = (long long)q.j * g.nx + q.i;
+    const int i = q.i, j = q.j;  // a lane past the plane works on column (0, 0) and stores nothing
+    // In-plane neighbours: a Sommerfeld boundary reads the mirror image (the
+    // eliminated ghost point), a Dirichlet one a zero (the boundary values are
+    // not unknowns).  Every load is issued, from a valid node, before any
+    // arithmetic; a Dirichlet neighbour on the boundary is selected away.
+    const int im = i > 0 ? i - 1 : 1, ip = i < g.nx - 1 ? i + 1 : g.nx - 2;
+    const int jm = j > 0 ? j - 1 : 1, jp = j < g.ny - 1 ? j + 1 : g.ny - 2;
+    const bool use_im = BC == BC_SOMMERFELD || i > 1, use_ip = BC == BC_SOMMERFELD || i < g.nx - 2;
+    const bool use_jm = BC == BC_SOMMERFELD || j > 1, use_jp = BC == BC_SOMMERFELD || j < g.ny - 2;
+    const int col = j * g.nx + i;
+    const int nf_col = (i == 0) + (i == g.nx - 1) + (j == 0) + (j == g.ny - 1);
+    auto ld = [&](int z, int c) -> c128 { return cvt<double>(xr[(long long)z * g.plane + c]); };
+    auto zmir = [&](int z) { return z < 0 ? 1 : (z > g.nz - 1 ? g.nz - 2 : z); };
     double acc[3] = {0.0, 0.0, 0.0};
-    if (q.valid) {
-        auto ldz = [&](int z) -> c128 {
-            if (BC == BC_DIRICHLET && (z < 1 || z > g.nz - 2)) return czero<double>();
-            return cvt<double>(xr[(long long)z * g.plane + col]);
-        };
-        const bool bnd_col = BC == BC_DIRICHLET &&
-                             (q.i == 0 || q.j == 0 || q.i == g.nx - 1 || q.j == g.ny - 1);
-        c128 xm = z0 > 0 ? ldz(z0 - 1) : czero<double>();
-        c128 xc = ldz(z0);
-        for (int z = z0; z < z1; ++z) {
-            c128 xp = z + 1 < g.nz ? ldz(z + 1) : czero<double>();
-            const long long idx = (long long)z * g.plane + col;
-            c128 out;
-            if (BC == BC_DIRICHLET && (bnd_col || z == 0 || z == g.nz - 1)) {
-                out = czero<double>();
-            } else {
-                const cx<TX>* pl = xr + (long long)z * g.plane;
-                auto ld = [&](int ii, int jj) -> c128 { return cvt<double>(pl[(long long)jj * g.nx + ii]); };
-                c128 s = inplane_sum<BC, double>(ld, q.i, q.j, g.nx, g.ny);
-                c128 zm = xm, zpv = xp;
-                if (BC == BC_SOMMERFELD) {
-                    if (z == 0) zm = xp;
-                    if (z == g.nz - 1) zpv = xm;
-                }
-                s = s + zm;
-                s = s + zpv;
-                const double kk = k2[idx];
-                c128 d = mk(6.0 * ih2 - sr * kk, -si * kk);
-                if (BC == BC_SOMMERFELD) {
-                    const int nf = faces(q.i, q.j, z, g.nx, g.ny, g.nz);
-                    if (nf) d.im -= nf * two_over_h * kb[idx];
-                }
-                out = d * xc - ih2 * s;
+    // planes in pairs: the loads of both planes (and of the column's planes
+    // below and above) are in flight together
+    for (int z = z0; z < z1; z += 2) {
+        // planes z and z + 1 (the second clamped into the grid, computed only if < z1);
+        // the column on planes z - 1 .. z + 2, mirrored at the ends
+        const int zs = min(z + 1, g.nz - 1);
+        c128 xcol[4], xin[2][4], aux_v[2];
+        double kk[2], kbv[2];
+        const int zc[4] = {zmir(z - 1), z, zmir(z + 1), zmir(z + 2)};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) xcol[m] = ld(zc[m], col);
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int zz = p == 0 ? z : zs;
+            xin[p][0] = ld(zz, j * g.nx + im);
+            xin[p][1] = ld(zz, j * g.nx + ip);
+            xin[p][2] = ld(zz, jm * g.nx + i);
+            xin[p][3] = ld(zz, jp * g.nx + i);
+            const long long idx = (long long)zz * g.plane + col;
+            kk[p] = k2[idx];
+            const int nf = nf_col + (zz == 0) + (zz == g.nz - 1);
+            // interior nodes all read kb[0] (one cache line): no branch around the load
+            kbv[p] = kb[nf ? idx : 0];
+            if (MODE != OP_PLAIN) aux_v[p] = aux[roff + idx];
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int zz = z + p;
+            if (zz >= z1) break;
+            const long long idx = (long long)zz * g.plane + col;
+            const c128 xc = xcol[p + 1];
+            c128 s = (use_im ? xin[p][0] : czero<double>()) + (use_ip ? xin[p][1] : czero<double>());
+            s = s + (use_jm ? xin[p][2] : czero<double>());
+            s = s + (use_jp ? xin[p][3] : czero<double>());
+            c128 zm = xcol[p], zpv = xcol[p + 2];
+            if (BC == BC_DIRICHLET) {
+                if (zz - 1 < 1) zm = czero<double>();
+                if (zz + 1 > g.nz - 2) zpv = czero<double>();
             }
-            yr[idx] = out;
-            if (MODE == OP_V) {
-                c128 rh = aux[roff + idx];
-                c128 t = cdot(rh, out);
-                acc[0] += t.re;
-                acc[1] += t.im;
-            } else if (MODE == OP_T) {
-                c128 sv = aux[roff + idx];
-                c128 t = cdot(out, sv);
-                acc[0] += t.re;
-                acc[1] += t.im;
-                acc[2] += abs2(out);
+            s = s + zm;
+            s = s + zpv;
+            c128 d = mk(6.0 * ih2 - sr * kk[p], -si * kk[p]);
+            const int nf = nf_col + (zz == 0) + (zz == g.nz - 1);
+            if (BC == BC_SOMMERFELD && nf) d.im -= nf * two_over_h * kbv[p];
+            c128 out = d * xc - ih2 * s;
+            if (BC == BC_DIRICHLET && (nf_col || zz == 0 || zz == g.nz - 1)) out = czero<double>();
+            if (q.valid) {
+                yr[idx] = out;
+                if (MODE == OP_V) {
+                    const c128 t = cdot(aux_v[p], out);
+                    acc[0] += t.re;
+                    acc[1] += t.im;
+                } else if (MODE == OP_T) {
+                    const c128 t = cdot(out, aux_v[p]);
+                    acc[0] += t.re;
+                    acc[1] += t.im;
+                    acc[2] += abs2(out);
+                }
             }
-            xm = xc;
-            xc = xp;
         }
     }
     if (MODE == OP_V || MODE == OP_T) {

@@ -22,6 +22,15 @@ using namespace hh;
 namespace {
 
 constexpr int NRHS_LIMIT = 16;
+// kernels timed by the "trace" option (the ids of hh_time_kernel) and the
+// launches of one Bi-CGSTAB step that carry them
+constexpr int NTRACE_KERNEL = 6;
+enum TraceLaunch : int { TL_APPLY_V, TL_APPLY_T, TL_UPDATE_XR, TL_DOWN_P, TL_DOWN_S, TL_UP_P, TL_UP_S,
+                         TL_P, TL_S, NTRACE_LAUNCH };
+constexpr int trace_kernel_of(int launch) {
+    return launch <= TL_APPLY_T ? 0 : launch == TL_UPDATE_XR ? 1 : launch <= TL_DOWN_S ? 2
+           : launch <= TL_UP_S ? 3 : launch == TL_P ? 4 : 5;
+}
 constexpr long long NBLK_CAP = 65536;   // workgroups of a reduction-producing launch
 constexpr int COARSE_UNK_CAP = 2048;    // unknowns of the dense coarsest solve
 constexpr int MAX_RESTARTS = 5;
@@ -82,6 +91,12 @@ struct hh_ctx {
     std::vector<int> zb_down_set, zb_up_set;
     size_t tail_lds_cap = 65536;
     float last_ms = 0.f;
+    // in-solve kernel timing (option "trace"): HIP events around the fine-level
+    // kernels of every step, check_every steps per host check
+    bool trace = false;
+    std::vector<hipEvent_t> tev;
+    double tsum[NTRACE_KERNEL] = {};
+    long long tcnt[NTRACE_KERNEL] = {};
     std::string err;
 };
 
@@ -170,6 +185,8 @@ void free_all(hh_ctx* c) {
     if (c->st_host) (void)hipHostFree(c->st_host);
     if (c->bad_host) (void)hipHostFree(c->bad_host);
     if (c->cap) (void)hipStreamDestroy(c->cap);
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+    c->tev.clear();
 }
 
 void invalidate_graphs(hh_ctx* c) {
@@ -257,9 +274,11 @@ void apply_launch(hh_ctx* c) {
 // V-cycle enqueue: z = V(bin) in precision R; level-0 input of type TB and
 // output of type TO (complex128, or complex64 inside the mixed solve).
 // -------------------------------------------------------------------------
+// ev_down / ev_up (may be null): event pairs recorded around the level-0 passes
 template <typename R, typename TB, typename TO>
 void enqueue_vcycle_t(hh_ctx* c, hipStream_t s, int nrhs, const cx<TB>* bin, cx<TO>* bout,
-                      const RhsState* st, int gate) {
+                      const RhsState* st, int gate, hipEvent_t* ev_down = nullptr,
+                      hipEvent_t* ev_up = nullptr) {
     const int bc = c->cfg.bc;
     const int T = c->tail_first;
     const MgParams P{c->cfg.beta1, c->cfg.beta2, c->cfg.omega};
@@ -267,8 +286,10 @@ void enqueue_vcycle_t(hh_ctx* c, hipStream_t s, int nrhs, const cx<TB>* bin, cx<
     auto K = [](void* p) { return reinterpret_cast<const R*>(p); };
     LevelBuf& f = c->lv[0];
     // down: one fused pass per level writes the next level's right-hand side
+    if (ev_down) (void)hipEventRecord(ev_down[0], s);
     launch_mg_down<TB, R>(s, bc, f.g, c->lv[1].g, f.zb_down, nrhs, bin, f.g.n, K(f.k2l), P,
                           C(c->lv[1].b), st, gate);
+    if (ev_down) (void)hipEventRecord(ev_down[1], s);
     for (int l = 1; l < T; ++l) {
         LevelBuf& a = c->lv[l];
         LevelBuf& n = c->lv[l + 1];
@@ -283,24 +304,28 @@ void enqueue_vcycle_t(hh_ctx* c, hipStream_t s, int nrhs, const cx<TB>* bin, cx<
         launch_mg_up<R, R, R>(s, bc, a.g, n.g, a.zb_up, nrhs, C(a.b), a.g.n, K(a.k2l), P, C(n.e), C(a.e),
                               a.g.n, st, gate);
     }
+    if (ev_up) (void)hipEventRecord(ev_up[0], s);
     launch_mg_up<TB, R, TO>(s, bc, f.g, c->lv[1].g, f.zb_up, nrhs, bin, f.g.n, K(f.k2l), P,
                             C(c->lv[1].e), bout, f.g.n, st, gate);
+    if (ev_up) (void)hipEventRecord(ev_up[1], s);
 }
 
 // complex128 in and out (the standalone V-cycle and the FP64 solve)
 void enqueue_vcycle(hh_ctx* c, hipStream_t s, int nrhs, const c128* bin, c128* bout,
-                    const RhsState* st, int gate) {
-    if (c->mixed) enqueue_vcycle_t<float, double, double>(c, s, nrhs, bin, bout, st, gate);
-    else enqueue_vcycle_t<double, double, double>(c, s, nrhs, bin, bout, st, gate);
+                    const RhsState* st, int gate, hipEvent_t* ev_down = nullptr,
+                    hipEvent_t* ev_up = nullptr) {
+    if (c->mixed) enqueue_vcycle_t<float, double, double>(c, s, nrhs, bin, bout, st, gate, ev_down, ev_up);
+    else enqueue_vcycle_t<double, double, double>(c, s, nrhs, bin, bout, st, gate, ev_down, ev_up);
 }
 
 // One step of the iteration; the mixed solve keeps the preconditioner's inputs
 // and outputs in complex64.  Its results are those of complex128 inputs and
 // outputs bit for bit: the preconditioner rounds its input to complex64 on
 // entry, and its output is a complex64 value either way.
+// ev (may be null): NTRACE_LAUNCH event pairs recorded around the traced launches
 template <typename TH>
 void enqueue_iteration_t(hh_ctx* c, hipStream_t s, int nrhs, cx<TH>* ph, cx<TH>* sh, c64* p_low,
-                         c64* s_low) {
+                         c64* s_low, hipEvent_t* ev) {
     const Geo& g = c->lv[0].g;
     const long long n = g.n;
     const long long nb = c->nblk0;
@@ -309,30 +334,46 @@ void enqueue_iteration_t(hh_ctx* c, hipStream_t s, int nrhs, cx<TH>* ph, cx<TH>*
     F.flat_cap = (int)nb;  // flat kernels use exactly nblk0 workgroups: same partial count
     launch_finalize(s, FIN_RHO, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
     constexpr bool low = sizeof(TH) == sizeof(float);
+    auto E = [&](int launch) -> hipEvent_t* { return ev ? ev + 2 * launch : nullptr; };
+    auto mark = [&](int launch, int end) {
+        if (ev) (void)hipEventRecord(ev[2 * launch + end], s);
+    };
+    mark(TL_P, 0);
     launch_p_update(s, n, nrhs, c->p, c->r, c->v, p_low, c->st, F);
-    if constexpr (low) enqueue_vcycle_t<float, float, float>(c, s, nrhs, p_low, ph, c->st, ST_RUN);
-    else enqueue_vcycle(c, s, nrhs, c->p, ph, c->st, ST_RUN);
+    mark(TL_P, 1);
+    if constexpr (low)
+        enqueue_vcycle_t<float, float, float>(c, s, nrhs, p_low, ph, c->st, ST_RUN, E(TL_DOWN_P), E(TL_UP_P));
+    else enqueue_vcycle(c, s, nrhs, c->p, ph, c->st, ST_RUN, E(TL_DOWN_P), E(TL_UP_P));
+    mark(TL_APPLY_V, 0);
     launch_apply(s, bc, OP_V, g, c->L0, nrhs, ph, c->v, c->k2, c->kb, 1.0, 0.0, c->rhat, c->part, NBLK_CAP,
                  c->st, ST_RUN);
+    mark(TL_APPLY_V, 1);
     launch_finalize(s, FIN_ALPHA, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
+    mark(TL_S, 0);
     launch_s_update(s, n, nrhs, c->s, c->r, c->v, s_low, c->st, c->part, NBLK_CAP, F);
-    if constexpr (low) enqueue_vcycle_t<float, float, float>(c, s, nrhs, s_low, sh, c->st, ST_RUN);
-    else enqueue_vcycle(c, s, nrhs, c->s, sh, c->st, ST_RUN);
+    mark(TL_S, 1);
+    if constexpr (low)
+        enqueue_vcycle_t<float, float, float>(c, s, nrhs, s_low, sh, c->st, ST_RUN, E(TL_DOWN_S), E(TL_UP_S));
+    else enqueue_vcycle(c, s, nrhs, c->s, sh, c->st, ST_RUN, E(TL_DOWN_S), E(TL_UP_S));
+    mark(TL_APPLY_T, 0);
     launch_apply(s, bc, OP_T, g, c->L0, nrhs, sh, c->t, c->k2, c->kb, 1.0, 0.0, c->s, c->part, NBLK_CAP,
                  c->st, ST_RUN);
+    mark(TL_APPLY_T, 1);
     launch_finalize(s, FIN_OMEGA, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
+    mark(TL_UPDATE_XR, 0);
     launch_update_xr<TH>(s, n, nrhs, c->xk, c->r, ph, sh, c->s, c->t, c->rhat, c->st, c->part, NBLK_CAP, F);
+    mark(TL_UPDATE_XR, 1);
 }
 
 // One Bi-CGSTAB step for all right-hand sides still iterating (device-side
 // scalars).  A right-hand side that meets the tolerance at the half step gets
 // x += alpha p_hat in the x / r update and is marked converged by the next FIN_RHO.
-void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs) {
+void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs, hipEvent_t* ev = nullptr) {
     if (c->mixed)
         enqueue_iteration_t<float>(c, s, nrhs, reinterpret_cast<c64*>(c->ph), reinterpret_cast<c64*>(c->sh),
-                                   c->p_low, c->s_low);
+                                   c->p_low, c->s_low, ev);
     else
-        enqueue_iteration_t<double>(c, s, nrhs, c->ph, c->sh, nullptr, nullptr);
+        enqueue_iteration_t<double>(c, s, nrhs, c->ph, c->sh, nullptr, nullptr, ev);
 }
 
 hh_status get_graph(hh_ctx* c, int nrhs, hipGraphExec_t* out) {
@@ -745,7 +786,19 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
         if (c->st_host[r].bnorm2 == 0.0)
             HIPCHK(c, hipMemsetAsync(c->xk + (size_t)r * g.n, 0, sizeof(c128) * g.n, c->stream));
     hipGraphExec_t exec = nullptr;
-    if (c->use_graph) CHK(get_graph(c, nrhs, &exec));
+    if (c->use_graph && !c->trace) CHK(get_graph(c, nrhs, &exec));
+    const size_t ev_per_step = 2 * NTRACE_LAUNCH;
+    if (c->trace)
+        while (c->tev.size() < ev_per_step * (size_t)c->check_every) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->tev.push_back(e);
+        }
+    auto all_running = [&]() {
+        for (int r = 0; r < nrhs; ++r)
+            if (c->st_host[r].status != ST_RUN) return false;
+        return true;
+    };
     int guard = 0;
     while (true) {
         bool any_run = false, any_half = false;
@@ -754,12 +807,26 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
             any_half |= c->st_host[r].status == ST_HALF;
         }
         if (any_run) {
+            const bool full_before = all_running();
             for (int k = 0; k < c->check_every; ++k) {
                 if (exec) HIPCHK(c, hipGraphLaunch(exec, c->stream));
-                else enqueue_iteration(c, c->stream, nrhs);
+                else enqueue_iteration(c, c->stream, nrhs, c->trace ? &c->tev[ev_per_step * k] : nullptr);
             }
             HIPCHK(c, hipGetLastError());
             CHK(read_states(c, nrhs));
+            if (c->trace && full_before && all_running()) {
+                // every right-hand side iterated through the whole window: each
+                // traced launch did its full work
+                for (int k = 0; k < c->check_every; ++k)
+                    for (int l = 0; l < NTRACE_LAUNCH; ++l) {
+                        float ms = 0.f;
+                        hipEvent_t* e = &c->tev[ev_per_step * k + 2 * l];
+                        if (hipEventElapsedTime(&ms, e[0], e[1]) == hipSuccess) {
+                            c->tsum[trace_kernel_of(l)] += ms;
+                            c->tcnt[trace_kernel_of(l)] += 1;
+                        }
+                    }
+            }
             if (++guard > 4 * (maxit + 8) * (MAX_RESTARTS + 1)) return fail(c, HH_ERR_STATE, "driver did not terminate");
             continue;
         }
@@ -835,6 +902,12 @@ hh_status hh_set_option(hh_ctx* c, const char* name, long long value) {
     } else if (n == "check_every") {
         if (value < 1 || value > 1000) return fail(c, HH_ERR_ARG, "check_every must be in 1..1000");
         c->check_every = (int)value;
+    } else if (n == "trace") {
+        c->trace = value != 0;
+        for (int k = 0; k < NTRACE_KERNEL; ++k) {
+            c->tsum[k] = 0.0;
+            c->tcnt[k] = 0;
+        }
     } else if (n == "block") {
         if (value != 64 && value != 128 && value != 256 && value != 512)
             return fail(c, HH_ERR_ARG, "block must be 64, 128, 256 or 512");
@@ -888,6 +961,7 @@ hh_status hh_get_option(const hh_ctx* c, const char* name, long long* value) {
     }
     else if (n == "tail_first") *value = c->tail_first;
     else if (n == "check_every") *value = c->check_every;
+    else if (n == "trace") *value = c->trace;
     else if (n == "block") *value = c->L0.block;
     else if (n == "zb") *value = c->L0.zb;
     else if (n == "n_levels") *value = (long long)c->lv.size();
@@ -983,6 +1057,15 @@ hh_status hh_time_kernel(hh_ctx* c, int which, int nrhs, int reps, float* ms_avg
     *ms_avg = ms / reps;
     launch_fill_status(c->stream, c->cfg.nrhs_max, c->st, ST_IDLE, 0);
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HH_OK;
+}
+
+hh_status hh_kernel_times(const hh_ctx* c, double* ms_avg, long long* launches) {
+    if (!c || !ms_avg || !launches) return HH_ERR_ARG;
+    for (int k = 0; k < NTRACE_KERNEL; ++k) {
+        launches[k] = c->tcnt[k];
+        ms_avg[k] = c->tcnt[k] ? c->tsum[k] / (double)c->tcnt[k] : 0.0;
+    }
     return HH_OK;
 }
 

@@ -204,6 +204,14 @@ class Solver:
         check(self.lib.hh_time_kernel(self.ctx, int(which), int(nrhs), int(reps), C.byref(ms)), self.ctx)
         return ms.value
 
+    def kernel_times(self):
+        """In-solve kernel timing of the solves since ``set_option("trace", 1)``:
+        (average ms per launch, launches) per kernel id of ``time_kernel``."""
+        ms = (C.c_double * 6)()
+        n = (C.c_longlong * 6)()
+        check(self.lib.hh_kernel_times(self.ctx, ms, n), self.ctx)
+        return list(ms), list(n)
+
     def autotune(self, nrhs: int = 1):
         check(self.lib.hh_autotune(self.ctx, int(nrhs)), self.ctx)
         return self.get_option("block"), self.get_option("zb")

@@ -224,6 +224,34 @@ def test_graph_and_direct_launch_bitwise_and_repeatable():
     assert np.array_equal(x1, x2) and np.array_equal(x1, x3) and np.array_equal(x1, x4)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_traced_solve_bitwise_and_kernel_times(prec):
+    """The event-traced solve runs the same kernels as the graph replay (same
+    result bit for bit) and times every fine-level launch of the full windows."""
+    wl = W.wedge(10.0, 17, 17, 33)
+    nodes = [(0, 8, 8), (0, 4, 12)]
+    s = _solver(wl.shape, wl.h, SOMMERFELD, prec=prec, nrhs_max=2)
+    s.set_model(dev(wl.k))
+    s.set_point_sources(nodes)
+    x1, st1 = s.solve(rtol=1e-8)
+    x1 = host(x1)
+    s.set_option("trace", 1)
+    x2, st2 = s.solve(rtol=1e-8)
+    x2 = host(x2)
+    ms, n = s.kernel_times()
+    s.set_option("trace", 0)
+    assert np.array_equal(x1, x2)
+    assert [a.iterations for a in st1] == [b.iterations for b in st2]
+    # full windows: every right-hand side iterating; 4 steps per window
+    steps = 4 * (int(min(a.iterations for a in st1)) // 4 - 1)
+    assert steps > 0
+    assert n[1] >= steps and n[4] == n[1] and n[5] == n[1]      # one launch per step
+    assert n[0] == 2 * n[1] and n[2] == 2 * n[1] and n[3] == 2 * n[1]  # two per step
+    assert all(0.0 < m < 50.0 for m in ms)
+    s.set_option("trace", 1)  # re-enabling resets the sums
+    assert s.kernel_times()[1] == [0] * 6
+
+
 def test_resume_from_initial_guess():
     wl = W.wedge(10.0, 17, 17, 33)
     s = _solver(wl.shape, wl.h, SOMMERFELD)
