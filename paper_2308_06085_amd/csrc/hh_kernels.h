@@ -55,6 +55,7 @@ int mg_up_blocks(const Geo& g, int zb);
 constexpr int MAX_TAIL = 8;
 struct TailLevel {
     int nx, ny, nz, n, off;
+    unsigned rcp_nx, rcp_plane;  // ceil(2^32 / nx), ceil(2^32 / (nx ny)): index division by multiply-high
     double h;
     const void* k2;  // level k^2 in the multigrid precision (device)
 };

@@ -30,12 +30,13 @@ struct TailCoef {
     R ih2, six_ih2, two_over_h, sr, si, omega;
 };
 
-// node index -> (x, y, z)
+// node index -> (x, y, z).  The quotients are multiply-highs by ceil(2^32 / d),
+// exact for index and divisor below 2^16 (the tail levels are far smaller).
 __device__ __forceinline__ void unflat(int i, const TailLevel& L, int& x, int& y, int& z) {
     const int plane = L.nx * L.ny;
-    z = i / plane;
+    z = (int)__umulhi((unsigned)i, L.rcp_plane);
     const int rem = i - z * plane;
-    y = rem / L.nx;
+    y = (int)__umulhi((unsigned)rem, L.rcp_nx);
     x = rem - y * L.nx;
 }
 
@@ -103,6 +104,31 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, const cx<R>* __res
         return (x == 0) + (x == L.nx - 1) + (y == 0) + (y == L.ny - 1) + (z == 0) + (z == L.nz - 1);
     };
     const int nl = D.nlev;
+    // Coarsest solve layout: G lanes per row (a power of two <= 64, so a group
+    // stays inside one wavefront); lane j of a group sums the columns
+    // c = j, j + G, ..., then the group adds its partial sums with a fixed
+    // butterfly.  When every row fits one pass and a lane has at most
+    // MAX_PRE columns, the lane's inverse entries and node indices are loaded
+    // here, with the staging loads, instead of after the down passes.
+    constexpr int MAX_PRE = 8;
+    int G = 1;
+    while (G < 64 && 2 * G * D.n_unk <= nt) G *= 2;
+    const int sub = t & (G - 1);
+    const bool pre = D.n_unk <= nt / G && D.n_unk <= MAX_PRE * G;
+    const cx<R>* minv = reinterpret_cast<const cx<R>*>(D.minv);
+    cx<R> mv[MAX_PRE];
+    int ci[MAX_PRE];
+    int crow = 0;  // node of this lane's row
+    if (pre) {
+        const int row = min(t / G, D.n_unk - 1);
+        crow = D.cidx[row];
+#pragma unroll
+        for (int k = 0; k < MAX_PRE; ++k) {
+            const int cc = min(sub + k * G, D.n_unk - 1);
+            mv[k] = minv[(long long)cc * D.n_unk + row];
+            ci[k] = D.cidx[cc];
+        }
+    }
     // stage the right-hand side of the first level and every level's k^2
     const cx<R>* bsrc = b_first + (long long)r * D.lv[0].n;
     for (int i = t; i < D.lv[0].n; i += nt) B(0)[i] = bsrc[i];
@@ -170,16 +196,21 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, const cx<R>* __res
         const TailLevel& L = D.lv[nl - 1];
         cx<R>* b = B(nl - 1);
         cx<R>* u = U(nl - 1);
-        const cx<R>* minv = reinterpret_cast<const cx<R>*>(D.minv);
         for (int i = t; i < L.n; i += nt) u[i] = czero<R>();
         __syncthreads();
-        // G lanes per row (a power of two <= 64, so a group stays inside one
-        // wavefront): lane j of a group sums the columns c = j, j + G, ..., then
-        // the group adds its partial sums with a fixed butterfly.
-        int G = 1;
-        while (G < 64 && 2 * G * D.n_unk <= nt) G *= 2;
-        const int sub = t & (G - 1);
-        for (int row0 = 0; row0 < D.n_unk; row0 += nt / G) {
+        if (pre) {
+            const int row = t / G;
+            cx<R> s = czero<R>();
+#pragma unroll
+            for (int k = 0; k < MAX_PRE; ++k)
+                if (sub + k * G < D.n_unk) s = s + mv[k] * b[ci[k]];
+            for (int off = G >> 1; off > 0; off >>= 1) {
+                s.re += __shfl_xor(s.re, off, 64);
+                s.im += __shfl_xor(s.im, off, 64);
+            }
+            if (row < D.n_unk && sub == 0) u[crow] = s;
+        }
+        for (int row0 = 0; !pre && row0 < D.n_unk; row0 += nt / G) {
             const int row = row0 + t / G;
             cx<R> s = czero<R>();
             if (row < D.n_unk)

@@ -243,6 +243,8 @@ TailDesc tail_desc(hh_ctx* c) {
         D.lv[i].nz = B.g.nz;
         D.lv[i].n = (int)B.g.n;
         D.lv[i].off = off;
+        D.lv[i].rcp_nx = (unsigned)((0x100000000ull + B.g.nx - 1) / B.g.nx);
+        D.lv[i].rcp_plane = (unsigned)((0x100000000ull + B.g.plane - 1) / B.g.plane);
         D.lv[i].h = B.g.h;
         D.lv[i].k2 = B.k2l;
         off += (int)B.g.n;
