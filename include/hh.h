@@ -159,7 +159,7 @@ hh_status hh_grad_slowness2(hh_ctx* ctx, const void* u, const void* w, const dou
 /* Options: "graph" (1 = replay each Bi-CGSTAB step as a captured hipGraph,
  * default 1), "check_every" (steps between host convergence checks, default 4),
  * "block" (threads per workgroup of the stencil kernels: 64, 128, 256, 512;
- * default 512), "zb" (z-planes per workgroup of the stencil kernels, default 2,
+ * default 256), "zb" (z-planes per workgroup of the stencil kernels, default 4,
  * 0 = automatic), "trace" (1 = time the fine-level kernels of every solve with
  * HIP events, see hh_kernel_times), "zb_down" / "zb_up" (z-planes per workgroup of the finest
  * level's multigrid down / up pass, 0 = automatic), "zb_down:<l>" / "zb_up:<l>"
@@ -198,8 +198,12 @@ hh_status hh_time_kernel(hh_ctx* ctx, int which, int nrhs, int reps, float* ms_a
  * launches are host arrays of 6 entries. */
 hh_status hh_kernel_times(const hh_ctx* ctx, double* ms_avg, long long* launches);
 
-/* Sweep workgroup shapes of the fine-grid kernels for the current grid and
- * keep the fastest (by HIP-event timing on the context stream). */
+/* Sweep the workgroup shape of the fine-grid stencil and Krylov kernels
+ * (lanes 128 / 256 / 512 x z-planes 2 / 4 / 8; default 256 x 4) and keep the
+ * fastest: each shape runs the first Bi-CGSTAB steps of the current sources
+ * (nrhs of them must be set) from a fresh start, replayed as a graph and timed
+ * with HIP events on the context stream.  Leaves the iterate undefined; the
+ * next hh_solve starts afresh. */
 hh_status hh_autotune(hh_ctx* ctx, int nrhs);
 
 #ifdef __cplusplus

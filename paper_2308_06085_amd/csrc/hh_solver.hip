@@ -652,8 +652,9 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
     launch_fill_status(c->stream, R, c->st, ST_IDLE, 0);
     if (ze != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess)
         return bail(fail(c, HH_ERR_HIP, "initialisation failed"));
-    c->base.block = 512;
-    c->base.zb = 2;
+    // 256 lanes x 4 planes: fastest in whole-solve timing on the wedge (mixed and FP64)
+    c->base.block = 256;
+    c->base.zb = 4;
     // the tail kernel may use up to 128 KB of LDS where the device allows it
     c->tail_lds_cap = mg_tail_allow_lds(131072) ? 131072 : 65536;
     (void)hipGetLastError();
@@ -792,8 +793,10 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
     const size_t ev_per_step = 2 * NTRACE_LAUNCH;
     if (c->trace)
         while (c->tev.size() < ev_per_step * (size_t)c->check_every) {
+            // no system-scope fence at record: the events only bracket kernels
+            // on this stream, and a fence per record would lengthen every bracket
             hipEvent_t e;
-            HIPCHK(c, hipEventCreate(&e));
+            HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
             c->tev.push_back(e);
         }
     auto all_running = [&]() {
@@ -1073,26 +1076,46 @@ hh_status hh_kernel_times(const hh_ctx* c, double* ms_avg, long long* launches) 
 
 hh_status hh_autotune(hh_ctx* c, int nrhs) {
     CHK(check_ready(c, nrhs));
-    const int blocks[] = {64, 128, 256, 512};
-    const int zbs[] = {2, 4, 8, 16, 32};
+    if (c->nrhs_cur < nrhs) return fail(c, HH_ERR_STATE, "autotune needs %d right-hand sides set", nrhs);
+    // Each candidate shape runs the first steps of a solve of the current
+    // sources (a fresh start, graph replay) and is timed with HIP events on
+    // the context stream: kernels see the data flow and cache state of a
+    // solve, not a repeated launch on warm inputs.
+    constexpr int kSteps = 8, kWarm = 2;
+    const int blocks[] = {128, 256, 512};
+    const int zbs[] = {2, 4, 8};
+    const Geo& g = c->lv[0].g;
     Launch best = c->base;
     float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
     for (int b : blocks)
         for (int z : zbs) {
             c->base.block = b;
             c->base.zb = z;
             apply_launch(c);
-            float tot = 0.f;
-            for (int which : {0, 2, 3}) {
-                float ms = 0.f;
-                CHK(hh_time_kernel(c, which, nrhs, 5, &ms));
-                tot += ms;
-            }
-            if (tot < best_ms) {
-                best_ms = tot;
+            hipGraphExec_t exec = nullptr;
+            CHK(get_graph(c, nrhs, &exec));
+            // tolerance 0: no right-hand side stops within the few steps timed
+            launch_fill_status(c->stream, nrhs, c->st, ST_RUN, 2 * (kSteps + kWarm + 1));
+            launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v,
+                        c->k2, c->kb, 0, c->part, NBLK_CAP, c->st, ST_RUN);
+            launch_finalize(c->stream, FIN_INIT, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, 0.0);
+            for (int k = 0; k < kWarm; ++k) HIPCHK(c, hipGraphLaunch(exec, c->stream));
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            for (int k = 0; k < kSteps; ++k) HIPCHK(c, hipGraphLaunch(exec, c->stream));
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
                 best = c->base;
             }
         }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     c->base = best;
     apply_launch(c);
     return HH_OK;

@@ -252,6 +252,44 @@ def test_traced_solve_bitwise_and_kernel_times(prec):
     assert s.kernel_times()[1] == [0] * 6
 
 
+def test_launch_shape_options_and_autotune():
+    """Per-level z-block options, the stencil launch shape and the autotuner:
+    every choice solves the same problem to the tolerance, and the multigrid
+    result does not depend on the z-blocks (each node's arithmetic is fixed)."""
+    from paper_2308_06085_amd._lib import HHError
+
+    wl = W.wedge(10.0, 33, 33, 65)
+    s = _solver(wl.shape, wl.h, SOMMERFELD, prec="mixed")
+    s.set_model(dev(wl.k))
+    s.set_point_sources(wl.sources)
+    nlev = s.get_option("n_levels")
+    first_tail = s.get_option("tail_first")
+    assert 1 <= first_tail < nlev
+    r = dev(W.random_complex(wl.shape, seed=3)).unsqueeze(0)
+    z_ref = host(s.apply_vcycle(r))
+    for l in range(first_tail):
+        for opt in (f"zb_down:{l}", f"zb_up:{l}"):
+            s.set_option(opt, 1)
+            assert s.get_option(opt) == 1
+    assert np.array_equal(host(s.apply_vcycle(r)), z_ref)
+    with pytest.raises(HHError):
+        s.set_option(f"zb_down:{nlev - 1}", 2)   # the coarsest level has no pass
+    with pytest.raises(HHError):
+        s.set_option("zb_up:x", 2)
+    for l in range(first_tail):
+        s.set_option(f"zb_down:{l}", 0)
+        s.set_option(f"zb_up:{l}", 0)
+    for block, zb in ((128, 8), (512, 2)):
+        s.set_option("block", block)
+        s.set_option("zb", zb)
+        x, st = s.solve(rtol=1e-7)
+        assert st[0].status == "HH_OK" and st[0].relres_true <= 1e-7
+    block, zb = s.autotune(1)
+    assert block in (128, 256, 512) and zb in (2, 4, 8)
+    x, st = s.solve(rtol=1e-7)
+    assert st[0].status == "HH_OK" and st[0].relres_true <= 1e-7
+
+
 def test_resume_from_initial_guess():
     wl = W.wedge(10.0, 17, 17, 33)
     s = _solver(wl.shape, wl.h, SOMMERFELD)
