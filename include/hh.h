@@ -190,12 +190,14 @@ hh_status hh_time_kernel(hh_ctx* ctx, int which, int nrhs, int reps, float* ms_a
  * replay.  Only check windows (check_every steps) through which every
  * right-hand side kept iterating are counted, so each counted launch did the
  * full work of all right-hand sides.  hh_kernel_times returns, per kernel id
- * of hh_time_kernel (0 = the
- * operator apply with its dot products, both launches of a step; 1 = x / r
- * update; 2 / 3 = finest-level multigrid down / up pass, both V-cycles;
- * 4 = p update; 5 = s update), the average duration in milliseconds of the
- * traced launches since tracing was enabled and their number.  ms_avg and
- * launches are host arrays of 6 entries. */
+ * of hh_time_kernel (0 = the operator apply with its dot products, both
+ * launches of a step; 1 = x / r update; 2 / 3 = finest-level multigrid
+ * down / up pass, both V-cycles; 4 = p update; 5 = s update) and id 6 (an
+ * extra launch of the operator apply per step with every workgroup gated off:
+ * what the event bracket around one launch adds to a kernel's own duration),
+ * the average bracketed duration in milliseconds of the traced launches since
+ * tracing was enabled and their number.  ms_avg and launches are host arrays
+ * of 7 entries. */
 hh_status hh_kernel_times(const hh_ctx* ctx, double* ms_avg, long long* launches);
 
 /* Sweep the workgroup shape of the fine-grid stencil and Krylov kernels

@@ -24,12 +24,14 @@ namespace {
 constexpr int NRHS_LIMIT = 16;
 // kernels timed by the "trace" option (the ids of hh_time_kernel) and the
 // launches of one Bi-CGSTAB step that carry them
-constexpr int NTRACE_KERNEL = 6;
+// (and id 6: an empty launch of the operator apply, every workgroup gated
+// off, which measures what an event bracket around one launch adds)
+constexpr int NTRACE_KERNEL = 7;
 enum TraceLaunch : int { TL_APPLY_V, TL_APPLY_T, TL_UPDATE_XR, TL_DOWN_P, TL_DOWN_S, TL_UP_P, TL_UP_S,
-                         TL_P, TL_S, NTRACE_LAUNCH };
+                         TL_P, TL_S, TL_EMPTY, NTRACE_LAUNCH };
 constexpr int trace_kernel_of(int launch) {
     return launch <= TL_APPLY_T ? 0 : launch == TL_UPDATE_XR ? 1 : launch <= TL_DOWN_S ? 2
-           : launch <= TL_UP_S ? 3 : launch == TL_P ? 4 : 5;
+           : launch <= TL_UP_S ? 3 : launch == TL_P ? 4 : launch == TL_S ? 5 : 6;
 }
 constexpr long long NBLK_CAP = 65536;   // workgroups of a reduction-producing launch
 constexpr int COARSE_UNK_CAP = 2048;    // unknowns of the dense coarsest solve
@@ -346,6 +348,14 @@ void enqueue_iteration_t(hh_ctx* c, hipStream_t s, int nrhs, cx<TH>* ph, cx<TH>*
     if constexpr (low)
         enqueue_vcycle_t<float, float, float>(c, s, nrhs, p_low, ph, c->st, ST_RUN, E(TL_DOWN_P), E(TL_UP_P));
     else enqueue_vcycle(c, s, nrhs, c->p, ph, c->st, ST_RUN, E(TL_DOWN_P), E(TL_UP_P));
+    if (ev) {
+        // the same launch with every right-hand side gated off (no iterating
+        // one has status "idle"): the cost of the event bracket itself
+        mark(TL_EMPTY, 0);
+        launch_apply(s, bc, OP_V, g, c->L0, nrhs, ph, c->v, c->k2, c->kb, 1.0, 0.0, c->rhat, c->part,
+                     NBLK_CAP, c->st, ST_IDLE);
+        mark(TL_EMPTY, 1);
+    }
     mark(TL_APPLY_V, 0);
     launch_apply(s, bc, OP_V, g, c->L0, nrhs, ph, c->v, c->k2, c->kb, 1.0, 0.0, c->rhat, c->part, NBLK_CAP,
                  c->st, ST_RUN);

@@ -206,9 +206,10 @@ class Solver:
 
     def kernel_times(self):
         """In-solve kernel timing of the solves since ``set_option("trace", 1)``:
-        (average ms per launch, launches) per kernel id of ``time_kernel``."""
-        ms = (C.c_double * 6)()
-        n = (C.c_longlong * 6)()
+        (average ms per launch, launches) per kernel id of ``time_kernel``, and
+        at index 6 the event-bracket cost (an empty launch per step)."""
+        ms = (C.c_double * 7)()
+        n = (C.c_longlong * 7)()
         check(self.lib.hh_kernel_times(self.ctx, ms, n), self.ctx)
         return list(ms), list(n)
 

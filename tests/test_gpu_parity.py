@@ -245,11 +245,12 @@ def test_traced_solve_bitwise_and_kernel_times(prec):
     # full windows: every right-hand side iterating; 4 steps per window
     steps = 4 * (int(min(a.iterations for a in st1)) // 4 - 1)
     assert steps > 0
-    assert n[1] >= steps and n[4] == n[1] and n[5] == n[1]      # one launch per step
+    assert n[1] >= steps and n[4] == n[1] and n[5] == n[1] and n[6] == n[1]  # one launch per step
     assert n[0] == 2 * n[1] and n[2] == 2 * n[1] and n[3] == 2 * n[1]  # two per step
     assert all(0.0 < m < 50.0 for m in ms)
+    assert ms[6] < ms[0]  # the empty bracket costs less than a working apply
     s.set_option("trace", 1)  # re-enabling resets the sums
-    assert s.kernel_times()[1] == [0] * 6
+    assert s.kernel_times()[1] == [0] * 7
 
 
 def test_launch_shape_options_and_autotune():
