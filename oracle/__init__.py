@@ -14,7 +14,8 @@ Modules
                     (paper section 2.1, 2.4; section 3.3; Algorithm 2).
 ``multigrid``       damped Jacobi, full weighting, trilinear interpolation,
                     rediscretised coarse operators, exact coarsest solve,
-                    recursive V-cycle (section 3.4, Algorithm 1, section 4.2).
+                    recursive V- and F-cycles (section 3.4, Algorithm 1,
+                    section 4.2).
 ``krylov``          right-preconditioned Bi-CGSTAB with the true-residual
                     stopping rule of section 5.
 ``adjoint``         misfit gradient with respect to squared slowness by one
@@ -42,6 +43,7 @@ from .multigrid import (  # noqa: F401
     restrict_fw,
     prolong_trilinear,
     vcycle,
+    fcycle,
 )
 from .krylov import bicgstab, SolveResult, Status  # noqa: F401
 from .adjoint import misfit_and_gradient, adjoint_gradient_pointwise, solve_forward  # noqa: F401

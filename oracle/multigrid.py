@@ -1,8 +1,8 @@
 """Geometric multigrid for the CSLP preconditioner (oracle; test infrastructure only).
 
 Paper section 3.4 and Algorithm 1 (two-grid cycle), applied recursively as
-a V-cycle with one pre- and one post-smoothing step per level (section
-3.4.5):
+a V-cycle, or an F-cycle, with one pre- and one post-smoothing step per level
+(section 3.4.5):
 
 * smoother: damped Jacobi with omega = 0.8 (section 3.4.1),
       u <- u + omega D^{-1} (b - M u),  D = diag(M) incl. boundary terms;
@@ -237,6 +237,36 @@ def vcycle(b, hier: Hierarchy, level=0):
     return u.astype(hier.dtype)
 
 
+def fcycle(b, hier: Hierarchy, level=0):
+    """u ~= M_l^{-1} b by one F(1,1) cycle with zero initial guess (section
+    3.4.5).  The cycle first descends to the coarsest grid; on the way back up,
+    every level reached for the first time gets one more V-cycle down to the
+    coarsest grid.  Written recursively: as the V-cycle, but the coarse error
+    equation is solved by one F-cycle followed by one V-cycle on the coarse
+    residual that F-cycle leaves.  On the coarsest level the F-cycle is the
+    exact solve, which leaves no residual, so no further cycle follows there."""
+    lvl = hier.levels[level]
+    if level == len(hier.levels) - 1:
+        return coarse_solve(b, hier)
+    wd = (hier.omega / hier.diags[level]).astype(hier.dtype)
+    u = np.zeros_like(b)
+    u = jacobi_sweep(u, b, lvl, wd, hier.beta1, hier.beta2)          # pre-smoothing
+    r = b - apply_M(u, lvl, hier.beta1, hier.beta2)                  # residual
+    bc_ = restrict_fw(r, lvl.bc)                                     # restriction
+    coarse = hier.levels[level + 1]
+    if lvl.bc == DIRICHLET:
+        bc_ = bc_ * unknown_mask(coarse.shape, DIRICHLET)
+    e = fcycle(bc_, hier, level + 1)                                 # F-cycle on the coarse level
+    if level + 1 < len(hier.levels) - 1:
+        rc = bc_ - apply_M(e, coarse, hier.beta1, hier.beta2)        # its remaining residual
+        e = e + vcycle(rc, hier, level + 1)                          # the additional V-cycle
+    u = u + prolong_trilinear(e, lvl.shape)                          # correction
+    u = jacobi_sweep(u, b, lvl, wd, hier.beta1, hier.beta2)          # post-smoothing
+    if lvl.bc == DIRICHLET:
+        u = u * unknown_mask(lvl.shape, DIRICHLET)
+    return u.astype(hier.dtype)
+
+
 def vcycle_mixed_entry(b, hier32: Hierarchy):
     """Mixed-precision preconditioner: complex128 in, complex64 V-cycle, complex128 out."""
     return vcycle(b.astype(np.complex64), hier32).astype(np.complex128)
@@ -244,6 +274,6 @@ def vcycle_mixed_entry(b, hier32: Hierarchy):
 
 __all__ = [
     "Hierarchy", "build_hierarchy", "level_shapes", "coarsen_shape", "coarse_solve",
-    "jacobi_sweep", "restrict_fw", "prolong_trilinear", "vcycle", "vcycle_mixed_entry",
+    "jacobi_sweep", "restrict_fw", "prolong_trilinear", "vcycle", "fcycle", "vcycle_mixed_entry",
     "SOMMERFELD", "DIRICHLET",
 ]

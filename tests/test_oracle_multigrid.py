@@ -1,12 +1,12 @@
 """Pins of the oracle's multigrid (paper section 3.4: damped Jacobi, full weighting,
 trilinear interpolation, rediscretised coarse operators; Algorithm 1 applied
-recursively as a V-cycle)."""
+recursively as a V-cycle or an F-cycle)."""
 import numpy as np
 import pytest
 
 import oracle as O
 from oracle.discretization import DIRICHLET, SOMMERFELD, Level, boundary_directions, unknown_mask
-from oracle.multigrid import build_hierarchy, coarsen_shape, level_shapes, vcycle
+from oracle.multigrid import build_hierarchy, coarsen_shape, fcycle, level_shapes, vcycle
 
 from test_oracle_operator import sine_eigenvalue, sine_mode
 
@@ -235,3 +235,113 @@ def test_vcycle_mixed_precision_close_to_double():
     u32 = vcycle(b.astype(np.complex64), h32)
     assert u32.dtype == np.complex64
     assert np.linalg.norm(u32 - u64) <= 1e-5 * np.linalg.norm(u64)
+
+
+def _two_grid_mats(hier, bc, coarse_inv, l):
+    """Dense level-l pieces: M_l, W = omega D_l^-1, R, P and the V-type two-grid matrix
+    W + (I - W M)(W + P C R (I - M W)) for a given coarse solver matrix C."""
+    lv, lc = hier.levels[l], hier.levels[l + 1]
+    mf, mcm = unknown_mask(lv.shape, bc), unknown_mask(lc.shape, bc)
+    M = _dense(lambda x: O.apply_M(x, lv), lv.shape, mf, mf)
+    W = np.diag(0.8 / O.diag_M(lv)[mf])
+    R = _dense(lambda x: O.restrict_fw(x, bc), lv.shape, mf, mcm)
+    P = _dense(lambda x: O.prolong_trilinear(x, lv.shape), lc.shape, mcm, mf)
+    I = np.eye(M.shape[0])
+    return M, W + (I - W @ M) @ (W + P @ coarse_inv @ R @ (I - M @ W))
+
+
+def test_fcycle_with_two_levels_is_the_vcycle():
+    """With one coarse level the coarse solve is exact, so no extra cycle is made."""
+    n = 9
+    rng = np.random.default_rng(41)
+    for bc in (DIRICHLET, SOMMERFELD):
+        hier = build_hierarchy(rng.uniform(3, 8, (n, n, n)), 1 / 8, bc, n_levels=2)
+        b = rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
+        b = b * unknown_mask((n, n, n), bc)
+        assert np.array_equal(fcycle(b, hier), vcycle(b, hier))
+
+
+@pytest.mark.parametrize("bc", [DIRICHLET, SOMMERFELD])
+def test_fcycle_with_three_levels_is_the_wcycle(bc):
+    """Three levels: the F-cycle visits the middle level twice, which is the W-cycle
+    (two two-grid iterations on the middle level, the second started from the first's
+    result).  Assembled from dense matrices: C_1 = 2 B_1 - B_1 M_1 B_1, with B_1 the
+    middle level's two-grid matrix over the exact coarsest inverse."""
+    n = 9
+    rng = np.random.default_rng(42)
+    k = rng.uniform(3.0, 8.0, (n, n, n))
+    hier = build_hierarchy(k, 1.0 / (n - 1), bc)
+    assert len(hier.levels) == 3
+    lv = hier.levels[2]
+    mc = unknown_mask(lv.shape, bc)
+    inv2 = np.linalg.inv(_dense(lambda x: O.apply_M(x, lv), lv.shape, mc, mc))
+    M1, B1 = _two_grid_mats(hier, bc, inv2, 1)
+    C1 = 2 * B1 - B1 @ M1 @ B1
+    _, F0 = _two_grid_mats(hier, bc, C1, 0)
+    _, V0 = _two_grid_mats(hier, bc, B1, 0)
+    mf = unknown_mask((n, n, n), bc)
+    b = (rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))) * mf
+    u = fcycle(b, hier)
+    ref = F0 @ b[mf]
+    assert np.abs(u[mf] - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(u[~mf]).max() == 0 if bc == DIRICHLET else True
+    # and it is not the V-cycle
+    assert np.abs(u[mf] - V0 @ b[mf]).max() > 1e-3 * np.abs(ref).max()
+
+
+def test_fcycle_is_linear_and_batched():
+    n = 17
+    rng = np.random.default_rng(43)
+    hier = build_hierarchy(rng.uniform(5, 12, (n, n, n)), 1 / 16, SOMMERFELD)
+    x = rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
+    y = rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
+    a, c = 0.3 - 1.2j, 2.0 + 0.5j
+    lhs = fcycle(a * x + c * y, hier)
+    rhs = a * fcycle(x, hier) + c * fcycle(y, hier)
+    assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+    ub = fcycle(np.stack([x, y]), hier)
+    assert np.array_equal(ub[0], fcycle(x, hier)) and np.array_equal(ub[1], fcycle(y, hier))
+
+
+def _wcycle(b, hier, level=0):
+    """W(1,1) cycle from zero, composed here from the oracle's level primitives:
+    the coarse error equation gets two cycles, the second on the first's residual."""
+    from oracle.multigrid import coarse_solve, jacobi_sweep, prolong_trilinear, restrict_fw
+
+    lvl = hier.levels[level]
+    if level == len(hier.levels) - 1:
+        return coarse_solve(b, hier)
+    wd = hier.omega / hier.diags[level]
+    u = jacobi_sweep(np.zeros_like(b), b, lvl, wd, hier.beta1, hier.beta2)
+    coarse = hier.levels[level + 1]
+    mc, mf = unknown_mask(coarse.shape, lvl.bc), unknown_mask(lvl.shape, lvl.bc)
+    bc_ = restrict_fw(b - O.apply_M(u, lvl, hier.beta1, hier.beta2), lvl.bc) * mc
+    e = _wcycle(bc_, hier, level + 1)
+    e = e + _wcycle(bc_ - O.apply_M(e, coarse, hier.beta1, hier.beta2), hier, level + 1)
+    u = jacobi_sweep(u + prolong_trilinear(e, lvl.shape), b, lvl, wd, hier.beta1, hier.beta2)
+    return u * mf
+
+
+def _contraction_of(cycle, n, iters=12):
+    k = np.zeros((n, n, n))
+    hier = build_hierarchy(k, 1.0 / (n - 1), DIRICHLET)
+    lvl = hier.levels[0]
+    mask = unknown_mask(lvl.shape, DIRICHLET)
+    e = np.random.default_rng(7).standard_normal((n, n, n)) * mask + 0j
+    norms = []
+    for _ in range(iters):
+        e = (e - cycle(O.apply_A(e, lvl), hier)) * mask
+        norms.append(np.linalg.norm(e))
+    return (norms[-1] / norms[-5]) ** 0.25
+
+
+def test_fcycle_contraction_between_w_and_v_for_k0():
+    """k = 0 Dirichlet on 33^3 (5 levels): the F-cycle's asymptotic contraction lies
+    between the W-cycle's and the V-cycle's (textbook ordering), and does not grow
+    from 17^3 to 33^3."""
+    rv = _contraction_of(vcycle, 33)
+    rf = _contraction_of(fcycle, 33)
+    rw = _contraction_of(_wcycle, 33)
+    assert rw <= rf + 1e-3 and rf < rv, (rw, rf, rv)
+    rf17 = _contraction_of(fcycle, 17)
+    assert rf <= rf17 + 0.05, (rf17, rf)
