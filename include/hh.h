@@ -10,10 +10,11 @@
  * ||b - A u|| / ||b|| <= rtol (section 5).  The preconditioner is the complex
  * shifted Laplacian M = -Laplace_h - (beta1 - beta2 i) k^2 I (section 3.3,
  * eq. preconditioner) inverted approximately by one geometric multigrid
- * V(1,1)-cycle: damped Jacobi (section 3.4.1), full-weighting restriction
- * (section 3.4.2), trilinear interpolation (section 3.4.3), rediscretised
- * coarse operators (section 3.4.4), recursive two-grid cycle (Algorithm 1),
- * exact solve on the coarsest grid.  Everything is matrix-free (Algorithm 2).
+ * V(1,1)-cycle, or one F(1,1)-cycle (section 3.4.5; option "cycle"): damped
+ * Jacobi (section 3.4.1), full-weighting restriction (section 3.4.2),
+ * trilinear interpolation (section 3.4.3), rediscretised coarse operators
+ * (section 3.4.4), recursive two-grid cycle (Algorithm 1), exact solve on the
+ * coarsest grid.  Everything is matrix-free (Algorithm 2).
  *
  * Conventions for every entry point
  * ---------------------------------
@@ -140,7 +141,12 @@ hh_status hh_apply_operator(hh_ctx* ctx, const void* x, void* y, int nrhs);
 hh_status hh_apply_shifted(hh_ctx* ctx, const void* x, void* y, int nrhs);
 
 /* z = V(r): one V(1,1)-cycle with zero initial guess approximating M^-1 r, in
- * the context's precision (complex128 in and out in both precisions). */
+ * the context's precision (complex128 in and out in both precisions).  With
+ * option "cycle" = 1 the cycle is the F(1,1)-cycle of section 3.4.5 instead:
+ * the coarse-grid equation of every level above the coarsest is solved by one
+ * F-cycle on the level below followed by one V-cycle on the residual it leaves
+ * (on the coarsest level the exact solve), which is the preconditioner the
+ * solve then uses too. */
 hh_status hh_apply_vcycle(hh_ctx* ctx, const void* r, void* z, int nrhs);
 
 /* Adjoint right-hand side rhs = D^-1 conj(g), D_j = 2^(-n_j) with n_j the number
@@ -165,6 +171,10 @@ hh_status hh_grad_slowness2(hh_ctx* ctx, const void* u, const void* w, const dou
  * level's multigrid down / up pass, 0 = automatic), "zb_down:<l>" / "zb_up:<l>"
  * (the same for level l, 0 <= l < n_levels - 1; levels run by the single-workgroup
  * tail kernel ignore it).  A level outside that range is HH_ERR_ARG.
+ * "cycle" (0 = V(1,1)-cycle, default; 1 = F(1,1)-cycle, section 3.4.5, which
+ * visits level l >= 1 l + 1 times per application instead of once and adds one
+ * residual pass on each level from 1 to the second coarsest; other values are
+ * HH_ERR_ARG).
  * hh_get_option also reports "n_levels", "coarse_unknowns", "tail_first" (first
  * level run by the tail kernel) and the z-planes in use under the same names. */
 hh_status hh_set_option(hh_ctx* ctx, const char* name, long long value);

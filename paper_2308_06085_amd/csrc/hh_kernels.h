@@ -45,7 +45,12 @@ void launch_mg_down(hipStream_t s, int bc, const Geo& gf, const Geo& gc, int zbc
 template <typename TB, typename R, typename TO>
 void launch_mg_up(hipStream_t s, int bc, const Geo& g, const Geo& gc, int zb, int nrhs,
                   const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
-                  const cx<R>* ec, cx<TO>* out, long long o_rstride, const RhsState* st, int gate);
+                  const cx<R>* ec, cx<TO>* out, long long o_rstride, const RhsState* st, int gate,
+                  bool acc = false);
+// b = b - M e in place on a level below the finest (one precision throughout)
+template <typename R>
+void launch_mg_resid(hipStream_t s, int bc, const Geo& g, int nrhs, cx<R>* b, const cx<R>* e, const R* k2l,
+                     const MgParams& P, const RhsState* st, int gate);
 int mg_down_blocks(const Geo& gc, int zbc);
 int mg_up_blocks(const Geo& g, int zb);
 
@@ -66,12 +71,21 @@ struct TailDesc {
     const void* minv;  // dense inverse of the coarsest M, column-major
     TailLevel lv[MAX_TAIL];
 };
+// A tail program: the passes to run, in order, each one byte (op << 4 | level).
+enum TailOp { TAIL_DOWN = 0, TAIL_COARSE = 1, TAIL_UP = 2, TAIL_RESID = 3, TAIL_ACC = 4 };
+constexpr int MAX_TAIL_OPS = 96;  // the F program on MAX_TAIL levels has 92 passes
+struct TailProg {
+    int n;
+    unsigned char op[MAX_TAIL_OPS];
+};
+TailProg tail_prog_v(int nlev);
+TailProg tail_prog_f(int nlev);
 size_t mg_tail_lds_bytes(const TailDesc& D, bool single);
 // Raise the kernel's dynamic-LDS limit to `bytes`; returns false if refused.
 bool mg_tail_allow_lds(size_t bytes);
 template <typename R>
-void launch_mg_tail(hipStream_t s, int bc, const TailDesc& D, int nrhs, const cx<R>* b_first,
-                    cx<R>* e_first, const RhsState* st, int gate);
+void launch_mg_tail(hipStream_t s, int bc, const TailDesc& D, const TailProg& P, int nrhs,
+                    const cx<R>* b_first, cx<R>* e_first, const RhsState* st, int gate);
 // p_low / s_low (may be null): a complex64 copy of the new p / s for a
 // single-precision preconditioner
 void launch_p_update(hipStream_t s, long long n, int nrhs, c128* p, const c128* r, const c128* v,

@@ -25,6 +25,8 @@
 // eliminated ghost point (its 2hik part is in c) and the even extension of the
 // full-weighting stencil; for Dirichlet levels the boundary values are zero and
 // boundary outputs are forced to zero.
+#include <type_traits>
+
 #include "hh_common.h"
 #include "hh_device.h"
 #include "hh_kernels.h"
@@ -305,14 +307,16 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
 // ---------------------------------------------------------------------------
 // Up: u3 = u2 + W (b - (1/h^2) lap(u2) + c u2), u2 = W b + P e_H.  Each lane
 // owns one node of the tile-plus-halo region; the lanes inside the halo
-// compute the output.  The workgroup marches over `zb` planes.
+// compute the output.  The workgroup marches over `zb` planes.  With ACC the
+// pass adds u3 to the output instead of storing it (the F-cycle's second
+// coarse-grid cycle).
 // ---------------------------------------------------------------------------
 // Waves per SIMD the up pass is compiled for: three 512-lane workgroups per CU
 // in single precision (<= 80 VGPRs), two in double (<= 128 VGPRs).
 template <typename R>
 constexpr int UP_WAVES_PER_SIMD = sizeof(R) == sizeof(float) ? 6 : 4;
 
-template <int BC, typename TB, typename R, typename TO, bool ONE>
+template <int BC, typename TB, typename R, typename TO, bool ONE, bool ACC>
 __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g, Geo gc, int zb,
                                                     const cx<TB>* __restrict__ b, long long b_rstride,
                                                     const R* __restrict__ k2l, double beta1,
@@ -414,7 +418,9 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
             lap = lap + (u - up[t]);
             cx<R> v = u + jacobi_w(L, c) * ((cvt<R>(bz) - L.ih2 * lap) + c * u);
             if (BC == BC_DIRICHLET && (unf || z == 0 || z == g.nz - 1)) v = czero<R>();
-            orr[(long long)z * g.plane + ooff] = cvt<TO>(v);
+            cx<TO>* o = orr + (long long)z * g.plane + ooff;
+            if constexpr (ACC) v = cvt<R>(*o) + v;  // out already holds an earlier cycle's result
+            *o = cvt<TO>(v);
         }
     };
     // per plane this lane keeps its own u2, b, c for the output step
@@ -514,6 +520,52 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
 }
 
 // ---------------------------------------------------------------------------
+// Residual in place: b = b - M e = b - (1/h^2) lap(e) + c e on a level below
+// the finest (the F-cycle's second coarse-grid cycle starts from it).  One
+// lane per in-plane node marching over `zb` planes; the neighbours are read
+// straight from global memory (the x and y ones from lines the workgroup
+// loads anyway, the z ones from the previous planes, in L2).
+// ---------------------------------------------------------------------------
+constexpr int RS_LANES = 256;
+
+template <int BC, typename R>
+__global__ __launch_bounds__(RS_LANES) void k_mg_resid(Geo g, int zb, cx<R>* __restrict__ b,
+                                                       const cx<R>* __restrict__ e,
+                                                       const R* __restrict__ k2l, double beta1,
+                                                       double beta2, double omega, const RhsState* st,
+                                                       int gate) {
+    const int r = blockIdx.z;
+    if (!gate_ok(st, r, gate)) return;
+    const int i = blockIdx.x * RS_LANES + threadIdx.x;
+    if (i >= g.plane) return;
+    const int y = i / g.nx, x = i - y * g.nx;
+    const int z0 = blockIdx.y * zb, z1 = min(g.nz, z0 + zb);
+    const LevelCoef<R> L = level_coef<R>(g, beta1, beta2, omega);
+    // neighbour offsets, a missing neighbour replaced by its mirror image
+    const int dxm = x > 0 ? -1 : 1, dxp = x < g.nx - 1 ? 1 : -1;
+    const int dym = y > 0 ? -g.nx : g.nx, dyp = y < g.ny - 1 ? g.nx : -g.nx;
+    const int nfxy = (x == 0) + (x == g.nx - 1) + (y == 0) + (y == g.ny - 1);
+    cx<R>* br = b + (long long)r * g.n;
+    const cx<R>* er = e + (long long)r * g.n;
+    for (int z = z0; z < z1; ++z) {
+        const long long j = (long long)z * g.plane + i;
+        const long long dzm = z > 0 ? -(long long)g.plane : g.plane;
+        const long long dzp = z < g.nz - 1 ? g.plane : -(long long)g.plane;
+        const cx<R> u = er[j];
+        cx<R> lap = (u - er[j + dxm]) + (u - er[j + dxp]);
+        lap = lap + (u - er[j + dym]);
+        lap = lap + (u - er[j + dyp]);
+        lap = lap + (u - er[j + dzm]);
+        lap = lap + (u - er[j + dzp]);
+        const int nf = nfxy + (z == 0) + (z == g.nz - 1);
+        const cx<R> c = shift_c(L, k2l[j], BC == BC_SOMMERFELD ? nf : 0);
+        cx<R> v = (br[j] - L.ih2 * lap) + c * u;
+        if (BC == BC_DIRICHLET && nf) v = czero<R>();
+        br[j] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 int mg_down_blocks(const Geo& gc, int zbc) {
@@ -547,21 +599,53 @@ void launch_mg_down(hipStream_t s, int bc, const Geo& gf, const Geo& gc, int zbc
 template <typename TB, typename R, typename TO>
 void launch_mg_up(hipStream_t s, int bc, const Geo& g, const Geo& gc, int zb, int nrhs,
                   const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
-                  const cx<R>* ec, cx<TO>* out, long long o_rstride, const RhsState* st, int gate) {
+                  const cx<R>* ec, cx<TO>* out, long long o_rstride, const RhsState* st, int gate,
+                  bool acc) {
     const TileShape T = up_tile_shape(g.nx, g.ny);
     dim3 grid(T.ntx * T.nty, (g.nz + zb - 1) / zb, nrhs);
-#define HH_UP(BCV, ONEV)                                                                                \
-    hipLaunchKernelGGL((k_mg_up<BCV, TB, R, TO, ONEV>), grid, dim3(UP_LANES), 0, s, g, gc, zb, b, b_rstride, \
-                       k2l, P.beta1, P.beta2, P.omega, ec, out, o_rstride, st, gate)
-    if (bc == BC_SOMMERFELD) {
-        if (zb == 1) HH_UP(BC_SOMMERFELD, true);
-        else HH_UP(BC_SOMMERFELD, false);
-    } else {
-        if (zb == 1) HH_UP(BC_DIRICHLET, true);
-        else HH_UP(BC_DIRICHLET, false);
+#define HH_UP(BCV, ONEV, ACCV)                                                                          \
+    hipLaunchKernelGGL((k_mg_up<BCV, TB, R, TO, ONEV, ACCV>), grid, dim3(UP_LANES), 0, s, g, gc, zb, b,    \
+                       b_rstride, k2l, P.beta1, P.beta2, P.omega, ec, out, o_rstride, st, gate)
+#define HH_UP_BC(ACCV)                                     \
+    if (bc == BC_SOMMERFELD) {                             \
+        if (zb == 1) HH_UP(BC_SOMMERFELD, true, ACCV);     \
+        else HH_UP(BC_SOMMERFELD, false, ACCV);            \
+    } else {                                               \
+        if (zb == 1) HH_UP(BC_DIRICHLET, true, ACCV);      \
+        else HH_UP(BC_DIRICHLET, false, ACCV);             \
     }
+    // accumulation only on the levels below the finest, where input, compute
+    // and output precision are one
+    if constexpr (std::is_same<TB, R>::value && std::is_same<TO, R>::value) {
+        if (acc) {
+            HH_UP_BC(true)
+            return;
+        }
+    }
+    HH_UP_BC(false)
+#undef HH_UP_BC
 #undef HH_UP
 }
+
+template <typename R>
+void launch_mg_resid(hipStream_t s, int bc, const Geo& g, int nrhs, cx<R>* b, const cx<R>* e, const R* k2l,
+                     const MgParams& P, const RhsState* st, int gate) {
+    // about four planes per lane, enough workgroups to spread over the chip
+    const int bx = (g.plane + RS_LANES - 1) / RS_LANES;
+    int zb = 4;
+    while (zb > 1 && (long long)bx * ((g.nz + zb - 1) / zb) * nrhs < 1024) zb >>= 1;
+    dim3 grid(bx, (g.nz + zb - 1) / zb, nrhs);
+    if (bc == BC_SOMMERFELD)
+        hipLaunchKernelGGL((k_mg_resid<BC_SOMMERFELD, R>), grid, dim3(RS_LANES), 0, s, g, zb, b, e, k2l,
+                           P.beta1, P.beta2, P.omega, st, gate);
+    else
+        hipLaunchKernelGGL((k_mg_resid<BC_DIRICHLET, R>), grid, dim3(RS_LANES), 0, s, g, zb, b, e, k2l,
+                           P.beta1, P.beta2, P.omega, st, gate);
+}
+template void launch_mg_resid<double>(hipStream_t, int, const Geo&, int, c128*, const c128*, const double*,
+                                      const MgParams&, const RhsState*, int);
+template void launch_mg_resid<float>(hipStream_t, int, const Geo&, int, c64*, const c64*, const float*,
+                                     const MgParams&, const RhsState*, int);
 
 #define HH_INST_F(TB, R, TO)                                                                           \
     template void launch_mg_down<TB, R>(hipStream_t, int, const Geo&, const Geo&, int, int, const cx<TB>*, \
@@ -569,7 +653,7 @@ void launch_mg_up(hipStream_t s, int bc, const Geo& g, const Geo& gc, int zb, in
                                         int);                                                             \
     template void launch_mg_up<TB, R, TO>(hipStream_t, int, const Geo&, const Geo&, int, int,              \
                                           const cx<TB>*, long long, const R*, const MgParams&,            \
-                                          const cx<R>*, cx<TO>*, long long, const RhsState*, int);
+                                          const cx<R>*, cx<TO>*, long long, const RhsState*, int, bool);
 HH_INST_F(double, double, double)
 HH_INST_F(double, float, double)
 HH_INST_F(float, float, float)

@@ -2,12 +2,14 @@
 //
 // Below a few thousand nodes a level's passes are pure latency: a separate
 // kernel per pass costs a launch and a memory round trip for microseconds of
-// work.  This kernel runs the whole rest of the V-cycle from level `first`
-// down to the coarsest level and back up (Algorithm 1 applied recursively:
-// damped-Jacobi pre-smoothing from zero, residual, full weighting, exact
-// coarsest solve with the dense inverse, trilinear prolongation, correction,
-// damped-Jacobi post-smoothing) with one workgroup per right-hand side; the
-// passes are separated by workgroup barriers instead of kernel boundaries.
+// work.  This kernel runs the rest of the cycle from level `first` down to the
+// coarsest level and back up (Algorithm 1 applied recursively: damped-Jacobi
+// pre-smoothing from zero, residual, full weighting, exact coarsest solve with
+// the dense inverse, trilinear prolongation, correction, damped-Jacobi
+// post-smoothing) with one workgroup per right-hand side; the passes are
+// separated by workgroup barriers instead of kernel boundaries.  The order of
+// the passes is a small program built on the host: the V-cycle, or the F-cycle's
+// coarse-grid solve, which adds residual passes and a second cycle.
 // Operators and boundary rules are those of the fused passes:
 //   M u = (1/h^2) lap(u) - c u,  lap(u)_j = sum_nb (u_j - u_nb) with the
 //   Sommerfeld ghost point replaced by its mirror image (its 2hik part is in c),
@@ -75,19 +77,23 @@ __device__ __forceinline__ cx<R> lap_at(const cx<R>* u, const TailLevel& L, int 
 }  // namespace
 
 template <int BC, typename R>
-__global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, const cx<R>* __restrict__ b_first,
+__global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, TailProg prog,
+                                                  const cx<R>* __restrict__ b_first,
                                                   cx<R>* __restrict__ e_first,
                                                   const RhsState* st, int gate) {
     extern __shared__ unsigned char tail_smem[];
     const int r = blockIdx.x;
     if (!gate_ok(st, r, gate)) return;
     const int t = threadIdx.x, nt = blockDim.x;
-    // LDS layout per level: b, u (the level's V-cycle result), w (scratch), k^2
+    // LDS layout: per level b, u (the level's cycle result) and w (scratch),
+    // then every level's s (an earlier result kept while another cycle runs),
+    // then every level's k^2
     cx<R>* base = reinterpret_cast<cx<R>*>(tail_smem);
     auto B = [&](int l) { return base + 3 * D.lv[l].off; };
     auto U = [&](int l) { return base + 3 * D.lv[l].off + D.lv[l].n; };
     auto T = [&](int l) { return base + 3 * D.lv[l].off + 2 * D.lv[l].n; };
-    R* kbase = reinterpret_cast<R*>(base + 3 * D.total);
+    auto S = [&](int l) { return base + 3 * D.total + D.lv[l].off; };
+    R* kbase = reinterpret_cast<R*>(base + 4 * D.total);
     auto K = [&](int l) { return kbase + D.lv[l].off; };
     auto coef = [&](int l) {
         TailCoef<R> C;
@@ -137,8 +143,9 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, const cx<R>* __res
         for (int i = t; i < D.lv[l].n; i += nt) K(l)[i] = kg[i];
     }
     __syncthreads();
-    // ---- down
-    for (int l = 0; l < nl - 1; ++l) {
+
+    // pre-smoothing from zero, residual and full weighting: b_{l+1} = R (b - M W b)
+    auto down = [&](int l) {
         const TailLevel& L = D.lv[l];
         const TailLevel& Lc = D.lv[l + 1];
         const TailCoef<R> C = coef(l);
@@ -146,7 +153,7 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, const cx<R>* __res
         cx<R>* u = U(l);
         cx<R>* w = T(l);
         const R* k2 = K(l);
-        // pre-smoothing from zero: u1 = W b
+        // u1 = W b
         for (int i = t; i < L.n; i += nt) {
             int x, y, z;
             unflat(i, L, x, y, z);
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, const cx<R>* __res
             u[i] = v;
         }
         __syncthreads();
-        // residual r = b - (1/h^2) lap(u1) + c u1
+        // r = b - (1/h^2) lap(u1) + c u1
         for (int i = t; i < L.n; i += nt) {
             int x, y, z;
             unflat(i, L, x, y, z);
@@ -190,9 +197,9 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, const cx<R>* __res
             bc[i] = acc;
         }
         __syncthreads();
-    }
-    // ---- coarsest: e = M_c^-1 b over the unknown nodes (inverse stored column-major)
-    {
+    };
+    // coarsest: e = M_c^-1 b over the unknown nodes (inverse stored column-major)
+    auto coarse = [&]() {
         const TailLevel& L = D.lv[nl - 1];
         cx<R>* b = B(nl - 1);
         cx<R>* u = U(nl - 1);
@@ -223,9 +230,10 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, const cx<R>* __res
             if (row < D.n_unk && sub == 0) u[D.cidx[row]] = s;
         }
         __syncthreads();
-    }
-    // ---- up
-    for (int l = nl - 2; l >= 0; --l) {
+    };
+    // trilinear prolongation, correction and post-smoothing:
+    // u2 = W b + P e_{l+1},  u3 = u2 + W (b - (1/h^2) lap(u2) + c u2)
+    auto up = [&](int l) {
         const TailLevel& L = D.lv[l];
         const TailLevel& Lc = D.lv[l + 1];
         const TailCoef<R> C = coef(l);
@@ -234,7 +242,6 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, const cx<R>* __res
         cx<R>* w = T(l);
         const cx<R>* ec = U(l + 1);
         const R* k2 = K(l);
-        // u2 = W b + P e (trilinear interpolation)
         for (int i = t; i < L.n; i += nt) {
             int x, y, z;
             unflat(i, L, x, y, z);
@@ -252,7 +259,6 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, const cx<R>* __res
             w[i] = v;
         }
         __syncthreads();
-        // post-smoothing: u3 = u2 + W (b - (1/h^2) lap(u2) + c u2)
         for (int i = t; i < L.n; i += nt) {
             int x, y, z;
             unflat(i, L, x, y, z);
@@ -264,6 +270,46 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, const cx<R>* __res
             u[i] = v;
         }
         __syncthreads();
+    };
+    // keep the level's result and replace its right-hand side by the residual:
+    // s = u, b = b - (1/h^2) lap(u) + c u  (b and s written only at the node itself)
+    auto resid = [&](int l) {
+        const TailLevel& L = D.lv[l];
+        const TailCoef<R> C = coef(l);
+        cx<R>* b = B(l);
+        const cx<R>* u = U(l);
+        cx<R>* sv = S(l);
+        const R* k2 = K(l);
+        for (int i = t; i < L.n; i += nt) {
+            int x, y, z;
+            unflat(i, L, x, y, z);
+            const int nf = faces(L, x, y, z);
+            const cx<R> ui = u[i];
+            cx<R> v = (b[i] - C.ih2 * lap_at(u, L, x, y, z)) + shift_c_t<BC>(C, k2[i], nf) * ui;
+            if (BC == BC_DIRICHLET && nf) v = czero<R>();
+            sv[i] = ui;
+            b[i] = v;
+        }
+        __syncthreads();
+    };
+    // u = s + u: the kept result plus the correction computed from its residual
+    auto accumulate = [&](int l) {
+        const TailLevel& L = D.lv[l];
+        cx<R>* u = U(l);
+        const cx<R>* sv = S(l);
+        for (int i = t; i < L.n; i += nt) u[i] = sv[i] + u[i];
+        __syncthreads();
+    };
+
+    for (int p = 0; p < prog.n; ++p) {
+        const int op = prog.op[p] >> 4, l = prog.op[p] & 15;
+        switch (op) {
+            case TAIL_DOWN: down(l); break;
+            case TAIL_COARSE: coarse(); break;
+            case TAIL_UP: up(l); break;
+            case TAIL_RESID: resid(l); break;
+            default: accumulate(l); break;
+        }
     }
     cx<R>* edst = e_first + (long long)r * D.lv[0].n;
     for (int i = t; i < D.lv[0].n; i += nt) edst[i] = U(0)[i];
@@ -272,7 +318,7 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, const cx<R>* __res
 size_t mg_tail_lds_bytes(const TailDesc& D, bool single) {
     const size_t cs = single ? sizeof(c64) : sizeof(c128);
     const size_t rs = single ? sizeof(float) : sizeof(double);
-    return (size_t)D.total * (3 * cs + rs);
+    return (size_t)D.total * (4 * cs + rs);
 }
 
 bool mg_tail_allow_lds(size_t bytes) {
@@ -288,19 +334,67 @@ bool mg_tail_allow_lds(size_t bytes) {
 }
 
 template <typename R>
-void launch_mg_tail(hipStream_t s, int bc, const TailDesc& D, int nrhs, const cx<R>* b_first,
-                    cx<R>* e_first, const RhsState* st, int gate) {
+void launch_mg_tail(hipStream_t s, int bc, const TailDesc& D, const TailProg& P, int nrhs,
+                    const cx<R>* b_first, cx<R>* e_first, const RhsState* st, int gate) {
     const size_t lds = mg_tail_lds_bytes(D, sizeof(R) == sizeof(float));
     if (bc == BC_SOMMERFELD)
-        hipLaunchKernelGGL((k_mg_tail<BC_SOMMERFELD, R>), dim3(nrhs), dim3(1024), lds, s, D, b_first, e_first,
-                           st, gate);
+        hipLaunchKernelGGL((k_mg_tail<BC_SOMMERFELD, R>), dim3(nrhs), dim3(1024), lds, s, D, P, b_first,
+                           e_first, st, gate);
     else
-        hipLaunchKernelGGL((k_mg_tail<BC_DIRICHLET, R>), dim3(nrhs), dim3(1024), lds, s, D, b_first, e_first,
-                           st, gate);
+        hipLaunchKernelGGL((k_mg_tail<BC_DIRICHLET, R>), dim3(nrhs), dim3(1024), lds, s, D, P, b_first,
+                           e_first, st, gate);
 }
-template void launch_mg_tail<double>(hipStream_t, int, const TailDesc&, int, const c128*, c128*,
-                                     const RhsState*, int);
-template void launch_mg_tail<float>(hipStream_t, int, const TailDesc&, int, const c64*, c64*,
-                                    const RhsState*, int);
+template void launch_mg_tail<double>(hipStream_t, int, const TailDesc&, const TailProg&, int, const c128*,
+                                     c128*, const RhsState*, int);
+template void launch_mg_tail<float>(hipStream_t, int, const TailDesc&, const TailProg&, int, const c64*,
+                                    c64*, const RhsState*, int);
+
+namespace {
+// Builds a tail program: F(l) = down l, coarse-grid solve C(l + 1), up l, where
+// C(l) is the F-cycle on level l followed, unless l is the coarsest level, by
+// one V-cycle on the residual that F-cycle leaves, added to its result
+// (section 3.4.5); F on the coarsest level is the exact solve.
+struct ProgBuilder {
+    TailProg P{};
+    int nlev;
+    void put(int op, int l) { P.op[P.n++] = (unsigned char)(op << 4 | l); }
+    void v(int l) {
+        for (int m = l; m < nlev - 1; ++m) put(TAIL_DOWN, m);
+        put(TAIL_COARSE, 0);
+        for (int m = nlev - 2; m >= l; --m) put(TAIL_UP, m);
+    }
+    void f(int l) {
+        if (l == nlev - 1) {
+            put(TAIL_COARSE, 0);
+            return;
+        }
+        put(TAIL_DOWN, l);
+        c(l + 1);
+        put(TAIL_UP, l);
+    }
+    void c(int l) {
+        f(l);
+        if (l < nlev - 1) {
+            put(TAIL_RESID, l);
+            v(l);
+            put(TAIL_ACC, l);
+        }
+    }
+};
+}  // namespace
+
+// The V-cycle from the tail's first level: down all levels, coarsest solve, up.
+TailProg tail_prog_v(int nlev) {
+    ProgBuilder b{TailProg{}, nlev};
+    b.v(0);
+    return b.P;
+}
+
+// The coarse-grid solver of an F-cycle one level above the tail's first level.
+TailProg tail_prog_f(int nlev) {
+    ProgBuilder b{TailProg{}, nlev};
+    b.c(0);
+    return b.P;
+}
 
 }  // namespace hh

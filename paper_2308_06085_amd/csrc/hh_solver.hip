@@ -88,6 +88,7 @@ struct hh_ctx {
     int check_every = 4;
     std::map<int, hipGraphExec_t> graphs;
     int tail_first = 0;   // first level run by the single-workgroup tail kernel
+    int cycle = 0;        // preconditioner cycle: 0 = V-cycle, 1 = F-cycle
     // z-planes per workgroup of each level's multigrid passes set by the caller
     // (0 = automatic); indexed by level, grown on demand
     std::vector<int> zb_down_set, zb_up_set;
@@ -215,7 +216,7 @@ int pick_zb(F blocks, int want) {
 // levels' LDS arrays fit the budget; level 0 always stays with the fused passes.
 void choose_tail(hh_ctx* c) {
     const int L = (int)c->lv.size();
-    const size_t per_node = c->mixed ? 3 * sizeof(c64) + sizeof(float) : 3 * sizeof(c128) + sizeof(double);
+    const size_t per_node = c->mixed ? 4 * sizeof(c64) + sizeof(float) : 4 * sizeof(c128) + sizeof(double);
     long long total = 0;
     int first = L - 1;
     total = c->lv[L - 1].g.n;
@@ -275,51 +276,92 @@ void apply_launch(hh_ctx* c) {
 }
 
 // -------------------------------------------------------------------------
-// V-cycle enqueue: z = V(bin) in precision R; level-0 input of type TB and
-// output of type TO (complex128, or complex64 inside the mixed solve).
+// Preconditioner cycle enqueue: z = V(bin) or F(bin) in precision R; level-0
+// input of type TB and output of type TO (complex128, or complex64 inside the
+// mixed solve).  Levels 1 .. tail_first - 1 run the fused passes, the rest the
+// tail kernel.
 // -------------------------------------------------------------------------
+template <typename R>
+struct CycleOps {
+    hh_ctx* c;
+    hipStream_t s;
+    int nrhs;
+    const RhsState* st;
+    int gate;
+    static cx<R>* C(void* p) { return reinterpret_cast<cx<R>*>(p); }
+    static const R* K(void* p) { return reinterpret_cast<const R*>(p); }
+    MgParams P() const { return MgParams{c->cfg.beta1, c->cfg.beta2, c->cfg.omega}; }
+    // b_{l+1} = R (b_l - M W b_l), 1 <= l < tail_first
+    void down(int l) const {
+        LevelBuf& a = c->lv[l];
+        LevelBuf& n = c->lv[l + 1];
+        launch_mg_down<R, R>(s, c->cfg.bc, a.g, n.g, a.zb_down, nrhs, C(a.b), a.g.n, K(a.k2l), P(), C(n.b), st,
+                             gate);
+    }
+    // e_l = post-smoothed (W b_l + P e_{l+1}); with acc added to e_l
+    void up(int l, bool acc) const {
+        LevelBuf& a = c->lv[l];
+        LevelBuf& n = c->lv[l + 1];
+        launch_mg_up<R, R, R>(s, c->cfg.bc, a.g, n.g, a.zb_up, nrhs, C(a.b), a.g.n, K(a.k2l), P(), C(n.e),
+                              C(a.e), a.g.n, st, gate, acc);
+    }
+    void tail(const TailProg& prog) const {
+        const int T = c->tail_first;
+        launch_mg_tail<R>(s, c->cfg.bc, tail_desc(c), prog, nrhs, C(c->lv[T].b), C(c->lv[T].e), st, gate);
+    }
+    // e_m = V(b_m); with acc, e_m += V(b_m)  (m < tail_first when acc)
+    void vcycle_from(int m, bool acc) const {
+        const int T = c->tail_first;
+        for (int l = m; l < T; ++l) down(l);
+        tail(tail_prog_v((int)c->lv.size() - T));
+        for (int l = T - 1; l >= m; --l) up(l, acc && l == m);
+    }
+    // The F-cycle's coarse-grid solve on level m >= 1 (section 3.4.5): e_m =
+    // F(b_m), then, below the coarsest level, e_m += V(b_m - M e_m).
+    void fcoarse(int m) const {
+        const int T = c->tail_first;
+        if (m >= T) {
+            tail(tail_prog_f((int)c->lv.size() - T));
+            return;
+        }
+        down(m);
+        fcoarse(m + 1);
+        up(m, false);
+        LevelBuf& a = c->lv[m];
+        launch_mg_resid<R>(s, c->cfg.bc, a.g, nrhs, C(a.b), C(a.e), K(a.k2l), P(), st, gate);
+        vcycle_from(m, true);
+    }
+};
+
 // ev_down / ev_up (may be null): event pairs recorded around the level-0 passes
 template <typename R, typename TB, typename TO>
-void enqueue_vcycle_t(hh_ctx* c, hipStream_t s, int nrhs, const cx<TB>* bin, cx<TO>* bout,
-                      const RhsState* st, int gate, hipEvent_t* ev_down = nullptr,
-                      hipEvent_t* ev_up = nullptr) {
+void enqueue_cycle_t(hh_ctx* c, hipStream_t s, int nrhs, const cx<TB>* bin, cx<TO>* bout,
+                     const RhsState* st, int gate, hipEvent_t* ev_down = nullptr,
+                     hipEvent_t* ev_up = nullptr) {
     const int bc = c->cfg.bc;
-    const int T = c->tail_first;
-    const MgParams P{c->cfg.beta1, c->cfg.beta2, c->cfg.omega};
-    auto C = [](void* p) { return reinterpret_cast<cx<R>*>(p); };
-    auto K = [](void* p) { return reinterpret_cast<const R*>(p); };
+    const CycleOps<R> ops{c, s, nrhs, st, gate};
     LevelBuf& f = c->lv[0];
     // down: one fused pass per level writes the next level's right-hand side
     if (ev_down) (void)hipEventRecord(ev_down[0], s);
-    launch_mg_down<TB, R>(s, bc, f.g, c->lv[1].g, f.zb_down, nrhs, bin, f.g.n, K(f.k2l), P,
-                          C(c->lv[1].b), st, gate);
+    launch_mg_down<TB, R>(s, bc, f.g, c->lv[1].g, f.zb_down, nrhs, bin, f.g.n, ops.K(f.k2l), ops.P(),
+                          ops.C(c->lv[1].b), st, gate);
     if (ev_down) (void)hipEventRecord(ev_down[1], s);
-    for (int l = 1; l < T; ++l) {
-        LevelBuf& a = c->lv[l];
-        LevelBuf& n = c->lv[l + 1];
-        launch_mg_down<R, R>(s, bc, a.g, n.g, a.zb_down, nrhs, C(a.b), a.g.n, K(a.k2l), P, C(n.b), st, gate);
-    }
-    // the smallest levels and the coarsest solve in one workgroup per right-hand side
-    launch_mg_tail<R>(s, bc, tail_desc(c), nrhs, C(c->lv[T].b), C(c->lv[T].e), st, gate);
-    // up: one fused pass per level writes the level's V-cycle result
-    for (int l = T - 1; l >= 1; --l) {
-        LevelBuf& a = c->lv[l];
-        LevelBuf& n = c->lv[l + 1];
-        launch_mg_up<R, R, R>(s, bc, a.g, n.g, a.zb_up, nrhs, C(a.b), a.g.n, K(a.k2l), P, C(n.e), C(a.e),
-                              a.g.n, st, gate);
-    }
+    // the coarse-grid solve: one V-cycle on level 1, or the F-cycle's
+    if (c->cycle == 1) ops.fcoarse(1);
+    else ops.vcycle_from(1, false);
+    // up: one fused pass writes the finest level's result
     if (ev_up) (void)hipEventRecord(ev_up[0], s);
-    launch_mg_up<TB, R, TO>(s, bc, f.g, c->lv[1].g, f.zb_up, nrhs, bin, f.g.n, K(f.k2l), P,
-                            C(c->lv[1].e), bout, f.g.n, st, gate);
+    launch_mg_up<TB, R, TO>(s, bc, f.g, c->lv[1].g, f.zb_up, nrhs, bin, f.g.n, ops.K(f.k2l), ops.P(),
+                            ops.C(c->lv[1].e), bout, f.g.n, st, gate);
     if (ev_up) (void)hipEventRecord(ev_up[1], s);
 }
 
-// complex128 in and out (the standalone V-cycle and the FP64 solve)
-void enqueue_vcycle(hh_ctx* c, hipStream_t s, int nrhs, const c128* bin, c128* bout,
-                    const RhsState* st, int gate, hipEvent_t* ev_down = nullptr,
-                    hipEvent_t* ev_up = nullptr) {
-    if (c->mixed) enqueue_vcycle_t<float, double, double>(c, s, nrhs, bin, bout, st, gate, ev_down, ev_up);
-    else enqueue_vcycle_t<double, double, double>(c, s, nrhs, bin, bout, st, gate, ev_down, ev_up);
+// complex128 in and out (the standalone cycle and the FP64 solve)
+void enqueue_cycle(hh_ctx* c, hipStream_t s, int nrhs, const c128* bin, c128* bout,
+                   const RhsState* st, int gate, hipEvent_t* ev_down = nullptr,
+                   hipEvent_t* ev_up = nullptr) {
+    if (c->mixed) enqueue_cycle_t<float, double, double>(c, s, nrhs, bin, bout, st, gate, ev_down, ev_up);
+    else enqueue_cycle_t<double, double, double>(c, s, nrhs, bin, bout, st, gate, ev_down, ev_up);
 }
 
 // One step of the iteration; the mixed solve keeps the preconditioner's inputs
@@ -346,8 +388,8 @@ void enqueue_iteration_t(hh_ctx* c, hipStream_t s, int nrhs, cx<TH>* ph, cx<TH>*
     launch_p_update(s, n, nrhs, c->p, c->r, c->v, p_low, c->st, F);
     mark(TL_P, 1);
     if constexpr (low)
-        enqueue_vcycle_t<float, float, float>(c, s, nrhs, p_low, ph, c->st, ST_RUN, E(TL_DOWN_P), E(TL_UP_P));
-    else enqueue_vcycle(c, s, nrhs, c->p, ph, c->st, ST_RUN, E(TL_DOWN_P), E(TL_UP_P));
+        enqueue_cycle_t<float, float, float>(c, s, nrhs, p_low, ph, c->st, ST_RUN, E(TL_DOWN_P), E(TL_UP_P));
+    else enqueue_cycle(c, s, nrhs, c->p, ph, c->st, ST_RUN, E(TL_DOWN_P), E(TL_UP_P));
     if (ev) {
         // the same launch with every right-hand side gated off (no iterating
         // one has status "idle"): the cost of the event bracket itself
@@ -365,8 +407,8 @@ void enqueue_iteration_t(hh_ctx* c, hipStream_t s, int nrhs, cx<TH>* ph, cx<TH>*
     launch_s_update(s, n, nrhs, c->s, c->r, c->v, s_low, c->st, c->part, NBLK_CAP, F);
     mark(TL_S, 1);
     if constexpr (low)
-        enqueue_vcycle_t<float, float, float>(c, s, nrhs, s_low, sh, c->st, ST_RUN, E(TL_DOWN_S), E(TL_UP_S));
-    else enqueue_vcycle(c, s, nrhs, c->s, sh, c->st, ST_RUN, E(TL_DOWN_S), E(TL_UP_S));
+        enqueue_cycle_t<float, float, float>(c, s, nrhs, s_low, sh, c->st, ST_RUN, E(TL_DOWN_S), E(TL_UP_S));
+    else enqueue_cycle(c, s, nrhs, c->s, sh, c->st, ST_RUN, E(TL_DOWN_S), E(TL_UP_S));
     mark(TL_APPLY_T, 0);
     launch_apply(s, bc, OP_T, g, c->L0, nrhs, sh, c->t, c->k2, c->kb, 1.0, 0.0, c->s, c->part, NBLK_CAP,
                  c->st, ST_RUN);
@@ -665,8 +707,13 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
     // 256 lanes x 4 planes: fastest in whole-solve timing on the wedge (mixed and FP64)
     c->base.block = 256;
     c->base.zb = 4;
-    // the tail kernel may use up to 128 KB of LDS where the device allows it
-    c->tail_lds_cap = mg_tail_allow_lds(131072) ? 131072 : 65536;
+    // the tail kernel may use up to 160 KB of LDS where the device allows it
+    c->tail_lds_cap = 65536;
+    for (size_t cap : {163840, 131072})
+        if (mg_tail_allow_lds(cap)) {
+            c->tail_lds_cap = cap;
+            break;
+        }
     (void)hipGetLastError();
     choose_tail(c);
     apply_launch(c);
@@ -769,7 +816,7 @@ hh_status hh_apply_shifted(hh_ctx* c, const void* x, void* y, int nrhs) {
 hh_status hh_apply_vcycle(hh_ctx* c, const void* r, void* z, int nrhs) {
     CHK(check_ready(c, nrhs));
     if (!r || !z) return fail(c, HH_ERR_ARG, "null pointer");
-    enqueue_vcycle(c, c->stream, nrhs, (const c128*)r, (c128*)z, nullptr, GATE_ALL);
+    enqueue_cycle(c, c->stream, nrhs, (const c128*)r, (c128*)z, nullptr, GATE_ALL);
     HIPCHK(c, hipGetLastError());
     return HH_OK;
 }
@@ -923,6 +970,10 @@ hh_status hh_set_option(hh_ctx* c, const char* name, long long value) {
             c->tsum[k] = 0.0;
             c->tcnt[k] = 0;
         }
+    } else if (n == "cycle") {
+        if (value != 0 && value != 1) return fail(c, HH_ERR_ARG, "cycle must be 0 (V-cycle) or 1 (F-cycle)");
+        c->cycle = (int)value;
+        invalidate_graphs(c);
     } else if (n == "block") {
         if (value != 64 && value != 128 && value != 256 && value != 512)
             return fail(c, HH_ERR_ARG, "block must be 64, 128, 256 or 512");
@@ -977,6 +1028,7 @@ hh_status hh_get_option(const hh_ctx* c, const char* name, long long* value) {
     else if (n == "tail_first") *value = c->tail_first;
     else if (n == "check_every") *value = c->check_every;
     else if (n == "trace") *value = c->trace;
+    else if (n == "cycle") *value = c->cycle;
     else if (n == "block") *value = c->L0.block;
     else if (n == "zb") *value = c->L0.zb;
     else if (n == "n_levels") *value = (long long)c->lv.size();

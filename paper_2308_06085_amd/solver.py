@@ -53,11 +53,12 @@ class Solver:
     bc: "sommerfeld" | "dirichlet"; prec: "fp64" | "mixed" (complex64 V-cycle
     inside a complex128 Bi-CGSTAB); beta = (beta1, beta2) of the CSLP
     M = -Laplace - (beta1 - beta2 i) k^2 (default (1, -0.5)); omega: Jacobi
-    weight (0.8); n_levels: 0 = coarsen while >= 3 nodes per axis remain.
+    weight (0.8); n_levels: 0 = coarsen while >= 3 nodes per axis remain;
+    cycle: "V" | "F", the multigrid cycle that approximates M^-1 (section 3.4.5).
     """
 
     def __init__(self, shape, h, bc="sommerfeld", prec="fp64", n_levels=0, nrhs_max=1,
-                 beta=(1.0, -0.5), omega=0.8, device=None):
+                 beta=(1.0, -0.5), omega=0.8, cycle="V", device=None):
         self.lib = _lib.load()
         nz, ny, nx = (int(v) for v in shape)
         self.shape = (nz, ny, nx)
@@ -81,6 +82,12 @@ class Solver:
         self.ctx = ctx
         self.nrhs = 0
         self._k = None
+        if cycle not in ("V", "F"):
+            self.close()
+            raise ValueError(f"cycle must be 'V' or 'F', not {cycle!r}")
+        self.cycle = cycle
+        if cycle == "F":
+            self.set_option("cycle", 1)
 
     # -- lifetime -----------------------------------------------------------
     def close(self):
@@ -182,7 +189,8 @@ class Solver:
         return self._apply(self.lib.hh_apply_shifted, x)
 
     def apply_vcycle(self, r):
-        """z = one V(1,1)-cycle applied to r (approximates M^-1 r)."""
+        """z = one multigrid (1,1) cycle applied to r (approximates M^-1 r): the
+        V-cycle, or the F-cycle when the solver was made with cycle="F"."""
         return self._apply(self.lib.hh_apply_vcycle, r)
 
     def adjoint_rhs(self, g):
