@@ -1,6 +1,7 @@
 """Benchmark: DoF-iterations/s of CSLP-preconditioned Bi-CGSTAB on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload wedge|cube513|batched]
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+                    [--workload wedge|cube513|batched|beta2_sweep]
 
 One step = one complete solve to ||b - A x|| / ||b|| <= 1e-6 of the workload
 (model and sources resident in HBM before the timed region).  The default
@@ -27,6 +28,15 @@ algorithmic bytes per launch / ``avg_ms``, against 8 TB/s HBM3E peak;
 ``launches`` is the number of launches behind the average.
 ``cpu_baseline`` times the CPU oracle on a bounded sample (a few Bi-CGSTAB
 steps of the same workload) on the host.
+
+``fcycle`` (wedge workload): the same solves with one F(1,1)-cycle instead of
+the V-cycle as the preconditioner (section 3.4.5), both precisions, timed the
+same way: iterations, time per solve and the time-to-solution ratio V / F.
+
+``--workload beta2_sweep``: the paper's F-cycle experiment (section 5), the
+wedge at 40 Hz on 193 x 193 x 321 nodes (h = 3.125 m), mixed precision, V- and
+F-cycle for beta2 = -0.5 ... -1.0: Bi-CGSTAB iterations and time per solve to
+1e-6 (at most 600 iterations); ``value`` is the fastest solve's time in ms.
 """
 from __future__ import annotations
 
@@ -96,6 +106,9 @@ def make_workload(name):
     if name == "cube513":
         wl = W.big_cube()
         return wl, wl.sources, "cube 513^3 k=160 kh=0.3125 Sommerfeld, 8 levels, 1 source"
+    if name == "beta2_sweep":
+        wl = W.wedge(40.0, 193, 193, 321)
+        return wl, wl.sources, "wedge 193x193x321 f=40Hz h=3.125m Sommerfeld, 1 source"
     if name == "batched":
         wl = W.wedge(10.0)
         src = W.batched_wedge_sources(16, seed=4)
@@ -178,12 +191,76 @@ def cpu_baseline(wl, nodes, n_iter):
                       f"NumPy/SciPy single thread on the host ({dt:.1f} s)"}
 
 
+def beta2_sweep(args, wl, nodes, desc):
+    """V- and F-cycle solves over the complex shift beta2 (mixed precision)."""
+    import torch
+
+    from paper_2308_06085_amd import Solver
+
+    k = torch.from_numpy(wl.k).cuda()
+    rows = []
+    for beta2 in (-0.5, -0.6, -0.7, -0.8, -0.9, -1.0):
+        for cyc in ("V", "F"):
+            s = Solver(wl.shape, wl.h, bc=wl.bc, prec="mixed", cycle=cyc, beta=(1.0, beta2))
+            s.set_model(k)
+            s.set_point_sources(nodes)
+            x = None
+            for _ in range(args.warmup):
+                x, _ = s.solve(rtol=1e-6, maxit=600, out=x)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                x, st = s.solve(rtol=1e-6, maxit=600, out=x)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / args.steps
+            rows.append({"beta2": beta2, "cycle": cyc, "iterations": st[0].iterations,
+                         "status": st[0].status, "relres_true": st[0].relres_true, "ms_per_solve": ms})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            s.close()
+            del x
+    ok = [r for r in rows if r["status"] == "HH_OK"]
+    best = min(ok, key=lambda r: r["ms_per_solve"])
+    line = {
+        "metric": "time to 1e-6 rel residual of CSLP-Bi-CGSTAB over beta2, V- vs F-cycle (mixed)",
+        "value": best["ms_per_solve"], "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": best["ms_per_solve"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64 cycle / c128 Krylov", "data": "synthetic",
+        "config": {"workload": desc, "unknowns": dof(wl), "nrhs": 1, "rtol": 1e-6, "maxit": 600,
+                   "precision": "mixed"},
+        "best": best, "sweep": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def fcycle_solves(args, wl, nodes, make, vres):
+    """The timed solves again with the F-cycle preconditioner."""
+    import torch
+
+    out = {}
+    for prec, v in vres.items():
+        s = make(prec)
+        s.set_option("cycle", 1)
+        x, stats, times, iters = run_solves(s, args.steps, args.warmup)
+        t = float(np.sum(times))
+        out[prec] = {"value": dof(wl) * float(np.sum(iters)) / t, "ms_per_step": 1e3 * t / args.steps,
+                     "iterations": float(np.mean(iters)), "relres_true_max": max(st.relres_true for st in stats),
+                     "status": sorted({st.status for st in stats}),
+                     "time_to_solution_speedup_vs_vcycle": v["ms_per_step"] / (1e3 * t / args.steps)}
+        s.close()
+        del x
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="wedge", choices=["wedge", "cube513", "batched"])
+    ap.add_argument("--workload", default="wedge", choices=["wedge", "cube513", "batched", "beta2_sweep"])
+    ap.add_argument("--no-fcycle", action="store_true", help="skip the F-cycle solves of the wedge")
+    ap.add_argument("--cycle", default="V", choices=["V", "F"],
+                    help="preconditioner cycle of the timed solves (default V; F implies --no-fcycle)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=4)
@@ -210,12 +287,15 @@ def main():
         torch.cuda.synchronize()
         del a, bbuf
     wl, nodes, desc = make_workload(args.workload)
+    if args.workload == "beta2_sweep":
+        beta2_sweep(args, wl, nodes, desc)
+        return
     nrhs = len(nodes)
     n_nodes = int(np.prod(wl.shape))
     k = torch.from_numpy(wl.k).cuda()
 
     def make(prec):
-        s = Solver(wl.shape, wl.h, bc=wl.bc, prec=prec, n_levels=wl.n_levels, nrhs_max=nrhs)
+        s = Solver(wl.shape, wl.h, bc=wl.bc, prec=prec, n_levels=wl.n_levels, nrhs_max=nrhs, cycle=args.cycle)
         s.set_model(k)
         s.set_point_sources(nodes)
         if args.autotune:
@@ -262,6 +342,9 @@ def main():
         del xr
     solutions.clear()
     torch.cuda.empty_cache()
+    fres = None
+    if args.workload == "wedge" and not args.no_fcycle and args.cycle == "V":
+        fres = fcycle_solves(args, wl, nodes, make, results)
 
     head = results["mixed"]
     dom = head["dominant"]
@@ -281,10 +364,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 V-cycle / c128 Krylov",
+        "dtype": f"c64 {args.cycle}-cycle / c128 Krylov",
         "data": "synthetic",
         "config": {"workload": desc, "unknowns": dof(wl), "nrhs": nrhs, "rtol": 1e-6,
-                   "precision": "mixed"},
+                   "precision": "mixed", "cycle": args.cycle},
         "iterations": head["iterations"],
         "relres_true_max": head["relres_true_max"],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": row["GBs"], "peak": HBM_PEAK_GBS,
@@ -306,6 +389,8 @@ def main():
                                                / (head["ms_per_step"] / head["iterations"]))
     if ref_err is not None:
         line["error_vs_fp64_reference"] = ref_err
+    if fres is not None:
+        line["fcycle"] = fres
     if not args.no_cpu and args.workload != "cube513":
         line["cpu_baseline"] = cpu_baseline(wl, nodes, args.cpu_iters)
     print(json.dumps(line), flush=True)
