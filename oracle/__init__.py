@@ -16,8 +16,8 @@ Modules
                     rediscretised coarse operators, exact coarsest solve,
                     recursive V- and F-cycles (section 3.4, Algorithm 1,
                     section 4.2).
-``krylov``          right-preconditioned Bi-CGSTAB with the true-residual
-                    stopping rule of section 5.
+``krylov``          right-preconditioned Bi-CGSTAB and IDR(s) with the
+                    true-residual stopping rule of section 5.
 ``adjoint``         misfit gradient with respect to squared slowness by one
                     adjoint solve.
 
@@ -45,5 +45,5 @@ from .multigrid import (  # noqa: F401
     vcycle,
     fcycle,
 )
-from .krylov import bicgstab, SolveResult, Status  # noqa: F401
+from .krylov import bicgstab, idrs, SolveResult, Status  # noqa: F401
 from .adjoint import misfit_and_gradient, adjoint_gradient_pointwise, solve_forward  # noqa: F401

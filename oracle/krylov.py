@@ -1,4 +1,4 @@
-"""Right-preconditioned Bi-CGSTAB (oracle; test infrastructure only).
+"""Right-preconditioned Bi-CGSTAB and IDR(s) (oracle; test infrastructure only).
 
 The paper uses Bi-CGSTAB (van der Vorst 1992) with right preconditioning
 (section 3.2), so the recursively updated residual is the true one, and stops
@@ -156,3 +156,155 @@ def bicgstab(apply_A, precond, b, x0=None, tol=1e-6, maxit=1000, max_restarts=5,
         matvecs += 1
     true_rel = _norm(b - apply_A(x)) / bnorm
     return SolveResult(x, status, iters, matvecs, relres, true_rel, history)
+
+
+def idrs(apply_A, precond, b, P, x0=None, tol=1e-6, maxit=2000, kappa=0.7, max_restarts=5,
+         breakdown_tol=1e-300, fixed_steps=None, monitor=None) -> SolveResult:
+    """Solve A x = b by right-preconditioned IDR(s), s = len(P) (section 3.1:
+    the paper's IDR(4), after Sonneveld and van Gijzen; stopped, like
+    Bi-CGSTAB, on the true relative residual of section 5).
+
+    The paper does not print the algorithm.  This is the biorthogonal variant
+    (van Gijzen and Sonneveld, ACM TOMS 38(1), 2011), with the preconditioner
+    K (one multigrid cycle on M) applied on the right so that r stays the
+    residual b - A x of the unpreconditioned system:
+
+        r = b - A x;  G = U = 0 (s vectors each);  Ms = I (s x s);  om = 1
+        repeat
+            f = P^H r                                   (f_i = <p_i, r>)
+            for k = 1 .. s
+                c = Ms[k:s, k:s]^-1 f[k:s]              (lower triangular)
+                v = K (r - sum_{j>=k} c_j g_j)
+                u_k = sum_{j>=k} c_j u_j + om v
+                g_k = A u_k
+                for i = 1 .. k-1                         (make g_k orthogonal to p_1..p_{k-1})
+                    a = <p_i, g_k> / Ms[i, i]
+                    g_k -= a g_i;  u_k -= a u_i
+                Ms[i, k] = <p_i, g_k>  for i = k .. s
+                beta = f_k / Ms[k, k]
+                r -= beta g_k;  x += beta u_k           (now r is orthogonal to p_1..p_k)
+                stop if ||r|| / ||b|| <= tol
+                f[k+1:s] -= beta Ms[k+1:s, k]
+            v = K r;  t = A v                            (dimension reduction)
+            om = <t, r> / <t, t>,  enlarged by kappa / rho when
+                 rho = |<t, r>| / (||t|| ||r||) < kappa   (kappa = 0.7; 0 disables)
+            x += om v;  r -= om t
+            stop if ||r|| / ||b|| <= tol
+
+    Counting: ``iterations`` = products with A after the initial residual
+    (s + 1 per cycle); ``matvecs`` adds the initial residual (and one per
+    restart), the paper's #Matvec.  After the loop the true residual decides,
+    as in ``bicgstab``: a miss restarts from x with G = U = 0.
+
+    P           : array (s,) + b.shape of shadow vectors (linearly independent).
+    fixed_steps : stop after exactly this many A-products, no stopping test.
+    monitor     : optional callable(k, x, r, G, U, Ms) after every update of r
+                  (k = inner step 0 .. s-1, or s for the reduction step).
+    """
+    b = np.asarray(b)
+    P = np.asarray(P)
+    s_dim = P.shape[0]
+    bnorm = _norm(b)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=b.dtype)
+    if bnorm == 0.0:
+        return SolveResult(np.zeros_like(b), Status.OK, 0, 0, 0.0, 0.0)
+    history = []
+    steps = 0
+    matvecs = 1
+    restarts = 0
+    status = Status.NOT_CONVERGED
+    relres = np.inf
+
+    def done():
+        if fixed_steps is not None:
+            return steps >= fixed_steps
+        return relres <= tol
+
+    while True:
+        r = b - apply_A(x) if (x0 is not None or restarts > 0) else b.copy()
+        relres = _norm(r) / bnorm
+        G = np.zeros((s_dim,) + b.shape, dtype=b.dtype)
+        U = np.zeros((s_dim,) + b.shape, dtype=b.dtype)
+        Ms = np.eye(s_dim, dtype=np.complex128)
+        om = 1.0 + 0j
+        stop = done()
+        while not stop and (steps < maxit or fixed_steps is not None):
+            f = np.array([_vdot(P[i], r) for i in range(s_dim)])
+            for k in range(s_dim):
+                c = np.linalg.solve(np.tril(Ms[k:, k:]), f[k:])
+                v = r.copy()
+                for j in range(k, s_dim):
+                    v = v - c[j - k] * G[j]
+                v = precond(v)
+                uk = om * v
+                for j in range(k, s_dim):
+                    uk = uk + c[j - k] * U[j]
+                U[k] = uk
+                G[k] = apply_A(U[k])
+                steps += 1
+                matvecs += 1
+                for i in range(k):
+                    a = _vdot(P[i], G[k]) / Ms[i, i]
+                    G[k] = G[k] - a * G[i]
+                    U[k] = U[k] - a * U[i]
+                for i in range(k, s_dim):
+                    Ms[i, k] = _vdot(P[i], G[k])
+                if abs(Ms[k, k]) <= breakdown_tol * _norm(P[k]) * _norm(G[k]):
+                    status = Status.BREAKDOWN
+                    stop = True
+                    break
+                beta = f[k] / Ms[k, k]
+                r = r - beta * G[k]
+                x = x + beta * U[k]
+                relres = _norm(r) / bnorm
+                history.append(relres)
+                if monitor is not None:
+                    monitor(k, x, r, G, U, Ms)
+                if done() or (fixed_steps is None and steps >= maxit):
+                    stop = True
+                    break
+                f[k + 1:] = f[k + 1:] - beta * Ms[k + 1:, k]
+            if stop:
+                break
+            v = precond(r)
+            t = apply_A(v)
+            steps += 1
+            matvecs += 1
+            tt = _vdot(t, t)
+            if tt == 0.0:
+                status = Status.BREAKDOWN
+                break
+            tr = _vdot(t, r)
+            om = tr / tt
+            rho = abs(tr) / (np.sqrt(tt.real) * _norm(r))
+            if rho < kappa:
+                om = om * kappa / rho
+            if abs(om) <= breakdown_tol:
+                status = Status.BREAKDOWN
+                break
+            x = x + om * v
+            r = r - om * t
+            relres = _norm(r) / bnorm
+            history.append(relres)
+            if monitor is not None:
+                monitor(s_dim, x, r, G, U, Ms)
+            stop = done()
+        if fixed_steps is not None:
+            status = Status.OK
+            break
+        if status == Status.BREAKDOWN:
+            break
+        if relres > tol:
+            status = Status.NOT_CONVERGED
+            break
+        true_rel = _norm(b - apply_A(x)) / bnorm
+        if true_rel <= tol:
+            status = Status.OK
+            break
+        restarts += 1
+        if restarts > max_restarts or steps >= maxit:
+            status = Status.NOT_CONVERGED
+            break
+        matvecs += 1
+    true_rel = _norm(b - apply_A(x)) / bnorm
+    return SolveResult(x, status, steps, matvecs, relres, true_rel, history)

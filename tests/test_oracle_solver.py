@@ -204,3 +204,86 @@ def test_fcycle_preconditioner_beats_vcycle_at_large_shift():
     rf = O.bicgstab(lambda x: O.apply_A(x, lvl), lambda r: fcycle(r, hier), b, maxit=200)
     assert rv.status == O.Status.OK and rf.status == O.Status.OK
     assert rf.iterations < rv.iterations, (rf.iterations, rv.iterations)
+
+
+# --------------------------------------------------------------------------
+# IDR(s)
+# --------------------------------------------------------------------------
+def _shadow(s, shape, seed, mask=None):
+    rng = np.random.default_rng(seed)
+    P = rng.standard_normal((s,) + shape) + 1j * rng.standard_normal((s,) + shape)
+    return P if mask is None else P * mask
+
+
+def test_idr1_with_r0_shadow_equals_bicgstab():
+    """IDR(1) with the shadow vector r_0 and the plain minimal-residual omega
+    (kappa = 0) is Bi-CGSTAB: after 2j products with A its iterate is
+    Bi-CGSTAB's after j steps (Sonneveld and van Gijzen 2008)."""
+    lvl, hier, b = _problem(17, SOMMERFELD, seed=3)
+    A = lambda x: O.apply_A(x, lvl)  # noqa: E731
+    K = lambda r: vcycle(r, hier)  # noqa: E731
+    for j in (1, 2, 5):
+        ri = O.idrs(A, K, b, b[None], kappa=0.0, fixed_steps=2 * j)
+        rb = O.bicgstab(A, K, b, fixed_iterations=j)
+        assert np.abs(ri.x - rb.x).max() <= 1e-11 * np.abs(rb.x).max(), j
+
+
+def test_idrs_biorthogonality_and_true_residual():
+    """IDR(4) invariants after every update of r: r = b - A x; after inner step k
+    r is orthogonal to p_1..p_k; g_k is orthogonal to p_1..p_{k-1}; the small
+    matrix holds the inner products <p_i, g_j> and is lower triangular."""
+    lvl, hier, b = _problem(17, SOMMERFELD, seed=4)
+    A = lambda x: O.apply_A(x, lvl)  # noqa: E731
+    P = _shadow(4, b.shape, 5)
+    nb = np.linalg.norm(b)
+    seen = []
+
+    def mon(k, x, r, G, U, Ms):
+        assert np.linalg.norm(b - A(x) - r) <= 1e-10 * nb
+        if k < 4:
+            for i in range(k + 1):
+                assert abs(np.vdot(P[i], r)) <= 1e-9 * np.linalg.norm(P[i]) * nb, (k, i)
+            for i in range(k):
+                assert abs(np.vdot(P[i], G[k])) <= 1e-9 * np.linalg.norm(P[i]) * np.linalg.norm(G[k])
+            for i in range(k, 4):
+                assert abs(Ms[i, k] - np.vdot(P[i], G[k])) <= 1e-12 * abs(Ms[i, k]) + 1e-300
+            assert np.all(np.triu(Ms[: k + 1, : k + 1], 1) == 0)
+        seen.append(k)
+
+    res = O.idrs(A, lambda r: vcycle(r, hier), b, P, fixed_steps=15, monitor=mon)
+    assert res.iterations == 15 and seen == [0, 1, 2, 3, 4] * 3
+
+
+@pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
+def test_idrs_solution_matches_dense_direct_solve(bc):
+    lvl, hier, b = _problem(9, bc, seed=6)
+    mask = unknown_mask(lvl.shape, bc)
+    res = O.idrs(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, _shadow(4, b.shape, 7, mask),
+                 tol=1e-12)
+    assert res.status == O.Status.OK
+    idx = np.flatnonzero(mask.ravel())
+    cols = []
+    for j in idx:
+        e = np.zeros(lvl.shape, dtype=np.complex128)
+        e.ravel()[j] = 1.0
+        cols.append(O.apply_A(e, lvl).ravel()[idx])
+    xd = np.linalg.solve(np.array(cols).T, b.ravel()[idx])
+    assert np.abs(res.x.ravel()[idx] - xd).max() <= 1e-9 * np.abs(xd).max()
+
+
+def test_paper_table1_idr4_matvec_band():
+    """Table 1: IDR(4) needs 192 matvecs (np = 1) to 211 on the closed-off 65^3,
+    k = 40 problem; the count depends on the random shadow vectors and on
+    rounding.  Band [0.8 min, 1.15 max] as for Bi-CGSTAB, and clearly fewer
+    matvecs than Bi-CGSTAB on the same problem."""
+    with open(os.path.join(GOLDEN, "table1_bicgstab_matvec.json")) as f:
+        gold = json.load(f)
+    lvl, b, uex = O.closed_off_problem(gold["problem"]["n"], gold["problem"]["k"])
+    hier = build_hierarchy(lvl.k, lvl.h, lvl.bc, rule="paper17")
+    P = _shadow(4, b.shape, 0, unknown_mask(lvl.shape, lvl.bc))
+    res = O.idrs(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, P, tol=gold["problem"]["tol"])
+    assert res.status == O.Status.OK
+    lo, hi = 0.8 * min(gold["idr4"]), 1.15 * max(gold["idr4"])
+    assert lo <= res.matvecs <= hi, res.matvecs
+    assert res.matvecs < 0.75 * min(gold["bicgstab"])
+    assert np.abs(res.x - uex).max() < 2e-3
