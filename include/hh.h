@@ -6,7 +6,8 @@
  * spacing h (Chen, Dwarka, Vuik, arXiv 2308.06085, section 2.4, eq. Helmstencil),
  * with homogeneous Dirichlet or first-order Sommerfeld boundary conditions
  * (section 2; Sommerfeld ghost points eliminated by eq. elimination), by
- * right-preconditioned Bi-CGSTAB (section 3.1, 3.2) stopped at
+ * right-preconditioned Bi-CGSTAB, or IDR(s) (section 3.1, 3.2; option
+ * "method"), stopped at
  * ||b - A u|| / ||b|| <= rtol (section 5).  The preconditioner is the complex
  * shifted Laplacian M = -Laplace_h - (beta1 - beta2 i) k^2 I (section 3.3,
  * eq. preconditioner) inverted approximately by one geometric multigrid
@@ -30,8 +31,9 @@
  * - Ownership: the caller owns every pointer it passes; the library copies what
  *   it keeps (model, sources) and never retains a caller pointer after a call
  *   returns.  All scratch (Krylov vectors, grid hierarchy, coarse inverse,
- *   graphs) is owned by the context and allocated in hh_create / hh_set_model;
- *   hh_solve and the hh_apply_* calls allocate nothing.
+ *   graphs) is owned by the context and allocated in hh_create / hh_set_model
+ *   (the IDR(s) vectors when option "method" = 1, "idr_s" or hh_set_shadow asks
+ *   for them); hh_solve and the hh_apply_* calls allocate nothing.
  * - Streams: all device work is enqueued on the stream given to hh_create.
  *   hh_create, hh_set_model, hh_solve return after the work has completed;
  *   hh_set_sources, hh_apply_*, hh_adjoint_rhs and hh_grad_slowness2 return
@@ -129,8 +131,17 @@ hh_status hh_set_point_sources(hh_ctx* ctx, const int* ijk_host, int nrhs);
 /* Solve A x_r = b_r for the right-hand sides of the last hh_set_*sources call.
  * x: (nrhs, nz, ny, nx) complex128; read as the initial guess when use_x0 != 0,
  * else x0 = 0; overwritten with the solution.  rtol > 0, maxit >= 1 (full
- * Bi-CGSTAB steps).  stats_host: nrhs entries (may be NULL).  Returns HH_OK if
- * every right-hand side converged, else the first failing status. */
+ * Bi-CGSTAB steps; for IDR(s), products with A).  stats_host: nrhs entries (may
+ * be NULL).  Returns HH_OK if every right-hand side converged, else the first
+ * failing status.
+ * With option "method" = 1 the Krylov method is IDR(s) (the paper's IDR(4) for
+ * s = 4), biorthogonal variant (van Gijzen and Sonneveld, ACM TOMS 38(1), 2011)
+ * with the multigrid cycle applied on the right: s inner steps and one
+ * minimal-residual step per cycle, s + 1 products with A and with the
+ * preconditioner; the residual stays b - A x and is tested after every update.
+ * stats.iterations then counts products with A after the initial residual,
+ * stats.matvecs adds the initial residual and one per restart (the paper's
+ * #Matvec). */
 hh_status hh_solve(hh_ctx* ctx, void* x, double rtol, int maxit, int use_x0,
                    hh_stats* stats_host);
 
@@ -162,6 +173,18 @@ hh_status hh_adjoint_rhs(hh_ctx* ctx, const void* g, void* rhs, int nrhs);
 hh_status hh_grad_slowness2(hh_ctx* ctx, const void* u, const void* w, const double* s,
                             double omega, double* grad, int nrhs);
 
+/* Shadow vectors of IDR(s): P is (s, nz, ny, nx) complex128 on the device,
+ * 1 <= s <= 8; they are stored rounded to complex64 (only inner products
+ * <p_i, y> use them) and replace the generated ones until option "idr_s" or
+ * "idr_seed" changes.  Sets "idr_s" to s.  Any s linearly independent vectors
+ * work; the solution does not depend on them, the iterates do.  Without this
+ * call the library draws them from SplitMix64 (Steele, Lea and Flood 2014):
+ * entry e = i n + node of vector i takes its real and imaginary parts from the
+ * outputs for the counters seed 2^40 + 2e and seed 2^40 + 2e + 1, each mapped
+ * to [-1, 1) through its top 53 bits.  Allocates the IDR vectors if needed;
+ * HH_ERR_ARG for a null P or s outside 1..8. */
+hh_status hh_set_shadow(hh_ctx* ctx, const void* P, int s);
+
 /* Options: "graph" (1 = replay each Bi-CGSTAB step as a captured hipGraph,
  * default 1), "check_every" (steps between host convergence checks, default 4),
  * "block" (threads per workgroup of the stencil kernels: 64, 128, 256, 512;
@@ -175,6 +198,14 @@ hh_status hh_grad_slowness2(hh_ctx* ctx, const void* u, const void* w, const dou
  * visits level l >= 1 l + 1 times per application instead of once and adds one
  * residual pass on each level from 1 to the second coarsest; other values are
  * HH_ERR_ARG).
+ * "method" (0 = Bi-CGSTAB, default; 1 = IDR(s), see hh_solve; allocates
+ * 2 s complex128 vectors per right-hand side and s complex64 ones),
+ * "idr_s" (1..8, default 4), "idr_seed" (0..2^23 - 1, default 1: the generated
+ * shadow vectors), "idr_kappa_milli" (0..1000, default 700: the reduction step
+ * enlarges omega to kappa / rho times the minimal-residual value when
+ * rho = |<t, r>| / (|t| |r|) < kappa; 0 = plain minimal residual).  An IDR(s)
+ * solve replays one cycle per captured hipGraph; with "trace" its steps are
+ * launched directly and not timed.
  * hh_get_option also reports "n_levels", "coarse_unknowns", "tail_first" (first
  * level run by the tail kernel) and the z-planes in use under the same names. */
 hh_status hh_set_option(hh_ctx* ctx, const char* name, long long value);

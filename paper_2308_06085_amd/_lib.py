@@ -31,7 +31,7 @@ EXPORTS = [
     "hh_default_config", "hh_create", "hh_destroy", "hh_last_error", "hh_level_shape",
     "hh_set_model", "hh_set_sources", "hh_set_point_sources", "hh_solve",
     "hh_apply_operator", "hh_apply_shifted", "hh_apply_vcycle", "hh_adjoint_rhs",
-    "hh_grad_slowness2", "hh_set_option", "hh_get_option", "hh_time_kernel", "hh_kernel_times",
+    "hh_grad_slowness2", "hh_set_shadow", "hh_set_option", "hh_get_option", "hh_time_kernel", "hh_kernel_times",
     "hh_autotune",
 ]
 
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
         "hh_apply_vcycle": (ip, [vp, vp, vp, ip]),
         "hh_adjoint_rhs": (ip, [vp, vp, vp, ip]),
         "hh_grad_slowness2": (ip, [vp, vp, vp, vp, dp, vp, ip]),
+        "hh_set_shadow": (ip, [vp, vp, ip]),
         "hh_set_option": (ip, [vp, C.c_char_p, C.c_longlong]),
         "hh_get_option": (ip, [vp, C.c_char_p, C.POINTER(C.c_longlong)]),
         "hh_time_kernel": (ip, [vp, ip, ip, ip, C.POINTER(C.c_float)]),

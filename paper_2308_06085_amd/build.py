@@ -16,7 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhh.so")
-SOURCES = ["hh_kernels.hip", "hh_mg_fused.hip", "hh_mg_tail.hip", "hh_solver.hip"]
+SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
 ARCH = os.environ.get("HH_OFFLOAD_ARCH", "gfx950")
 
 
@@ -45,7 +45,8 @@ def build(verbose: bool = False) -> str:
         if verbose and noise:
             print("\n".join(noise), file=sys.stderr)
         objs.append(obj)
-    cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    # -z defs: a symbol no source defines fails the link instead of the first load
+    cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Wl,-z,defs", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc link failed:\n" + r.stderr)

@@ -43,6 +43,56 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NT], double* out, lo
     }
 }
 
+// Sum of the per-workgroup partials of NT consecutive rows (row t at
+// part[t * nblk_max]) in a fixed order, for the one-workgroup finalize kernels.
+// Every thread receives the sums.
+template <int NT>
+__device__ inline void block_fixed_sum(const double* __restrict__ part, long long nblk, long long nblk_max,
+                                double (&out)[NT]) {
+    __shared__ double sm[NT][16];
+    double v[NT];
+    // lane t adds partials t, t + blockDim, t + 2 blockDim, ... in that order; the
+    // loads of eight consecutive terms of that sequence are issued before their
+    // adds (out-of-range slots read a valid partial and add exactly zero)
+    constexpr int U = 8;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) v[t] = 0.0;
+    for (long long b0 = threadIdx.x; b0 < nblk; b0 += (long long)U * blockDim.x) {
+        double ld[NT][U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long b = b0 + (long long)u * blockDim.x;
+            const long long bc = b < nblk ? b : nblk - 1;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) ld[t][u] = part[t * nblk_max + bc];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool in = b0 + (long long)u * blockDim.x < nblk;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) v[t] += in ? ld[t][u] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) v[t] += __shfl_xor(v[t], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) sm[t][wid] = v[t];
+    }
+    __syncthreads();
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += sm[t][w];
+        out[t] = s;
+    }
+}
+
 __device__ __forceinline__ long long part_index(int r, int slot, int term, long long nblk_max) {
     return ((long long)(r * NSLOT + slot) * MAX_TERMS + term) * nblk_max;
 }

@@ -15,7 +15,7 @@ struct Launch {
     int flat_cap = 2048;
 };
 
-enum OpMode : int { OP_PLAIN = 0, OP_V = 1, OP_T = 2 };
+enum OpMode : int { OP_PLAIN = 0, OP_V = 1, OP_T = 2, OP_P = 3 };
 // FIN_OMEGA also takes the half-step test on ||s||: the s update writes its
 // partial sums beside those of t = A s_hat, so one finalize serves both.
 enum FinMode : int { FIN_INIT = 0, FIN_RHO = 1, FIN_ALPHA = 2, FIN_OMEGA = 4, FIN_TRUE = 5 };
@@ -29,6 +29,11 @@ template <typename TX>
 void launch_apply(hipStream_t s, int bc, int mode, const Geo& g, const Launch& L, int nrhs,
                   const cx<TX>* x, c128* y, const double* k2, const double* kb, double sr, double si,
                   const c128* aux, double* part, long long nblk_max, const RhsState* st, int gate);
+// y = A x and the IDR(s) shadow products <p_i, y>, i < ns <= IDR_SMAX, into
+// partial-sum rows 0 .. 2 ns - 1 (P: ns complex64 vectors of g.n nodes)
+void launch_apply_p(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs, int ns, const c128* x,
+                    c128* y, const double* k2, const double* kb, const c64* P, double* part,
+                    long long nblk_max, const RhsState* st, int gate);
 void launch_init(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs, const c128* b,
                  c128* x, c128* r, c128* rhat, c128* p, c128* v, const double* k2, const double* kb,
                  int use_x0, double* part, long long nblk_max, const RhsState* st, int gate);
@@ -99,6 +104,28 @@ void launch_update_xr(hipStream_t s, long long n, int nrhs, c128* x, c128* r, co
                       const RhsState* st, double* part, long long nblk_max, const Launch& L);
 void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const double* part,
                      long long nblk, long long nblk_max, double tol);
+
+// IDR(s) kernels (hh_idr.hip).  G and U: s vectors per right-hand side,
+// vector (j, r) at j * rsj + r * n; P: ns complex64 shadow vectors of n nodes.
+enum IdrFin : int { IDR_FIN_START = 0, IDR_FIN_STEP = 1, IDR_FIN_OMEGA = 2 };
+void launch_idr_v(hipStream_t s, long long n, int nrhs, int k, const c128* G, long long rsj, const c128* r,
+                  c128* v, c64* v_low, const IdrState* is, const RhsState* st, const Launch& L);
+template <typename TH>
+void launch_idr_u(hipStream_t s, long long n, int nrhs, int k, c128* U, long long rsj, const cx<TH>* vh,
+                  const IdrState* is, const RhsState* st, const Launch& L);
+void launch_idr_update(hipStream_t s, long long n, int nrhs, int k, c128* G, c128* U, long long rsj, c128* r,
+                       c128* x, c128* v, c64* v_low, const IdrState* is, const RhsState* st, double* part,
+                       long long nblk_max, const Launch& L);
+template <typename TH>
+void launch_idr_xr(hipStream_t s, long long n, int nrhs, int ns, c128* x, c128* r, const cx<TH>* vh,
+                   const c128* t, const c64* P, const IdrState* is, const RhsState* st, double* part,
+                   long long nblk_max, const Launch& L);
+void launch_idr_pr(hipStream_t s, long long n, int nrhs, int ns, const c128* r, const c64* P,
+                   const RhsState* st, double* part, long long nblk_max, const Launch& L);
+void launch_idr_finalize(hipStream_t s, int mode, int k, int reset, int nrhs, int ns, double kappa,
+                         RhsState* st, IdrState* is, const double* part, long long nblk, long long nblk_max);
+void launch_idr_gen_p(hipStream_t s, long long n, int ns, unsigned long long seed, c64* P);
+void launch_idr_set_p(hipStream_t s, long long total, const c128* src, c64* P);
 
 void launch_model_check(hipStream_t s, long long n, const double* k, double* k2, double* kb, int* bad);
 void launch_inject(hipStream_t s, const Geo& gf, const Geo& gc, const double* kf, double* kc);

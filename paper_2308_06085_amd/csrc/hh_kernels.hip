@@ -95,53 +95,6 @@ __device__ __forceinline__ bool on_boundary(int i, int j, int z, int nx, int ny,
 // would need a device-scope fence per workgroup, which on a multi-XCD device
 // writes back the XCD's L2 and costs more than the extra launch.)
 // ---------------------------------------------------------------------------
-template <int NT>
-__device__ void block_fixed_sum(const double* __restrict__ part, long long nblk, long long nblk_max,
-                                double (&out)[NT]) {
-    __shared__ double sm[NT][16];
-    double v[NT];
-    // lane t adds partials t, t + blockDim, t + 2 blockDim, ... in that order; the
-    // loads of eight consecutive terms of that sequence are issued before their
-    // adds (out-of-range slots read a valid partial and add exactly zero)
-    constexpr int U = 8;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) v[t] = 0.0;
-    for (long long b0 = threadIdx.x; b0 < nblk; b0 += (long long)U * blockDim.x) {
-        double ld[NT][U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const long long b = b0 + (long long)u * blockDim.x;
-            const long long bc = b < nblk ? b : nblk - 1;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) ld[t][u] = part[t * nblk_max + bc];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool in = b0 + (long long)u * blockDim.x < nblk;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) v[t] += in ? ld[t][u] : 0.0;
-        }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t) v[t] += __shfl_xor(v[t], off, 64);
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t) sm[t][wid] = v[t];
-    }
-    __syncthreads();
-    const int nw = (blockDim.x + 63) >> 6;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += sm[t][w];
-        out[t] = s;
-    }
-}
-
 __device__ __forceinline__ bool finite2(c128 a) { return isfinite(a.re) && isfinite(a.im); }
 
 // Scalar update of one right-hand side from the slot sums (one thread).
@@ -290,8 +243,11 @@ __global__ __launch_bounds__(1024) void k_finalize(int mode, RhsState* st, const
 //   OP_PLAIN : y = Op x
 //   OP_V     : y = A x, partials Re/Im sum conj(rhat) y          (slot V)
 //   OP_T     : y = A x, partials Re/Im sum conj(y) s, sum |y|^2   (slot T)
+//   OP_P     : y = A x, partials Re/Im sum conj(p_i) y for the NS complex64
+//              shadow vectors p_i of IDR(s) (rows 0 .. 2 NS - 1; aux points
+//              to them, NS vectors of n nodes, shared by all right-hand sides)
 // ---------------------------------------------------------------------------
-template <int BC, int MODE, typename TX>
+template <int BC, int MODE, typename TX, int NS = 0>
 __global__ __launch_bounds__(512) void k_apply(Geo g, int zb, const cx<TX>* __restrict__ x,
                                                c128* __restrict__ y, const double* __restrict__ k2,
                                                const double* __restrict__ kb, double sr, double si,
@@ -321,7 +277,11 @@ __global__ __launch_bounds__(512) void k_apply(Geo g, int zb, const cx<TX>* __re
     const int nf_col = (i == 0) + (i == g.nx - 1) + (j == 0) + (j == g.ny - 1);
     auto ld = [&](int z, int c) -> c128 { return cvt<double>(xr[(long long)z * g.plane + c]); };
     auto zmir = [&](int z) { return z < 0 ? 1 : (z > g.nz - 1 ? g.nz - 2 : z); };
-    double acc[3] = {0.0, 0.0, 0.0};
+    constexpr int NACC = MODE == OP_P ? 2 * NS : 3;
+    double acc[NACC];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) acc[a] = 0.0;
+    const c64* pshadow = reinterpret_cast<const c64*>(aux);
     // planes in pairs: the loads of both planes (and of the column's planes
     // below and above) are in flight together
     for (int z = z0; z < z1; z += 2) {
@@ -329,6 +289,7 @@ __global__ __launch_bounds__(512) void k_apply(Geo g, int zb, const cx<TX>* __re
         // the column on planes z - 1 .. z + 2, mirrored at the ends
         const int zs = min(z + 1, g.nz - 1);
         c128 xcol[4], xin[2][4], aux_v[2];
+        c64 pv[2][MODE == OP_P ? NS : 1];
         double kk[2], kbv[2];
         const int zc[4] = {zmir(z - 1), z, zmir(z + 1), zmir(z + 2)};
 #pragma unroll
@@ -345,7 +306,11 @@ __global__ __launch_bounds__(512) void k_apply(Geo g, int zb, const cx<TX>* __re
             const int nf = nf_col + (zz == 0) + (zz == g.nz - 1);
             // interior nodes all read kb[0] (one cache line): no branch around the load
             kbv[p] = kb[nf ? idx : 0];
-            if (MODE != OP_PLAIN) aux_v[p] = aux[roff + idx];
+            if (MODE == OP_V || MODE == OP_T) aux_v[p] = aux[roff + idx];
+            if constexpr (MODE == OP_P) {
+#pragma unroll
+                for (int a = 0; a < NS; ++a) pv[p][a] = pshadow[(long long)a * g.n + idx];
+            }
         }
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
@@ -379,14 +344,25 @@ __global__ __launch_bounds__(512) void k_apply(Geo g, int zb, const cx<TX>* __re
                     acc[0] += t.re;
                     acc[1] += t.im;
                     acc[2] += abs2(out);
+                } else if constexpr (MODE == OP_P) {
+#pragma unroll
+                    for (int a = 0; a < NS; ++a) {
+                        const c128 t = cdot(cvt<double>(pv[p][a]), out);
+                        acc[2 * a] += t.re;
+                        acc[2 * a + 1] += t.im;
+                    }
                 }
             }
         }
     }
-    if (MODE == OP_V || MODE == OP_T) {
+    if constexpr (MODE == OP_P) {
+        const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+        block_sum_store<NACC>(acc, part + part_index(r, 0, 0, nblk_max) + blk, nblk_max);
+    }
+    if constexpr (MODE == OP_V || MODE == OP_T) {
         const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
         const int slot = MODE == OP_V ? SLOT_V : SLOT_T;
-        if (MODE == OP_V) {
+        if constexpr (MODE == OP_V) {
             double v[2] = {acc[0], acc[1]};
             block_sum_store<2>(v, part + part_index(r, slot, 0, nblk_max) + blk, nblk_max);
         } else {
@@ -707,6 +683,35 @@ void launch_apply(hipStream_t s, int bc, int mode, const Geo& g, const Launch& L
     }
 #undef HH_APPLY
 }
+// y = A x with the fused IDR shadow products <p_i, y>, i < ns (rows 0 .. 2 ns - 1)
+void launch_apply_p(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs, int ns, const c128* x,
+                    c128* y, const double* k2, const double* kb, const c64* P, double* part,
+                    long long nblk_max, const RhsState* st, int gate) {
+    dim3 grid = grid_fine(g, L, nrhs);
+    const c128* aux = reinterpret_cast<const c128*>(P);
+#define HH_APPLY_P(BCV, NSV)                                                                             \
+    hipLaunchKernelGGL((k_apply<BCV, OP_P, double, NSV>), grid, dim3(L.block), 0, s, g, L.zb, x, y, k2, kb, \
+                       1.0, 0.0, aux, part, nblk_max, st, gate)
+#define HH_APPLY_P_NS(BCV)                \
+    switch (ns) {                         \
+        case 1: HH_APPLY_P(BCV, 1); break; \
+        case 2: HH_APPLY_P(BCV, 2); break; \
+        case 3: HH_APPLY_P(BCV, 3); break; \
+        case 4: HH_APPLY_P(BCV, 4); break; \
+        case 5: HH_APPLY_P(BCV, 5); break; \
+        case 6: HH_APPLY_P(BCV, 6); break; \
+        case 7: HH_APPLY_P(BCV, 7); break; \
+        default: HH_APPLY_P(BCV, 8); break; \
+    }
+    if (bc == BC_SOMMERFELD) {
+        HH_APPLY_P_NS(BC_SOMMERFELD)
+    } else {
+        HH_APPLY_P_NS(BC_DIRICHLET)
+    }
+#undef HH_APPLY_P_NS
+#undef HH_APPLY_P
+}
+
 template void launch_apply<double>(hipStream_t, int, int, const Geo&, const Launch&, int, const c128*,
                                    c128*, const double*, const double*, double, double, const c128*,
                                    double*, long long, const RhsState*, int);

@@ -89,6 +89,18 @@ struct hh_ctx {
     std::map<int, hipGraphExec_t> graphs;
     int tail_first = 0;   // first level run by the single-workgroup tail kernel
     int cycle = 0;        // preconditioner cycle: 0 = V-cycle, 1 = F-cycle
+    // Krylov method: 0 = Bi-CGSTAB, 1 = IDR(s)
+    int method = 0;
+    int idr_s = 4;                 // shadow-space dimension
+    int idr_s_alloc = 0;           // s the IDR buffers were allocated for
+    double idr_kappa = 0.7;        // omega safeguard of the reduction step (0 = plain minimal residual)
+    unsigned long long idr_seed = 1;
+    bool idr_p_user = false;       // shadow vectors set by hh_set_shadow
+    bool idr_p_ready = false;
+    c128 *idr_G = nullptr, *idr_U = nullptr;  // s vectors per right-hand side each
+    c64* idr_P = nullptr;                      // s shadow vectors, shared
+    IdrState* idr_st = nullptr;
+    std::map<int, hipGraphExec_t> idr_graphs;
     // z-planes per workgroup of each level's multigrid passes set by the caller
     // (0 = automatic); indexed by level, grown on demand
     std::vector<int> zb_down_set, zb_up_set;
@@ -175,6 +187,9 @@ hh_status dalloc(hh_ctx* c, T** p, size_t bytes) {
 void free_all(hh_ctx* c) {
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
+    for (auto& kv : c->idr_graphs) (void)hipGraphExecDestroy(kv.second);
+    c->idr_graphs.clear();
+    for (void* q : {(void*)c->idr_G, (void*)c->idr_U, (void*)c->idr_P, (void*)c->idr_st}) (void)hipFree(q);
     for (auto& L : c->lv) {
         (void)hipFree(L.k);
         (void)hipFree(L.k2l);
@@ -195,6 +210,30 @@ void free_all(hh_ctx* c) {
 void invalidate_graphs(hh_ctx* c) {
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
+    for (auto& kv : c->idr_graphs) (void)hipGraphExecDestroy(kv.second);
+    c->idr_graphs.clear();
+}
+
+// IDR(s) buffers for shadow dimension s: G and U (s complex128 vectors per
+// right-hand side each), the complex64 shadow vectors and the per-RHS state.
+// Grown only; freed with the context.
+hh_status idr_alloc(hh_ctx* c, int s) {
+    if (s <= c->idr_s_alloc) return HH_OK;
+    for (void* q : {(void*)c->idr_G, (void*)c->idr_U, (void*)c->idr_P}) (void)hipFree(q);
+    c->idr_G = c->idr_U = nullptr;
+    c->idr_P = nullptr;
+    c->idr_s_alloc = 0;
+    c->idr_p_ready = false;
+    c->idr_p_user = false;
+    const size_t n = (size_t)c->lv[0].g.n;
+    const size_t R = (size_t)c->cfg.nrhs_max;
+    CHK(dalloc(c, &c->idr_G, sizeof(c128) * s * R * n));
+    CHK(dalloc(c, &c->idr_U, sizeof(c128) * s * R * n));
+    CHK(dalloc(c, &c->idr_P, sizeof(c64) * s * n));
+    if (!c->idr_st) CHK(dalloc(c, &c->idr_st, sizeof(IdrState) * R));
+    HIPCHK(c, hipMemset(c->idr_st, 0, sizeof(IdrState) * R));
+    c->idr_s_alloc = s;
+    return HH_OK;
 }
 
 // z-planes per workgroup of a multigrid pass: long z-marches amortise the two
@@ -430,6 +469,80 @@ void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs, hipEvent_t* ev = null
         enqueue_iteration_t<double>(c, s, nrhs, c->ph, c->sh, nullptr, nullptr, ev);
 }
 
+// One IDR(s) cycle (s inner steps and the reduction step) for every
+// right-hand side still iterating; the preconditioner's input and output are
+// complex64 in the mixed solve, as in Bi-CGSTAB.
+template <typename TH>
+void enqueue_idr_cycle_t(hh_ctx* c, hipStream_t s, int nrhs, cx<TH>* vh, c64* v_low) {
+    const Geo& g = c->lv[0].g;
+    const long long n = g.n;
+    const long long nb = c->nblk0;
+    const int bc = c->cfg.bc;
+    const int S = c->idr_s;
+    const long long rsj = (long long)c->cfg.nrhs_max * n;
+    Launch F = c->L0;
+    F.flat_cap = (int)nb;
+    auto precond = [&]() {
+        if constexpr (sizeof(TH) == sizeof(float))
+            enqueue_cycle_t<float, float, float>(c, s, nrhs, v_low, vh, c->st, ST_RUN);
+        else enqueue_cycle(c, s, nrhs, c->p, vh, c->st, ST_RUN);
+    };
+    launch_idr_v(s, n, nrhs, 0, c->idr_G, rsj, c->r, c->p, v_low, c->idr_st, c->st, F);
+    for (int k = 0; k < S; ++k) {
+        precond();
+        launch_idr_u<TH>(s, n, nrhs, k, c->idr_U, rsj, vh, c->idr_st, c->st, F);
+        launch_apply_p(s, bc, g, c->L0, nrhs, S, c->idr_U + k * rsj, c->idr_G + k * rsj, c->k2, c->kb,
+                       c->idr_P, c->part, NBLK_CAP, c->st, ST_RUN);
+        launch_idr_finalize(s, IDR_FIN_STEP, k, 0, nrhs, S, c->idr_kappa, c->st, c->idr_st, c->part, nb,
+                            NBLK_CAP);
+        launch_idr_update(s, n, nrhs, k, c->idr_G, c->idr_U, rsj, c->r, c->xk, c->p, v_low, c->idr_st, c->st,
+                          c->part, NBLK_CAP, F);
+    }
+    // reduction step: v = r (written by the last inner step)
+    precond();
+    launch_apply(s, bc, OP_T, g, c->L0, nrhs, vh, c->t, c->k2, c->kb, 1.0, 0.0, c->r, c->part, NBLK_CAP, c->st,
+                 ST_RUN);
+    launch_idr_finalize(s, IDR_FIN_OMEGA, 0, 0, nrhs, S, c->idr_kappa, c->st, c->idr_st, c->part, nb, NBLK_CAP);
+    launch_idr_xr<TH>(s, n, nrhs, S, c->xk, c->r, vh, c->t, c->idr_P, c->idr_st, c->st, c->part, NBLK_CAP, F);
+    launch_idr_finalize(s, IDR_FIN_START, 0, 0, nrhs, S, c->idr_kappa, c->st, c->idr_st, c->part, nb, NBLK_CAP);
+}
+
+void enqueue_idr_cycle(hh_ctx* c, hipStream_t s, int nrhs) {
+    if (c->mixed) enqueue_idr_cycle_t<float>(c, s, nrhs, reinterpret_cast<c64*>(c->ph), c->p_low);
+    else enqueue_idr_cycle_t<double>(c, s, nrhs, c->ph, nullptr);
+}
+
+// <p_i, r> and the first inner step's coefficients after a (re)start
+void enqueue_idr_start(hh_ctx* c, hipStream_t s, int nrhs) {
+    Launch F = c->L0;
+    F.flat_cap = (int)c->nblk0;
+    launch_idr_pr(s, c->lv[0].g.n, nrhs, c->idr_s, c->r, c->idr_P, c->st, c->part, NBLK_CAP, F);
+    launch_idr_finalize(s, IDR_FIN_START, 0, 1, nrhs, c->idr_s, c->idr_kappa, c->st, c->idr_st, c->part,
+                        c->nblk0, NBLK_CAP);
+}
+
+hh_status get_idr_graph(hh_ctx* c, int nrhs, hipGraphExec_t* out) {
+    auto it = c->idr_graphs.find(nrhs);
+    if (it != c->idr_graphs.end()) {
+        *out = it->second;
+        return HH_OK;
+    }
+    hipGraph_t graph = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+    enqueue_idr_cycle(c, c->cap, nrhs);
+    hipError_t le = hipGetLastError();
+    hipError_t ee = hipStreamEndCapture(c->cap, &graph);
+    if (le != hipSuccess) return fail(c, HH_ERR_HIP, "launch during capture: %s", hipGetErrorString(le));
+    if (ee != hipSuccess) return fail(c, HH_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(c, HH_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    c->idr_graphs[nrhs] = exec;
+    *out = exec;
+    return HH_OK;
+}
+
 hh_status get_graph(hh_ctx* c, int nrhs, hipGraphExec_t* out) {
     auto it = c->graphs.find(nrhs);
     if (it != c->graphs.end()) {
@@ -560,6 +673,87 @@ hh_status check_ready(hh_ctx* c, int nrhs) {
     if (nrhs < 1 || nrhs > c->cfg.nrhs_max)
         return fail(c, HH_ERR_ARG, "nrhs=%d outside 1..%d", nrhs, c->cfg.nrhs_max);
     return HH_OK;
+}
+
+// IDR(s) iteration of hh_solve after the initial residual: one cycle per host
+// check; when every right-hand side has stopped, the true residual decides
+// (a converged one that misses rtol restarts from x with G = U = 0).
+hh_status run_idr(hh_ctx* c, int nrhs, int maxit) {
+    CHK(idr_alloc(c, c->idr_s));
+    const Geo& g = c->lv[0].g;
+    if (!c->idr_p_ready) {
+        launch_idr_gen_p(c->stream, g.n, c->idr_s, c->idr_seed, c->idr_P);
+        c->idr_p_ready = true;
+    }
+    enqueue_idr_start(c, c->stream, nrhs);
+    HIPCHK(c, hipGetLastError());
+    CHK(read_states(c, nrhs));
+    hipGraphExec_t exec = nullptr;
+    if (c->use_graph && !c->trace) CHK(get_idr_graph(c, nrhs, &exec));
+    long long guard = 0;
+    while (true) {
+        bool any_run = false;
+        for (int r = 0; r < nrhs; ++r) any_run |= c->st_host[r].status == ST_RUN;
+        if (any_run) {
+            if (exec) HIPCHK(c, hipGraphLaunch(exec, c->stream));
+            else enqueue_idr_cycle(c, c->stream, nrhs);
+            HIPCHK(c, hipGetLastError());
+            CHK(read_states(c, nrhs));
+            if (++guard > 2LL * (maxit + 8) * (MAX_RESTARTS + 1)) return fail(c, HH_ERR_STATE, "driver did not terminate");
+            continue;
+        }
+        launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->k2,
+                    c->kb, 1, c->part, NBLK_CAP, c->st, GATE_FINISHED);
+        launch_finalize(c->stream, FIN_TRUE, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, 0.0);
+        HIPCHK(c, hipGetLastError());
+        CHK(read_states(c, nrhs));
+        bool restarted = false;
+        for (int r = 0; r < nrhs; ++r) restarted |= c->st_host[r].status == ST_RUN;
+        if (!restarted) break;
+        enqueue_idr_start(c, c->stream, nrhs);
+        HIPCHK(c, hipGetLastError());
+        CHK(read_states(c, nrhs));
+    }
+    return HH_OK;
+}
+
+
+// Copy out the solution and fill the statistics of a finished solve.
+hh_status finish_solve(hh_ctx* c, void* x, int nrhs, hipEvent_t e0, hipEvent_t e1, hh_stats* stats) {
+    const size_t bytes = sizeof(c128) * c->lv[0].g.n * nrhs;
+    HIPCHK(c, hipMemcpyAsync(x, c->xk, bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    hh_status worst = HH_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        const RhsState& S = c->st_host[r];
+        hh_status sr;
+        switch (S.status) {
+            case ST_CONV: sr = HH_OK; break;
+            case ST_BREAK: sr = HH_ERR_BREAKDOWN; break;
+            case ST_MAXIT: sr = HH_ERR_NOT_CONVERGED; break;
+            case ST_NUMERIC: sr = HH_ERR_NUMERIC; break;
+            default: sr = HH_ERR_STATE; break;
+        }
+        if (S.status == ST_CONV && S.bnorm2 > 0.0 && S.true_rnorm2 > S.tol2) sr = HH_ERR_NOT_CONVERGED;
+        if (stats) {
+            hh_stats& o = stats[r];
+            o.iterations = 0.5 * S.iters2;
+            o.matvecs = S.matvecs;
+            o.relres = S.bnorm2 > 0.0 ? std::sqrt(S.rnorm2 / S.bnorm2) : 0.0;
+            o.relres_true = S.bnorm2 > 0.0 ? std::sqrt(S.true_rnorm2 / S.bnorm2) : 0.0;
+            o.status = sr;
+            o.restarts = S.restarts;
+        }
+        if (worst == HH_OK && sr != HH_OK) worst = sr;
+    }
+    c->last_ms = ms;
+    c->err = worst == HH_OK ? std::string() : std::string("not every right-hand side converged");
+    return worst;
 }
 
 }  // namespace
@@ -845,6 +1039,10 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
     for (int r = 0; r < nrhs; ++r)
         if (c->st_host[r].bnorm2 == 0.0)
             HIPCHK(c, hipMemsetAsync(c->xk + (size_t)r * g.n, 0, sizeof(c128) * g.n, c->stream));
+    if (c->method == 1) {
+        CHK(run_idr(c, nrhs, maxit));
+        return finish_solve(c, x, nrhs, e0, e1, stats);
+    }
     hipGraphExec_t exec = nullptr;
     if (c->use_graph && !c->trace) CHK(get_graph(c, nrhs, &exec));
     const size_t ev_per_step = 2 * NTRACE_LAUNCH;
@@ -904,40 +1102,9 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
         for (int r = 0; r < nrhs; ++r) restarted |= c->st_host[r].status == ST_RUN;
         if (!restarted) break;
     }
-    HIPCHK(c, hipMemcpyAsync(x, c->xk, bytes, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, hipEventRecord(e1, c->stream));
-    HIPCHK(c, hipEventSynchronize(e1));
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    hh_status worst = HH_OK;
-    for (int r = 0; r < nrhs; ++r) {
-        const RhsState& S = c->st_host[r];
-        hh_status sr;
-        switch (S.status) {
-            case ST_CONV: sr = HH_OK; break;
-            case ST_BREAK: sr = HH_ERR_BREAKDOWN; break;
-            case ST_MAXIT: sr = HH_ERR_NOT_CONVERGED; break;
-            case ST_NUMERIC: sr = HH_ERR_NUMERIC; break;
-            default: sr = HH_ERR_STATE; break;
-        }
-        if (S.status == ST_CONV && S.bnorm2 > 0.0 && S.true_rnorm2 > S.tol2) sr = HH_ERR_NOT_CONVERGED;
-        if (stats) {
-            hh_stats& o = stats[r];
-            o.iterations = 0.5 * S.iters2;
-            o.matvecs = S.matvecs;
-            o.relres = S.bnorm2 > 0.0 ? std::sqrt(S.rnorm2 / S.bnorm2) : 0.0;
-            o.relres_true = S.bnorm2 > 0.0 ? std::sqrt(S.true_rnorm2 / S.bnorm2) : 0.0;
-            o.status = sr;
-            o.restarts = S.restarts;
-        }
-        if (worst == HH_OK && sr != HH_OK) worst = sr;
-    }
-    c->last_ms = ms;
-    c->err = worst == HH_OK ? std::string() : std::string("not every right-hand side converged");
-    return worst;
+    return finish_solve(c, x, nrhs, e0, e1, stats);
 }
+
 
 hh_status hh_adjoint_rhs(hh_ctx* c, const void* g, void* rhs, int nrhs) {
     CHK(check_ready(c, nrhs));
@@ -956,6 +1123,20 @@ hh_status hh_grad_slowness2(hh_ctx* c, const void* u, const void* w, const doubl
     return HH_OK;
 }
 
+hh_status hh_set_shadow(hh_ctx* c, const void* P, int s) {
+    if (!c) return HH_ERR_ARG;
+    if (!P) return fail(c, HH_ERR_ARG, "null shadow vectors");
+    if (s < 1 || s > IDR_SMAX) return fail(c, HH_ERR_ARG, "s=%d outside 1..%d", s, IDR_SMAX);
+    if (s != c->idr_s) invalidate_graphs(c);
+    c->idr_s = s;
+    CHK(idr_alloc(c, s));
+    launch_idr_set_p(c->stream, (long long)s * c->lv[0].g.n, (const c128*)P, c->idr_P);
+    HIPCHK(c, hipGetLastError());
+    c->idr_p_user = true;
+    c->idr_p_ready = true;
+    return HH_OK;
+}
+
 hh_status hh_set_option(hh_ctx* c, const char* name, long long value) {
     if (!c || !name) return HH_ERR_ARG;
     std::string n(name);
@@ -970,6 +1151,27 @@ hh_status hh_set_option(hh_ctx* c, const char* name, long long value) {
             c->tsum[k] = 0.0;
             c->tcnt[k] = 0;
         }
+    } else if (n == "method") {
+        if (value != 0 && value != 1) return fail(c, HH_ERR_ARG, "method must be 0 (Bi-CGSTAB) or 1 (IDR(s))");
+        if (value == 1) CHK(idr_alloc(c, c->idr_s));
+        c->method = (int)value;
+    } else if (n == "idr_s") {
+        if (value < 1 || value > IDR_SMAX) return fail(c, HH_ERR_ARG, "idr_s must be in 1..%d", IDR_SMAX);
+        if (value != c->idr_s) {
+            c->idr_s = (int)value;
+            c->idr_p_ready = false;  // shadow vectors of the old dimension are dropped
+            c->idr_p_user = false;
+            invalidate_graphs(c);
+        }
+        if (c->method == 1) CHK(idr_alloc(c, c->idr_s));
+    } else if (n == "idr_seed") {
+        if (value < 0 || value >= (1LL << 23)) return fail(c, HH_ERR_ARG, "idr_seed must be in 0..2^23-1");
+        c->idr_seed = (unsigned long long)value;
+        if (!c->idr_p_user) c->idr_p_ready = false;
+    } else if (n == "idr_kappa_milli") {
+        if (value < 0 || value > 1000) return fail(c, HH_ERR_ARG, "idr_kappa_milli must be in 0..1000");
+        c->idr_kappa = value / 1000.0;
+        invalidate_graphs(c);
     } else if (n == "cycle") {
         if (value != 0 && value != 1) return fail(c, HH_ERR_ARG, "cycle must be 0 (V-cycle) or 1 (F-cycle)");
         c->cycle = (int)value;
@@ -1029,6 +1231,10 @@ hh_status hh_get_option(const hh_ctx* c, const char* name, long long* value) {
     else if (n == "check_every") *value = c->check_every;
     else if (n == "trace") *value = c->trace;
     else if (n == "cycle") *value = c->cycle;
+    else if (n == "method") *value = c->method;
+    else if (n == "idr_s") *value = c->idr_s;
+    else if (n == "idr_seed") *value = (long long)c->idr_seed;
+    else if (n == "idr_kappa_milli") *value = (long long)std::llround(c->idr_kappa * 1000.0);
     else if (n == "block") *value = c->L0.block;
     else if (n == "zb") *value = c->L0.zb;
     else if (n == "n_levels") *value = (long long)c->lv.size();

@@ -54,11 +54,12 @@ class Solver:
     inside a complex128 Bi-CGSTAB); beta = (beta1, beta2) of the CSLP
     M = -Laplace - (beta1 - beta2 i) k^2 (default (1, -0.5)); omega: Jacobi
     weight (0.8); n_levels: 0 = coarsen while >= 3 nodes per axis remain;
-    cycle: "V" | "F", the multigrid cycle that approximates M^-1 (section 3.4.5).
+    cycle: "V" | "F", the multigrid cycle that approximates M^-1 (section 3.4.5);
+    method: "bicgstab" | "idrs" (IDR(s) with s = idr_s, section 3.1).
     """
 
     def __init__(self, shape, h, bc="sommerfeld", prec="fp64", n_levels=0, nrhs_max=1,
-                 beta=(1.0, -0.5), omega=0.8, cycle="V", device=None):
+                 beta=(1.0, -0.5), omega=0.8, cycle="V", method="bicgstab", idr_s=4, device=None):
         self.lib = _lib.load()
         nz, ny, nx = (int(v) for v in shape)
         self.shape = (nz, ny, nx)
@@ -88,6 +89,13 @@ class Solver:
         self.cycle = cycle
         if cycle == "F":
             self.set_option("cycle", 1)
+        if method not in ("bicgstab", "idrs"):
+            self.close()
+            raise ValueError(f"method must be 'bicgstab' or 'idrs', not {method!r}")
+        self.method = method
+        if method == "idrs":
+            self.set_option("idr_s", int(idr_s))
+            self.set_option("method", 1)
 
     # -- lifetime -----------------------------------------------------------
     def close(self):
@@ -148,6 +156,12 @@ class Solver:
         arr = (C.c_int * len(flat))(*flat)
         check(self.lib.hh_set_point_sources(self.ctx, arr, len(nodes)), self.ctx)
         self.nrhs = len(nodes)
+
+    def set_shadow(self, P: torch.Tensor):
+        """IDR(s) shadow vectors, complex128 (s, nz, ny, nx) on the device; stored
+        rounded to complex64.  Sets idr_s = s."""
+        _require(P, torch.complex128, (P.shape[0],) + self.shape, "P")
+        check(self.lib.hh_set_shadow(self.ctx, _ptr(P), P.shape[0]), self.ctx)
 
     # -- solve / apply ------------------------------------------------------
     def solve(self, x0: torch.Tensor | None = None, rtol=1e-6, maxit=1000, raise_on_fail=False,
