@@ -29,14 +29,20 @@ algorithmic bytes per launch / ``avg_ms``, against 8 TB/s HBM3E peak;
 ``cpu_baseline`` times the CPU oracle on a bounded sample (a few Bi-CGSTAB
 steps of the same workload) on the host.
 
-``fcycle`` (wedge workload): the same solves with one F(1,1)-cycle instead of
-the V-cycle as the preconditioner (section 3.4.5), both precisions, timed the
-same way: iterations, time per solve and the time-to-solution ratio V / F.
+``variants`` (wedge workload): the same solves with the paper's other
+solver settings, both precisions, timed the same way: Bi-CGSTAB with one
+F(1,1)-cycle (section 3.4.5), and IDR(4) (section 3.1) with the V- and with
+the F-cycle.  Each gives iterations (Bi-CGSTAB steps, or IDR products with A),
+products with A (``matvecs``, the paper's #Matvec), time per solve, and the
+time-to-solution ratio against the headline Bi-CGSTAB + V-cycle solve.
+
+``--method idrs`` / ``--cycle F`` change the headline solves themselves.
 
 ``--workload beta2_sweep``: the paper's F-cycle experiment (section 5), the
-wedge at 40 Hz on 193 x 193 x 321 nodes (h = 3.125 m), mixed precision, V- and
-F-cycle for beta2 = -0.5 ... -1.0: Bi-CGSTAB iterations and time per solve to
-1e-6 (at most 600 iterations); ``value`` is the fastest solve's time in ms.
+wedge at 40 Hz on 193 x 193 x 321 nodes (h = 3.125 m), mixed precision,
+Bi-CGSTAB and IDR(4), V- and F-cycle, for beta2 = -0.5 ... -1.0: iterations,
+products with A and time per solve to 1e-6 (at most 1200 products with A);
+``value`` is the fastest solve's time in ms.
 """
 from __future__ import annotations
 
@@ -200,55 +206,62 @@ def beta2_sweep(args, wl, nodes, desc):
     k = torch.from_numpy(wl.k).cuda()
     rows = []
     for beta2 in (-0.5, -0.6, -0.7, -0.8, -0.9, -1.0):
-        for cyc in ("V", "F"):
-            s = Solver(wl.shape, wl.h, bc=wl.bc, prec="mixed", cycle=cyc, beta=(1.0, beta2))
-            s.set_model(k)
-            s.set_point_sources(nodes)
-            x = None
-            for _ in range(args.warmup):
-                x, _ = s.solve(rtol=1e-6, maxit=600, out=x)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                x, st = s.solve(rtol=1e-6, maxit=600, out=x)
-            torch.cuda.synchronize()
-            ms = 1e3 * (time.perf_counter() - t0) / args.steps
-            rows.append({"beta2": beta2, "cycle": cyc, "iterations": st[0].iterations,
-                         "status": st[0].status, "relres_true": st[0].relres_true, "ms_per_solve": ms})
-            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
-            s.close()
-            del x
+        for method in ("bicgstab", "idrs"):
+            for cyc in ("V", "F"):
+                s = Solver(wl.shape, wl.h, bc=wl.bc, prec="mixed", cycle=cyc, beta=(1.0, beta2), method=method)
+                s.set_model(k)
+                s.set_point_sources(nodes)
+                maxit = 600 if method == "bicgstab" else 1200  # at most 1200 products with A either way
+                x = None
+                for _ in range(args.warmup):
+                    x, _ = s.solve(rtol=1e-6, maxit=maxit, out=x)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    x, st = s.solve(rtol=1e-6, maxit=maxit, out=x)
+                torch.cuda.synchronize()
+                ms = 1e3 * (time.perf_counter() - t0) / args.steps
+                rows.append({"beta2": beta2, "method": method, "cycle": cyc, "iterations": st[0].iterations,
+                             "matvecs": st[0].matvecs, "status": st[0].status,
+                             "relres_true": st[0].relres_true, "ms_per_solve": ms})
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+                s.close()
+                del x
     ok = [r for r in rows if r["status"] == "HH_OK"]
     best = min(ok, key=lambda r: r["ms_per_solve"])
     line = {
-        "metric": "time to 1e-6 rel residual of CSLP-Bi-CGSTAB over beta2, V- vs F-cycle (mixed)",
+        "metric": "time to 1e-6 rel residual over beta2: Bi-CGSTAB and IDR(4), V- and F-cycle (mixed)",
         "value": best["ms_per_solve"], "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": best["ms_per_solve"], "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "c64 cycle / c128 Krylov", "data": "synthetic",
-        "config": {"workload": desc, "unknowns": dof(wl), "nrhs": 1, "rtol": 1e-6, "maxit": 600,
-                   "precision": "mixed"},
+        "config": {"workload": desc, "unknowns": dof(wl), "nrhs": 1, "rtol": 1e-6,
+                   "max_products_with_A": 1200, "precision": "mixed"},
         "best": best, "sweep": rows,
     }
     print(json.dumps(line), flush=True)
 
 
-def fcycle_solves(args, wl, nodes, make, vres):
-    """The timed solves again with the F-cycle preconditioner."""
+def variant_solves(args, wl, nodes, make, vres):
+    """The timed solves again with the other Krylov method / multigrid cycle."""
     import torch
 
     out = {}
-    for prec, v in vres.items():
-        s = make(prec)
-        s.set_option("cycle", 1)
-        x, stats, times, iters = run_solves(s, args.steps, args.warmup)
-        t = float(np.sum(times))
-        out[prec] = {"value": dof(wl) * float(np.sum(iters)) / t, "ms_per_step": 1e3 * t / args.steps,
-                     "iterations": float(np.mean(iters)), "relres_true_max": max(st.relres_true for st in stats),
-                     "status": sorted({st.status for st in stats}),
-                     "time_to_solution_speedup_vs_vcycle": v["ms_per_step"] / (1e3 * t / args.steps)}
-        s.close()
-        del x
-        torch.cuda.empty_cache()
+    for method, cyc in (("bicgstab", "F"), ("idrs", "V"), ("idrs", "F")):
+        key = f"{method}+{cyc}"
+        out[key] = {}
+        for prec, v in vres.items():
+            s = make(prec, method=method, cycle=cyc)
+            x, stats, times, iters = run_solves(s, args.steps, args.warmup)
+            t = float(np.sum(times))
+            out[key][prec] = {
+                "iterations": float(np.mean(iters)), "matvecs": int(np.mean([st.matvecs for st in stats])),
+                "ms_per_step": 1e3 * t / args.steps,
+                "relres_true_max": max(st.relres_true for st in stats),
+                "status": sorted({st.status for st in stats}),
+                "time_to_solution_speedup_vs_headline": v["ms_per_step"] / (1e3 * t / args.steps)}
+            s.close()
+            del x
+            torch.cuda.empty_cache()
     return out
 
 
@@ -258,9 +271,12 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="wedge", choices=["wedge", "cube513", "batched", "beta2_sweep"])
-    ap.add_argument("--no-fcycle", action="store_true", help="skip the F-cycle solves of the wedge")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the F-cycle and IDR(4) solves of the wedge")
     ap.add_argument("--cycle", default="V", choices=["V", "F"],
-                    help="preconditioner cycle of the timed solves (default V; F implies --no-fcycle)")
+                    help="preconditioner cycle of the headline solves (default V)")
+    ap.add_argument("--method", default="bicgstab", choices=["bicgstab", "idrs"],
+                    help="Krylov method of the headline solves (default bicgstab; idrs = IDR(4))")
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=4)
@@ -294,8 +310,9 @@ def main():
     n_nodes = int(np.prod(wl.shape))
     k = torch.from_numpy(wl.k).cuda()
 
-    def make(prec):
-        s = Solver(wl.shape, wl.h, bc=wl.bc, prec=prec, n_levels=wl.n_levels, nrhs_max=nrhs, cycle=args.cycle)
+    def make(prec, method=None, cycle=None):
+        s = Solver(wl.shape, wl.h, bc=wl.bc, prec=prec, n_levels=wl.n_levels, nrhs_max=nrhs,
+                   cycle=cycle or args.cycle, method=method or args.method)
         s.set_model(k)
         s.set_point_sources(nodes)
         if args.autotune:
@@ -311,7 +328,11 @@ def main():
         t = float(np.sum(times))
         it = float(np.mean(iters))
         rel = true_relres(wl, x, nodes) if args.workload != "cube513" else [s_.relres_true for s_ in stats]
-        dom, rows, bracket = kernel_roofline(s, nrhs, 0 if prec == "fp64" else 1, n_nodes, x, max(1, args.steps))
+        if args.method == "bicgstab":
+            dom, rows, bracket = kernel_roofline(s, nrhs, 0 if prec == "fp64" else 1, n_nodes, x,
+                                                 max(1, args.steps))
+        else:  # the library's in-solve kernel tracing covers the Bi-CGSTAB step only
+            dom, rows, bracket = None, {}, None
         results[prec] = {
             "value": dof(wl) * float(np.sum(iters)) / t,
             "ms_per_step": 1e3 * t / args.steps,
@@ -343,16 +364,23 @@ def main():
     solutions.clear()
     torch.cuda.empty_cache()
     fres = None
-    if args.workload == "wedge" and not args.no_fcycle and args.cycle == "V":
-        fres = fcycle_solves(args, wl, nodes, make, results)
+    if args.workload == "wedge" and not args.no_variants and args.cycle == "V" and args.method == "bicgstab":
+        fres = variant_solves(args, wl, nodes, make, results)
 
     head = results["mixed"]
     dom = head["dominant"]
-    row = head["kernels"][dom]
+    row = head["kernels"].get(dom)
     traffic = None
     key = (dom, args.workload, "mixed")
     if key in TRAFFIC and TRAFFIC[key][1] == kernel_source_sha():
         traffic = TRAFFIC[key][0]
+    roofline = None
+    if row is not None and row["GBs"]:
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": row["GBs"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": row["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
+                    "algorithmic_bytes_per_launch": row["bytes"], "avg_ms": row["ms"],
+                    "avg_ms_bracketed": row["ms_bracketed"], "event_bracket_ms": head["event_bracket_ms"],
+                    "launches": row["launches"]}
     line = {
         "metric": METRIC,
         "value": head["value"],
@@ -367,14 +395,11 @@ def main():
         "dtype": f"c64 {args.cycle}-cycle / c128 Krylov",
         "data": "synthetic",
         "config": {"workload": desc, "unknowns": dof(wl), "nrhs": nrhs, "rtol": 1e-6,
-                   "precision": "mixed", "cycle": args.cycle},
+                   "precision": "mixed", "cycle": args.cycle,
+                   "method": "IDR(4)" if args.method == "idrs" else "Bi-CGSTAB"},
         "iterations": head["iterations"],
         "relres_true_max": head["relres_true_max"],
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": row["GBs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": row["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": row["bytes"], "avg_ms": row["ms"],
-                     "avg_ms_bracketed": row["ms_bracketed"], "event_bracket_ms": head["event_bracket_ms"],
-                     "launches": row["launches"]},
+        "roofline": roofline,
         "kernels_mixed": {k_: {"ms": v["ms"], "GBs": v["GBs"] and round(v["GBs"], 1)}
                           for k_, v in head["kernels"].items()},
     }
@@ -390,7 +415,7 @@ def main():
     if ref_err is not None:
         line["error_vs_fp64_reference"] = ref_err
     if fres is not None:
-        line["fcycle"] = fres
+        line["variants"] = fres
     if not args.no_cpu and args.workload != "cube513":
         line["cpu_baseline"] = cpu_baseline(wl, nodes, args.cpu_iters)
     print(json.dumps(line), flush=True)

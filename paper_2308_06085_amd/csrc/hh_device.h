@@ -52,9 +52,11 @@ __device__ inline void block_fixed_sum(const double* __restrict__ part, long lon
     __shared__ double sm[NT][16];
     double v[NT];
     // lane t adds partials t, t + blockDim, t + 2 blockDim, ... in that order; the
-    // loads of eight consecutive terms of that sequence are issued before their
-    // adds (out-of-range slots read a valid partial and add exactly zero)
-    constexpr int U = 8;
+    // loads of U consecutive terms of that sequence are issued before their adds
+    // (out-of-range slots read a valid partial and add exactly zero).  U only
+    // sets how many loads are in flight (fewer for many rows, to stay in
+    // registers); the order of the adds, and so the sum, does not depend on it.
+    constexpr int U = NT <= 4 ? 8 : (NT <= 8 ? 4 : 2);
 #pragma unroll
     for (int t = 0; t < NT; ++t) v[t] = 0.0;
     for (long long b0 = threadIdx.x; b0 < nblk; b0 += (long long)U * blockDim.x) {

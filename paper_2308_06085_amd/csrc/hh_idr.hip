@@ -267,13 +267,28 @@ __device__ void sum_dots(int s, const double* part, long long nblk, long long nb
     }
 }
 
+// The state is staged in LDS for the one-thread algebra (a chain of dependent
+// global loads and stores would cost far more than the arithmetic) and
+// written back by all lanes.
+constexpr int IDR_STATE_WORDS = sizeof(IdrState) / sizeof(double);
+static_assert(sizeof(IdrState) % sizeof(double) == 0, "IdrState is copied as doubles");
+
+__device__ void idr_fin_algebra(int mode, int k, int reset, int s, double kappa, RhsState& R, IdrState& S,
+                                const double* d, double rn2, const double* tsum);
+
 __global__ __launch_bounds__(1024) void k_idr_finalize(int mode, int k, int reset, int s, double kappa,
                                                        RhsState* st, IdrState* is, const double* part,
                                                        long long nblk, long long nblk_max) {
     const int r = blockIdx.x;
-    RhsState& R = st[r];
-    if (R.status != ST_RUN) return;
-    IdrState& S = is[r];
+    if (st[r].status != ST_RUN) return;
+    __shared__ IdrState sS;
+    __shared__ RhsState sR;
+    {
+        const double* src = reinterpret_cast<const double*>(&is[r]);
+        double* dst = reinterpret_cast<double*>(&sS);
+        for (int w = threadIdx.x; w < IDR_STATE_WORDS; w += blockDim.x) dst[w] = src[w];
+        if (threadIdx.x == 0) sR = st[r];
+    }
     double d[2 * IDR_SMAX] = {};
     double rn2 = 0.0, tsum[3] = {0.0, 0.0, 0.0};
     if (mode != IDR_FIN_OMEGA) sum_dots(s, part + idr_row(r, 0, nblk_max), nblk, nblk_max, d);
@@ -284,7 +299,19 @@ __global__ __launch_bounds__(1024) void k_idr_finalize(int mode, int k, int rese
         block_fixed_sum<1>(part + idr_row(r, IDR_ROW_RN, nblk_max), nblk, nblk_max, o);
         rn2 = o[0];
     }
-    if (threadIdx.x != 0) return;
+    __syncthreads();
+    if (threadIdx.x == 0) idr_fin_algebra(mode, k, reset, s, kappa, sR, sS, d, rn2, tsum);
+    __syncthreads();
+    {
+        const double* src = reinterpret_cast<const double*>(&sS);
+        double* dst = reinterpret_cast<double*>(&is[r]);
+        for (int w = threadIdx.x; w < IDR_STATE_WORDS; w += blockDim.x) dst[w] = src[w];
+        if (threadIdx.x == 0) st[r] = sR;
+    }
+}
+
+__device__ void idr_fin_algebra(int mode, int k, int reset, int s, double kappa, RhsState& R, IdrState& S,
+                                const double* d, double rn2, const double* tsum) {
     const double tiny = 1e-300;
     // stop test on the residual of the previous update (none before step 0)
     if (mode != IDR_FIN_STEP || k > 0) {
