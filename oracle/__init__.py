@@ -17,7 +17,8 @@ Modules
                     recursive V- and F-cycles (section 3.4, Algorithm 1,
                     section 4.2).
 ``krylov``          right-preconditioned Bi-CGSTAB and IDR(s) with the
-                    true-residual stopping rule of section 5.
+                    true-residual stopping rule of section 5; left-preconditioned
+                    full GMRES with the preconditioned-residual rule.
 ``adjoint``         misfit gradient with respect to squared slowness by one
                     adjoint solve.
 
@@ -45,5 +46,5 @@ from .multigrid import (  # noqa: F401
     vcycle,
     fcycle,
 )
-from .krylov import bicgstab, idrs, SolveResult, Status  # noqa: F401
+from .krylov import bicgstab, gmres, idrs, SolveResult, Status  # noqa: F401
 from .adjoint import misfit_and_gradient, adjoint_gradient_pointwise, solve_forward  # noqa: F401

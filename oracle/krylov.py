@@ -1,4 +1,5 @@
-"""Right-preconditioned Bi-CGSTAB and IDR(s) (oracle; test infrastructure only).
+"""Right-preconditioned Bi-CGSTAB and IDR(s), left-preconditioned full GMRES
+(oracle; test infrastructure only).
 
 The paper uses Bi-CGSTAB (van der Vorst 1992) with right preconditioning
 (section 3.2), so the recursively updated residual is the true one, and stops
@@ -308,3 +309,101 @@ def idrs(apply_A, precond, b, P, x0=None, tol=1e-6, maxit=2000, kappa=0.7, max_r
         matvecs += 1
     true_rel = _norm(b - apply_A(x)) / bnorm
     return SolveResult(x, status, steps, matvecs, relres, true_rel, history)
+
+
+def gmres(apply_A, precond, b, x0=None, tol=1e-6, maxit=1000, monitor=None) -> SolveResult:
+    """Solve A x = b by full GMRES on the left-preconditioned system
+    K A x = K b, K = one multigrid cycle on M (sections 3.1, 3.2), stopped at
+    ||K b - K A x|| / ||K b|| <= tol (the paper's GMRES criterion, section 5).
+
+    No restart.  Arnoldi with modified Gram-Schmidt, Givens rotations for the
+    least-squares problem (Saad and Schultz 1986):
+
+        r = K (b - A x0);  beta = ||r||;  v_1 = r / beta;  g = beta e_1
+        for j = 1, 2, ...
+            w = K A v_j
+            for i = 1 .. j:  h_ij = <v_i, w>;  w -= h_ij v_i
+            h_{j+1,j} = ||w||;  v_{j+1} = w / h_{j+1,j}
+            apply the earlier rotations to column j, then the rotation that
+            zeroes h_{j+1,j}; |g_{j+1}| is the preconditioned residual norm
+            stop if |g_{j+1}| / ||K b|| <= tol
+        x = x0 + V y,  H y = g (upper triangular)
+
+    Counting: ``iterations`` = Arnoldi steps (products with A after the initial
+    residual); ``matvecs`` adds the initial residual when x0 is given (with
+    x0 = 0 the initial residual is b and costs no product).  ``relres`` is the
+    preconditioned relative residual, ``relres_true`` the unpreconditioned one.
+    monitor: optional callable(j, V, Hbar) after Arnoldi step j: V the j + 2
+    basis vectors, Hbar the (j + 2) x (j + 1) Hessenberg matrix before rotations.
+    """
+    b = np.asarray(b)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=b.dtype)
+    if _norm(b) == 0.0:
+        return SolveResult(np.zeros_like(b), Status.OK, 0, 0, 0.0, 0.0)
+    kb = precond(b)
+    kbn = _norm(kb)
+    matvecs = 0
+    if x0 is None:
+        r = kb
+    else:
+        r = precond(b - apply_A(x))
+        matvecs += 1
+    beta = _norm(r)
+    history = [beta / kbn]
+    if beta / kbn <= tol:
+        true_rel = _norm(b - apply_A(x)) / _norm(b)
+        return SolveResult(x, Status.OK, 0, matvecs, beta / kbn, true_rel, history)
+    V = [r / beta]
+    H = np.zeros((maxit + 1, maxit), dtype=np.complex128)
+    Hbar = np.zeros((maxit + 1, maxit), dtype=np.complex128) if monitor is not None else None
+    cs = np.zeros(maxit, dtype=np.complex128)
+    sn = np.zeros(maxit, dtype=np.complex128)
+    g = np.zeros(maxit + 1, dtype=np.complex128)
+    g[0] = beta
+    status = Status.NOT_CONVERGED
+    m = 0
+    relres = beta / kbn
+    for j in range(maxit):
+        w = precond(apply_A(V[j]))
+        matvecs += 1
+        for i in range(j + 1):
+            H[i, j] = _vdot(V[i], w)
+            w = w - H[i, j] * V[i]
+        H[j + 1, j] = _norm(w)
+        if monitor is not None and H[j + 1, j] != 0.0:
+            Hbar[: j + 2, j] = H[: j + 2, j]
+            monitor(j, V + [w / H[j + 1, j]], Hbar[: j + 2, : j + 1])
+        # earlier rotations on the new column
+        for i in range(j):
+            t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+            H[i + 1, j] = -np.conj(sn[i]) * H[i, j] + np.conj(cs[i]) * H[i + 1, j]
+            H[i, j] = t
+        # rotation zeroing H[j+1, j]:  [c s; -conj(s) conj(c)] with c real
+        a, bb = H[j, j], H[j + 1, j]
+        den = np.sqrt(abs(a) ** 2 + abs(bb) ** 2)
+        if den == 0.0:
+            status = Status.BREAKDOWN
+            m = j
+            break
+        cs[j] = abs(a) / den
+        sn[j] = (a / abs(a)) * np.conj(bb) / den if a != 0 else 1.0
+        H[j, j] = cs[j] * a + sn[j] * bb
+        H[j + 1, j] = 0.0
+        g[j + 1] = -np.conj(sn[j]) * g[j]
+        g[j] = cs[j] * g[j]
+        m = j + 1
+        relres = abs(g[j + 1]) / kbn
+        history.append(relres)
+        if relres <= tol:
+            status = Status.OK
+            break
+        if H[j + 1, j] == 0.0 and den == 0.0:
+            break
+        V.append(w / _norm(w))
+    y = np.zeros(m, dtype=np.complex128)
+    for i in range(m - 1, -1, -1):
+        y[i] = (g[i] - H[i, i + 1: m] @ y[i + 1: m]) / H[i, i]
+    for i in range(m):
+        x = x + y[i] * V[i]
+    true_rel = _norm(b - apply_A(x)) / _norm(b)
+    return SolveResult(x, status, m, matvecs, relres, true_rel, history)

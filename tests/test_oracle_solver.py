@@ -287,3 +287,77 @@ def test_paper_table1_idr4_matvec_band():
     assert lo <= res.matvecs <= hi, res.matvecs
     assert res.matvecs < 0.75 * min(gold["bicgstab"])
     assert np.abs(res.x - uex).max() < 2e-3
+
+
+# --------------------------------------------------------------------------
+# GMRES
+# --------------------------------------------------------------------------
+def test_gmres_iterate_minimises_the_preconditioned_residual():
+    """After m Arnoldi steps x_m minimises ||K (b - A x)|| over the Krylov space
+    span{K b, (K A) K b, ..., (K A)^{m-1} K b}: checked against a least-squares
+    solve on an explicitly built (QR-orthonormalised) Krylov matrix."""
+    lvl, hier, b = _problem(9, SOMMERFELD, seed=8)
+    A = lambda x: O.apply_A(x, lvl)  # noqa: E731
+    K = lambda r: vcycle(r, hier)  # noqa: E731
+    kb = K(b).ravel()
+    cols = [kb]
+    for _ in range(7):
+        cols.append(K(A(cols[-1].reshape(b.shape))).ravel())
+    for m in (1, 3, 8):
+        Q, _ = np.linalg.qr(np.array(cols[:m]).T)
+        KAQ = np.array([K(A(Q[:, i].reshape(b.shape))).ravel() for i in range(m)]).T
+        y, *_ = np.linalg.lstsq(KAQ, kb, rcond=None)
+        x_ls = (Q @ y).reshape(b.shape)
+        res = O.gmres(A, K, b, tol=0.0, maxit=m)
+        assert res.iterations == m
+        assert np.abs(res.x - x_ls).max() <= 1e-10 * np.abs(x_ls).max(), m
+
+
+def test_gmres_arnoldi_relation_and_orthonormal_basis():
+    lvl, hier, b = _problem(9, DIRICHLET, seed=9)
+    A = lambda x: O.apply_A(x, lvl)  # noqa: E731
+    K = lambda r: vcycle(r, hier)  # noqa: E731
+    seen = []
+
+    def mon(j, V, Hbar):
+        Vm = np.array([v.ravel() for v in V]).T
+        assert np.abs(Vm.conj().T @ Vm - np.eye(j + 2)).max() <= 1e-12
+        KAV = np.array([K(A(V[i])).ravel() for i in range(j + 1)]).T
+        assert np.abs(KAV - Vm @ Hbar).max() <= 1e-12 * np.abs(KAV).max()
+        assert np.all(np.tril(Hbar, -2) == 0)
+        seen.append(j)
+
+    O.gmres(A, K, b, tol=0.0, maxit=6, monitor=mon)
+    assert seen == list(range(6))
+
+
+@pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
+def test_gmres_matches_dense_direct_solve(bc):
+    lvl, hier, b = _problem(9, bc, seed=10)
+    res = O.gmres(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, tol=1e-13)
+    assert res.status == O.Status.OK
+    mask = unknown_mask(lvl.shape, bc)
+    idx = np.flatnonzero(mask.ravel())
+    cols = []
+    for j in idx:
+        e = np.zeros(lvl.shape, dtype=np.complex128)
+        e.ravel()[j] = 1.0
+        cols.append(O.apply_A(e, lvl).ravel()[idx])
+    xd = np.linalg.solve(np.array(cols).T, b.ravel()[idx])
+    assert np.abs(res.x.ravel()[idx] - xd).max() <= 1e-9 * np.abs(xd).max()
+
+
+def test_paper_table1_gmres_matvecs_exact():
+    """Table 1: full GMRES needs 145 matvecs on the closed-off 65^3, k = 40
+    problem with the 17^3 coarsest grid, the same for every partition (the
+    paper: GMRES is insensitive to rounding and reordering).  The oracle's
+    count is that exact value."""
+    with open(os.path.join(GOLDEN, "table1_bicgstab_matvec.json")) as f:
+        gold = json.load(f)
+    lvl, b, uex = O.closed_off_problem(gold["problem"]["n"], gold["problem"]["k"])
+    hier = build_hierarchy(lvl.k, lvl.h, lvl.bc, rule="paper17")
+    res = O.gmres(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, tol=gold["problem"]["tol"])
+    assert res.status == O.Status.OK
+    assert set(gold["gmres"]) == {145}
+    assert res.matvecs == 145
+    assert np.abs(res.x - uex).max() < 2e-3
