@@ -6,8 +6,8 @@
  * spacing h (Chen, Dwarka, Vuik, arXiv 2308.06085, section 2.4, eq. Helmstencil),
  * with homogeneous Dirichlet or first-order Sommerfeld boundary conditions
  * (section 2; Sommerfeld ghost points eliminated by eq. elimination), by
- * right-preconditioned Bi-CGSTAB, or IDR(s) (section 3.1, 3.2; option
- * "method"), stopped at
+ * right-preconditioned Bi-CGSTAB, or IDR(s), or left-preconditioned full GMRES
+ * (section 3.1, 3.2; option "method"), stopped at
  * ||b - A u|| / ||b|| <= rtol (section 5).  The preconditioner is the complex
  * shifted Laplacian M = -Laplace_h - (beta1 - beta2 i) k^2 I (section 3.3,
  * eq. preconditioner) inverted approximately by one geometric multigrid
@@ -141,7 +141,16 @@ hh_status hh_set_point_sources(hh_ctx* ctx, const int* ijk_host, int nrhs);
  * preconditioner; the residual stays b - A x and is tested after every update.
  * stats.iterations then counts products with A after the initial residual,
  * stats.matvecs adds the initial residual and one per restart (the paper's
- * #Matvec). */
+ * #Matvec).
+ * With "method" = 2 the method is full GMRES on the left-preconditioned system
+ * K A x = K b (K = one multigrid cycle), Arnoldi with classical Gram-Schmidt
+ * applied twice, Givens rotations on the device; it stops when
+ * ||K (b - A x)|| / ||K b|| <= rtol (the paper's GMRES criterion) and restarts
+ * from the current x when the basis of "gmres_m" vectors is full.
+ * stats.iterations counts Arnoldi steps, stats.relres is that preconditioned
+ * relative residual and stats.relres_true the plain one (not tested against
+ * rtol); stats.matvecs counts products with A (none for the initial residual
+ * when x0 = 0). */
 hh_status hh_solve(hh_ctx* ctx, void* x, double rtol, int maxit, int use_x0,
                    hh_stats* stats_host);
 
@@ -199,7 +208,10 @@ hh_status hh_set_shadow(hh_ctx* ctx, const void* P, int s);
  * residual pass on each level from 1 to the second coarsest; other values are
  * HH_ERR_ARG).
  * "method" (0 = Bi-CGSTAB, default; 1 = IDR(s), see hh_solve; allocates
- * 2 s complex128 vectors per right-hand side and s complex64 ones),
+ * 2 s complex128 vectors per right-hand side and s complex64 ones; 2 = full
+ * GMRES, allocates gmres_m + 1 complex128 vectors per right-hand side),
+ * "gmres_m" (1..1024, default 200: GMRES basis size before a restart; GMRES
+ * launches its steps directly, without graph or trace),
  * "idr_s" (1..8, default 4), "idr_seed" (0..2^23 - 1, default 1: the generated
  * shadow vectors), "idr_kappa_milli" (0..1000, default 700: the reduction step
  * enlarges omega to kappa / rho times the minimal-residual value when

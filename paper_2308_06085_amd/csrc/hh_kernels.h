@@ -18,7 +18,9 @@ struct Launch {
 enum OpMode : int { OP_PLAIN = 0, OP_V = 1, OP_T = 2, OP_P = 3 };
 // FIN_OMEGA also takes the half-step test on ||s||: the s update writes its
 // partial sums beside those of t = A s_hat, so one finalize serves both.
-enum FinMode : int { FIN_INIT = 0, FIN_RHO = 1, FIN_ALPHA = 2, FIN_OMEGA = 4, FIN_TRUE = 5 };
+// FIN_TRUE_RECORD: the true residual only, no restart (GMRES stops on the
+// preconditioned residual)
+enum FinMode : int { FIN_INIT = 0, FIN_RHO = 1, FIN_ALPHA = 2, FIN_OMEGA = 4, FIN_TRUE = 5, FIN_TRUE_RECORD = 6 };
 constexpr int GATE_ALL = -1;       // act on every right-hand side
 constexpr int GATE_FINISHED = -2;  // act on right-hand sides that stopped iterating
 
@@ -126,6 +128,38 @@ void launch_idr_finalize(hipStream_t s, int mode, int k, int reset, int nrhs, in
                          RhsState* st, IdrState* is, const double* part, long long nblk, long long nblk_max);
 void launch_idr_gen_p(hipStream_t s, long long n, int ns, unsigned long long seed, c64* P);
 void launch_idr_set_p(hipStream_t s, long long total, const c128* src, c64* P);
+
+// Full GMRES kernels (hh_gmres.hip).  Basis vector (i, r) at V + i * rsv + r * n;
+// per right-hand side a GmHead and its arrays (GmLayout, in doubles); partial
+// sums of GM_NBLK workgroups per row, `rows` rows per right-hand side.
+constexpr int GM_NBLK = 1024;
+struct alignas(16) GmHead {
+    double beta, kbn, scale, pad0;
+    int m, update, pad1, pad2;
+};
+static_assert(sizeof(GmHead) % 16 == 0, "GmHead keeps the arrays after it 16-byte aligned");
+struct GmLayout {
+    long long H, cs, sn, g, y, h1, dots, words;
+    int norm_row, rows;
+};
+GmLayout gm_host_layout(int M);
+enum GmFin : int { GM_FIN_START = 0, GM_FIN_DOTS1 = 1, GM_FIN_DOTS2 = 2 };
+void launch_gm_dots(hipStream_t s, long long n, int nrhs, int j, const c128* w, const c128* V, long long rsv,
+                    double* part, long long rows_per_rhs, const RhsState* st);
+void launch_gm_axpy(hipStream_t s, long long n, int nrhs, int j, const c128* w_in, c128* w_out, const c128* V,
+                    long long rsv, const double* gst, long long gst_words, long long coef_off, bool norm,
+                    double* part, long long rows_per_rhs, int norm_row, const RhsState* st);
+void launch_gm_rowsum(hipStream_t s, int nrhs, int row_begin, int nrows, const double* part, long long rows_per_rhs,
+                      double* gst, long long gst_words, long long dots_off, const RhsState* st);
+void launch_gm_norm2(hipStream_t s, long long n, int nrhs, const c128* a, double* part, long long rows_per_rhs,
+                     int row, const RhsState* st);
+void launch_gm_scale(hipStream_t s, long long n, int nrhs, const c128* src, c128* dst, const double* gst,
+                     long long gst_words, const RhsState* st);
+void launch_gm_xupdate(hipStream_t s, long long n, int nrhs, c128* xk, const c128* V, long long rsv,
+                       const double* gst, long long gst_words, long long y_off);
+void launch_gm_clear(hipStream_t s, int nrhs, double* gst, long long gst_words);
+void launch_gm_finalize(hipStream_t s, int mode, int j, int M, int kb, double tol, int nrhs, RhsState* st,
+                        double* gst, long long gst_words);
 
 void launch_model_check(hipStream_t s, long long n, const double* k, double* k2, double* kb, int* bad);
 void launch_inject(hipStream_t s, const Geo& gf, const Geo& gc, const double* kf, double* kc);

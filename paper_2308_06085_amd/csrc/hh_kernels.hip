@@ -118,6 +118,10 @@ __device__ void fin_update(int mode, RhsState& S, const double* s, double tol) {
             if (!isfinite(s[0]) || !isfinite(s[3])) S.status = ST_NUMERIC;
             else if (s[3] == 0.0 || s[0] <= S.tol2) S.status = ST_CONV;
             return;
+        case FIN_TRUE_RECORD:
+            S.true_rnorm2 = s[0];
+            if (!isfinite(s[0])) S.status = ST_NUMERIC;
+            return;
         case FIN_TRUE:
             S.true_rnorm2 = s[0];
             if (!isfinite(s[0])) {
@@ -195,7 +199,8 @@ __device__ __forceinline__ int fin_terms(int mode) {
         case FIN_ALPHA: return 2;
         case FIN_OMEGA: return 4;
         case FIN_RHO: return 3;
-        case FIN_TRUE: return 1;
+        case FIN_TRUE:
+        case FIN_TRUE_RECORD: return 1;
         default: return 4;
     }
 }
@@ -217,7 +222,8 @@ __global__ __launch_bounds__(1024) void k_finalize(int mode, RhsState* st, const
     const int status = S.status;
     bool act;
     switch (mode) {
-        case FIN_TRUE: act = status != ST_RUN && status != ST_IDLE && status != ST_HALF; break;
+        case FIN_TRUE:
+        case FIN_TRUE_RECORD: act = status != ST_RUN && status != ST_IDLE && status != ST_HALF; break;
         case FIN_RHO: act = status == ST_RUN || status == ST_HALF; break;
         default: act = status == ST_RUN; break;
     }

@@ -89,8 +89,13 @@ struct hh_ctx {
     std::map<int, hipGraphExec_t> graphs;
     int tail_first = 0;   // first level run by the single-workgroup tail kernel
     int cycle = 0;        // preconditioner cycle: 0 = V-cycle, 1 = F-cycle
-    // Krylov method: 0 = Bi-CGSTAB, 1 = IDR(s)
+    // Krylov method: 0 = Bi-CGSTAB, 1 = IDR(s), 2 = full GMRES
     int method = 0;
+    int gm_M = 200;                // GMRES basis size before a restart
+    int gm_alloc_M = 0;
+    c128* gm_V = nullptr;          // (M + 1) basis vectors per right-hand side
+    double* gm_part = nullptr;     // partial sums, GmLayout::rows rows of GM_NBLK per RHS
+    double* gm_st = nullptr;       // per-RHS GmHead and arrays
     int idr_s = 4;                 // shadow-space dimension
     int idr_s_alloc = 0;           // s the IDR buffers were allocated for
     double idr_kappa = 0.7;        // omega safeguard of the reduction step (0 = plain minimal residual)
@@ -190,6 +195,7 @@ void free_all(hh_ctx* c) {
     for (auto& kv : c->idr_graphs) (void)hipGraphExecDestroy(kv.second);
     c->idr_graphs.clear();
     for (void* q : {(void*)c->idr_G, (void*)c->idr_U, (void*)c->idr_P, (void*)c->idr_st}) (void)hipFree(q);
+    for (void* q : {(void*)c->gm_V, (void*)c->gm_part, (void*)c->gm_st}) (void)hipFree(q);
     for (auto& L : c->lv) {
         (void)hipFree(L.k);
         (void)hipFree(L.k2l);
@@ -212,6 +218,24 @@ void invalidate_graphs(hh_ctx* c) {
     c->graphs.clear();
     for (auto& kv : c->idr_graphs) (void)hipGraphExecDestroy(kv.second);
     c->idr_graphs.clear();
+}
+
+// GMRES buffers for a basis of M + 1 vectors per right-hand side.
+hh_status gm_alloc(hh_ctx* c, int M) {
+    if (M <= c->gm_alloc_M) return HH_OK;
+    for (void* q : {(void*)c->gm_V, (void*)c->gm_part, (void*)c->gm_st}) (void)hipFree(q);
+    c->gm_V = nullptr;
+    c->gm_part = c->gm_st = nullptr;
+    c->gm_alloc_M = 0;
+    const size_t n = (size_t)c->lv[0].g.n;
+    const size_t R = (size_t)c->cfg.nrhs_max;
+    const GmLayout L = gm_host_layout(M);
+    CHK(dalloc(c, &c->gm_V, sizeof(c128) * (size_t)(M + 1) * R * n));
+    CHK(dalloc(c, &c->gm_part, sizeof(double) * R * (size_t)L.rows * GM_NBLK));
+    CHK(dalloc(c, &c->gm_st, sizeof(double) * R * (size_t)L.words));
+    HIPCHK(c, hipMemset(c->gm_st, 0, sizeof(double) * R * (size_t)L.words));
+    c->gm_alloc_M = M;
+    return HH_OK;
 }
 
 // IDR(s) buffers for shadow dimension s: G and U (s complex128 vectors per
@@ -719,6 +743,84 @@ hh_status run_idr(hh_ctx* c, int nrhs, int maxit) {
 
 
 // Copy out the solution and fill the statistics of a finished solve.
+// Full GMRES iteration of hh_solve after the initial residual r = b - A x0
+// (restarted from the current x when the basis of gm_M vectors is full);
+// direct launches, states read every check_every Arnoldi steps.
+hh_status run_gmres(hh_ctx* c, int nrhs, int maxit, double rtol, int use_x0) {
+    const int M = c->gm_M;
+    CHK(gm_alloc(c, M));
+    const GmLayout L = gm_host_layout(M);
+    const Geo& g = c->lv[0].g;
+    const long long n = g.n;
+    const long long rsv = (long long)c->cfg.nrhs_max * n;
+    const long long rows = L.rows, words = L.words;
+    hipStream_t s = c->stream;
+    RhsState* st = c->st;
+    auto start = [&](int kb) {
+        enqueue_cycle(c, s, nrhs, c->r, c->t, st, ST_RUN);  // K r0
+        launch_gm_norm2(s, n, nrhs, c->t, c->gm_part, rows, L.norm_row, st);
+        if (kb == 1) {
+            enqueue_cycle(c, s, nrhs, c->bsrc, c->s, st, ST_RUN);  // K b
+            launch_gm_norm2(s, n, nrhs, c->s, c->gm_part, rows, L.norm_row + 1, st);
+        }
+        launch_gm_rowsum(s, nrhs, L.norm_row, kb == 1 ? 2 : 1, c->gm_part, rows, c->gm_st, words, L.dots, st);
+        launch_gm_finalize(s, GM_FIN_START, 0, M, kb, rtol, nrhs, st, c->gm_st, words);
+        launch_gm_scale(s, n, nrhs, c->t, c->gm_V, c->gm_st, words, st);
+    };
+    auto step = [&](int j) {
+        launch_apply<double>(s, c->cfg.bc, OP_PLAIN, g, c->L0, nrhs, c->gm_V + j * rsv, c->v, c->k2, c->kb, 1.0,
+                             0.0, nullptr, nullptr, NBLK_CAP, st, ST_RUN);
+        enqueue_cycle(c, s, nrhs, c->v, c->t, st, ST_RUN);  // w = K A v_j
+        // first sweep: h1 = V^H w, w1 = w - V h1
+        launch_gm_dots(s, n, nrhs, j, c->t, c->gm_V, rsv, c->gm_part, rows, st);
+        launch_gm_rowsum(s, nrhs, 0, 2 * (j + 1), c->gm_part, rows, c->gm_st, words, L.dots, st);
+        launch_gm_finalize(s, GM_FIN_DOTS1, j, M, 0, rtol, nrhs, st, c->gm_st, words);
+        launch_gm_axpy(s, n, nrhs, j, c->t, c->s, c->gm_V, rsv, c->gm_st, words, L.h1, false, c->gm_part, rows,
+                       L.norm_row, st);
+        // second sweep: h2 = V^H w1, w2 = w1 - V h2, ||w2||
+        launch_gm_dots(s, n, nrhs, j, c->s, c->gm_V, rsv, c->gm_part, rows, st);
+        launch_gm_rowsum(s, nrhs, 0, 2 * (j + 1), c->gm_part, rows, c->gm_st, words, L.dots, st);
+        launch_gm_axpy(s, n, nrhs, j, c->s, c->t, c->gm_V, rsv, c->gm_st, words, L.dots, true, c->gm_part, rows,
+                       L.norm_row, st);
+        launch_gm_rowsum(s, nrhs, L.norm_row, 1, c->gm_part, rows, c->gm_st, words, L.dots, st);
+        launch_gm_finalize(s, GM_FIN_DOTS2, j, M, 0, rtol, nrhs, st, c->gm_st, words);
+        launch_gm_scale(s, n, nrhs, c->t, c->gm_V + (j + 1) * rsv, c->gm_st, words, st);
+    };
+    start(use_x0 ? 1 : 0);
+    HIPCHK(c, hipGetLastError());
+    CHK(read_states(c, nrhs));
+    int j = 0;
+    long long guard = 0;
+    while (true) {
+        bool any_run = false;
+        for (int r = 0; r < nrhs; ++r) any_run |= c->st_host[r].status == ST_RUN;
+        if (!any_run) break;
+        for (int k = 0; k < c->check_every && j < M; ++k, ++j) step(j);
+        // x += V y for every right-hand side whose cycle ended in this window
+        launch_gm_xupdate(s, n, nrhs, c->xk, c->gm_V, rsv, c->gm_st, words, L.y);
+        launch_gm_clear(s, nrhs, c->gm_st, words);
+        HIPCHK(c, hipGetLastError());
+        CHK(read_states(c, nrhs));
+        if (j == M) {
+            // full basis: restart the iterating ones from the updated x
+            launch_init(s, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->k2, c->kb, 1,
+                        c->part, NBLK_CAP, st, ST_RUN);
+            start(2);
+            HIPCHK(c, hipGetLastError());
+            CHK(read_states(c, nrhs));
+            j = 0;
+        }
+        if (++guard > 4LL * (maxit + 8) * (MAX_RESTARTS + 1)) return fail(c, HH_ERR_STATE, "driver did not terminate");
+    }
+    // the true residual of every solution (GMRES stops on the preconditioned one)
+    launch_init(s, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->k2, c->kb, 1, c->part,
+                NBLK_CAP, st, GATE_FINISHED);
+    launch_finalize(s, FIN_TRUE_RECORD, nrhs, st, c->part, c->nblk0, NBLK_CAP, 0.0);
+    HIPCHK(c, hipGetLastError());
+    CHK(read_states(c, nrhs));
+    return HH_OK;
+}
+
 hh_status finish_solve(hh_ctx* c, void* x, int nrhs, hipEvent_t e0, hipEvent_t e1, hh_stats* stats) {
     const size_t bytes = sizeof(c128) * c->lv[0].g.n * nrhs;
     HIPCHK(c, hipMemcpyAsync(x, c->xk, bytes, hipMemcpyDeviceToDevice, c->stream));
@@ -739,7 +841,9 @@ hh_status finish_solve(hh_ctx* c, void* x, int nrhs, hipEvent_t e0, hipEvent_t e
             case ST_NUMERIC: sr = HH_ERR_NUMERIC; break;
             default: sr = HH_ERR_STATE; break;
         }
-        if (S.status == ST_CONV && S.bnorm2 > 0.0 && S.true_rnorm2 > S.tol2) sr = HH_ERR_NOT_CONVERGED;
+        // Bi-CGSTAB and IDR(s) stop on the true residual; GMRES on the preconditioned one
+        if (c->method != 2 && S.status == ST_CONV && S.bnorm2 > 0.0 && S.true_rnorm2 > S.tol2)
+            sr = HH_ERR_NOT_CONVERGED;
         if (stats) {
             hh_stats& o = stats[r];
             o.iterations = 0.5 * S.iters2;
@@ -1043,6 +1147,10 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
         CHK(run_idr(c, nrhs, maxit));
         return finish_solve(c, x, nrhs, e0, e1, stats);
     }
+    if (c->method == 2) {
+        CHK(run_gmres(c, nrhs, maxit, rtol, use_x0));
+        return finish_solve(c, x, nrhs, e0, e1, stats);
+    }
     hipGraphExec_t exec = nullptr;
     if (c->use_graph && !c->trace) CHK(get_graph(c, nrhs, &exec));
     const size_t ev_per_step = 2 * NTRACE_LAUNCH;
@@ -1152,9 +1260,15 @@ hh_status hh_set_option(hh_ctx* c, const char* name, long long value) {
             c->tcnt[k] = 0;
         }
     } else if (n == "method") {
-        if (value != 0 && value != 1) return fail(c, HH_ERR_ARG, "method must be 0 (Bi-CGSTAB) or 1 (IDR(s))");
+        if (value < 0 || value > 2)
+            return fail(c, HH_ERR_ARG, "method must be 0 (Bi-CGSTAB), 1 (IDR(s)) or 2 (GMRES)");
         if (value == 1) CHK(idr_alloc(c, c->idr_s));
+        if (value == 2) CHK(gm_alloc(c, c->gm_M));
         c->method = (int)value;
+    } else if (n == "gmres_m") {
+        if (value < 1 || value > 1024) return fail(c, HH_ERR_ARG, "gmres_m must be in 1..1024");
+        c->gm_M = (int)value;
+        if (c->method == 2) CHK(gm_alloc(c, c->gm_M));
     } else if (n == "idr_s") {
         if (value < 1 || value > IDR_SMAX) return fail(c, HH_ERR_ARG, "idr_s must be in 1..%d", IDR_SMAX);
         if (value != c->idr_s) {
@@ -1232,6 +1346,7 @@ hh_status hh_get_option(const hh_ctx* c, const char* name, long long* value) {
     else if (n == "trace") *value = c->trace;
     else if (n == "cycle") *value = c->cycle;
     else if (n == "method") *value = c->method;
+    else if (n == "gmres_m") *value = c->gm_M;
     else if (n == "idr_s") *value = c->idr_s;
     else if (n == "idr_seed") *value = (long long)c->idr_seed;
     else if (n == "idr_kappa_milli") *value = (long long)std::llround(c->idr_kappa * 1000.0);

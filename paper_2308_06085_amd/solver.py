@@ -55,11 +55,12 @@ class Solver:
     M = -Laplace - (beta1 - beta2 i) k^2 (default (1, -0.5)); omega: Jacobi
     weight (0.8); n_levels: 0 = coarsen while >= 3 nodes per axis remain;
     cycle: "V" | "F", the multigrid cycle that approximates M^-1 (section 3.4.5);
-    method: "bicgstab" | "idrs" (IDR(s) with s = idr_s, section 3.1).
+    method: "bicgstab" | "idrs" (IDR(s) with s = idr_s, section 3.1) | "gmres" (full
+    GMRES on the left-preconditioned system, restarted after gmres_m steps).
     """
 
     def __init__(self, shape, h, bc="sommerfeld", prec="fp64", n_levels=0, nrhs_max=1,
-                 beta=(1.0, -0.5), omega=0.8, cycle="V", method="bicgstab", idr_s=4, device=None):
+                 beta=(1.0, -0.5), omega=0.8, cycle="V", method="bicgstab", idr_s=4, gmres_m=200, device=None):
         self.lib = _lib.load()
         nz, ny, nx = (int(v) for v in shape)
         self.shape = (nz, ny, nx)
@@ -89,13 +90,16 @@ class Solver:
         self.cycle = cycle
         if cycle == "F":
             self.set_option("cycle", 1)
-        if method not in ("bicgstab", "idrs"):
+        if method not in ("bicgstab", "idrs", "gmres"):
             self.close()
-            raise ValueError(f"method must be 'bicgstab' or 'idrs', not {method!r}")
+            raise ValueError(f"method must be 'bicgstab', 'idrs' or 'gmres', not {method!r}")
         self.method = method
         if method == "idrs":
             self.set_option("idr_s", int(idr_s))
             self.set_option("method", 1)
+        elif method == "gmres":
+            self.set_option("gmres_m", int(gmres_m))
+            self.set_option("method", 2)
 
     # -- lifetime -----------------------------------------------------------
     def close(self):

@@ -169,7 +169,7 @@ def test_idrs_batched_graph_and_generated_shadow():
     with pytest.raises(HHError):
         s.set_option("idr_s", 9)
     with pytest.raises(HHError):
-        s.set_option("method", 2)
+        s.set_option("method", 3)
     with pytest.raises(HHError):
         s.set_shadow(dev(np.zeros((9,) + wl.shape, dtype=np.complex128)))
     # back to Bi-CGSTAB on the same context
