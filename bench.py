@@ -31,10 +31,13 @@ steps of the same workload) on the host.
 
 ``variants`` (wedge workload): the same solves with the paper's other
 solver settings, both precisions, timed the same way: Bi-CGSTAB with one
-F(1,1)-cycle (section 3.4.5), and IDR(4) (section 3.1) with the V- and with
-the F-cycle.  Each gives iterations (Bi-CGSTAB steps, or IDR products with A),
-products with A (``matvecs``, the paper's #Matvec), time per solve, and the
-time-to-solution ratio against the headline Bi-CGSTAB + V-cycle solve.
+F(1,1)-cycle (section 3.4.5), IDR(4) (section 3.1) with the V- and with the
+F-cycle, and full GMRES (left preconditioning, stopped on the preconditioned
+residual as in the paper) with the V- and the F-cycle.  Each gives iterations
+(Bi-CGSTAB steps, IDR products with A, GMRES Arnoldi steps), products with A
+(``matvecs``, the paper's #Matvec), time per solve, the true relative
+residual, and the time-to-solution ratio against the headline Bi-CGSTAB +
+V-cycle solve.
 
 ``--method idrs`` / ``--cycle F`` change the headline solves themselves.
 
@@ -79,27 +82,31 @@ KERNELS = {
 
 # HBM traffic per launch, FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scale factors
 # from a 1 GiB reference copy) from two rocprofv3 --pmc runs of
-# `bench.py --steps 1 --warmup 0 --no-cpu --no-fp64 --copy-calibration`
+# `bench.py --steps 1 --warmup 0 --no-cpu --no-fp64 --no-variants --copy-calibration`
 # (profiles/wedge_129x129x257_solve.md).  Valid only for the kernel sources it
 # was measured on (kernel_source_sha); otherwise reported as null.
 TRAFFIC = {
-    ("apply_A+dots", "wedge", "mixed"): (215.9e6, "f489bd6a3733a975"),
-    ("update_xr+dots", "wedge", "mixed"): (479.5e6, "f489bd6a3733a975"),
-    ("mg_down_L0", "wedge", "mixed"): (74.5e6, "f489bd6a3733a975"),
-    ("mg_up_L0", "wedge", "mixed"): (99.3e6, "f489bd6a3733a975"),
-    ("p_update", "wedge", "mixed"): (307.9e6, "f489bd6a3733a975"),
-    ("s_update+dot", "wedge", "mixed"): (239.7e6, "f489bd6a3733a975"),
+    ("apply_A+dots", "wedge", "mixed"): (214.3e6, "412c39d9f72d1a31"),
+    ("update_xr+dots", "wedge", "mixed"): (479.5e6, "412c39d9f72d1a31"),
+    ("mg_down_L0", "wedge", "mixed"): (74.3e6, "412c39d9f72d1a31"),
+    ("mg_up_L0", "wedge", "mixed"): (99.4e6, "412c39d9f72d1a31"),
+    ("p_update", "wedge", "mixed"): (307.9e6, "412c39d9f72d1a31"),
+    ("s_update+dot", "wedge", "mixed"): (239.7e6, "412c39d9f72d1a31"),
 }
 
 
+# the sources that define the kernels of the TRAFFIC table (the operator apply
+# and Krylov updates, the multigrid passes) and the device headers they include
+TRAFFIC_SOURCES = ("hh_kernels.hip", "hh_mg_fused.hip", "hh_common.h", "hh_device.h", "hh_kernels.h")
+
+
 def kernel_source_sha() -> str:
-    """sha256 (16 hex digits) of every HIP source and header of the library."""
+    """sha256 (16 hex digits) of the sources of the kernels in TRAFFIC."""
     csrc = os.path.join(ROOT, "paper_2308_06085_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -246,7 +253,7 @@ def variant_solves(args, wl, nodes, make, vres):
     import torch
 
     out = {}
-    for method, cyc in (("bicgstab", "F"), ("idrs", "V"), ("idrs", "F")):
+    for method, cyc in (("bicgstab", "F"), ("idrs", "V"), ("idrs", "F"), ("gmres", "V"), ("gmres", "F")):
         key = f"{method}+{cyc}"
         out[key] = {}
         for prec, v in vres.items():
@@ -275,8 +282,8 @@ def main():
                     help="skip the F-cycle and IDR(4) solves of the wedge")
     ap.add_argument("--cycle", default="V", choices=["V", "F"],
                     help="preconditioner cycle of the headline solves (default V)")
-    ap.add_argument("--method", default="bicgstab", choices=["bicgstab", "idrs"],
-                    help="Krylov method of the headline solves (default bicgstab; idrs = IDR(4))")
+    ap.add_argument("--method", default="bicgstab", choices=["bicgstab", "idrs", "gmres"],
+                    help="Krylov method of the headline solves (default bicgstab; idrs = IDR(4); gmres = full GMRES)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=4)
@@ -396,7 +403,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "unknowns": dof(wl), "nrhs": nrhs, "rtol": 1e-6,
                    "precision": "mixed", "cycle": args.cycle,
-                   "method": "IDR(4)" if args.method == "idrs" else "Bi-CGSTAB"},
+                   "method": {"idrs": "IDR(4)", "gmres": "GMRES"}.get(args.method, "Bi-CGSTAB")},
         "iterations": head["iterations"],
         "relres_true_max": head["relres_true_max"],
         "roofline": roofline,
