@@ -26,6 +26,10 @@ subtracted from each kernel's average bracketed duration (``avg_ms_bracketed``)
 to give ``avg_ms``, the kernel's own duration.  ``achieved`` = the kernel's
 algorithmic bytes per launch / ``avg_ms``, against 8 TB/s HBM3E peak;
 ``launches`` is the number of launches behind the average.
+``hbm_per_iteration``: the algorithmic bytes of one whole Bi-CGSTAB step as
+built (every kernel of KERNELS, the coarse multigrid levels at 1/7 of the
+level-0 passes) per DoF, times DoF x iterations / solve time: the whole
+iteration's HBM rate, beside the dominant kernel's.
 ``cpu_baseline`` times the CPU oracle on a bounded sample (a few Bi-CGSTAB
 steps of the same workload) on the host.
 
@@ -37,7 +41,7 @@ residual as in the paper) with the V- and the F-cycle.  Each gives iterations
 (Bi-CGSTAB steps, IDR products with A, GMRES Arnoldi steps), products with A
 (``matvecs``, the paper's #Matvec), time per solve, the true relative
 residual, and the time-to-solution ratio against the headline Bi-CGSTAB +
-V-cycle solve.
+V-cycle solve.  The batched workload reports Bi-CGSTAB with the F-cycle.
 
 ``--method idrs`` / ``--cycle F`` change the headline solves themselves.
 
@@ -79,6 +83,16 @@ KERNELS = {
     4: ("p_update", 1, (4 * 16, 4 * 16 + 8)),
     5: ("s_update+dot", 1, (3 * 16, 3 * 16 + 8)),
 }
+
+# Coarse multigrid levels per preconditioner application: the level-0 pass
+# bytes (down + up) times sum_{l>=1} 8^-l = 1/7; two applications per step.
+def step_bytes_per_dof(prec_idx: int) -> float:
+    """Algorithmic bytes per DoF of one Bi-CGSTAB step as built: every level-0
+    kernel of KERNELS times its launches per step, plus the coarse levels."""
+    total = sum(per * nb[prec_idx] for _, per, nb in KERNELS.values())
+    mg = KERNELS[2][2][prec_idx] + KERNELS[3][2][prec_idx]
+    return total + 2 * mg / 7.0
+
 
 # HBM traffic per launch, FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scale factors
 # from a 1 GiB reference copy) from two rocprofv3 --pmc runs of
@@ -248,12 +262,12 @@ def beta2_sweep(args, wl, nodes, desc):
     print(json.dumps(line), flush=True)
 
 
-def variant_solves(args, wl, nodes, make, vres):
+def variant_solves(args, wl, nodes, make, vres, combos):
     """The timed solves again with the other Krylov method / multigrid cycle."""
     import torch
 
     out = {}
-    for method, cyc in (("bicgstab", "F"), ("idrs", "V"), ("idrs", "F"), ("gmres", "V"), ("gmres", "F")):
+    for method, cyc in combos:
         key = f"{method}+{cyc}"
         out[key] = {}
         for prec, v in vres.items():
@@ -340,7 +354,11 @@ def main():
                                                  max(1, args.steps))
         else:  # the library's in-solve kernel tracing covers the Bi-CGSTAB step only
             dom, rows, bracket = None, {}, None
+        bpd = step_bytes_per_dof(0 if prec == "fp64" else 1)
+        step_gbs = bpd * dof(wl) * float(np.sum(iters)) / t / 1e9
         results[prec] = {
+            "hbm_per_iteration": {"bytes_per_dof": round(bpd, 1), "GBs": step_gbs,
+                                  "frac": step_gbs / HBM_PEAK_GBS} if args.method == "bicgstab" else None,
             "value": dof(wl) * float(np.sum(iters)) / t,
             "ms_per_step": 1e3 * t / args.steps,
             "iterations": it,
@@ -371,8 +389,12 @@ def main():
     solutions.clear()
     torch.cuda.empty_cache()
     fres = None
-    if args.workload == "wedge" and not args.no_variants and args.cycle == "V" and args.method == "bicgstab":
-        fres = variant_solves(args, wl, nodes, make, results)
+    if not args.no_variants and args.cycle == "V" and args.method == "bicgstab":
+        if args.workload == "wedge":
+            fres = variant_solves(args, wl, nodes, make, results,
+                                  (("bicgstab", "F"), ("idrs", "V"), ("idrs", "F"), ("gmres", "V"), ("gmres", "F")))
+        elif args.workload == "batched":
+            fres = variant_solves(args, wl, nodes, make, results, (("bicgstab", "F"),))
 
     head = results["mixed"]
     dom = head["dominant"]
@@ -406,6 +428,7 @@ def main():
                    "method": {"idrs": "IDR(4)", "gmres": "GMRES"}.get(args.method, "Bi-CGSTAB")},
         "iterations": head["iterations"],
         "relres_true_max": head["relres_true_max"],
+        "hbm_per_iteration": head["hbm_per_iteration"],
         "roofline": roofline,
         "kernels_mixed": {k_: {"ms": v["ms"], "GBs": v["GBs"] and round(v["GBs"], 1)}
                           for k_, v in head["kernels"].items()},
@@ -413,6 +436,7 @@ def main():
     if "fp64" in results:
         f = results["fp64"]
         line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "iterations": f["iterations"],
+                        "hbm_per_iteration": f["hbm_per_iteration"],
                         "relres_true_max": f["relres_true_max"], "dominant": f["dominant"],
                         "kernels": {k_: {"ms": v["ms"], "GBs": v["GBs"] and round(v["GBs"], 1)}
                                     for k_, v in f["kernels"].items()}}

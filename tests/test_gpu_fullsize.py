@@ -1,9 +1,10 @@
 """GPU parity at the full workload sizes, in the launch configuration bench.py uses.
 
-* wedge 129 x 129 x 257 (4,276,737 unknowns, Sommerfeld, 10 Hz): operator and
-  one V-cycle against the oracle element by element on the whole grid; FP64 and
-  mixed solves checked by the true residual under the oracle's operator; the
-  mixed solution against a tight FP64 solve.
+* wedge 129 x 129 x 257 (4,276,737 unknowns, Sommerfeld, 10 Hz): operator,
+  one V-cycle and one F-cycle against the oracle element by element on the
+  whole grid; FP64 and mixed Bi-CGSTAB solves, and mixed IDR(4) and GMRES
+  solves, checked by the true residual under the oracle's operator; the mixed
+  solution against a tight FP64 solve.
 * the same wedge with 16 seeded top-face sources, one batched mixed solve:
   every right-hand side's true residual under the oracle's operator.
 * 513^3 cube, k = 160, 8 levels: the operator on z-slabs against the oracle,
@@ -199,3 +200,39 @@ def test_adjoint_workload_gradient():
     fd, ad = np.array(fd), np.array(ad)
     cos_fd = fd @ ad / (np.linalg.norm(fd) * np.linalg.norm(ad))
     assert cos_fd >= 0.999, (cos_fd, fd, ad)
+
+
+def test_wedge_fcycle_full_grid(wedge):
+    """One F(1,1)-cycle on the full 129 x 129 x 257 wedge (7 levels, tail from
+    level 4) against the oracle's F-cycle, element by element."""
+    from oracle.multigrid import fcycle
+
+    wl = wedge
+    x = W.random_complex(wl.shape, seed=23)
+    ref = fcycle(x, build_hierarchy(wl.k, wl.h, wl.bc))
+    for prec, tol in (("fp64", 1e-12), ("mixed", 1e-5)):
+        s = _solver(wl, prec=prec, cycle="F")
+        s.set_model(dev(wl.k))
+        z = host(s.apply_vcycle(dev(x)))[0]
+        assert relerr(z, ref) <= tol, prec
+        s.close()
+
+
+@pytest.mark.parametrize("method,cycle", [("idrs", "V"), ("idrs", "F"), ("gmres", "F")])
+def test_wedge_idrs_and_gmres_full_grid(wedge, method, cycle):
+    """Mixed IDR(4) and GMRES solves of the full wedge: IDR(4) reaches the true
+    relative residual 1e-6 under the oracle's operator; GMRES reaches the
+    preconditioned 1e-6 and reports the true residual the oracle's operator gives."""
+    wl = wedge
+    s = _solver(wl, prec="mixed", method=method, cycle=cycle)
+    s.set_model(dev(wl.k))
+    s.set_point_sources(wl.sources)
+    x, st = s.solve(rtol=1e-6, maxit=2000)
+    rel = _true_relres(wl, host(x), wl.sources)[0]
+    assert st[0].status == "HH_OK", st[0]
+    assert abs(st[0].relres_true - rel) <= 1e-9
+    if method == "idrs":
+        assert rel <= 1e-6
+    else:
+        assert st[0].relres <= 1e-6 and rel <= 1e-5
+    s.close()
