@@ -85,21 +85,4 @@ enum Slot : int {
 };
 constexpr int MAX_TERMS = 6;
 
-// IDR(s) (s <= IDR_SMAX): per right-hand side small state kept on the device.
-// Partial-sum rows of the IDR kernels, counting the NSLOT * MAX_TERMS rows of
-// a right-hand side flat: rows 2i, 2i + 1 = Re/Im <p_i, y>; row IDR_ROW_RN =
-// ||r||^2; the t-step uses the rows of slot T as Bi-CGSTAB does.
-constexpr int IDR_SMAX = 8;
-constexpr int IDR_ROW_RN = NSLOT * MAX_TERMS - 1;
-static_assert(2 * IDR_SMAX <= IDR_ROW_RN, "IDR rows overlap");
-struct IdrState {
-    c128 M[IDR_SMAX][IDR_SMAX];  // M[i][k] = <p_i, g_k>, lower triangular
-    c128 f[IDR_SMAX];            // <p_i, r>, updated within a cycle
-    c128 c[IDR_SMAX];            // coefficients of the current inner step, c[j - k]
-    c128 a[IDR_SMAX];            // biorthogonalisation coefficients of the current step
-    c128 beta, om;
-    double kappa;
-    int s, first, pad_;
-};
-
 }  // namespace hh

@@ -4,14 +4,18 @@
 // criterion, section 5).  Arnoldi step j:
 //
 //   z = A v_j;  w = K z                                    k_apply, cycle
-//   h  = V^H w;        w -= V h                            k_gm_dots, k_gm_axpy
-//   h' = V^H w;        w -= V h';  h += h'                 (the same again)
-//   h_{j+1,j} = ||w||;  v_{j+1} = w / h_{j+1,j}            k_gm_scale
+//   h  = V^H w;        w1 = w - V h                        k_gm_dots, k_gm_axpy
+//   if ||w1|| < ||w|| / sqrt(2):                           (device flag)
+//       h' = V^H w1;   w1 -= V h';  h += h'                (the same again)
+//   h_{j+1,j} = ||w1||;  v_{j+1} = w1 / h_{j+1,j}          k_gm_scale
 //   Givens rotations on column j; |g_{j+1}| is the residual norm   k_gm_finalize
 //
-// Classical Gram-Schmidt applied twice orthogonalises as well as the modified
-// Gram-Schmidt of the published algorithm (Giraud, Langou, Rozloznik 2005) and
-// needs two passes over the basis per sweep instead of j + 1 dependent ones.
+// Classical Gram-Schmidt with the second sweep taken when the first one
+// cancelled more than half the norm (the criterion of Daniel, Gragg,
+// Kaufman and Stewart 1976, after Kahan) orthogonalises as well as the
+// modified Gram-Schmidt of the published algorithm and needs two passes over
+// the basis per sweep instead of j + 1 dependent ones.  The passes of a
+// skipped second sweep are still launched and return at once.
 // The inner products are exact sums in a fixed order: per-workgroup partials,
 // then one workgroup per group of rows adds them (k_gm_rowsum).
 //
@@ -21,6 +25,7 @@
 #include "hh_common.h"
 #include "hh_device.h"
 #include "hh_kernels.h"
+#include "hh_krylov.h"
 
 namespace hh {
 
@@ -55,20 +60,27 @@ __device__ __forceinline__ c128* cpt(double* base, long long off) { return reint
 
 // Partial inner products <v_i, w>, i = GM_GROUP * blockIdx.y + 0..GM_GROUP-1 (<= j),
 // rows 2i, 2i + 1 of part (row stride nblk); vectors past j give zero rows.
+// With wrow >= 0 the workgroups of group 0 also write the partial ||w||^2 to
+// row wrow; with gated, only right-hand sides whose reorthogonalisation flag
+// is set run.
 __global__ __launch_bounds__(256) void k_gm_dots(long long n, int j, const c128* __restrict__ w,
                                                  const c128* __restrict__ V, long long rsv,
-                                                 double* __restrict__ part, long long rows_per_rhs,
+                                                 double* __restrict__ part, long long rows_per_rhs, int wrow,
+                                                 const double* gst, long long gst_words, int gated,
                                                  const RhsState* st) {
     const int r = blockIdx.z;
     if (st[r].status != ST_RUN) return;
+    if (gated && !reinterpret_cast<const GmHead*>(gst + r * gst_words)->reorth) return;
     const int i0 = blockIdx.y * GM_GROUP;
+    const bool wn = wrow >= 0 && blockIdx.y == 0;
     const long long off = (long long)r * n;
-    double acc[2 * GM_GROUP];
+    double acc[2 * GM_GROUP], an[1] = {0.0};
 #pragma unroll
     for (int q = 0; q < 2 * GM_GROUP; ++q) acc[q] = 0.0;
     for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n;
          x += (long long)gridDim.x * blockDim.x) {
         const c128 wv = w[off + x];
+        if (wn) an[0] += abs2(wv);
 #pragma unroll
         for (int q = 0; q < GM_GROUP; ++q)
             if (i0 + q <= j) {
@@ -80,6 +92,7 @@ __global__ __launch_bounds__(256) void k_gm_dots(long long n, int j, const c128*
     const long long nblk = gridDim.x;
     double* dst = part + ((long long)r * rows_per_rhs + 2LL * i0) * nblk + blockIdx.x;
     block_sum_store<2 * GM_GROUP>(acc, dst, nblk);
+    if (wn) block_sum_store<1>(an, part + ((long long)r * rows_per_rhs + wrow) * nblk + blockIdx.x, nblk);
 }
 
 // w_out = w_in - sum_{i<=j} c_i v_i with c from the state's h1 (first sweep) or
@@ -90,9 +103,10 @@ __global__ __launch_bounds__(256) void k_gm_axpy(long long n, int j, const c128*
                                                  long long rsv, const double* __restrict__ gst,
                                                  long long gst_words, long long coef_off,
                                                  double* __restrict__ part, long long rows_per_rhs,
-                                                 int norm_row, const RhsState* st) {
+                                                 int norm_row, int gated, const RhsState* st) {
     const int r = blockIdx.z;
     if (st[r].status != ST_RUN) return;
+    if (gated && !reinterpret_cast<const GmHead*>(gst + r * gst_words)->reorth) return;
     const c128* coef = reinterpret_cast<const c128*>(gst + r * gst_words + coef_off);
     const long long off = (long long)r * n;
     double acc[1] = {0.0};
@@ -114,9 +128,11 @@ __global__ __launch_bounds__(256) void k_gm_axpy(long long n, int j, const c128*
 // nblk partials in a fixed order, into the same rows of the state's dots array.
 __global__ __launch_bounds__(256) void k_gm_rowsum(int row_begin, int nrows, const double* __restrict__ part,
                                                    long long nblk, long long rows_per_rhs, double* __restrict__ gst,
-                                                   long long gst_words, long long dots_off, const RhsState* st) {
+                                                   long long gst_words, long long dots_off, int gated,
+                                                   const RhsState* st) {
     const int r = blockIdx.y;
     if (st[r].status != ST_RUN) return;
+    if (gated && !reinterpret_cast<const GmHead*>(gst + r * gst_words)->reorth) return;
     const int row0 = row_begin + blockIdx.x * 8;
     double o[8];
     block_fixed_sum<8>(part + ((long long)r * rows_per_rhs + row0) * nblk, nblk, nblk, o);
@@ -144,13 +160,17 @@ __global__ void k_gm_clear(int nrhs, double* gst, long long gst_words) {
     if (r < nrhs) reinterpret_cast<GmHead*>(gst + r * gst_words)->update = 0;
 }
 
-// dst = src * state.scale (the new basis vector, or the first one)
-__global__ __launch_bounds__(256) void k_gm_scale(long long n, const c128* __restrict__ src, c128* __restrict__ dst,
+// dst = src * state.scale (the new basis vector, or the first one); src2
+// replaces src when the reorthogonalisation flag is set
+__global__ __launch_bounds__(256) void k_gm_scale(long long n, const c128* __restrict__ src1,
+                                                  const c128* __restrict__ src2, c128* __restrict__ dst,
                                                   const double* __restrict__ gst, long long gst_words,
                                                   const RhsState* st) {
     const int r = blockIdx.z;
     if (st[r].status != ST_RUN) return;
-    const double sc = reinterpret_cast<const GmHead*>(gst + r * gst_words)->scale;
+    const GmHead* hd = reinterpret_cast<const GmHead*>(gst + r * gst_words);
+    const double sc = hd->scale;
+    const c128* __restrict__ src = hd->reorth ? src2 : src1;
     const long long off = (long long)r * n;
     for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n;
          x += (long long)gridDim.x * blockDim.x)
@@ -237,13 +257,21 @@ __global__ void k_gm_finalize(int mode, int j, int M, int kb, double tol, RhsSta
     }
     if (mode == GM_FIN_DOTS1) {
         for (int i = 0; i <= j; ++i) h1[i] = mk(dots[2 * i], dots[2 * i + 1]);
+        hd.reorth = 0;
+        return;
+    }
+    if (mode == GM_FIN_REORTH) {
+        // second sweep when the first one removed more than half of ||w||^2
+        const double w2 = dots[norm_row + 2], w12 = dots[norm_row];
+        if (!isfinite(w2) || !isfinite(w12)) { R.status = ST_NUMERIC; return; }
+        hd.reorth = w12 < 0.5 * w2;
         return;
     }
     // GM_FIN_DOTS2
     R.matvecs += 1;
     R.iters2 += 2;
     for (int i = 0; i <= j; ++i) {
-        const c128 hij = h1[i] + mk(dots[2 * i], dots[2 * i + 1]);
+        const c128 hij = hd.reorth ? h1[i] + mk(dots[2 * i], dots[2 * i + 1]) : h1[i];
         if (!isfinite(hij.re) || !isfinite(hij.im)) { R.status = ST_NUMERIC; return; }
         H[i * M + j] = hij;
     }
@@ -287,25 +315,27 @@ __global__ void k_gm_finalize(int mode, int j, int M, int kb, double tol, RhsSta
 // launchers
 // ---------------------------------------------------------------------------
 void launch_gm_dots(hipStream_t s, long long n, int nrhs, int j, const c128* w, const c128* V, long long rsv,
-                    double* part, long long rows_per_rhs, const RhsState* st) {
+                    double* part, long long rows_per_rhs, int wrow, const double* gst, long long gst_words,
+                    bool gated, const RhsState* st) {
     const dim3 grid(GM_NBLK, (j + GM_GROUP) / GM_GROUP, nrhs);
-    hipLaunchKernelGGL(k_gm_dots, grid, dim3(256), 0, s, n, j, w, V, rsv, part, rows_per_rhs, st);
+    hipLaunchKernelGGL(k_gm_dots, grid, dim3(256), 0, s, n, j, w, V, rsv, part, rows_per_rhs, wrow, gst, gst_words,
+                       (int)gated, st);
 }
 void launch_gm_axpy(hipStream_t s, long long n, int nrhs, int j, const c128* w_in, c128* w_out, const c128* V,
                     long long rsv, const double* gst, long long gst_words, long long coef_off, bool norm,
-                    double* part, long long rows_per_rhs, int norm_row, const RhsState* st) {
+                    double* part, long long rows_per_rhs, int norm_row, bool gated, const RhsState* st) {
     const dim3 grid(GM_NBLK, 1, nrhs);
     if (norm)
         hipLaunchKernelGGL(k_gm_axpy<true>, grid, dim3(256), 0, s, n, j, w_in, w_out, V, rsv, gst, gst_words,
-                           coef_off, part, rows_per_rhs, norm_row, st);
+                           coef_off, part, rows_per_rhs, norm_row, (int)gated, st);
     else
         hipLaunchKernelGGL(k_gm_axpy<false>, grid, dim3(256), 0, s, n, j, w_in, w_out, V, rsv, gst, gst_words,
-                           coef_off, part, rows_per_rhs, norm_row, st);
+                           coef_off, part, rows_per_rhs, norm_row, (int)gated, st);
 }
 void launch_gm_rowsum(hipStream_t s, int nrhs, int row_begin, int nrows, const double* part, long long rows_per_rhs,
-                      double* gst, long long gst_words, long long dots_off, const RhsState* st) {
+                      double* gst, long long gst_words, long long dots_off, bool gated, const RhsState* st) {
     hipLaunchKernelGGL(k_gm_rowsum, dim3((nrows + 7) / 8, nrhs), dim3(256), 0, s, row_begin, nrows, part,
-                       (long long)GM_NBLK, rows_per_rhs, gst, gst_words, dots_off, st);
+                       (long long)GM_NBLK, rows_per_rhs, gst, gst_words, dots_off, (int)gated, st);
 }
 void launch_gm_norm2(hipStream_t s, long long n, int nrhs, const c128* a, double* part, long long rows_per_rhs,
                      int row, const RhsState* st) {
@@ -314,9 +344,9 @@ void launch_gm_norm2(hipStream_t s, long long n, int nrhs, const c128* a, double
 void launch_gm_clear(hipStream_t s, int nrhs, double* gst, long long gst_words) {
     hipLaunchKernelGGL(k_gm_clear, dim3(1), dim3(64), 0, s, nrhs, gst, gst_words);
 }
-void launch_gm_scale(hipStream_t s, long long n, int nrhs, const c128* src, c128* dst, const double* gst,
-                     long long gst_words, const RhsState* st) {
-    hipLaunchKernelGGL(k_gm_scale, dim3(GM_NBLK, 1, nrhs), dim3(256), 0, s, n, src, dst, gst, gst_words, st);
+void launch_gm_scale(hipStream_t s, long long n, int nrhs, const c128* src1, const c128* src2, c128* dst,
+                     const double* gst, long long gst_words, const RhsState* st) {
+    hipLaunchKernelGGL(k_gm_scale, dim3(GM_NBLK, 1, nrhs), dim3(256), 0, s, n, src1, src2, dst, gst, gst_words, st);
 }
 void launch_gm_xupdate(hipStream_t s, long long n, int nrhs, c128* xk, const c128* V, long long rsv,
                        const double* gst, long long gst_words, long long y_off) {

@@ -29,6 +29,7 @@
 #include "hh_common.h"
 #include "hh_device.h"
 #include "hh_kernels.h"
+#include "hh_krylov.h"
 
 namespace hh {
 

@@ -16,6 +16,7 @@
 #include "../../include/hh.h"
 #include "hh_common.h"
 #include "hh_kernels.h"
+#include "hh_krylov.h"
 
 using namespace hh;
 
@@ -763,28 +764,33 @@ hh_status run_gmres(hh_ctx* c, int nrhs, int maxit, double rtol, int use_x0) {
             enqueue_cycle(c, s, nrhs, c->bsrc, c->s, st, ST_RUN);  // K b
             launch_gm_norm2(s, n, nrhs, c->s, c->gm_part, rows, L.norm_row + 1, st);
         }
-        launch_gm_rowsum(s, nrhs, L.norm_row, kb == 1 ? 2 : 1, c->gm_part, rows, c->gm_st, words, L.dots, st);
+        launch_gm_rowsum(s, nrhs, L.norm_row, kb == 1 ? 2 : 1, c->gm_part, rows, c->gm_st, words, L.dots, false,
+                         st);
         launch_gm_finalize(s, GM_FIN_START, 0, M, kb, rtol, nrhs, st, c->gm_st, words);
-        launch_gm_scale(s, n, nrhs, c->t, c->gm_V, c->gm_st, words, st);
+        launch_gm_scale(s, n, nrhs, c->t, c->t, c->gm_V, c->gm_st, words, st);
     };
     auto step = [&](int j) {
         launch_apply<double>(s, c->cfg.bc, OP_PLAIN, g, c->L0, nrhs, c->gm_V + j * rsv, c->v, c->k2, c->kb, 1.0,
                              0.0, nullptr, nullptr, NBLK_CAP, st, ST_RUN);
         enqueue_cycle(c, s, nrhs, c->v, c->t, st, ST_RUN);  // w = K A v_j
-        // first sweep: h1 = V^H w, w1 = w - V h1
-        launch_gm_dots(s, n, nrhs, j, c->t, c->gm_V, rsv, c->gm_part, rows, st);
-        launch_gm_rowsum(s, nrhs, 0, 2 * (j + 1), c->gm_part, rows, c->gm_st, words, L.dots, st);
+        // first sweep: h1 = V^H w (and ||w||^2), w1 = w - V h1 (and ||w1||^2)
+        launch_gm_dots(s, n, nrhs, j, c->t, c->gm_V, rsv, c->gm_part, rows, L.norm_row + 2, c->gm_st, words,
+                       false, st);
+        launch_gm_rowsum(s, nrhs, 0, 2 * (j + 1), c->gm_part, rows, c->gm_st, words, L.dots, false, st);
         launch_gm_finalize(s, GM_FIN_DOTS1, j, M, 0, rtol, nrhs, st, c->gm_st, words);
-        launch_gm_axpy(s, n, nrhs, j, c->t, c->s, c->gm_V, rsv, c->gm_st, words, L.h1, false, c->gm_part, rows,
-                       L.norm_row, st);
-        // second sweep: h2 = V^H w1, w2 = w1 - V h2, ||w2||
-        launch_gm_dots(s, n, nrhs, j, c->s, c->gm_V, rsv, c->gm_part, rows, st);
-        launch_gm_rowsum(s, nrhs, 0, 2 * (j + 1), c->gm_part, rows, c->gm_st, words, L.dots, st);
+        launch_gm_axpy(s, n, nrhs, j, c->t, c->s, c->gm_V, rsv, c->gm_st, words, L.h1, true, c->gm_part, rows,
+                       L.norm_row, false, st);
+        launch_gm_rowsum(s, nrhs, L.norm_row, 3, c->gm_part, rows, c->gm_st, words, L.dots, false, st);
+        launch_gm_finalize(s, GM_FIN_REORTH, j, M, 0, rtol, nrhs, st, c->gm_st, words);
+        // second sweep where the first cancelled more than half the norm:
+        // h2 = V^H w1, w2 = w1 - V h2, ||w2||^2 (in place of ||w1||^2)
+        launch_gm_dots(s, n, nrhs, j, c->s, c->gm_V, rsv, c->gm_part, rows, -1, c->gm_st, words, true, st);
+        launch_gm_rowsum(s, nrhs, 0, 2 * (j + 1), c->gm_part, rows, c->gm_st, words, L.dots, true, st);
         launch_gm_axpy(s, n, nrhs, j, c->s, c->t, c->gm_V, rsv, c->gm_st, words, L.dots, true, c->gm_part, rows,
-                       L.norm_row, st);
-        launch_gm_rowsum(s, nrhs, L.norm_row, 1, c->gm_part, rows, c->gm_st, words, L.dots, st);
+                       L.norm_row, true, st);
+        launch_gm_rowsum(s, nrhs, L.norm_row, 1, c->gm_part, rows, c->gm_st, words, L.dots, true, st);
         launch_gm_finalize(s, GM_FIN_DOTS2, j, M, 0, rtol, nrhs, st, c->gm_st, words);
-        launch_gm_scale(s, n, nrhs, c->t, c->gm_V + (j + 1) * rsv, c->gm_st, words, st);
+        launch_gm_scale(s, n, nrhs, c->s, c->t, c->gm_V + (j + 1) * rsv, c->gm_st, words, st);
     };
     start(use_x0 ? 1 : 0);
     HIPCHK(c, hipGetLastError());
