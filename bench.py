@@ -100,12 +100,12 @@ def step_bytes_per_dof(prec_idx: int) -> float:
 # (profiles/wedge_129x129x257_solve.md).  Valid only for the kernel sources it
 # was measured on (kernel_source_sha); otherwise reported as null.
 TRAFFIC = {
-    ("apply_A+dots", "wedge", "mixed"): (214.3e6, "412c39d9f72d1a31"),
-    ("update_xr+dots", "wedge", "mixed"): (479.5e6, "412c39d9f72d1a31"),
-    ("mg_down_L0", "wedge", "mixed"): (74.3e6, "412c39d9f72d1a31"),
-    ("mg_up_L0", "wedge", "mixed"): (99.4e6, "412c39d9f72d1a31"),
-    ("p_update", "wedge", "mixed"): (307.9e6, "412c39d9f72d1a31"),
-    ("s_update+dot", "wedge", "mixed"): (239.7e6, "412c39d9f72d1a31"),
+    ("apply_A+dots", "wedge", "mixed"): (214.2e6, "95be697129147b1f"),
+    ("update_xr+dots", "wedge", "mixed"): (479.5e6, "95be697129147b1f"),
+    ("mg_down_L0", "wedge", "mixed"): (74.5e6, "95be697129147b1f"),
+    ("mg_up_L0", "wedge", "mixed"): (99.4e6, "95be697129147b1f"),
+    ("p_update", "wedge", "mixed"): (307.9e6, "95be697129147b1f"),
+    ("s_update+dot", "wedge", "mixed"): (239.7e6, "95be697129147b1f"),
 }
 
 
