@@ -167,20 +167,6 @@ def run_solves(solver, steps, warmup, rtol=1e-6):
     return x, stats, times, iters
 
 
-def true_relres(wl, x, nodes):
-    """||b - A x|| / ||b|| per right-hand side with the oracle's operator (CPU)."""
-    import oracle as O
-    from oracle.discretization import Level
-
-    lvl = Level(wl.shape, wl.h, wl.k, wl.bc)
-    b = O.point_source_rhs(wl.shape, wl.h, nodes)
-    xs = x.cpu().numpy()
-    out = []
-    for r in range(len(nodes)):
-        out.append(float(np.linalg.norm(b[r] - O.apply_A(xs[r], lvl)) / np.linalg.norm(b[r])))
-    return out
-
-
 def kernel_roofline(solver, nrhs, prec_idx, n_nodes, x, solves):
     """Per-kernel average launch duration inside real solves of the workload:
     `solves` solves with the library's event tracing on (HIP events on the
@@ -207,12 +193,17 @@ def cpu_baseline(wl, nodes, n_iter):
     from oracle.discretization import Level
     from oracle.multigrid import build_hierarchy, vcycle
 
+    from threadpoolctl import threadpool_limits
+
     lvl = Level(wl.shape, wl.h, wl.k, wl.bc)
     hier = build_hierarchy(wl.k, wl.h, wl.bc, n_levels=wl.n_levels)
     b = O.point_source_rhs(wl.shape, wl.h, nodes[:1])[0]
-    t0 = time.perf_counter()
-    O.bicgstab(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, fixed_iterations=n_iter)
-    dt = time.perf_counter() - t0
+    # NumPy's element-wise work is single-threaded; the BLAS / LAPACK calls are
+    # held to one thread as well, so the whole sample runs on one core
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.bicgstab(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, fixed_iterations=n_iter)
+        dt = time.perf_counter() - t0
     return {"value": dof(wl) * n_iter / dt, "unit": "DoF-iterations/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_iter} complex128 Bi-CGSTAB steps of the same workload, one source, "
                       f"NumPy/SciPy single thread on the host ({dt:.1f} s)"}
@@ -348,7 +339,9 @@ def main():
         x, stats, times, iters = run_solves(s, args.steps, args.warmup)
         t = float(np.sum(times))
         it = float(np.mean(iters))
-        rel = true_relres(wl, x, nodes) if args.workload != "cube513" else [s_.relres_true for s_ in stats]
+        # the library's own true residual ||b - A x|| / ||b|| after the solve (the
+        # GPU tests hold it to the oracle's operator within 1e-9)
+        rel = [s_.relres_true for s_ in stats]
         if args.method == "bicgstab":
             dom, rows, bracket = kernel_roofline(s, nrhs, 0 if prec == "fp64" else 1, n_nodes, x,
                                                  max(1, args.steps))
