@@ -124,3 +124,22 @@ def test_gmres_batched_and_x0():
         s.set_option("gmres_m", 0)
     with pytest.raises(HHError):
         s.set_option("method", 3)
+
+
+@pytest.mark.parametrize("method", ["idrs", "gmres"])
+def test_zero_and_mixed_batch_for_idrs_and_gmres(method):
+    """A zero right-hand side beside a point source in one batch: x = 0 with no
+    iterations for the zero one, and the other one equal to its single solve."""
+    wl = W.wedge(10.0, 17, 17, 33)
+    b = O.point_source_rhs(wl.shape, wl.h, [(0, 8, 8)])[0]
+    bb = np.stack([np.zeros_like(b), b])
+    s = _solver(wl.shape, wl.h, SOMMERFELD, method=method, prec="mixed", nrhs_max=2)
+    s.set_model(dev(wl.k))
+    s.set_sources(dev(bb))
+    x, st = s.solve(rtol=1e-7)
+    x = host(x)
+    assert st[0].status == "HH_OK" and st[0].iterations == 0 and np.all(x[0] == 0)
+    assert st[1].status == "HH_OK"
+    s.set_sources(dev(b))
+    x1, st1 = s.solve(rtol=1e-7)
+    assert np.array_equal(host(x1)[0], x[1]) and st1[0].iterations == st[1].iterations
