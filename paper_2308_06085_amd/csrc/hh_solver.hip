@@ -244,6 +244,7 @@ hh_status gm_alloc(hh_ctx* c, int M) {
 // Grown only; freed with the context.
 hh_status idr_alloc(hh_ctx* c, int s) {
     if (s <= c->idr_s_alloc) return HH_OK;
+    invalidate_graphs(c);  // captured cycles hold the old buffers' addresses
     for (void* q : {(void*)c->idr_G, (void*)c->idr_U, (void*)c->idr_P}) (void)hipFree(q);
     c->idr_G = c->idr_U = nullptr;
     c->idr_P = nullptr;

@@ -176,3 +176,28 @@ def test_idrs_batched_graph_and_generated_shadow():
     s.set_option("method", 0)
     xbi, stbi = s.solve(rtol=1e-8)
     assert stbi[0].status == "HH_OK"
+
+
+def test_idrs_shadow_dimension_change_on_one_context():
+    """Growing s on a context that has already solved (new buffers, new captured
+    cycles) gives the result of a fresh context with that s, bit for bit."""
+    wl = W.wedge(10.0, 17, 17, 33)
+    P2, P8 = shadow64(2, wl.shape, 51), shadow64(8, wl.shape, 52)
+
+    def make():
+        s = _solver(wl.shape, wl.h, SOMMERFELD, method="idrs")
+        s.set_model(dev(wl.k))
+        s.set_point_sources(wl.sources)
+        return s
+
+    a = make()
+    a.set_shadow(dev(P2))
+    xa2, sta2 = a.solve(rtol=1e-8)
+    a.set_shadow(dev(P8))
+    assert a.get_option("idr_s") == 8
+    xa8, sta8 = a.solve(rtol=1e-8)
+    b = make()
+    b.set_shadow(dev(P8))
+    xb8, stb8 = b.solve(rtol=1e-8)
+    assert sta2[0].status == "HH_OK" and sta8[0].status == "HH_OK"
+    assert np.array_equal(host(xa8), host(xb8)) and sta8[0].iterations == stb8[0].iterations
