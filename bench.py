@@ -295,7 +295,7 @@ def main():
                     help="Krylov method of the headline solves (default bicgstab; idrs = IDR(4); gmres = full GMRES)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=5)
+    ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
