@@ -196,8 +196,9 @@ hh_status hh_set_shadow(hh_ctx* ctx, const void* P, int s);
 
 /* Options: "graph" (1 = replay each Bi-CGSTAB step as a captured hipGraph,
  * default 1), "check_every" (steps between host convergence checks, default 4),
- * "block" (threads per workgroup of the stencil kernels: 64, 128, 256, 512;
- * default 256), "zb" (z-planes per workgroup of the stencil kernels, default 4,
+ * "block" (threads per workgroup of the flat Krylov vector kernels: 64, 128,
+ * 256, 512; default 256), "zb" (z-planes per workgroup of the operator apply and
+ * the start-residual kernel, whose workgroups are 256-node x-y tiles; default 4,
  * 0 = automatic), "trace" (1 = time the fine-level kernels of every solve with
  * HIP events, see hh_kernel_times), "zb_down" / "zb_up" (z-planes per workgroup of the finest
  * level's multigrid down / up pass, 0 = automatic), "zb_down:<l>" / "zb_up:<l>"

@@ -4,16 +4,48 @@
 
 namespace hh {
 
-// Launch shape of the fine-grid kernels: `block` lanes over a flattened x-y
-// plane, `zb` z-planes per workgroup.  The flat (grid-stride) Krylov vector
-// kernels launch exactly `flat_cap` workgroups, set to the workgroup count of
-// the fine-grid kernels so every reduction slot holds the same number of
-// partial sums.
+// Launch shape of the fine-grid kernels: `zb` z-planes per workgroup of the
+// operator kernels (tiles of ap_tile_shape()), `block` lanes per workgroup of
+// the flat (grid-stride) Krylov vector kernels, which launch exactly
+// `flat_cap` workgroups, set to the operator kernels' workgroup count so every
+// reduction slot holds the same number of partial sums.
 struct Launch {
     int block = 256;
     int zb = 8;
     int flat_cap = 2048;
 };
+
+// Runtime tile shape of a level: width = ceil(n / ceil(n / maxw)) so a row of
+// 2^k + 1 nodes splits into nearly equal tiles, height = as many rows as the
+// workgroup's lanes allow (at most maxh).
+struct TileShape {
+    int tw, th, ntx, nty;
+};
+__host__ __device__ inline TileShape tile_shape(int nx, int ny, int maxw, int lanes, int maxh) {
+    TileShape T;
+    T.ntx = (nx + maxw - 1) / maxw;
+    T.tw = (nx + T.ntx - 1) / T.ntx;
+    T.th = lanes / T.tw;
+    if (T.th > maxh) T.th = maxh;
+    if (T.th > ny) T.th = ny;
+    T.nty = (ny + T.th - 1) / T.th;
+    return T;
+}
+
+// Tiling of the fine-grid operator kernels (operator apply, start residual):
+// a workgroup of AP_LANES lanes owns a tw x th tile of an x-y plane, one node
+// per lane, and marches along z; the apply stages the tile and its one-node
+// halo, (tw + 2)(th + 2) <= AP_REGION nodes, in LDS (AP_REGION / AP_LANES
+// region nodes per lane).  Every axis has >= 3 nodes, so tw >= 3 and the
+// region bound holds without shrinking th (the loop is a guard).
+constexpr int AP_LANES = 256, AP_MAXW = 64, AP_REGION = 512;
+static_assert(AP_REGION % AP_LANES == 0, "every lane's region slots must lie inside the LDS arrays");
+__host__ __device__ inline TileShape ap_tile_shape(int nx, int ny) {
+    TileShape T = tile_shape(nx, ny, AP_MAXW, AP_LANES, AP_LANES);
+    while (T.th > 1 && (T.tw + 2) * (T.th + 2) > AP_REGION) --T.th;
+    T.nty = (ny + T.th - 1) / T.th;
+    return T;
+}
 
 enum OpMode : int { OP_PLAIN = 0, OP_V = 1, OP_T = 2, OP_P = 3 };
 // FIN_OMEGA also takes the half-step test on ||s||: the s update writes its

@@ -25,31 +25,33 @@
 
 namespace hh {
 
-struct Pos {
-    int i, j;        // x, y of this lane's column
-    bool valid;      // lane owns a node of the plane
+// Workgroup and lane position in the operator kernels' tiling
+// (ap_tile_shape(); gridDim = (tiles, z chunks, right-hand sides)).  The
+// XCD-aware map keeps neighbouring tiles, which share halo nodes, on one XCD
+// and so in one L2.
+struct ApPos {
+    int X0, Y0;   // origin of the workgroup's tile
+    int z0, z1;   // its z-planes [z0, z1)
+    int ox, oy;   // this lane's node in the tile
+    int i, j;     // its x, y; column (0, 0) for a lane without a node
+    bool own;     // the lane owns a node of the grid
 };
-
-// Column of this lane in plane chunk `bx` (blockDim.x nodes of the flattened plane).
-__device__ __forceinline__ Pos plane_pos(int nx, int plane, int bx) {
-    Pos q;
-    int p = bx * blockDim.x + threadIdx.x;
-    q.valid = p < plane;
-    if (!q.valid) p = 0;
-    q.j = p / nx;
-    q.i = p - q.j * nx;
-    return q;
-}
-
-// (plane chunk, z chunk) of this workgroup of a stencil kernel whose grid is
-// (chunks per plane, z chunks).  The XCD-aware map keeps z-neighbouring chunks,
-// which share their boundary planes, on one XCD and so in one L2.
-struct StencilTile {
-    int bx, bz;
-};
-__device__ __forceinline__ StencilTile stencil_tile() {
+__device__ __forceinline__ ApPos ap_pos(const Geo& g, const TileShape& T, int zb) {
+    ApPos q;
     const int id = xcd_tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    return {id % (int)gridDim.x, id / (int)gridDim.x};
+    const int bz = id / (int)gridDim.x, tile = id - bz * (int)gridDim.x;
+    const int tyi = tile / T.ntx, txi = tile - tyi * T.ntx;
+    q.X0 = txi * T.tw;
+    q.Y0 = tyi * T.th;
+    q.z0 = bz * zb;
+    q.z1 = min(g.nz, q.z0 + zb);
+    q.oy = (int)threadIdx.x / T.tw;
+    q.ox = (int)threadIdx.x - q.oy * T.tw;
+    const int gx = q.X0 + q.ox, gy = q.Y0 + q.oy;
+    q.own = q.oy < T.th && gx < g.nx && gy < g.ny;
+    q.i = q.own ? gx : 0;
+    q.j = q.own ? gy : 0;
+    return q;
 }
 
 // Neighbour sum with the boundary rule of the level.  `ld(i, j)` returns the
@@ -254,126 +256,141 @@ __global__ __launch_bounds__(1024) void k_finalize(int mode, RhsState* st, const
 //              to them, NS vectors of n nodes, shared by all right-hand sides)
 // ---------------------------------------------------------------------------
 template <int BC, int MODE, typename TX, int NS = 0>
-__global__ __launch_bounds__(512) void k_apply(Geo g, int zb, const cx<TX>* __restrict__ x,
-                                               c128* __restrict__ y, const double* __restrict__ k2,
-                                               const double* __restrict__ kb, double sr, double si,
-                                               const c128* __restrict__ aux, double* __restrict__ part,
-                                               long long nblk_max, const RhsState* st, int gate) {
+__global__ __launch_bounds__(AP_LANES) void k_apply(Geo g, int zb, const cx<TX>* __restrict__ x,
+                                                    c128* __restrict__ y, const double* __restrict__ k2,
+                                                    const double* __restrict__ kb, double sr, double si,
+                                                    const c128* __restrict__ aux, double* __restrict__ part,
+                                                    long long nblk_max, const RhsState* st, int gate) {
+    constexpr int NSL = AP_REGION / AP_LANES;  // region slots per lane
+    // ring of three planes of the tile and its halo: z - 1 is kept in a
+    // register, planes z and z + 1 are read from here
+    __shared__ cx<TX> xs[3][AP_REGION];
     const int r = blockIdx.z;
     if (!gate_ok(st, r, gate)) return;
-    const StencilTile tl = stencil_tile();
-    const Pos q = plane_pos(g.nx, g.plane, tl.bx);
-    const int z0 = tl.bz * zb;
-    const int z1 = min(g.nz, z0 + zb);
+    const TileShape T = ap_tile_shape(g.nx, g.ny);
+    const ApPos q = ap_pos(g, T, zb);
+    const int t = threadIdx.x;
+    const int RW = T.tw + 2, RN = RW * (T.th + 2);
     const double ih2 = 1.0 / (g.h * g.h);
     const double two_over_h = 2.0 / g.h;
     const long long roff = (long long)r * g.n;
     const cx<TX>* xr = x + roff;
     c128* yr = y + roff;
-    const int i = q.i, j = q.j;  // a lane past the plane works on column (0, 0) and stores nothing
-    // In-plane neighbours: a Sommerfeld boundary reads the mirror image (the
-    // eliminated ghost point), a Dirichlet one a zero (the boundary values are
-    // not unknowns).  Every load is issued, from a valid node, before any
-    // arithmetic; a Dirichlet neighbour on the boundary is selected away.
-    const int im = i > 0 ? i - 1 : 1, ip = i < g.nx - 1 ? i + 1 : g.nx - 2;
-    const int jm = j > 0 ? j - 1 : 1, jp = j < g.ny - 1 ? j + 1 : g.ny - 2;
+    const int i = q.i, j = q.j;
+    // Halo nodes outside the domain hold their mirror image: for a Sommerfeld
+    // boundary that is the eliminated ghost point; a Dirichlet neighbour on the
+    // boundary (not an unknown) is selected away below.
     const bool use_im = BC == BC_SOMMERFELD || i > 1, use_ip = BC == BC_SOMMERFELD || i < g.nx - 2;
     const bool use_jm = BC == BC_SOMMERFELD || j > 1, use_jp = BC == BC_SOMMERFELD || j < g.ny - 2;
     const int col = j * g.nx + i;
     const int nf_col = (i == 0) + (i == g.nx - 1) + (j == 0) + (j == g.ny - 1);
-    auto ld = [&](int z, int c) -> c128 { return cvt<double>(xr[(long long)z * g.plane + c]); };
-    auto zmir = [&](int z) { return z < 0 ? 1 : (z > g.nz - 1 ? g.nz - 2 : z); };
+    // the lane's LDS slot (a lane without a node reads the tile's first one)
+    const int ls = q.own ? (q.oy + 1) * RW + q.ox + 1 : RW + 1;
+    // in-plane offsets of this lane's region slots t, t + AP_LANES, ...
+    int off[NSL];
+    bool has[NSL];
+#pragma unroll
+    for (int m = 0; m < NSL; ++m) {
+        const int sl = t + m * AP_LANES;
+        has[m] = sl < RN;
+        const int ly = sl / RW, lx = sl - ly * RW;
+        off[m] = has[m] ? mirror_clamp(q.Y0 - 1 + ly, g.ny) * g.nx + mirror_clamp(q.X0 - 1 + lx, g.nx) : 0;
+    }
+    auto plane = [&](int z) {
+        const int zz = z < 0 ? 1 : (z > g.nz - 1 ? g.nz - 2 : z);
+        return xr + (long long)zz * g.plane;
+    };
     constexpr int NACC = MODE == OP_P ? 2 * NS : 3;
     double acc[NACC];
 #pragma unroll
     for (int a = 0; a < NACC; ++a) acc[a] = 0.0;
     const c64* pshadow = reinterpret_cast<const c64*>(aux);
-    // planes in pairs: the loads of both planes (and of the column's planes
-    // below and above) are in flight together
-    for (int z = z0; z < z1; z += 2) {
-        // planes z and z + 1 (the second clamped into the grid, computed only if < z1);
-        // the column on planes z - 1 .. z + 2, mirrored at the ends
-        const int zs = min(z + 1, g.nz - 1);
-        c128 xcol[4], xin[2][4], aux_v[2];
-        c64 pv[2][MODE == OP_P ? NS : 1];
-        double kk[2], kbv[2];
-        const int zc[4] = {zmir(z - 1), z, zmir(z + 1), zmir(z + 2)};
+    // prologue: plane z0 into LDS, plane z0 + 1 into registers, the lane's node below z0
+    cx<TX> nxt[NSL];
+    {
+        const cx<TX>* p0 = plane(q.z0);
+        const cx<TX>* p1 = plane(q.z0 + 1);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) xcol[m] = ld(zc[m], col);
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const int zz = p == 0 ? z : zs;
-            xin[p][0] = ld(zz, j * g.nx + im);
-            xin[p][1] = ld(zz, j * g.nx + ip);
-            xin[p][2] = ld(zz, jm * g.nx + i);
-            xin[p][3] = ld(zz, jp * g.nx + i);
-            const long long idx = (long long)zz * g.plane + col;
-            kk[p] = k2[idx];
-            const int nf = nf_col + (zz == 0) + (zz == g.nz - 1);
-            // interior nodes all read kb[0] (one cache line): no branch around the load
-            kbv[p] = kb[nf ? idx : 0];
-            if (MODE == OP_V || MODE == OP_T) aux_v[p] = aux[roff + idx];
-            if constexpr (MODE == OP_P) {
-#pragma unroll
-                for (int a = 0; a < NS; ++a) pv[p][a] = pshadow[(long long)a * g.n + idx];
-            }
+        for (int m = 0; m < NSL; ++m) {
+            if (has[m]) xs[q.z0 % 3][t + m * AP_LANES] = p0[off[m]];
+            nxt[m] = has[m] ? p1[off[m]] : cx<TX>{};
         }
+    }
+    c128 xm = cvt<double>(plane(q.z0 - 1)[col]);
+    for (int z = q.z0; z < q.z1; ++z) {
+        const int cur = z % 3, up = (z + 1) % 3;
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const int zz = z + p;
-            if (zz >= z1) break;
-            const long long idx = (long long)zz * g.plane + col;
-            const c128 xc = xcol[p + 1];
-            c128 s = (use_im ? xin[p][0] : czero<double>()) + (use_ip ? xin[p][1] : czero<double>());
-            s = s + (use_jm ? xin[p][2] : czero<double>());
-            s = s + (use_jp ? xin[p][3] : czero<double>());
-            c128 zm = xcol[p], zpv = xcol[p + 2];
-            if (BC == BC_DIRICHLET) {
-                if (zz - 1 < 1) zm = czero<double>();
-                if (zz + 1 > g.nz - 2) zpv = czero<double>();
-            }
-            s = s + zm;
-            s = s + zpv;
-            c128 d = mk(6.0 * ih2 - sr * kk[p], -si * kk[p]);
-            const int nf = nf_col + (zz == 0) + (zz == g.nz - 1);
-            if (BC == BC_SOMMERFELD && nf) d.im -= nf * two_over_h * kbv[p];
-            c128 out = d * xc - ih2 * s;
-            if (BC == BC_DIRICHLET && (nf_col || zz == 0 || zz == g.nz - 1)) out = czero<double>();
-            if (q.valid) {
-                yr[idx] = out;
-                if (MODE == OP_V) {
-                    const c128 t = cdot(aux_v[p], out);
-                    acc[0] += t.re;
-                    acc[1] += t.im;
-                } else if (MODE == OP_T) {
-                    const c128 t = cdot(out, aux_v[p]);
-                    acc[0] += t.re;
-                    acc[1] += t.im;
-                    acc[2] += abs2(out);
-                } else if constexpr (MODE == OP_P) {
+        for (int m = 0; m < NSL; ++m)
+            if (has[m]) xs[up][t + m * AP_LANES] = nxt[m];
+        // the global loads of plane z + 2 stay in flight while plane z is computed
+        if (z + 1 < q.z1) {
+            const cx<TX>* p2 = plane(z + 2);
 #pragma unroll
-                    for (int a = 0; a < NS; ++a) {
-                        const c128 t = cdot(cvt<double>(pv[p][a]), out);
-                        acc[2 * a] += t.re;
-                        acc[2 * a + 1] += t.im;
-                    }
+            for (int m = 0; m < NSL; ++m)
+                if (has[m]) nxt[m] = p2[off[m]];
+        }
+        const long long idx = (long long)z * g.plane + col;
+        const double kk = k2[idx];
+        const int nf = nf_col + (z == 0) + (z == g.nz - 1);
+        // interior nodes all read kb[0] (one cache line): no branch around the load
+        const double kbv = kb[nf ? idx : 0];
+        c128 aux_v = czero<double>();
+        c64 pv[MODE == OP_P ? NS : 1];
+        if (MODE == OP_V || MODE == OP_T) aux_v = aux[roff + idx];
+        if constexpr (MODE == OP_P) {
+#pragma unroll
+            for (int a = 0; a < NS; ++a) pv[a] = pshadow[(long long)a * g.n + idx];
+        }
+        __syncthreads();
+        const cx<TX>* b = xs[cur];
+        const c128 xc = cvt<double>(b[ls]);
+        c128 s = (use_im ? cvt<double>(b[ls - 1]) : czero<double>()) +
+                 (use_ip ? cvt<double>(b[ls + 1]) : czero<double>());
+        s = s + (use_jm ? cvt<double>(b[ls - RW]) : czero<double>());
+        s = s + (use_jp ? cvt<double>(b[ls + RW]) : czero<double>());
+        c128 zm = xm, zpv = cvt<double>(xs[up][ls]);
+        if (BC == BC_DIRICHLET) {
+            if (z - 1 < 1) zm = czero<double>();
+            if (z + 1 > g.nz - 2) zpv = czero<double>();
+        }
+        s = s + zm;
+        s = s + zpv;
+        c128 d = mk(6.0 * ih2 - sr * kk, -si * kk);
+        if (BC == BC_SOMMERFELD && nf) d.im -= nf * two_over_h * kbv;
+        c128 out = d * xc - ih2 * s;
+        if (BC == BC_DIRICHLET && (nf_col || z == 0 || z == g.nz - 1)) out = czero<double>();
+        if (q.own) {
+            yr[idx] = out;
+            if (MODE == OP_V) {
+                const c128 w = cdot(aux_v, out);
+                acc[0] += w.re;
+                acc[1] += w.im;
+            } else if (MODE == OP_T) {
+                const c128 w = cdot(out, aux_v);
+                acc[0] += w.re;
+                acc[1] += w.im;
+                acc[2] += abs2(out);
+            } else if constexpr (MODE == OP_P) {
+#pragma unroll
+                for (int a = 0; a < NS; ++a) {
+                    const c128 w = cdot(cvt<double>(pv[a]), out);
+                    acc[2 * a] += w.re;
+                    acc[2 * a + 1] += w.im;
                 }
             }
         }
+        xm = xc;
     }
+    const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
     if constexpr (MODE == OP_P) {
-        const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
         block_sum_store<NACC>(acc, part + part_index(r, 0, 0, nblk_max) + blk, nblk_max);
     }
-    if constexpr (MODE == OP_V || MODE == OP_T) {
-        const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
-        const int slot = MODE == OP_V ? SLOT_V : SLOT_T;
-        if constexpr (MODE == OP_V) {
-            double v[2] = {acc[0], acc[1]};
-            block_sum_store<2>(v, part + part_index(r, slot, 0, nblk_max) + blk, nblk_max);
-        } else {
-            block_sum_store<3>(acc, part + part_index(r, slot, 0, nblk_max) + blk, nblk_max);
-        }
+    if constexpr (MODE == OP_V) {
+        double v[2] = {acc[0], acc[1]};
+        block_sum_store<2>(v, part + part_index(r, SLOT_V, 0, nblk_max) + blk, nblk_max);
+    }
+    if constexpr (MODE == OP_T) {
+        block_sum_store<3>(acc, part + part_index(r, SLOT_T, 0, nblk_max) + blk, nblk_max);
     }
 }
 
@@ -382,7 +399,7 @@ __global__ __launch_bounds__(512) void k_apply(Geo g, int zb, const cx<TX>* __re
 // p = v = 0; partials ||r||^2, Re/Im r_hat^H r (= ||r||^2, 0), ||b||^2 (slot R).
 // ---------------------------------------------------------------------------
 template <int BC>
-__global__ __launch_bounds__(512) void k_init(Geo g, int zb, const c128* __restrict__ b,
+__global__ __launch_bounds__(AP_LANES) void k_init(Geo g, int zb, const c128* __restrict__ b,
                                               c128* __restrict__ x, c128* __restrict__ rr,
                                               c128* __restrict__ rhat, c128* __restrict__ p,
                                               c128* __restrict__ v, const double* __restrict__ k2,
@@ -391,16 +408,14 @@ __global__ __launch_bounds__(512) void k_init(Geo g, int zb, const c128* __restr
                                               const RhsState* st, int gate) {
     const int r = blockIdx.z;
     if (!gate_ok(st, r, gate)) return;
-    const StencilTile tl = stencil_tile();
-    const Pos q = plane_pos(g.nx, g.plane, tl.bx);
-    const int z0 = tl.bz * zb;
-    const int z1 = min(g.nz, z0 + zb);
+    const ApPos q = ap_pos(g, ap_tile_shape(g.nx, g.ny), zb);
+    const int z0 = q.z0, z1 = q.z1;
     const double ih2 = 1.0 / (g.h * g.h);
     const double two_over_h = 2.0 / g.h;
     const long long roff = (long long)r * g.n;
     const long long col = (long long)q.j * g.nx + q.i;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (q.valid) {
+    if (q.own) {
         const c128* xr = x + roff;
         auto ldz = [&](int z) -> c128 {
             if (BC == BC_DIRICHLET && (z < 1 || z > g.nz - 2)) return czero<double>();
@@ -655,12 +670,13 @@ __global__ void k_fill_status(int n, RhsState* st, int status, int maxit2, doubl
 // Host-side launchers
 // ---------------------------------------------------------------------------
 static inline dim3 grid_fine(const Geo& g, const Launch& L, int nrhs) {
-    return dim3((unsigned)((g.plane + L.block - 1) / L.block), (unsigned)((g.nz + L.zb - 1) / L.zb),
-                (unsigned)nrhs);
+    const TileShape T = ap_tile_shape(g.nx, g.ny);
+    return dim3((unsigned)(T.ntx * T.nty), (unsigned)((g.nz + L.zb - 1) / L.zb), (unsigned)nrhs);
 }
 
 long long nblk_of(const Geo& g, const Launch& L) {
-    return (long long)((g.plane + L.block - 1) / L.block) * ((g.nz + L.zb - 1) / L.zb);
+    const TileShape T = ap_tile_shape(g.nx, g.ny);
+    return (long long)T.ntx * T.nty * ((g.nz + L.zb - 1) / L.zb);
 }
 
 static inline unsigned flat_blocks(long long n, int block, int cap) {
@@ -676,7 +692,7 @@ void launch_apply(hipStream_t s, int bc, int mode, const Geo& g, const Launch& L
                   const c128* aux, double* part, long long nblk_max, const RhsState* st, int gate) {
     dim3 grid = grid_fine(g, L, nrhs);
 #define HH_APPLY(BCV, MV)                                                                             \
-    hipLaunchKernelGGL((k_apply<BCV, MV, TX>), grid, dim3(L.block), 0, s, g, L.zb, x, y, k2, kb, sr, si, \
+    hipLaunchKernelGGL((k_apply<BCV, MV, TX>), grid, dim3(AP_LANES), 0, s, g, L.zb, x, y, k2, kb, sr, si, \
                        aux, part, nblk_max, st, gate)
     if (bc == BC_SOMMERFELD) {
         if (mode == OP_PLAIN) HH_APPLY(BC_SOMMERFELD, OP_PLAIN);
@@ -696,7 +712,7 @@ void launch_apply_p(hipStream_t s, int bc, const Geo& g, const Launch& L, int nr
     dim3 grid = grid_fine(g, L, nrhs);
     const c128* aux = reinterpret_cast<const c128*>(P);
 #define HH_APPLY_P(BCV, NSV)                                                                             \
-    hipLaunchKernelGGL((k_apply<BCV, OP_P, double, NSV>), grid, dim3(L.block), 0, s, g, L.zb, x, y, k2, kb, \
+    hipLaunchKernelGGL((k_apply<BCV, OP_P, double, NSV>), grid, dim3(AP_LANES), 0, s, g, L.zb, x, y, k2, kb, \
                        1.0, 0.0, aux, part, nblk_max, st, gate)
 #define HH_APPLY_P_NS(BCV)                \
     switch (ns) {                         \
@@ -730,10 +746,10 @@ void launch_init(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs,
                  int use_x0, double* part, long long nblk_max, const RhsState* st, int gate) {
     dim3 grid = grid_fine(g, L, nrhs);
     if (bc == BC_SOMMERFELD)
-        hipLaunchKernelGGL((k_init<BC_SOMMERFELD>), grid, dim3(L.block), 0, s, g, L.zb, b, x, r, rhat,
+        hipLaunchKernelGGL((k_init<BC_SOMMERFELD>), grid, dim3(AP_LANES), 0, s, g, L.zb, b, x, r, rhat,
                            p, v, k2, kb, use_x0, part, nblk_max, st, gate);
     else
-        hipLaunchKernelGGL((k_init<BC_DIRICHLET>), grid, dim3(L.block), 0, s, g, L.zb, b, x, r, rhat,
+        hipLaunchKernelGGL((k_init<BC_DIRICHLET>), grid, dim3(AP_LANES), 0, s, g, L.zb, b, x, r, rhat,
                            p, v, k2, kb, use_x0, part, nblk_max, st, gate);
 }
 

@@ -35,23 +35,6 @@ namespace hh {
 
 __device__ __forceinline__ int ring3(int f) { return ((f % 3) + 3) % 3; }
 
-// Runtime tile shape of a level: width = ceil(n / ceil(n / maxw)) so a row of
-// 2^k + 1 nodes splits into nearly equal tiles, height = as many rows as the
-// workgroup's lanes allow (at most maxh).
-struct TileShape {
-    int tw, th, ntx, nty;
-};
-__host__ __device__ inline TileShape tile_shape(int nx, int ny, int maxw, int lanes, int maxh) {
-    TileShape T;
-    T.ntx = (nx + maxw - 1) / maxw;
-    T.tw = (nx + T.ntx - 1) / T.ntx;
-    T.th = lanes / T.tw;
-    if (T.th > maxh) T.th = maxh;
-    if (T.th > ny) T.th = ny;
-    T.nty = (ny + T.th - 1) / T.th;
-    return T;
-}
-
 constexpr int DN_LANES = 256, DN_MAXW = 32, DN_MAXH = 16;
 constexpr int DN_REGION = 1280;  // >= (2 tw + 3)(2 th + 3) for every shape tile_shape() returns
 static_assert(DN_REGION % DN_LANES == 0, "every lane's region slots must lie inside the LDS arrays");

@@ -159,21 +159,23 @@ Geo make_geo(int nx, int ny, int nz, double h) {
     return g;
 }
 
-// Workgroup shape of a level: `base` lanes (fewer on small planes) and enough
-// z-planes per workgroup to keep the reduction partials below NBLK_CAP while
-// leaving >= ~2048 workgroups where the grid allows it.
+// Launch shape of a level: `base` lanes for the flat kernels (fewer on small
+// planes) and enough z-planes per operator-kernel workgroup to keep the
+// reduction partials below NBLK_CAP while leaving >= ~4096 workgroups where
+// the grid allows it.
 Launch level_launch(const Geo& g, const Launch& base) {
     Launch L = base;
     while (L.block > 64 && L.block / 2 >= g.plane) L.block /= 2;
-    const long long pb = (g.plane + L.block - 1) / L.block;
+    const TileShape T = ap_tile_shape(g.nx, g.ny);
+    const long long tiles = (long long)T.ntx * T.nty;
     int zb = base.zb > 0 ? base.zb : 8;
     if (base.zb <= 0) {
-        // automatic: aim for ~4096 workgroups, at least 4 planes per workgroup when that still fills the chip
-        long long want = std::max<long long>(1, (pb * g.nz) / 4096);
+        // automatic: about 4096 workgroups, at most 32 planes each
+        long long want = std::max<long long>(1, (tiles * g.nz) / 4096);
         zb = (int)std::min<long long>(std::max<long long>(want, 1), 32);
     }
     zb = std::max(1, std::min(zb, g.nz));
-    while (pb * ((g.nz + zb - 1) / zb) > NBLK_CAP) ++zb;
+    while (tiles * ((g.nz + zb - 1) / zb) > NBLK_CAP) ++zb;
     L.zb = zb;
     return L;
 }
