@@ -71,6 +71,28 @@ def test_apply_operator_and_shifted(bc, shape):
     assert relerr(ym, refm) <= 1e-13
 
 
+@pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
+def test_apply_tiles_and_zblocks(bc):
+    """The operator apply on planes that give one tile five nodes wide, a
+    ragged last tile in x or y and four tiles across a row (x-y tiles of at
+    most 256 nodes with a one-node halo): every result matches the oracle,
+    and does not depend on the z-planes per workgroup, bit for bit (each
+    node's arithmetic is fixed)."""
+    for shape in [(5, 5, 5), (9, 5, 5), (9, 17, 193), (5, 257, 5), (9, 33, 97)]:
+        h = 1.0 / (max(shape) - 1)
+        k = hetero_k(shape, 5)
+        lvl = Level(shape, h, k, bc)
+        x = W.random_complex(shape, seed=6)
+        s = _solver(shape, h, bc)
+        s.set_model(dev(k))
+        y0 = host(s.apply_operator(dev(x)))[0]
+        assert relerr(y0, O.apply_A(x, lvl)) <= 1e-13, shape
+        for zb in (1, 2, 3, 7):
+            s.set_option("zb", zb)
+            assert np.array_equal(host(s.apply_operator(dev(x)))[0], y0), (shape, zb)
+        s.close()
+
+
 def test_dirichlet_inputs_on_the_boundary_are_ignored():
     shape = (9, 9, 9)
     h = 1 / 8
