@@ -100,12 +100,12 @@ def step_bytes_per_dof(prec_idx: int) -> float:
 # (profiles/wedge_129x129x257_solve.md).  Valid only for the kernel sources it
 # was measured on (kernel_source_sha); otherwise reported as null.
 TRAFFIC = {
-    ("apply_A+dots", "wedge", "mixed"): (214.2e6, "95be697129147b1f"),
-    ("update_xr+dots", "wedge", "mixed"): (479.5e6, "95be697129147b1f"),
-    ("mg_down_L0", "wedge", "mixed"): (74.5e6, "95be697129147b1f"),
-    ("mg_up_L0", "wedge", "mixed"): (99.4e6, "95be697129147b1f"),
-    ("p_update", "wedge", "mixed"): (307.9e6, "95be697129147b1f"),
-    ("s_update+dot", "wedge", "mixed"): (239.7e6, "95be697129147b1f"),
+    ("apply_A+dots", "wedge", "mixed"): (214.2e6, "2a1b237b43c04bd6"),
+    ("update_xr+dots", "wedge", "mixed"): (479.6e6, "2a1b237b43c04bd6"),
+    ("mg_down_L0", "wedge", "mixed"): (74.3e6, "2a1b237b43c04bd6"),
+    ("mg_up_L0", "wedge", "mixed"): (99.4e6, "2a1b237b43c04bd6"),
+    ("p_update", "wedge", "mixed"): (307.9e6, "2a1b237b43c04bd6"),
+    ("s_update+dot", "wedge", "mixed"): (239.7e6, "2a1b237b43c04bd6"),
 }
 
 
@@ -303,7 +303,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver keeps the whole grid on one device "
-              "(multi-GPU sharding is not part of this build)", file=sys.stderr)
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
