@@ -1,11 +1,11 @@
 // gfx950 kernels of the matrix-free CSLP / multigrid / Bi-CGSTAB Helmholtz solver.
 //
-// Launch shape of every fine-grid kernel: a workgroup owns `blockDim.x`
-// consecutive nodes of one x-y plane (the plane is flattened, so a row of
-// length nx never leaves lanes idle except in the last workgroup of a plane)
-// and marches along z over `zb` planes, keeping the z-1 / z / z+1 values of its
-// own column in registers; the four in-plane neighbours are read from the
-// caches.  gridDim = (plane blocks, z chunks, right-hand sides).
+// Launch shape of the fine-grid operator kernels (apply, start residual): a
+// workgroup owns an x-y tile of at most AP_LANES nodes, one per lane, and
+// marches along z over `zb` planes; the apply stages the tile and its
+// one-node halo in LDS (a ring of three planes).  gridDim = (tiles, z chunks,
+// right-hand sides).  The Krylov vector kernels are flat grid-stride loops
+// with the same workgroup count.
 //
 // The operator (paper section 2.4, eq. Helmstencil; Algorithm 2):
 //   (A x)_j = D_j x_j - (1/h^2) sum'_nb x_nb,
