@@ -100,12 +100,12 @@ def step_bytes_per_dof(prec_idx: int) -> float:
 # (profiles/wedge_129x129x257_solve.md).  Valid only for the kernel sources it
 # was measured on (kernel_source_sha); otherwise reported as null.
 TRAFFIC = {
-    ("apply_A+dots", "wedge", "mixed"): (214.2e6, "49cb912fa8fb8612"),
-    ("update_xr+dots", "wedge", "mixed"): (479.6e6, "49cb912fa8fb8612"),
-    ("mg_down_L0", "wedge", "mixed"): (74.3e6, "49cb912fa8fb8612"),
-    ("mg_up_L0", "wedge", "mixed"): (99.4e6, "49cb912fa8fb8612"),
-    ("p_update", "wedge", "mixed"): (307.9e6, "49cb912fa8fb8612"),
-    ("s_update+dot", "wedge", "mixed"): (239.7e6, "49cb912fa8fb8612"),
+    ("apply_A+dots", "wedge", "mixed"): (214.1e6, "60e602cc0a601b08"),
+    ("update_xr+dots", "wedge", "mixed"): (479.6e6, "60e602cc0a601b08"),
+    ("mg_down_L0", "wedge", "mixed"): (74.3e6, "60e602cc0a601b08"),
+    ("mg_up_L0", "wedge", "mixed"): (99.1e6, "60e602cc0a601b08"),
+    ("p_update", "wedge", "mixed"): (307.9e6, "60e602cc0a601b08"),
+    ("s_update+dot", "wedge", "mixed"): (239.7e6, "60e602cc0a601b08"),
 }
 
 

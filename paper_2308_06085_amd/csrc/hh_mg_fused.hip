@@ -34,10 +34,23 @@
 namespace hh {
 
 __device__ __forceinline__ int ring3(int f) { return ((f % 3) + 3) % 3; }
+__device__ __forceinline__ int ring4(int f) { return f & 3; }  // also for f = -1
 
 constexpr int DN_LANES = 256, DN_MAXW = 32, DN_MAXH = 16;
-constexpr int DN_REGION = 1280;  // >= (2 tw + 3)(2 th + 3) for every shape tile_shape() returns
+constexpr int DN_REGION = 1280;  // fine region nodes of a down-pass tile, see dn_tile_shape()
 static_assert(DN_REGION % DN_LANES == 0, "every lane's region slots must lie inside the LDS arrays");
+// Tile of the down pass on the coarse grid: tile_shape() with the height
+// bounded so that the fine region, (2 tw + 3)(2 th + 3) nodes, fits DN_REGION
+// (tw <= DN_MAXW leaves th >= 1).
+__host__ __device__ inline TileShape dn_tile_shape(int nx, int ny) {
+    TileShape T = tile_shape(nx, ny, DN_MAXW, DN_LANES, DN_MAXH);
+    const int hmax = (DN_REGION / (2 * T.tw + 3) - 3) / 2;
+    if (T.th > hmax) {
+        T.th = hmax;
+        T.nty = (ny + T.th - 1) / T.th;
+    }
+    return T;
+}
 constexpr int UP_LANES = 512, UP_MAXW = 32;  // up pass: one lane per region node
 // Tile of the up pass: the tile plus a one-node halo must fit the lanes,
 // (tw + 2)(th + 2) <= lanes.
@@ -130,7 +143,7 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
     const int r = blockIdx.z;
     if (!gate_ok(st, r, gate)) return;
     const int t = threadIdx.x;
-    const TileShape T = tile_shape(gc.nx, gc.ny, DN_MAXW, DN_LANES, DN_MAXH);
+    const TileShape T = dn_tile_shape(gc.nx, gc.ny);
     const int RW = 2 * T.tw + 3, RH = 2 * T.th + 3;
     const int id = xcd_tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int tz = id / gridDim.x;
@@ -307,7 +320,9 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
                                                     const cx<R>* __restrict__ ec,
                                                     cx<TO>* __restrict__ out, long long o_rstride,
                                                     const RhsState* st, int gate) {
-    __shared__ cx<R> us[3][UP_LANES];
+    // a ring of four u2 planes: the stencil of plane z reads z - 1 .. z + 1
+    // while plane z + 2 is written, so one barrier per plane suffices
+    __shared__ cx<R> us[4][UP_LANES];
 
     const int r = blockIdx.z;
     if (!gate_ok(st, r, gate)) return;
@@ -348,6 +363,14 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
         R k;
         cx<R> e[8];
     };
+    // shift c of a node, made with its u2 and kept for its output step; in
+    // double precision also its Jacobi weight W = omega / (6/h^2 - c) (in
+    // single precision recomputing W is cheaper than the registers that
+    // would push the pass past its occupancy bound)
+    constexpr bool KEEP_W = sizeof(R) == sizeof(double);
+    struct CW {
+        cx<R> c, w;
+    };
     auto fetch = [&](int f, Raw& w) {
         const int fz = mirror_clamp(min(f, z1), g.nz);
         const long long base = (long long)fz * g.plane;
@@ -366,7 +389,7 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
     };
     // u2 at this lane's node of plane f, also written to the ring for the
     // stencil of the output lanes; c is returned for the output step
-    auto make_u2 = [&](int f, const Raw& w, cx<R>& c_out) -> cx<R> {
+    auto make_u2 = [&](int f, const Raw& w, CW& k_out) -> cx<R> {
         const int fz = mirror_clamp(f, g.nz);
         const int zf = (fz == 0) + (fz == g.nz - 1);
         const R wz = (fz & 1) ? R(0.5) : R(1), bz = R(1) - wz;
@@ -377,10 +400,12 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
         const cx<R> p3 = ax * w.e[6] + bx * w.e[7];
         const cx<R> pe = wz * (ay * p0 + by * p1) + bz * (ay * p2 + by * p3);
         const int nf = BC == BC_SOMMERFELD ? unf + zf : 0;
-        c_out = shift_c(L, w.k, nf);
-        cx<R> v = jacobi_w(L, c_out) * cvt<R>(w.b) + pe;
+        k_out.c = shift_c(L, w.k, nf);
+        const cx<R> wj = jacobi_w(L, k_out.c);
+        if constexpr (KEEP_W) k_out.w = wj;
+        cx<R> v = wj * cvt<R>(w.b) + pe;
         if (BC == BC_DIRICHLET && (unf || zf)) v = czero<R>();
-        us[ring3(f)][t] = v;  // unguarded: lanes past the region write slots never read
+        us[ring4(f)][t] = v;  // unguarded: lanes past the region write slots never read
         return v;
     };
 
@@ -389,17 +414,18 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
     // u3 of plane z at the output lanes, from the u2 ring and this lane's u2, b, c.
     // Past the bottom / top plane the stencil reads the mirror image, plane 1 /
     // nz - 2 (the eliminated ghost point), whose u2 is already in the ring.
-    auto emit = [&](int z, const cx<R>& u, const cx<R>& c, const cx<TB>& bz) {
+    auto emit = [&](int z, const cx<R>& u, const CW& k, const cx<TB>& bz) {
         if (own) {
-            const cx<R>* um = us[ring3(z == 0 ? 1 : z - 1)];
-            const cx<R>* uc = us[ring3(z)];
-            const cx<R>* up = us[ring3(z == g.nz - 1 ? g.nz - 2 : z + 1)];
+            const cx<R>* um = us[ring4(z == 0 ? 1 : z - 1)];
+            const cx<R>* uc = us[ring4(z)];
+            const cx<R>* up = us[ring4(z == g.nz - 1 ? g.nz - 2 : z + 1)];
             cx<R> lap = (u - uc[t - 1]) + (u - uc[t + 1]);
             lap = lap + (u - uc[t - RW]);
             lap = lap + (u - uc[t + RW]);
             lap = lap + (u - um[t]);
             lap = lap + (u - up[t]);
-            cx<R> v = u + jacobi_w(L, c) * ((cvt<R>(bz) - L.ih2 * lap) + c * u);
+            const cx<R> wj = KEEP_W ? k.w : jacobi_w(L, k.c);
+            cx<R> v = u + wj * ((cvt<R>(bz) - L.ih2 * lap) + k.c * u);
             if (BC == BC_DIRICHLET && (unf || z == 0 || z == g.nz - 1)) v = czero<R>();
             cx<TO>* o = orr + (long long)z * g.plane + ooff;
             if constexpr (ACC) v = cvt<R>(*o) + v;  // out already holds an earlier cycle's result
@@ -408,7 +434,8 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
     };
     // per plane this lane keeps its own u2, b, c for the output step
     Raw w, w2;
-    cx<R> u_cur, c_cur, c_nxt, c_unused;
+    cx<R> u_cur;
+    CW c_cur, c_nxt, c_unused;
     cx<TB> b_cur, b_nxt;
     if constexpr (ONE) {
         // one plane per workgroup (the small levels, where latency rules):
@@ -451,7 +478,7 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
             return ay * p0 + by * p1;
         };
         cx<R> carry;  // in-plane interpolation on the previous plane's c1
-        auto make_c = [&](int f, const RawC& v, cx<R>& c_out) -> cx<R> {
+        auto make_c = [&](int f, const RawC& v, CW& k_out) -> cx<R> {
             const int fc = min(max(f, plo), phi);
             const int zf = (fc == 0) + (fc == g.nz - 1);
             const R wz = (fc & 1) ? R(0.5) : R(1), bz = R(1) - wz;
@@ -459,10 +486,12 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
             const cx<R> pe = wz * ((fc & 1) ? carry : pn) + bz * pn;
             carry = pn;
             const int nf = BC == BC_SOMMERFELD ? unf + zf : 0;
-            c_out = shift_c(L, v.k, nf);
-            cx<R> u = jacobi_w(L, c_out) * cvt<R>(v.b) + pe;
+            k_out.c = shift_c(L, v.k, nf);
+            const cx<R> wj = jacobi_w(L, k_out.c);
+            if constexpr (KEEP_W) k_out.w = wj;
+            cx<R> u = wj * cvt<R>(v.b) + pe;
             if (BC == BC_DIRICHLET && (unf || zf)) u = czero<R>();
-            us[ring3(f)][t] = u;  // unguarded: lanes past the region write slots never read
+            us[ring4(f)][t] = u;  // unguarded: lanes past the region write slots never read
             return u;
         };
         auto step = [&](int z, RawC& v) {
@@ -474,7 +503,6 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
             u_cur = u_nxt;
             c_cur = c_nxt;
             b_cur = b_nxt;
-            __syncthreads();
         };
         // set A holds the planes z0 - 1 + even, set B the odd ones
         RawC A, B;
@@ -552,7 +580,7 @@ __global__ __launch_bounds__(RS_LANES) void k_mg_resid(Geo g, int zb, cx<R>* __r
 // launchers
 // ---------------------------------------------------------------------------
 int mg_down_blocks(const Geo& gc, int zbc) {
-    const TileShape T = tile_shape(gc.nx, gc.ny, DN_MAXW, DN_LANES, DN_MAXH);
+    const TileShape T = dn_tile_shape(gc.nx, gc.ny);
     return T.ntx * T.nty * ((gc.nz + zbc - 1) / zbc);
 }
 int mg_up_blocks(const Geo& g, int zb) {
@@ -564,7 +592,7 @@ template <typename TB, typename R>
 void launch_mg_down(hipStream_t s, int bc, const Geo& gf, const Geo& gc, int zbc, int nrhs,
                     const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
                     cx<R>* bc_out, const RhsState* st, int gate) {
-    const TileShape T = tile_shape(gc.nx, gc.ny, DN_MAXW, DN_LANES, DN_MAXH);
+    const TileShape T = dn_tile_shape(gc.nx, gc.ny);
     dim3 grid(T.ntx * T.nty, (gc.nz + zbc - 1) / zbc, nrhs);
 #define HH_DOWN(BCV, ONEV)                                                                                \
     hipLaunchKernelGGL((k_mg_down<BCV, TB, R, ONEV>), grid, dim3(DN_LANES), 0, s, gf, gc, zbc, b, b_rstride, \
