@@ -131,6 +131,34 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
+def streaming_reference(torch) -> dict:
+    """The rate of PyTorch's own streaming kernels on this device, as a practical
+    HBM ceiling beside the 8 TB/s peak: c = a + b (two reads, one write) and a
+    copy, on 2 GiB float64 vectors, 20 launches each timed with HIP events."""
+    n = (2 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.empty_like(a)
+
+    def rate(fn, nbytes, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+
+    add = rate(lambda: torch.add(a, b, out=c), 3 * 8 * n)
+    copy = rate(lambda: c.copy_(a), 2 * 8 * n)
+    del a, b, c
+    torch.cuda.empty_cache()
+    return {"kernel": "torch.add c = a + b on 2 GiB float64 vectors (2 reads + 1 write)",
+            "GBs": round(add, 1), "copy_GBs": round(copy, 1)}
+
+
 def make_workload(name):
     import workloads as W
 
@@ -408,12 +436,13 @@ def main():
     if key in TRAFFIC and TRAFFIC[key][1] == kernel_source_sha():
         traffic = TRAFFIC[key][0]
     roofline = None
+    ref = streaming_reference(torch)
     if row is not None and row["GBs"]:
         roofline = {"bound": "hbm", "kernel": dom, "achieved": row["GBs"], "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": row["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
                     "algorithmic_bytes_per_launch": row["bytes"], "avg_ms": row["ms"],
                     "avg_ms_bracketed": row["ms_bracketed"], "event_bracket_ms": head["event_bracket_ms"],
-                    "launches": row["launches"]}
+                    "launches": row["launches"], "frac_of_streaming_reference": row["GBs"] / ref["GBs"]}
     line = {
         "metric": METRIC,
         "value": head["value"],
@@ -434,6 +463,7 @@ def main():
         "relres_true_max": head["relres_true_max"],
         "hbm_per_iteration": head["hbm_per_iteration"],
         "roofline": roofline,
+        "streaming_reference": ref,
         "kernels_mixed": {k_: {"ms": v["ms"], "GBs": v["GBs"] and round(v["GBs"], 1)}
                           for k_, v in head["kernels"].items()},
     }
