@@ -101,7 +101,8 @@ void hh_default_config(hh_config* cfg, int nx, int ny, int nz, double h);
 /* Validate cfg, allocate every device buffer for up to nrhs_max right-hand sides
  * (grid hierarchy, Krylov vectors, reductions) on the current HIP device, and
  * bind the context to hip_stream (a hipStream_t; NULL = the default stream).
- * HH_ERR_ARG for an invalid configuration, HH_ERR_OOM if allocation fails. */
+ * HH_ERR_ARG for an invalid configuration (among them a coarsest grid of more
+ * than 8192 unknowns), HH_ERR_OOM if allocation fails. */
 hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out);
 
 /* Free every resource of ctx.  ctx may be NULL. */
@@ -116,8 +117,15 @@ hh_status hh_level_shape(const hh_ctx* ctx, int l, int* nx, int* ny, int* nz, in
 /* Set the real wavenumber k(x) >= 0 (section 2: k = 2 pi f / c), device array
  * (nz, ny, nx) of doubles, copied.  Builds the hierarchy: coarse k by injection
  * k_{l+1}(i) = k_l(2i), per-level Jacobi factors omega D^-1 of the
- * rediscretised M, and the dense inverse of the coarsest M (host LU with
- * partial pivoting).  HH_ERR_NUMERIC if k holds NaN/Inf or a negative value. */
+ * rediscretised M, and the dense inverse of the coarsest M over its unknowns
+ * (Gauss-Jordan elimination with partial pivoting in complex128: on the host up
+ * to 256 unknowns, on the device above, where it takes about a second for the
+ * 4913 unknowns of a 17^3 Sommerfeld grid).  A coarsest level of at most 1024
+ * unknowns whose arrays fit one workgroup's LDS is solved inside the tail
+ * kernel; a larger one (up to 8192 unknowns, such as the paper's 17^3 coarsest
+ * grid of its closed-off experiments) by a multi-workgroup product with the
+ * inverse.  HH_ERR_NUMERIC if k holds NaN/Inf or a negative value, or if the
+ * coarsest M is singular. */
 hh_status hh_set_model(hh_ctx* ctx, const double* k);
 
 /* Copy nrhs right-hand sides (nrhs, nz, ny, nx) complex128 into the context. */
@@ -220,7 +228,8 @@ hh_status hh_set_shadow(hh_ctx* ctx, const void* P, int s);
  * solve replays one cycle per captured hipGraph; with "trace" its steps are
  * launched directly and not timed.
  * hh_get_option also reports "n_levels", "coarse_unknowns", "tail_first" (first
- * level run by the tail kernel) and the z-planes in use under the same names. */
+ * level run by the tail kernel, or the coarsest level when the multi-workgroup
+ * coarsest solve is in use) and the z-planes in use under the same names. */
 hh_status hh_set_option(hh_ctx* ctx, const char* name, long long value);
 hh_status hh_get_option(const hh_ctx* ctx, const char* name, long long* value);
 

@@ -1,0 +1,31 @@
+// Host-callable launchers of the large-coarsest-grid kernels (internal to the
+// library): the device Gauss-Jordan inverse of the coarsest rediscretised M and
+// the multi-workgroup dense solve that replaces the single-workgroup tail when
+// the coarsest level does not fit one workgroup's LDS.
+#pragma once
+#include "hh_common.h"
+
+namespace hh {
+
+// inv = I (n x n, complex128)
+void launch_gj_identity(hipStream_t s, int n, c128* inv);
+// One Gauss-Jordan step on the n x n row-major matrices a and inv (complex128):
+// partial pivoting over rows col .. n - 1 of column col (the row of largest
+// modulus, the first one on ties), row swap, scaling of the pivot row, and
+// elimination of column col from every other row.  piv, pval, f (n entries)
+// and bad are device scratch; bad is set when the pivot is zero or not finite.
+void launch_gj_step(hipStream_t s, int n, c128* a, c128* inv, int col, int* piv, c128* pval, c128* f,
+                    int* bad);
+// minv[j * n + r] = inv[r * n + j] (column-major, the layout of the coarsest
+// solve), rounded to complex64 when low is set.
+void launch_gj_store(hipStream_t s, int n, const c128* inv, void* minv, bool low);
+
+// e = M_c^-1 b on the coarsest level for every right-hand side the gate
+// admits: unknown u of node cidx[u] gets sum_c minv[c * n_unk + u] b[cidx[c]]
+// (fixed summation order), nodes with unk_of[i] < 0 (Dirichlet boundary) get 0.
+// b and e hold nrhs slices of nnode nodes.
+template <typename R>
+void launch_coarse_gemv(hipStream_t s, int nnode, int n_unk, const int* unk_of, const int* cidx,
+                        const cx<R>* minv, const cx<R>* b, cx<R>* e, int nrhs, const RhsState* st, int gate);
+
+}  // namespace hh

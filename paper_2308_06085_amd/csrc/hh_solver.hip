@@ -15,6 +15,7 @@
 
 #include "../../include/hh.h"
 #include "hh_common.h"
+#include "hh_coarse.h"
 #include "hh_kernels.h"
 #include "hh_krylov.h"
 
@@ -35,7 +36,9 @@ constexpr int trace_kernel_of(int launch) {
            : launch <= TL_UP_S ? 3 : launch == TL_P ? 4 : launch == TL_S ? 5 : 6;
 }
 constexpr long long NBLK_CAP = 65536;   // workgroups of a reduction-producing launch
-constexpr int COARSE_UNK_CAP = 2048;    // unknowns of the dense coarsest solve
+constexpr int COARSE_UNK_CAP = 8192;    // unknowns of the dense coarsest solve
+constexpr int HOST_INVERSE_MAX = 256;   // larger coarsest inverses are formed on the device
+constexpr int TAIL_UNK_MAX = 1024;      // larger coarsest solves run as a multi-workgroup product
 constexpr int MAX_RESTARTS = 5;
 
 std::string g_create_error;
@@ -80,8 +83,10 @@ struct hh_ctx {
     int* bad_host = nullptr;
     // coarsest level
     int* cidx = nullptr;
+    int* unk_of = nullptr;  // coarsest node -> unknown, -1 on a Dirichlet boundary
     void* minv = nullptr;
     int n_unk = 0;
+    bool coarse_gemv = false;  // coarsest solve by launch_coarse_gemv instead of the tail kernel
     // state
     bool model_set = false;
     int nrhs_cur = 0;
@@ -207,7 +212,7 @@ void free_all(hh_ctx* c) {
     }
     c->lv.clear();
     void* ptrs[] = {c->k2, c->kb, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->s, c->t,
-                    c->ph, c->sh, c->p_low, c->s_low, c->st, c->part, c->bad, c->cidx, c->minv};
+                    c->ph, c->sh, c->p_low, c->s_low, c->st, c->part, c->bad, c->cidx, c->unk_of, c->minv};
     for (void* q : ptrs) (void)hipFree(q);
     if (c->st_host) (void)hipHostFree(c->st_host);
     if (c->bad_host) (void)hipHostFree(c->bad_host);
@@ -287,6 +292,13 @@ void choose_tail(hh_ctx* c) {
     long long total = 0;
     int first = L - 1;
     total = c->lv[L - 1].g.n;
+    // a coarsest level too large for one workgroup: the fused passes run down
+    // to it and a multi-workgroup product with its inverse solves it
+    c->coarse_gemv = (size_t)total * per_node > c->tail_lds_cap || c->n_unk > TAIL_UNK_MAX;
+    if (c->coarse_gemv) {
+        c->tail_first = first;
+        return;
+    }
     while (first - 1 >= 1 && first - 1 >= L - MAX_TAIL &&
            (size_t)(total + c->lv[first - 1].g.n) * per_node <= c->tail_lds_cap) {
         --first;
@@ -374,6 +386,13 @@ struct CycleOps {
     }
     void tail(const TailProg& prog) const {
         const int T = c->tail_first;
+        if (c->coarse_gemv) {
+            // the tail is the coarsest level alone, where V and F are the exact solve
+            const LevelBuf& cl = c->lv[T];
+            launch_coarse_gemv<R>(s, (int)cl.g.n, c->n_unk, c->unk_of, c->cidx,
+                                  reinterpret_cast<const cx<R>*>(c->minv), C(cl.b), C(cl.e), nrhs, st, gate);
+            return;
+        }
         launch_mg_tail<R>(s, c->cfg.bc, tail_desc(c), prog, nrhs, C(c->lv[T].b), C(c->lv[T].e), st, gate);
     }
     // e_m = V(b_m); with acc, e_m += V(b_m)  (m < tail_first when acc)
@@ -600,8 +619,43 @@ hh_status read_states(hh_ctx* c, int nrhs) {
     return HH_OK;
 }
 
+// Gauss-Jordan inverse of the row-major n x n matrix a on the device, stored
+// into c->minv (column-major, in the multigrid precision).  Set-up only: the
+// work buffers are allocated and freed here.
+hh_status device_inverse(hh_ctx* c, int n, const std::complex<double>* a) {
+    const size_t nn = (size_t)n * n;
+    c128 *da = nullptr, *dinv = nullptr, *f = nullptr, *pval = nullptr;
+    int *piv = nullptr, *bad = nullptr;
+    auto release = [&]() {
+        for (void* q : {(void*)da, (void*)dinv, (void*)f, (void*)pval, (void*)piv, (void*)bad}) (void)hipFree(q);
+    };
+    hh_status st = HH_OK;
+    if ((st = dalloc(c, &da, sizeof(c128) * nn)) != HH_OK || (st = dalloc(c, &dinv, sizeof(c128) * nn)) != HH_OK ||
+        (st = dalloc(c, &f, sizeof(c128) * n)) != HH_OK || (st = dalloc(c, &pval, sizeof(c128))) != HH_OK ||
+        (st = dalloc(c, &piv, sizeof(int))) != HH_OK || (st = dalloc(c, &bad, sizeof(int))) != HH_OK) {
+        release();
+        return st;
+    }
+    hipError_t e = hipMemcpyAsync(da, a, sizeof(c128) * nn, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), c->stream);
+    if (e == hipSuccess) {
+        launch_gj_identity(c->stream, n, dinv);
+        for (int col = 0; col < n; ++col) launch_gj_step(c->stream, n, da, dinv, col, piv, pval, f, bad);
+        launch_gj_store(c->stream, n, dinv, c->minv, c->mixed);
+        e = hipGetLastError();
+    }
+    int bad_h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    release();
+    if (e != hipSuccess) return fail(c, HH_ERR_HIP, "coarsest inverse on the device: %s", hipGetErrorString(e));
+    if (bad_h) return fail(c, HH_ERR_NUMERIC, "coarsest M is singular");
+    return HH_OK;
+}
+
 // Dense inverse of the coarsest rediscretised M over its unknowns (Gauss-Jordan
-// with partial pivoting in complex double), stored column-major.
+// with partial pivoting in complex double), stored column-major: on the host
+// for small grids, on the device above HOST_INVERSE_MAX unknowns.
 hh_status build_coarse(hh_ctx* c) {
     LevelBuf& cl = c->lv.back();
     const Geo& g = cl.g;
@@ -621,7 +675,7 @@ hh_status build_coarse(hh_ctx* c) {
             }
     const int n = (int)node_of.size();
     typedef std::complex<double> C;
-    std::vector<C> a((size_t)n * n, C(0, 0)), inv((size_t)n * n, C(0, 0));
+    std::vector<C> a((size_t)n * n, C(0, 0));
     const double ih2 = 1.0 / (g.h * g.h);
     const C sigma(c->cfg.beta1, -c->cfg.beta2);
     for (int u = 0; u < n; ++u) {
@@ -647,6 +701,12 @@ hh_status build_coarse(hh_ctx* c) {
             }
         a[(size_t)u * n + u] += d;
     }
+    // cidx / unk_of / minv were sized in hh_create for this level, so captured graphs keep valid pointers
+    if (n != c->n_unk) return fail(c, HH_ERR_STATE, "coarsest unknown count changed");
+    HIPCHK(c, hipMemcpy(c->cidx, node_of.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->unk_of, unk_of.data(), sizeof(int) * g.n, hipMemcpyHostToDevice));
+    if (n > HOST_INVERSE_MAX) return device_inverse(c, n, a.data());
+    std::vector<C> inv((size_t)n * n, C(0, 0));
     for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
     for (int col = 0; col < n; ++col) {
         int piv = col;
@@ -676,9 +736,6 @@ hh_status build_coarse(hh_ctx* c) {
             }
         }
     }
-    // cidx / minv were sized in hh_create for this level, so captured graphs keep valid pointers
-    if (n != c->n_unk) return fail(c, HH_ERR_STATE, "coarsest unknown count changed");
-    HIPCHK(c, hipMemcpy(c->cidx, node_of.data(), sizeof(int) * n, hipMemcpyHostToDevice));
     if (c->mixed) {
         std::vector<c64> cm((size_t)n * n);
         for (int r = 0; r < n; ++r)
@@ -987,6 +1044,7 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
                              COARSE_UNK_CAP));
         c->n_unk = (int)nu;
         if ((s = dalloc(c, &c->cidx, sizeof(int) * nu)) != HH_OK) return bail(s);
+        if ((s = dalloc(c, &c->unk_of, sizeof(int) * gcst.n)) != HH_OK) return bail(s);
         if ((s = dalloc(c, (char**)&c->minv, c->csize * nu * nu)) != HH_OK) return bail(s);
     }
     if (hipHostMalloc((void**)&c->st_host, sizeof(RhsState) * R, hipHostMallocDefault) != hipSuccess ||

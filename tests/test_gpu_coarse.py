@@ -1,0 +1,121 @@
+"""Large coarsest grids on the GPU: the device Gauss-Jordan inverse of the
+coarsest rediscretised M and the multi-workgroup coarsest solve that replaces
+the single-workgroup tail (the exact coarsest solve of section 3.4; the paper's
+closed-off runs of Table 1 stop coarsening at 17^3).
+
+Parity: one V-cycle against the oracle's with the same hierarchy (1e-11 in
+complex128, 1e-5 in complex64), on coarsest grids that take the device inverse
+with and without the tail kernel.  The whole solver on the Table 1
+configuration (closed-off 65^3, k = 40, coarsest 17^3, relative residual 1e-6:
+the true one for Bi-CGSTAB and IDR(4), the preconditioned one for GMRES)
+against the paper's printed matvec counts: GMRES 145, Bi-CGSTAB and IDR(4)
+inside the band of the paper's partitions.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle.discretization import DIRICHLET, SOMMERFELD, unknown_mask
+from oracle.multigrid import build_hierarchy, fcycle, vcycle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _solver(shape, h, bc, **kw):
+    from paper_2308_06085_amd import Solver
+
+    return Solver(shape, h, bc=bc, **kw)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+# (shape, bc, coarsest unknowns): device inverse with the tail kernel (729),
+# device inverse with the multi-workgroup solve (3375 Dirichlet, 4913 Sommerfeld)
+CASES = [((17, 17, 17), SOMMERFELD, 729), ((33, 33, 33), DIRICHLET, 3375), ((33, 33, 33), SOMMERFELD, 4913)]
+
+
+@pytest.mark.parametrize("shape,bc,nunk", CASES)
+def test_large_coarsest_cycle_parity(shape, bc, nunk):
+    h = 1.0 / (shape[0] - 1)
+    k = np.random.default_rng(21).uniform(4.0, 12.0, shape)
+    hier = build_hierarchy(k, h, bc, n_levels=2)
+    r = W.random_complex((2,) + shape, seed=22) * unknown_mask(shape, bc)
+    ref_v = vcycle(r, hier)
+    s = _solver(shape, h, bc, n_levels=2, nrhs_max=2)
+    assert s.get_option("coarse_unknowns") == nunk
+    s.set_model(dev(k))
+    assert relerr(host(s.apply_vcycle(dev(r))), ref_v) <= 1e-11
+    # with two levels the F-cycle's coarse-grid solve is the exact solve as well
+    s.set_option("cycle", 1)
+    assert relerr(host(s.apply_vcycle(dev(r))), fcycle(r, hier)) <= 1e-11
+    s.close()
+    m = _solver(shape, h, bc, n_levels=2, nrhs_max=2, prec="mixed")
+    m.set_model(dev(k))
+    assert relerr(host(m.apply_vcycle(dev(r))), ref_v) <= 1e-5
+    m.close()
+
+
+def test_large_coarsest_three_levels_and_model_change():
+    """Three levels down to a 17^3 coarsest grid (the fused passes on level 1
+    feed the multi-workgroup solve), and a new model rebuilds the inverse."""
+    shape, h, bc = (65, 65, 65), 1 / 64, SOMMERFELD
+    r = W.random_complex(shape, seed=23)
+    s = _solver(shape, h, bc, n_levels=3)
+    assert s.get_option("coarse_unknowns") == 17**3
+    for seed in (24, 25):
+        k = np.random.default_rng(seed).uniform(10.0, 30.0, shape)
+        s.set_model(dev(k))
+        ref = vcycle(r, build_hierarchy(k, h, bc, n_levels=3))
+        assert relerr(host(s.apply_vcycle(dev(r)))[0], ref) <= 1e-11, seed
+    s.close()
+
+
+@pytest.mark.parametrize("method", ["gmres", "bicgstab", "idrs"])
+def test_paper_table1_counts_on_gpu(method):
+    """Table 1 (section 5.1.3): closed-off 65^3, k = 40, CSLP (1, -0.5) by one
+    V(1,1)-cycle with omega = 0.8 down to a 17^3 coarsest grid, stop at
+    relative residual 1e-6, FP64."""
+    with open(os.path.join(GOLDEN, "table1_bicgstab_matvec.json")) as f:
+        gold = json.load(f)
+    n, kk = gold["problem"]["n"], gold["problem"]["k"]
+    lvl, b, uex = O.closed_off_problem(n, kk)
+    s = _solver(lvl.shape, lvl.h, DIRICHLET, n_levels=3, method=method)
+    assert s.level_shapes()[-1] == (17, 17, 17)
+    s.set_model(dev(np.full(lvl.shape, kk)))
+    s.set_sources(dev(b))
+    x, st = s.solve(rtol=gold["problem"]["tol"], maxit=1000)
+    x = host(x)[0]
+    assert st[0].status == "HH_OK"
+    true_rel = np.linalg.norm(b - O.apply_A(x, lvl)) / np.linalg.norm(b)
+    if method == "gmres":
+        # GMRES on the left-preconditioned system stops on ||K(b - A x)|| / ||K b||
+        assert st[0].relres <= gold["problem"]["tol"] and true_rel <= 1e-5, (st[0].relres, true_rel)
+    else:
+        assert true_rel <= gold["problem"]["tol"]
+    assert np.abs(x - uex).max() < 2e-3
+    mv = st[0].matvecs
+    print(f"Table 1 on the GPU, {method}: {mv} matvecs, true relative residual {true_rel:.2e}")
+    if method == "gmres":
+        assert abs(mv - 145) <= 1, mv
+    else:
+        key = "bicgstab" if method == "bicgstab" else "idr4"
+        assert 0.8 * min(gold[key]) <= mv <= 1.15 * max(gold[key]), mv
+    s.close()
