@@ -1,7 +1,7 @@
 """Benchmark: DoF-iterations/s of CSLP-preconditioned Bi-CGSTAB on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
-                    [--workload wedge|cube513|batched|beta2_sweep]
+                    [--workload wedge|cube513|batched|beta2_sweep|closedoff129]
 
 One step = one complete solve to ||b - A x|| / ||b|| <= 1e-6 of the workload
 (model and sources resident in HBM before the timed region).  The default
@@ -50,12 +50,19 @@ wedge at 40 Hz on 193 x 193 x 321 nodes (h = 3.125 m), mixed precision,
 Bi-CGSTAB, IDR(4) and GMRES, V- and F-cycle, for beta2 = -0.5 ... -1.0:
 iterations, products with A and time per solve to 1e-6 (at most 1200
 products with A, 400 GMRES steps); ``value`` is the fastest solve's time in ms.
+
+``--workload closedoff129``: the closed-off problem of section 2.1 on 129^3
+nodes with k = 40 and the coarsening stopped at 17^3 (the configuration of the
+paper's scaling runs, section 5.2): GMRES, IDR(4) and Bi-CGSTAB with the
+V-cycle, FP64 and mixed, to relative residual 1e-6; ``value`` is the FP64
+IDR(4) solve's time in ms, every run is listed under ``runs``.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -157,6 +164,57 @@ def streaming_reference(torch) -> dict:
     torch.cuda.empty_cache()
     return {"kernel": "torch.add c = a + b on 2 GiB float64 vectors (2 reads + 1 write)",
             "GBs": round(add, 1), "copy_GBs": round(copy, 1)}
+
+
+def closed_off_runs(args, n=129, kk=40.0):
+    """The paper's closed-off problem (section 2.1; its scaling runs of section
+    5.2) on n^3 nodes with k = 40 and the coarsening stopped at 17^3: GMRES,
+    IDR(4) and Bi-CGSTAB with the V-cycle, FP64 and mixed, to relative residual
+    1e-6 (the preconditioned one for GMRES)."""
+    import torch
+
+    import workloads as W
+    from paper_2308_06085_amd import Solver
+
+    k, b, _ = W.closed_off_rhs(n, kk)
+    k, b = torch.from_numpy(k).cuda(), torch.from_numpy(b).cuda()
+    levels = int(round(math.log2((n - 1) / 16))) + 1
+    unknowns = (n - 2) ** 3
+    rows = []
+    for prec in ("fp64", "mixed"):
+        for method in ("gmres", "idrs", "bicgstab"):
+            s = Solver((n, n, n), 1.0 / (n - 1), bc="dirichlet", prec=prec, n_levels=levels, method=method)
+            assert s.level_shapes()[-1] == (17, 17, 17)
+            s.set_model(k)
+            s.set_sources(b)
+            warm, reps = (0, 1) if method == "gmres" else (args.warmup, args.steps)
+            x = None
+            for _ in range(warm):
+                x, _ = s.solve(rtol=1e-6, maxit=2000, out=x)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                x, st = s.solve(rtol=1e-6, maxit=2000, out=x)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / reps
+            rows.append({"precision": prec, "method": method, "iterations": st[0].iterations,
+                         "matvecs": st[0].matvecs, "status": st[0].status, "relres": st[0].relres,
+                         "relres_true": st[0].relres_true, "ms_per_solve": ms,
+                         "dof_matvecs_per_s": unknowns * st[0].matvecs / (ms * 1e-3)})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            s.close()
+            del x
+    head = next(r for r in rows if r["precision"] == "fp64" and r["method"] == "idrs")
+    line = {
+        "metric": "time to 1e-6 rel residual, closed-off problem with a 17^3 coarsest grid: GMRES, IDR(4), Bi-CGSTAB",
+        "value": head["ms_per_solve"], "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_solve"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128 (fp64 rows) / c64 cycle + c128 Krylov (mixed rows)", "data": "synthetic",
+        "config": {"workload": f"closed-off {n}^3 k={kk:g} Dirichlet u=1, {levels} levels down to 17^3",
+                   "unknowns": unknowns, "nrhs": 1, "rtol": 1e-6, "headline_row": "fp64 IDR(4)"},
+        "runs": rows,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def make_workload(name):
@@ -321,7 +379,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="wedge", choices=["wedge", "cube513", "batched", "beta2_sweep"])
+    ap.add_argument("--workload", default="wedge", choices=["wedge", "cube513", "batched", "beta2_sweep", "closedoff129"])
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the F-cycle and IDR(4) solves of the wedge")
     ap.add_argument("--cycle", default="V", choices=["V", "F"],
@@ -353,6 +411,9 @@ def main():
             bbuf.copy_(a)
         torch.cuda.synchronize()
         del a, bbuf
+    if args.workload == "closedoff129":
+        closed_off_runs(args)
+        return
     wl, nodes, desc = make_workload(args.workload)
     if args.workload == "beta2_sweep":
         beta2_sweep(args, wl, nodes, desc)

@@ -17,15 +17,20 @@ void launch_gj_identity(hipStream_t s, int n, c128* inv);
 void launch_gj_step(hipStream_t s, int n, c128* a, c128* inv, int col, int* piv, c128* pval, c128* f,
                     int* bad);
 // minv[j * n + r] = inv[r * n + j] (column-major, the layout of the coarsest
-// solve), rounded to complex64 when low is set.
+// solve), rounded to complex64 when low is set (the tail kernel's inverse in
+// the mixed form).
 void launch_gj_store(hipStream_t s, int n, const c128* inv, void* minv, bool low);
 
 // e = M_c^-1 b on the coarsest level for every right-hand side the gate
 // admits: unknown u of node cidx[u] gets sum_c minv[c * n_unk + u] b[cidx[c]]
-// (fixed summation order), nodes with unk_of[i] < 0 (Dirichlet boundary) get 0.
-// b and e hold nrhs slices of nnode nodes.
+// (complex128 inverse and sums, fixed summation order), nodes with
+// unk_of[i] < 0 (Dirichlet boundary) get 0.  b and e hold nrhs slices of
+// nnode nodes in the multigrid precision; part is device scratch of
+// nrhs x coarse_gemv_chunks(n_unk) x n_unk complex128 values.
+int coarse_gemv_chunks(int n_unk);
 template <typename R>
 void launch_coarse_gemv(hipStream_t s, int nnode, int n_unk, const int* unk_of, const int* cidx,
-                        const cx<R>* minv, const cx<R>* b, cx<R>* e, int nrhs, const RhsState* st, int gate);
+                        const c128* minv, const cx<R>* b, cx<R>* e, c128* part, int nrhs, const RhsState* st,
+                        int gate);
 
 }  // namespace hh

@@ -130,43 +130,67 @@ __global__ __launch_bounds__(GJ_LANES) void k_gj_store(int n, const c128* __rest
     minv[i] = cvt<T>(inv[(long long)r * n + j]);
 }
 
-// e = M_c^-1 b.  A workgroup of 256 lanes takes 64 rows (unknowns); wave w
-// sums its quarter of the columns for each of them (lanes of a wave read one
-// column's 64 consecutive rows: coalesced), then the four partial sums are
-// added in wave order.  Every workgroup first zeroes its share of the
-// non-unknown nodes.  gridDim = (row blocks, 1, right-hand sides).
-constexpr int GEMV_ROWS = 64, GEMV_LANES = 256, GEMV_WAVES = GEMV_LANES / GEMV_ROWS;
+// e = M_c^-1 b with the inverse and the sums in complex128 for either
+// multigrid precision (a large coarsest grid's solve adds thousands of terms
+// per row; complex64 sums perturb the preconditioner enough to cost Krylov
+// steps).  Two passes so that the product fills the chip:
+//   k_coarse_gemv: workgroup (row block, column chunk) of 256 lanes = 64 rows x
+//     4 waves; the chunk's CG_COLS gathered right-hand-side entries are staged
+//     in LDS, wave w sums its quarter of the chunk for the 64 rows (the lanes of
+//     a wave read one column's 64 consecutive rows: coalesced), and the four
+//     wave sums are added in wave order into part[rhs][chunk][row];
+//   k_coarse_sum: e at every node of the level: the chunk sums of its unknown
+//     in chunk order, or 0 at a node that is not an unknown.
+// gridDim = (row blocks, chunks, right-hand sides) and (node blocks, 1, rhs).
+constexpr int CG_ROWS = 64, CG_LANES = 256, CG_WAVES = CG_LANES / CG_ROWS, CG_COLS = 128;
+static_assert(CG_COLS <= CG_LANES, "one staging load per lane");
 
 template <typename R>
-__global__ __launch_bounds__(GEMV_LANES) void k_coarse_gemv(int nnode, int n, const int* __restrict__ unk_of,
-                                                            const int* __restrict__ cidx,
-                                                            const cx<R>* __restrict__ minv,
-                                                            const cx<R>* __restrict__ b, cx<R>* __restrict__ e,
-                                                            const RhsState* st, int gate) {
-    __shared__ cx<R> part[GEMV_WAVES][GEMV_ROWS];
+__global__ __launch_bounds__(CG_LANES) void k_coarse_gemv(int nnode, int n, const int* __restrict__ cidx,
+                                                          const c128* __restrict__ minv,
+                                                          const cx<R>* __restrict__ b, c128* __restrict__ part,
+                                                          const RhsState* st, int gate) {
+    __shared__ c128 bg[CG_COLS];
+    __shared__ c128 ps[CG_WAVES][CG_ROWS];
     const int r = blockIdx.z;
     if (!gate_ok(st, r, gate)) return;
     const int t = threadIdx.x;
+    const int chunk = blockIdx.y, nch = gridDim.y;
+    const int c0 = chunk * CG_COLS, c1 = min(n, c0 + CG_COLS);
     const cx<R>* br = b + (long long)r * nnode;
-    cx<R>* er = e + (long long)r * nnode;
-    for (int i = blockIdx.x * GEMV_LANES + t; i < nnode; i += gridDim.x * GEMV_LANES)
-        if (unk_of[i] < 0) er[i] = czero<R>();
-    const int lane = t & (GEMV_ROWS - 1), w = t / GEMV_ROWS;
-    const int row = blockIdx.x * GEMV_ROWS + lane;
+    if (t < c1 - c0) bg[t] = cvt<double>(br[cidx[c0 + t]]);
+    __syncthreads();
+    const int lane = t & (CG_ROWS - 1), w = t / CG_ROWS;
+    const int row = blockIdx.x * CG_ROWS + lane;
     const int rr = row < n ? row : n - 1;  // lanes past the last row read a valid row and store nothing
-    const int per = (n + GEMV_WAVES - 1) / GEMV_WAVES;
-    const int c0 = w * per, c1 = min(n, c0 + per);
-    cx<R> acc = czero<R>();
+    constexpr int PER = CG_COLS / CG_WAVES;
+    const int a0 = c0 + w * PER, a1 = min(c1, a0 + PER);
+    c128 acc = czero<double>();
 #pragma unroll 8
-    for (int c = c0; c < c1; ++c) acc = acc + minv[(long long)c * n + rr] * br[cidx[c]];
-    part[w][lane] = acc;
+    for (int c = a0; c < a1; ++c) acc = acc + minv[(long long)c * n + rr] * bg[c - c0];
+    ps[w][lane] = acc;
     __syncthreads();
     if (w == 0 && row < n) {
-        cx<R> s = part[0][lane];
+        c128 sum = ps[0][lane];
 #pragma unroll
-        for (int q = 1; q < GEMV_WAVES; ++q) s = s + part[q][lane];
-        er[cidx[row]] = s;
+        for (int q = 1; q < CG_WAVES; ++q) sum = sum + ps[q][lane];
+        part[((long long)r * nch + chunk) * n + row] = sum;
     }
+}
+
+template <typename R>
+__global__ __launch_bounds__(CG_LANES) void k_coarse_sum(int nnode, int n, int nch, const int* __restrict__ unk_of,
+                                                         const c128* __restrict__ part, cx<R>* __restrict__ e,
+                                                         const RhsState* st, int gate) {
+    const int r = blockIdx.z;
+    if (!gate_ok(st, r, gate)) return;
+    const int i = blockIdx.x * CG_LANES + threadIdx.x;
+    if (i >= nnode) return;
+    const int u = unk_of[i];
+    c128 sum = czero<double>();
+    if (u >= 0)
+        for (int ch = 0; ch < nch; ++ch) sum = sum + part[((long long)r * nch + ch) * n + u];
+    e[(long long)r * nnode + i] = cvt<R>(sum);
 }
 
 // ---------------------------------------------------------------------------
@@ -196,16 +220,22 @@ void launch_gj_store(hipStream_t s, int n, const c128* inv, void* minv, bool low
     else hipLaunchKernelGGL(k_gj_store<double>, grid, dim3(GJ_LANES), 0, s, n, inv, (c128*)minv);
 }
 
+int coarse_gemv_chunks(int n_unk) { return (n_unk + CG_COLS - 1) / CG_COLS; }
+
 template <typename R>
 void launch_coarse_gemv(hipStream_t s, int nnode, int n_unk, const int* unk_of, const int* cidx,
-                        const cx<R>* minv, const cx<R>* b, cx<R>* e, int nrhs, const RhsState* st, int gate) {
-    const dim3 grid((unsigned)((n_unk + GEMV_ROWS - 1) / GEMV_ROWS), 1, (unsigned)nrhs);
-    hipLaunchKernelGGL((k_coarse_gemv<R>), grid, dim3(GEMV_LANES), 0, s, nnode, n_unk, unk_of, cidx, minv, b, e,
-                       st, gate);
+                        const c128* minv, const cx<R>* b, cx<R>* e, c128* part, int nrhs, const RhsState* st,
+                        int gate) {
+    const int nch = coarse_gemv_chunks(n_unk);
+    hipLaunchKernelGGL((k_coarse_gemv<R>), dim3((unsigned)((n_unk + CG_ROWS - 1) / CG_ROWS), (unsigned)nch,
+                                                (unsigned)nrhs),
+                       dim3(CG_LANES), 0, s, nnode, n_unk, cidx, minv, b, part, st, gate);
+    hipLaunchKernelGGL((k_coarse_sum<R>), dim3((unsigned)((nnode + CG_LANES - 1) / CG_LANES), 1, (unsigned)nrhs),
+                       dim3(CG_LANES), 0, s, nnode, n_unk, nch, unk_of, part, e, st, gate);
 }
 template void launch_coarse_gemv<double>(hipStream_t, int, int, const int*, const int*, const c128*, const c128*,
-                                         c128*, int, const RhsState*, int);
-template void launch_coarse_gemv<float>(hipStream_t, int, int, const int*, const int*, const c64*, const c64*,
-                                        c64*, int, const RhsState*, int);
+                                         c128*, c128*, int, const RhsState*, int);
+template void launch_coarse_gemv<float>(hipStream_t, int, int, const int*, const int*, const c128*, const c64*,
+                                        c64*, c128*, int, const RhsState*, int);
 
 }  // namespace hh

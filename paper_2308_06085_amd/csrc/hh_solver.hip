@@ -87,6 +87,7 @@ struct hh_ctx {
     void* minv = nullptr;
     int n_unk = 0;
     bool coarse_gemv = false;  // coarsest solve by launch_coarse_gemv instead of the tail kernel
+    c128* cg_part = nullptr;   // its per-chunk row sums
     // state
     bool model_set = false;
     int nrhs_cur = 0;
@@ -212,7 +213,8 @@ void free_all(hh_ctx* c) {
     }
     c->lv.clear();
     void* ptrs[] = {c->k2, c->kb, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->s, c->t,
-                    c->ph, c->sh, c->p_low, c->s_low, c->st, c->part, c->bad, c->cidx, c->unk_of, c->minv};
+                    c->ph, c->sh, c->p_low, c->s_low, c->st, c->part, c->bad, c->cidx, c->unk_of, c->minv,
+                    c->cg_part};
     for (void* q : ptrs) (void)hipFree(q);
     if (c->st_host) (void)hipHostFree(c->st_host);
     if (c->bad_host) (void)hipHostFree(c->bad_host);
@@ -389,8 +391,8 @@ struct CycleOps {
         if (c->coarse_gemv) {
             // the tail is the coarsest level alone, where V and F are the exact solve
             const LevelBuf& cl = c->lv[T];
-            launch_coarse_gemv<R>(s, (int)cl.g.n, c->n_unk, c->unk_of, c->cidx,
-                                  reinterpret_cast<const cx<R>*>(c->minv), C(cl.b), C(cl.e), nrhs, st, gate);
+            launch_coarse_gemv<R>(s, (int)cl.g.n, c->n_unk, c->unk_of, c->cidx, reinterpret_cast<const c128*>(c->minv),
+                                  C(cl.b), C(cl.e), c->cg_part, nrhs, st, gate);
             return;
         }
         launch_mg_tail<R>(s, c->cfg.bc, tail_desc(c), prog, nrhs, C(c->lv[T].b), C(c->lv[T].e), st, gate);
@@ -641,7 +643,7 @@ hh_status device_inverse(hh_ctx* c, int n, const std::complex<double>* a) {
     if (e == hipSuccess) {
         launch_gj_identity(c->stream, n, dinv);
         for (int col = 0; col < n; ++col) launch_gj_step(c->stream, n, da, dinv, col, piv, pval, f, bad);
-        launch_gj_store(c->stream, n, dinv, c->minv, c->mixed);
+        launch_gj_store(c->stream, n, dinv, c->minv, c->mixed && !c->coarse_gemv);
         e = hipGetLastError();
     }
     int bad_h = 0;
@@ -736,7 +738,9 @@ hh_status build_coarse(hh_ctx* c) {
             }
         }
     }
-    if (c->mixed) {
+    // complex64 for the tail kernel of the mixed form; the multi-workgroup solve
+    // keeps the inverse in complex128 in both forms
+    if (c->mixed && !c->coarse_gemv) {
         std::vector<c64> cm((size_t)n * n);
         for (int r = 0; r < n; ++r)
             for (int j = 0; j < n; ++j)
@@ -1045,7 +1049,9 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
         c->n_unk = (int)nu;
         if ((s = dalloc(c, &c->cidx, sizeof(int) * nu)) != HH_OK) return bail(s);
         if ((s = dalloc(c, &c->unk_of, sizeof(int) * gcst.n)) != HH_OK) return bail(s);
-        if ((s = dalloc(c, (char**)&c->minv, c->csize * nu * nu)) != HH_OK) return bail(s);
+        // complex128 even in the mixed form: the multi-workgroup coarsest solve
+        // keeps its inverse in double (the tail kernel's complex64 copy fits too)
+        if ((s = dalloc(c, (char**)&c->minv, sizeof(c128) * nu * nu)) != HH_OK) return bail(s);
     }
     if (hipHostMalloc((void**)&c->st_host, sizeof(RhsState) * R, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->bad_host, sizeof(int), hipHostMallocDefault) != hipSuccess)
@@ -1081,6 +1087,9 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
         }
     (void)hipGetLastError();
     choose_tail(c);
+    if (c->coarse_gemv &&
+        (s = dalloc(c, &c->cg_part, sizeof(c128) * R * coarse_gemv_chunks(c->n_unk) * c->n_unk)) != HH_OK)
+        return bail(s);
     apply_launch(c);
     *out = c;
     return HH_OK;

@@ -38,6 +38,7 @@ __all__ = [
     "adjoint_workload",
     "random_complex",
     "receivers_top_grid",
+    "closed_off_rhs",
 ]
 
 
@@ -104,6 +105,31 @@ def wedge(freq: float = 10.0, nx: int = 129, ny: int = 129, nz: int = 257,
     src = [(0, (ny - 1) // 2, (nx - 1) // 2)]
     return Workload(k, h, "sommerfeld", src, n_levels,
                     f"wedge {nx}x{ny}x{nz} f={freq:g}Hz h={h:g}m")
+
+
+def closed_off_rhs(n: int, k: float):
+    """Data of the closed-off problem of section 2.1 on n^3 nodes of the unit
+    cube with constant k: f = (21 pi^2 - k^2) sin(pi x) sin(2 pi y) sin(4 pi z)
+    - k^2 in the interior, u = 1 on the boundary.  The boundary value is moved
+    into the right-hand side of the interior nodes next to the boundary (g / h^2
+    per boundary neighbour, g = 1), so b and the returned exact solution are zero
+    on the boundary.  Returns (k array, b complex128, u_exact), all (n, n, n)."""
+    h = 1.0 / (n - 1)
+    t = np.linspace(0.0, 1.0, n)
+    z, y, x = np.meshgrid(t, t, t, indexing="ij")
+    sss = np.sin(np.pi * x) * np.sin(2 * np.pi * y) * np.sin(4 * np.pi * z)
+    f = (21 * np.pi**2 - k**2) * sss - k**2
+    near = np.zeros((n, n, n))
+    for ax in range(3):
+        for i in (1, n - 2):
+            idx = [slice(None)] * 3
+            idx[ax] = i
+            near[tuple(idx)] += 1.0
+    interior = np.zeros((n, n, n), dtype=bool)
+    interior[1:-1, 1:-1, 1:-1] = True
+    b = np.where(interior, f + near / h**2, 0.0).astype(np.complex128)
+    u = np.where(interior, sss + 1.0, 0.0)
+    return np.full((n, n, n), float(k)), b, u
 
 
 def big_cube(n: int = 513, k: float = 160.0, n_levels: int = 8) -> Workload:
