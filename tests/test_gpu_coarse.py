@@ -78,7 +78,8 @@ def test_large_coarsest_cycle_parity(shape, bc, nunk):
 
 def test_large_coarsest_three_levels_and_model_change():
     """Three levels down to a 17^3 coarsest grid (the fused passes on level 1
-    feed the multi-workgroup solve), and a new model rebuilds the inverse."""
+    feed the multi-workgroup solve), V- and F-cycle, and a new model rebuilds
+    the inverse."""
     shape, h, bc = (65, 65, 65), 1 / 64, SOMMERFELD
     r = W.random_complex(shape, seed=23)
     s = _solver(shape, h, bc, n_levels=3)
@@ -86,8 +87,12 @@ def test_large_coarsest_three_levels_and_model_change():
     for seed in (24, 25):
         k = np.random.default_rng(seed).uniform(10.0, 30.0, shape)
         s.set_model(dev(k))
-        ref = vcycle(r, build_hierarchy(k, h, bc, n_levels=3))
-        assert relerr(host(s.apply_vcycle(dev(r)))[0], ref) <= 1e-11, seed
+        hier = build_hierarchy(k, h, bc, n_levels=3)
+        s.set_option("cycle", 0)
+        assert relerr(host(s.apply_vcycle(dev(r)))[0], vcycle(r, hier)) <= 1e-11, seed
+        # F-cycle: level 1 is visited twice, each visit ending in the multi-workgroup solve
+        s.set_option("cycle", 1)
+        assert relerr(host(s.apply_vcycle(dev(r)))[0], fcycle(r, hier)) <= 1e-11, seed
     s.close()
 
 
