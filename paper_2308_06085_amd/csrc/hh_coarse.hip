@@ -6,10 +6,12 @@
 // The multigrid cycle ends in an exact solve on the coarsest level (paper
 // section 3.4, Algorithm 1; the paper's own runs use GMRES to a 1e-11 residual
 // there, which is the exact solve up to that tolerance).  Small coarsest grids
-// are solved inside the single-workgroup tail kernel with an inverse formed on
-// the host; a grid such as the 17^3 coarsest level of the paper's closed-off
-// experiments (Table 1) has thousands of unknowns, too many for one
-// workgroup's LDS and for a host elimination at set-up, so it takes this path.
+// are solved inside the single-workgroup tail kernel, with an inverse formed
+// on the host up to 256 unknowns and here above.  A grid such as the 17^3
+// coarsest level of the paper's closed-off experiments (Table 1) has
+// thousands of unknowns, too many for one workgroup's LDS and for a host
+// elimination at set-up: its inverse is formed here and the solve is the
+// multi-workgroup product below.
 #include "hh_coarse.h"
 #include "hh_device.h"
 
