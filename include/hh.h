@@ -119,8 +119,8 @@ hh_status hh_level_shape(const hh_ctx* ctx, int l, int* nx, int* ny, int* nz, in
  * k_{l+1}(i) = k_l(2i), per-level Jacobi factors omega D^-1 of the
  * rediscretised M, and the dense inverse of the coarsest M over its unknowns
  * (Gauss-Jordan elimination with partial pivoting in complex128: on the host up
- * to 256 unknowns, on the device above, where it takes about a second for the
- * 4913 unknowns of a 17^3 Sommerfeld grid).  A coarsest level of at most 1024
+ * to 256 unknowns, on the device above: about 0.2 s for the 3375 unknowns of
+ * the 17^3 Dirichlet grid of the paper's closed-off runs).  A coarsest level of at most 1024
  * unknowns whose arrays fit one workgroup's LDS is solved inside the tail
  * kernel; a larger one (up to 8192 unknowns, such as the paper's 17^3 coarsest
  * grid of its closed-off experiments) by a multi-workgroup product with the
