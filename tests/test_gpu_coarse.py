@@ -127,3 +127,26 @@ def test_paper_table1_counts_on_gpu(method):
         key = "bicgstab" if method == "bicgstab" else "idr4"
         assert 0.8 * min(gold[key]) <= mv <= 1.15 * max(gold[key]), mv
     s.close()
+
+
+def test_large_coarsest_batched_equals_single_solves():
+    """Two right-hand sides that stop at different steps share the
+    multi-workgroup coarsest solve (its kernels skip a stopped right-hand
+    side); each equals its single solve bit for bit."""
+    n, kk = 33, 20.0
+    lvl, b0, _ = O.closed_off_problem(n, kk)
+    b1 = O.point_source_rhs(lvl.shape, lvl.h, [(16, 16, 16)])[0]
+    b = np.stack([b0, b1])
+    s = _solver(lvl.shape, lvl.h, DIRICHLET, n_levels=2, nrhs_max=2)
+    assert s.get_option("coarse_unknowns") == 15**3
+    s.set_model(dev(np.full(lvl.shape, kk)))
+    s.set_sources(dev(b))
+    xb, stb = s.solve(rtol=1e-8)
+    xb = host(xb)
+    assert all(t.status == "HH_OK" for t in stb)
+    assert stb[0].iterations != stb[1].iterations
+    for r in range(2):
+        s.set_sources(dev(b[r]))
+        x1, st1 = s.solve(rtol=1e-8)
+        assert np.array_equal(host(x1)[0], xb[r]) and st1[0].iterations == stb[r].iterations, r
+    s.close()
