@@ -68,6 +68,24 @@ def test_solution_matches_dense_direct_solve(bc):
     assert err <= 1e-9, err
 
 
+def test_closed_off_inputs_of_the_benchmark_are_the_oracles_problem():
+    """bench.py builds the closed-off right-hand side with workloads.closed_off_rhs
+    (no oracle on the benchmark path); it is the oracle's problem bit for bit,
+    and the exact solution satisfies the discrete system up to the O(h^2)
+    truncation error."""
+    for n, k in ((17, 10.0), (33, 40.0)):
+        kk, b, u = W.closed_off_rhs(n, k)
+        lvl, b_o, u_o = O.closed_off_problem(n, k)
+        assert np.array_equal(kk, lvl.k) and np.array_equal(b, b_o) and np.array_equal(u, u_o)
+    # truncation error of the manufactured solution falls by about 4 per halving of h
+    res = []
+    for n in (17, 33):
+        kk, b, u = W.closed_off_rhs(n, 10.0)
+        lvl = Level(kk.shape, 1.0 / (n - 1), kk, DIRICHLET)
+        res.append(np.abs(O.apply_A(u.astype(np.complex128), lvl) - b).max())
+    assert 3.0 < res[0] / res[1] < 5.0, res
+
+
 def test_closed_off_problem_converges_at_second_order():
     """Manufactured solution of section 2.1, k = 10: max error drops by ~4 per halving of h."""
     errs = []
