@@ -33,7 +33,9 @@
  *   returns.  All scratch (Krylov vectors, grid hierarchy, coarse inverse,
  *   graphs) is owned by the context and allocated in hh_create / hh_set_model
  *   (the IDR(s) vectors when option "method" = 1, "idr_s" or hh_set_shadow asks
- *   for them); hh_solve and the hh_apply_* calls allocate nothing.
+ *   for them, the GMRES basis when "method" = 2 or "gmres_m" does; hh_set_model
+ *   also allocates and frees the work arrays of a device-side coarsest
+ *   inverse); hh_solve and the hh_apply_* calls allocate nothing.
  * - Streams: all device work is enqueued on the stream given to hh_create.
  *   hh_create, hh_set_model, hh_solve return after the work has completed;
  *   hh_set_sources, hh_apply_*, hh_adjoint_rhs and hh_grad_slowness2 return
