@@ -15,7 +15,7 @@ import pytest
 import oracle as O
 import workloads as W
 from oracle.discretization import DIRICHLET, SOMMERFELD, Level
-from oracle.multigrid import build_hierarchy, vcycle
+from oracle.multigrid import build_hierarchy, fcycle, vcycle
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -53,6 +53,27 @@ def test_gmres_fixed_step_iterates(bc, steps):
     ref = O.gmres(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, tol=0.0, maxit=steps)
     s = _solver(shape, h, bc, method="gmres")
     assert s.get_option("method") == 2
+    s.set_model(dev(k))
+    s.set_point_sources([src])
+    x, st = s.solve(rtol=1e-30, maxit=steps)
+    assert st[0].status == "HH_ERR_NOT_CONVERGED" and st[0].iterations == steps, st[0]
+    assert abs(st[0].relres - ref.relres) <= 1e-8 * ref.relres
+    assert relerr(host(x)[0], ref.x) <= 1e-9
+
+
+@pytest.mark.parametrize("steps", [2, 9])
+def test_gmres_fcycle_fixed_step_iterates(steps):
+    """Full GMRES with the F(1,1)-cycle preconditioner at beta2 = -1 (section 5)
+    against the oracle's gmres with its fcycle."""
+    shape = (17, 17, 33)
+    h = 1.0 / 32
+    k = np.random.default_rng(42).uniform(6.0, 14.0, shape)
+    lvl = Level(shape, h, k, SOMMERFELD)
+    hier = build_hierarchy(k, h, SOMMERFELD, beta2=-1.0)
+    src = (8, 8, 16)
+    b = O.point_source_rhs(shape, h, [src])[0]
+    ref = O.gmres(lambda x: O.apply_A(x, lvl), lambda r: fcycle(r, hier), b, tol=0.0, maxit=steps)
+    s = _solver(shape, h, SOMMERFELD, method="gmres", cycle="F", beta=(1.0, -1.0))
     s.set_model(dev(k))
     s.set_point_sources([src])
     x, st = s.solve(rtol=1e-30, maxit=steps)

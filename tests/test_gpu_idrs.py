@@ -15,7 +15,7 @@ import pytest
 import oracle as O
 import workloads as W
 from oracle.discretization import DIRICHLET, SOMMERFELD, Level, unknown_mask
-from oracle.multigrid import build_hierarchy, vcycle
+from oracle.multigrid import build_hierarchy, fcycle, vcycle
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -69,6 +69,26 @@ def test_idrs_fixed_step_iterates(bc, s, steps):
     sv.set_model(dev(k))
     sv.set_shadow(dev(P))
     assert sv.get_option("idr_s") == s and sv.get_option("method") == 1
+    sv.set_point_sources([src])
+    x, st = sv.solve(rtol=1e-14, maxit=steps)
+    assert st[0].status == "HH_ERR_NOT_CONVERGED" and st[0].iterations == steps, st[0]
+    assert relerr(host(x)[0], ref.x) <= 1e-9
+
+
+@pytest.mark.parametrize("steps", [3, 7])
+def test_idrs_fcycle_fixed_step_iterates(steps):
+    """IDR(4) with the F(1,1)-cycle preconditioner (the paper's F-cycle runs of
+    section 5) against the oracle's idrs with its fcycle."""
+    shape = (17, 17, 33)
+    k, h, src = _hetero(shape, SOMMERFELD, 34)
+    lvl = Level(shape, h, k, SOMMERFELD)
+    hier = build_hierarchy(k, h, SOMMERFELD, beta2=-1.0)
+    b = O.point_source_rhs(shape, h, [src])[0]
+    P = shadow64(4, shape, 35)
+    ref = O.idrs(lambda x: O.apply_A(x, lvl), lambda r: fcycle(r, hier), b, P, fixed_steps=steps)
+    sv = _solver(shape, h, SOMMERFELD, method="idrs", idr_s=4, cycle="F", beta=(1.0, -1.0))
+    sv.set_model(dev(k))
+    sv.set_shadow(dev(P))
     sv.set_point_sources([src])
     x, st = sv.solve(rtol=1e-14, maxit=steps)
     assert st[0].status == "HH_ERR_NOT_CONVERGED" and st[0].iterations == steps, st[0]
