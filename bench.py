@@ -107,12 +107,12 @@ def step_bytes_per_dof(prec_idx: int) -> float:
 # (profiles/wedge_129x129x257_solve.md).  Valid only for the kernel sources it
 # was measured on (kernel_source_sha); otherwise reported as null.
 TRAFFIC = {
-    ("apply_A+dots", "wedge", "mixed"): (214.1e6, "60e602cc0a601b08"),
-    ("update_xr+dots", "wedge", "mixed"): (479.6e6, "60e602cc0a601b08"),
-    ("mg_down_L0", "wedge", "mixed"): (74.3e6, "60e602cc0a601b08"),
-    ("mg_up_L0", "wedge", "mixed"): (99.1e6, "60e602cc0a601b08"),
-    ("p_update", "wedge", "mixed"): (307.9e6, "60e602cc0a601b08"),
-    ("s_update+dot", "wedge", "mixed"): (239.7e6, "60e602cc0a601b08"),
+    ("apply_A+dots", "wedge", "mixed"): (214.3e6, "3589f48a6f9934f1"),
+    ("update_xr+dots", "wedge", "mixed"): (479.6e6, "3589f48a6f9934f1"),
+    ("mg_down_L0", "wedge", "mixed"): (74.1e6, "3589f48a6f9934f1"),
+    ("mg_up_L0", "wedge", "mixed"): (99.2e6, "3589f48a6f9934f1"),
+    ("p_update", "wedge", "mixed"): (307.9e6, "3589f48a6f9934f1"),
+    ("s_update+dot", "wedge", "mixed"): (239.7e6, "3589f48a6f9934f1"),
 }
 
 

@@ -36,15 +36,18 @@ namespace hh {
 __device__ __forceinline__ int ring3(int f) { return ((f % 3) + 3) % 3; }
 __device__ __forceinline__ int ring4(int f) { return f & 3; }  // also for f = -1
 
-constexpr int DN_LANES = 256, DN_MAXW = 32, DN_MAXH = 16;
-constexpr int DN_REGION = 1280;  // fine region nodes of a down-pass tile, see dn_tile_shape()
-static_assert(DN_REGION % DN_LANES == 0, "every lane's region slots must lie inside the LDS arrays");
+constexpr int DN_LANES = 256, DN_MAXH = 16;
+// Fine region nodes staged by a down-pass workgroup: DN_REGION on the large
+// levels; the one-plane pass of the small levels may take a smaller region
+// (more workgroups, fewer region nodes per lane), see dn_region().
+constexpr int DN_REGION = 1280;
+__host__ __device__ constexpr int dn_maxw(int reg) { return reg >= 1280 ? 32 : reg >= 512 ? 16 : 8; }
 // Tile of the down pass on the coarse grid: tile_shape() with the height
-// bounded so that the fine region, (2 tw + 3)(2 th + 3) nodes, fits DN_REGION
-// (tw <= DN_MAXW leaves th >= 1).
-__host__ __device__ inline TileShape dn_tile_shape(int nx, int ny) {
-    TileShape T = tile_shape(nx, ny, DN_MAXW, DN_LANES, DN_MAXH);
-    const int hmax = (DN_REGION / (2 * T.tw + 3) - 3) / 2;
+// bounded so that the fine region, (2 tw + 3)(2 th + 3) nodes, fits reg
+// (tw <= dn_maxw(reg) leaves th >= 1).
+__host__ __device__ inline TileShape dn_tile_shape(int nx, int ny, int reg) {
+    TileShape T = tile_shape(nx, ny, dn_maxw(reg), DN_LANES, DN_MAXH);
+    const int hmax = (reg / (2 * T.tw + 3) - 3) / 2;
     if (T.th > hmax) {
         T.th = hmax;
         T.nty = (ny + T.th - 1) / T.th;
@@ -128,7 +131,7 @@ struct DownKeep {
     cx<R> c[NU];
 };
 
-template <int BC, typename TB, typename R, bool ONE>
+template <int BC, typename TB, typename R, bool ONE, int REG>
 __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
                                                       const cx<TB>* __restrict__ b,
                                                       long long b_rstride,
@@ -136,14 +139,15 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
                                                       double beta2, double omega,
                                                       cx<R>* __restrict__ bc_out,
                                                       const RhsState* st, int gate) {
-    constexpr int NU = (DN_REGION + DN_LANES - 1) / DN_LANES;
-    __shared__ cx<R> u1s[3][DN_REGION];
-    __shared__ cx<R> rs[DN_REGION];
+    static_assert(REG % DN_LANES == 0, "every lane's region slots must lie inside the LDS arrays");
+    constexpr int NU = REG / DN_LANES;
+    __shared__ cx<R> u1s[3][REG];
+    __shared__ cx<R> rs[REG];
 
     const int r = blockIdx.z;
     if (!gate_ok(st, r, gate)) return;
     const int t = threadIdx.x;
-    const TileShape T = dn_tile_shape(gc.nx, gc.ny);
+    const TileShape T = dn_tile_shape(gc.nx, gc.ny, REG);
     const int RW = 2 * T.tw + 3, RH = 2 * T.th + 3;
     const int id = xcd_tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int tz = id / gridDim.x;
@@ -198,7 +202,7 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
             const cx<R> bb = cvt<R>(w.b[k]);
             cx<R> v = jacobi_w(L, c) * bb;
             if (BC == BC_DIRICHLET && (ubnd[k] || zf)) v = czero<R>();
-            // unguarded: idx < NU * DN_LANES = DN_REGION, and slots past the
+            // unguarded: idx < NU * DN_LANES = REG, and slots past the
             // region are never read (a guard would sink the loads into it)
             dst[idx] = v;
             kp.b[k] = bb;
@@ -580,7 +584,7 @@ __global__ __launch_bounds__(RS_LANES) void k_mg_resid(Geo g, int zb, cx<R>* __r
 // launchers
 // ---------------------------------------------------------------------------
 int mg_down_blocks(const Geo& gc, int zbc) {
-    const TileShape T = dn_tile_shape(gc.nx, gc.ny);
+    const TileShape T = dn_tile_shape(gc.nx, gc.ny, DN_REGION);
     return T.ntx * T.nty * ((gc.nz + zbc - 1) / zbc);
 }
 int mg_up_blocks(const Geo& g, int zb) {
@@ -588,22 +592,52 @@ int mg_up_blocks(const Geo& g, int zb) {
     return T.ntx * T.nty * ((g.nz + zb - 1) / zb);
 }
 
+// Region of the down pass.  The z-marching pass (zbc > 1, the large levels)
+// keeps DN_REGION.  The one-plane pass runs on the small levels, where the
+// chain of region nodes a lane works through (REG / DN_LANES per plane) sets
+// the duration: a smaller region is taken when region nodes per lane times
+// waves per SIMD (rounded up; 256 CUs of 4 SIMDs) drops by at least 10 %.
+// Every node's arithmetic is the same for every region, so the output is too.
+int dn_region(const Geo& gc, int zbc, int nrhs) {
+    if (zbc != 1) return DN_REGION;
+    auto cost = [&](int reg) {
+        const TileShape T = dn_tile_shape(gc.nx, gc.ny, reg);
+        const long long waves = (long long)T.ntx * T.nty * gc.nz * nrhs * (DN_LANES / 64);
+        return (double)(reg / DN_LANES) * (double)((waves + 1023) / 1024);
+    };
+    int best = DN_REGION;
+    double cbest = cost(DN_REGION);
+    for (int reg : {512, 256}) {
+        const double cr = cost(reg);
+        if (cr < 0.9 * cbest) {
+            best = reg;
+            cbest = cr;
+        }
+    }
+    return best;
+}
+
 template <typename TB, typename R>
 void launch_mg_down(hipStream_t s, int bc, const Geo& gf, const Geo& gc, int zbc, int nrhs,
                     const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
                     cx<R>* bc_out, const RhsState* st, int gate) {
-    const TileShape T = dn_tile_shape(gc.nx, gc.ny);
+    const int reg = dn_region(gc, zbc, nrhs);
+    const TileShape T = dn_tile_shape(gc.nx, gc.ny, reg);
     dim3 grid(T.ntx * T.nty, (gc.nz + zbc - 1) / zbc, nrhs);
-#define HH_DOWN(BCV, ONEV)                                                                                \
-    hipLaunchKernelGGL((k_mg_down<BCV, TB, R, ONEV>), grid, dim3(DN_LANES), 0, s, gf, gc, zbc, b, b_rstride, \
+#define HH_DOWN(BCV, ONEV, REGV)                                                                                \
+    hipLaunchKernelGGL((k_mg_down<BCV, TB, R, ONEV, REGV>), grid, dim3(DN_LANES), 0, s, gf, gc, zbc, b, b_rstride, \
                        k2l, P.beta1, P.beta2, P.omega, bc_out, st, gate)
+#define HH_DOWN_BC(BCV)                                   \
+    if (zbc != 1) HH_DOWN(BCV, false, DN_REGION);         \
+    else if (reg == 256) HH_DOWN(BCV, true, 256);         \
+    else if (reg == 512) HH_DOWN(BCV, true, 512);         \
+    else HH_DOWN(BCV, true, DN_REGION);
     if (bc == BC_SOMMERFELD) {
-        if (zbc == 1) HH_DOWN(BC_SOMMERFELD, true);
-        else HH_DOWN(BC_SOMMERFELD, false);
+        HH_DOWN_BC(BC_SOMMERFELD)
     } else {
-        if (zbc == 1) HH_DOWN(BC_DIRICHLET, true);
-        else HH_DOWN(BC_DIRICHLET, false);
+        HH_DOWN_BC(BC_DIRICHLET)
     }
+#undef HH_DOWN_BC
 #undef HH_DOWN
 }
 
