@@ -150,6 +150,33 @@ def test_explicit_level_count_matches_oracle():
     assert relerr(host(s.apply_vcycle(dev(r)))[0], vcycle(r, hier)) <= 1e-12
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_down_pass_regions_batched_equals_single(prec):
+    """The one-plane down pass stages 1280, 512 or 256 fine nodes per
+    workgroup, chosen by the launch's size: on this grid's finest level 512
+    for one right-hand side, 256 for four and 1280 for sixteen.  Each node's
+    arithmetic is the same, so batched V-cycles equal the single ones bit for
+    bit; one of them is checked against the oracle."""
+    shape, h = (129, 65, 65), 1 / 64
+    k = hetero_k(shape, 11)
+    r = W.random_complex((16,) + shape, seed=12)
+    s = _solver(shape, h, SOMMERFELD, nrhs_max=16, prec=prec)
+    assert s.get_option("zb_down:0") == 1
+    s.set_model(dev(k))
+    single = [host(s.apply_vcycle(dev(r[i])))[0] for i in range(4)]
+    b4 = host(s.apply_vcycle(dev(r[:4])))
+    b16 = host(s.apply_vcycle(dev(r)))
+    for i in range(4):
+        assert np.array_equal(b4[i], single[i]) and np.array_equal(b16[i], single[i]), i
+    if prec == "fp64":
+        ref = vcycle(r[0], build_hierarchy(k, h, SOMMERFELD))
+        assert relerr(single[0], ref) <= 1e-12
+    else:
+        ref = vcycle(r[0].astype(np.complex64), build_hierarchy(k, h, SOMMERFELD, dtype=np.complex64))
+        assert relerr(single[0], ref.astype(np.complex128)) <= 1e-5
+    s.close()
+
+
 # --------------------------------------------------------------------------
 # solves
 # --------------------------------------------------------------------------
