@@ -150,6 +150,39 @@ def test_explicit_level_count_matches_oracle():
     assert relerr(host(s.apply_vcycle(dev(r)))[0], vcycle(r, hier)) <= 1e-12
 
 
+def _random_shapes(n, seed):
+    """Seeded grid sizes m 2^j + 1 per axis (m = 1, 3, 5, 7, so the hierarchy
+    coarsens down to a small grid) with 1..4 right-hand sides: tile splits,
+    ragged tiles and down-pass regions vary from case to case."""
+    sizes = [9, 13, 17, 21, 25, 29, 33, 41, 49, 57, 65]
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        shape = tuple(int(rng.choice(sizes)) for _ in range(3))
+        out.append((shape, int(rng.integers(1, 5))))
+    return out
+
+
+@pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
+@pytest.mark.parametrize("shape,nrhs", _random_shapes(6, 13))
+def test_vcycle_random_shapes(bc, shape, nrhs):
+    h = 1.0 / (max(shape) - 1)
+    k = hetero_k(shape, 14)
+    hier = build_hierarchy(k, h, bc)
+    r = W.random_complex((nrhs,) + shape, seed=15) * unknown_mask(shape, bc)
+    s = _solver(shape, h, bc, nrhs_max=nrhs)
+    assert s.level_shapes() == [lv.shape for lv in hier.levels]
+    s.set_model(dev(k))
+    assert relerr(host(s.apply_vcycle(dev(r))), vcycle(r, hier)) <= 1e-12, (shape, nrhs)
+    s.close()
+    m = _solver(shape, h, bc, nrhs_max=nrhs, prec="mixed")
+    m.set_model(dev(k))
+    h32 = build_hierarchy(k, h, bc, dtype=np.complex64)
+    ref32 = vcycle(r.astype(np.complex64), h32).astype(np.complex128)
+    assert relerr(host(m.apply_vcycle(dev(r))), ref32) <= 1e-5, (shape, nrhs)
+    m.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_down_pass_regions_batched_equals_single(prec):
     """The one-plane down pass stages 1280, 512 or 256 fine nodes per
