@@ -65,6 +65,28 @@ def test_fcycle_fp64(bc, shape):
     assert relerr(host(s.apply_vcycle(dev(r))), vcycle(r, hier)) <= 1e-12
 
 
+def _random_shapes(n, seed):
+    """Seeded grid sizes m 2^j + 1 per axis (m = 1, 3, 5, 7: deep hierarchies
+    with varying tails) with 1..4 right-hand sides."""
+    sizes = [9, 13, 17, 21, 25, 29, 33, 41, 49, 57, 65]
+    rng = np.random.default_rng(seed)
+    return [(tuple(int(rng.choice(sizes)) for _ in range(3)), int(rng.integers(1, 5))) for _ in range(n)]
+
+
+@pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
+@pytest.mark.parametrize("shape,nrhs", _random_shapes(4, 19))
+def test_fcycle_random_shapes(bc, shape, nrhs):
+    h = 1.0 / (max(shape) - 1)
+    k = hetero_k(shape, 20)
+    hier = build_hierarchy(k, h, bc)
+    r = W.random_complex((nrhs,) + shape, seed=21) * unknown_mask(shape, bc)
+    s = _solver(shape, h, bc, nrhs_max=nrhs, cycle="F")
+    assert s.level_shapes() == [lv.shape for lv in hier.levels]
+    s.set_model(dev(k))
+    assert relerr(host(s.apply_vcycle(dev(r))), fcycle(r, hier)) <= 1e-12, (shape, nrhs)
+    s.close()
+
+
 def test_fcycle_wedge_deep_hierarchy():
     """65 x 65 x 129 wedge: six levels, tail from level 3, so the F-cycle's
     coarse-grid solve recurses through two fused levels before the tail; with

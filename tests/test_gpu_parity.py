@@ -183,6 +183,20 @@ def test_vcycle_random_shapes(bc, shape, nrhs):
     m.close()
 
 
+@pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
+@pytest.mark.parametrize("shape,nrhs", _random_shapes(6, 16))
+def test_apply_random_shapes(bc, shape, nrhs):
+    h = 1.0 / (max(shape) - 1)
+    k = hetero_k(shape, 17)
+    lvl = Level(shape, h, k, bc)
+    x = W.random_complex((nrhs,) + shape, seed=18)
+    s = _solver(shape, h, bc, nrhs_max=nrhs)
+    s.set_model(dev(k))
+    assert relerr(host(s.apply_operator(dev(x))), O.apply_A(x, lvl)) <= 1e-13, (shape, nrhs)
+    assert relerr(host(s.apply_shifted(dev(x))), O.apply_M(x, lvl)) <= 1e-13, (shape, nrhs)
+    s.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_down_pass_regions_batched_equals_single(prec):
     """The one-plane down pass stages 1280, 512 or 256 fine nodes per
