@@ -269,6 +269,31 @@ def test_fixed_iteration_iterates(steps):
     assert relerr(host(x)[0], ref.x) <= 1e-9
 
 
+@pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
+@pytest.mark.parametrize("shape,nrhs", _random_shapes(3, 22))
+def test_fixed_iteration_random_shapes(bc, shape, nrhs):
+    """Five Bi-CGSTAB steps from x = 0 on seeded random shapes and right-hand
+    sides, all right-hand sides in one batched solve: each iterate matches the
+    oracle's single solve."""
+    steps = 5
+    h = 1.0 / (max(shape) - 1)
+    k = hetero_k(shape, 23)
+    lvl = Level(shape, h, k, bc)
+    hier = build_hierarchy(k, h, bc)
+    b = W.random_complex((nrhs,) + shape, seed=24) * unknown_mask(shape, bc)
+    s = _solver(shape, h, bc, nrhs_max=nrhs)
+    s.set_model(dev(k))
+    s.set_sources(dev(b))
+    x, st = s.solve(rtol=1e-14, maxit=steps)
+    x = host(x)
+    for i in range(nrhs):
+        ref = O.bicgstab(lambda v: O.apply_A(v, lvl), lambda v: vcycle(v, hier), b[i], tol=1e-6,
+                         fixed_iterations=steps)
+        assert st[i].status == "HH_ERR_NOT_CONVERGED" and st[i].iterations == steps, (shape, i)
+        assert relerr(x[i], ref.x) <= 1e-9, (shape, nrhs, i)
+    s.close()
+
+
 def test_solve_wedge_small_mixed_and_fp64():
     """Down-scaled wedge (33 x 33 x 65), Sommerfeld: both precisions reach the
     true relative residual 1e-6 under the oracle's operator; the mixed solution
