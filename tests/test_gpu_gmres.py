@@ -14,7 +14,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from oracle.discretization import DIRICHLET, SOMMERFELD, Level
+from oracle.discretization import DIRICHLET, SOMMERFELD, Level, unknown_mask
 from oracle.multigrid import build_hierarchy, fcycle, vcycle
 
 torch = pytest.importorskip("torch")
@@ -59,6 +59,34 @@ def test_gmres_fixed_step_iterates(bc, steps):
     assert st[0].status == "HH_ERR_NOT_CONVERGED" and st[0].iterations == steps, st[0]
     assert abs(st[0].relres - ref.relres) <= 1e-8 * ref.relres
     assert relerr(host(x)[0], ref.x) <= 1e-9
+
+
+def _random_shapes(n, seed):
+    """Seeded grid sizes m 2^j + 1 per axis (m = 1, 3, 5, 7: deep hierarchies)."""
+    sizes = [9, 13, 17, 21, 25, 29, 33, 41, 49, 57, 65]
+    rng = np.random.default_rng(seed)
+    return [tuple(int(rng.choice(sizes)) for _ in range(3)) for _ in range(n)]
+
+
+@pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
+@pytest.mark.parametrize("shape", _random_shapes(3, 43))
+def test_gmres_fixed_step_random_shapes(bc, shape):
+    """Six GMRES steps on seeded random shapes with a random right-hand side."""
+    steps = 6
+    h = 1.0 / (max(shape) - 1)
+    k = np.random.default_rng(44).uniform(6.0, 14.0, shape)
+    lvl = Level(shape, h, k, bc)
+    hier = build_hierarchy(k, h, bc)
+    b = W.random_complex(shape, seed=45) * unknown_mask(shape, bc)
+    ref = O.gmres(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, tol=0.0, maxit=steps)
+    s = _solver(shape, h, bc, method="gmres")
+    s.set_model(dev(k))
+    s.set_sources(dev(b))
+    x, st = s.solve(rtol=1e-30, maxit=steps)
+    assert st[0].status == "HH_ERR_NOT_CONVERGED" and st[0].iterations == steps, (shape, st[0])
+    assert abs(st[0].relres - ref.relres) <= 1e-8 * ref.relres, shape
+    assert relerr(host(x)[0], ref.x) <= 1e-9, shape
+    s.close()
 
 
 @pytest.mark.parametrize("steps", [2, 9])

@@ -75,6 +75,35 @@ def test_idrs_fixed_step_iterates(bc, s, steps):
     assert relerr(host(x)[0], ref.x) <= 1e-9
 
 
+def _random_shapes(n, seed):
+    """Seeded grid sizes m 2^j + 1 per axis (m = 1, 3, 5, 7: deep hierarchies)."""
+    sizes = [9, 13, 17, 21, 25, 29, 33, 41, 49, 57, 65]
+    rng = np.random.default_rng(seed)
+    return [tuple(int(rng.choice(sizes)) for _ in range(3)) for _ in range(n)]
+
+
+@pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
+@pytest.mark.parametrize("shape", _random_shapes(3, 36))
+def test_idrs_fixed_step_random_shapes(bc, shape):
+    """Six IDR(4) products on seeded random shapes with a random right-hand side."""
+    steps = 6
+    h = 1.0 / (max(shape) - 1)
+    k = np.random.default_rng(37).uniform(6.0, 14.0, shape)
+    lvl = Level(shape, h, k, bc)
+    hier = build_hierarchy(k, h, bc)
+    b = W.random_complex(shape, seed=38) * unknown_mask(shape, bc)
+    P = shadow64(4, shape, 39)
+    ref = O.idrs(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, P, fixed_steps=steps)
+    sv = _solver(shape, h, bc, method="idrs", idr_s=4)
+    sv.set_model(dev(k))
+    sv.set_shadow(dev(P))
+    sv.set_sources(dev(b))
+    x, st = sv.solve(rtol=1e-14, maxit=steps)
+    assert st[0].status == "HH_ERR_NOT_CONVERGED" and st[0].iterations == steps, (shape, st[0])
+    assert relerr(host(x)[0], ref.x) <= 1e-9, shape
+    sv.close()
+
+
 @pytest.mark.parametrize("steps", [3, 7])
 def test_idrs_fcycle_fixed_step_iterates(steps):
     """IDR(4) with the F(1,1)-cycle preconditioner (the paper's F-cycle runs of
