@@ -294,6 +294,29 @@ def test_fixed_iteration_random_shapes(bc, shape, nrhs):
     s.close()
 
 
+@pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
+@pytest.mark.parametrize("shape,nrhs", _random_shapes(3, 25))
+def test_solve_random_shapes(bc, shape, nrhs):
+    """Batched solves to relative residual 1e-6 on seeded random shapes (kh in
+    [0.1, 0.4]), FP64 and mixed: every right-hand side stops with its true
+    residual under the oracle's operator within the tolerance."""
+    h = 1.0 / (max(shape) - 1)
+    k = np.random.default_rng(26).uniform(0.1, 0.4, shape) / h
+    lvl = Level(shape, h, k, bc)
+    b = W.random_complex((nrhs,) + shape, seed=27) * unknown_mask(shape, bc)
+    for prec in ("fp64", "mixed"):
+        s = _solver(shape, h, bc, nrhs_max=nrhs, prec=prec)
+        s.set_model(dev(k))
+        s.set_sources(dev(b))
+        x, st = s.solve(rtol=1e-6, maxit=500)
+        x = host(x)
+        for i in range(nrhs):
+            assert st[i].status == "HH_OK", (shape, prec, i, st[i])
+            true_rel = np.linalg.norm(b[i] - O.apply_A(x[i], lvl)) / np.linalg.norm(b[i])
+            assert true_rel <= 1e-6, (shape, prec, i, true_rel)
+        s.close()
+
+
 def test_solve_wedge_small_mixed_and_fp64():
     """Down-scaled wedge (33 x 33 x 65), Sommerfeld: both precisions reach the
     true relative residual 1e-6 under the oracle's operator; the mixed solution
