@@ -76,6 +76,43 @@ def test_large_coarsest_cycle_parity(shape, bc, nunk):
     m.close()
 
 
+def _coarse_unknowns(shape, bc):
+    c = tuple((m - 1) // 2 + 1 for m in shape)
+    return int(np.prod(c)) if bc == SOMMERFELD else int(np.prod([m - 2 for m in c]))
+
+
+def _random_two_level_cases(n, seed):
+    """Seeded shapes whose two-level hierarchy has a coarsest grid of 257 to
+    4000 unknowns (device inverse; tail kernel or multi-workgroup solve),
+    alternating boundary conditions, 1..3 right-hand sides."""
+    sizes = [9, 13, 17, 21, 25, 29, 33, 41]
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        shape = tuple(int(rng.choice(sizes)) for _ in range(3))
+        bc = (SOMMERFELD, DIRICHLET)[len(out) % 2]
+        if 256 < _coarse_unknowns(shape, bc) <= 4000:
+            out.append((shape, bc, int(rng.integers(1, 4))))
+    return out
+
+
+@pytest.mark.parametrize("shape,bc,nrhs", _random_two_level_cases(4, 29) + _random_two_level_cases(4, 31))
+def test_large_coarsest_random_shapes(shape, bc, nrhs):
+    h = 1.0 / (max(shape) - 1)
+    k = np.random.default_rng(32).uniform(4.0, 12.0, shape)
+    hier = build_hierarchy(k, h, bc, n_levels=2)
+    r = W.random_complex((nrhs,) + shape, seed=33) * unknown_mask(shape, bc)
+    s = _solver(shape, h, bc, n_levels=2, nrhs_max=nrhs)
+    assert s.get_option("coarse_unknowns") == _coarse_unknowns(shape, bc)
+    s.set_model(dev(k))
+    assert relerr(host(s.apply_vcycle(dev(r))), vcycle(r, hier)) <= 1e-11, (shape, bc, nrhs)
+    s.close()
+    m = _solver(shape, h, bc, n_levels=2, nrhs_max=nrhs, prec="mixed")
+    m.set_model(dev(k))
+    assert relerr(host(m.apply_vcycle(dev(r))), vcycle(r, hier)) <= 1e-5, (shape, bc, nrhs)
+    m.close()
+
+
 def test_large_coarsest_three_levels_and_model_change():
     """Three levels down to a 17^3 coarsest grid (the fused passes on level 1
     feed the multi-workgroup solve), V- and F-cycle, and a new model rebuilds
