@@ -519,6 +519,27 @@ def test_adjoint_kernels_match_oracle():
     assert relerr(grad, ref) <= 1e-13
 
 
+@pytest.mark.parametrize("shape,nrhs", _random_shapes(4, 34))
+def test_adjoint_kernels_random_shapes(shape, nrhs):
+    """The adjoint right-hand side and the pointwise gradient (summed over the
+    right-hand sides) on seeded random shapes."""
+    from oracle.adjoint import adjoint_gradient_pointwise, adjoint_rhs
+
+    rng = np.random.default_rng(35)
+    s_sl = rng.uniform(1 / 3000**2, 1 / 1500**2, shape)
+    u = W.random_complex((nrhs,) + shape, 36)
+    w = W.random_complex((nrhs,) + shape, 37)
+    g = W.random_complex((nrhs,) + shape, 38)
+    omega, h = 3000.0, 0.1
+    s = _solver(shape, h, SOMMERFELD, nrhs_max=nrhs)
+    s.set_model(dev(omega * np.sqrt(s_sl)))
+    assert relerr(host(s.adjoint_rhs(dev(g))), adjoint_rhs(g, shape)) <= 1e-15, (shape, nrhs)
+    grad = host(s.grad_slowness2(dev(u), dev(w), dev(s_sl), omega))
+    ref = sum(adjoint_gradient_pointwise(u[r], w[r], s_sl, omega, h) for r in range(nrhs))
+    assert relerr(grad, ref) <= 1e-13, (shape, nrhs)
+    s.close()
+
+
 def test_adjoint_gradient_autograd_vs_oracle_and_fd():
     """17^3 version of the adjoint workload through torch.autograd."""
     from oracle.adjoint import misfit_and_gradient, sample, solve_forward
