@@ -101,32 +101,37 @@ def test_sommerfeld_zero_wavenumber_annihilates_constants():
     assert np.abs(y).max() <= 1e-12
 
 
-def test_matrix_free_equals_rowwise_assembly():
-    """Row-by-row sparse assembly of section 2.4 (7-point stencil, eliminated ghost
-    points: the inward neighbour's coupling doubles and the diagonal gains
-    -2ik/h per missing neighbour) against the matrix-free apply of Algorithm 2."""
+def rowwise_assembly(lvl, shift=1.0):
+    """Sparse matrix of -Laplace_h - shift k^2 I assembled row by row from section
+    2.4 (7-point stencil; at a Sommerfeld boundary the ghost point of eq.
+    elimination is replaced by mirror + 2 h i k u_j, so the inward neighbour's
+    coupling doubles and the diagonal gains -2ik/h per missing neighbour).
+    Dirichlet: rows and columns of the interior unknowns only, indexed like the
+    full grid (boundary rows are empty)."""
     import scipy.sparse as sp
 
-    shape = (4 + 1, 3 + 2, 7)
-    lvl = _random_level(shape, SOMMERFELD, seed=5)
-    nz, ny, nx = shape
+    nz, ny, nx = lvl.shape
     h = lvl.h
-    idx = np.arange(nz * ny * nx).reshape(shape)
+    idx = np.arange(nz * ny * nx).reshape(lvl.shape)
     rows, cols, vals = [], [], []
     for z in range(nz):
         for y in range(ny):
             for x in range(nx):
                 j = idx[z, y, x]
                 kk = lvl.k[z, y, x]
-                diag = 6.0 / h**2 - kk**2
+                interior = 0 < z < nz - 1 and 0 < y < ny - 1 and 0 < x < nx - 1
+                if lvl.bc == DIRICHLET and not interior:
+                    continue
+                diag = 6.0 / h**2 - shift * kk**2
                 for axis, pos, n in ((0, z, nz), (1, y, ny), (2, x, nx)):
                     for step in (-1, 1):
+                        nb = [z, y, x]
                         q = pos + step
                         if 0 <= q < n:
-                            nb = [z, y, x]
                             nb[axis] = q
+                            if lvl.bc == DIRICHLET and not (0 < q < n - 1):
+                                continue  # a boundary neighbour carries g = 0
                         else:
-                            nb = [z, y, x]
                             nb[axis] = pos - step
                             diag += -2j * kk / h
                         rows.append(j)
@@ -135,11 +140,47 @@ def test_matrix_free_equals_rowwise_assembly():
                 rows.append(j)
                 cols.append(j)
                 vals.append(diag)
-    A = sp.csr_matrix((vals, (rows, cols)), shape=(idx.size, idx.size))
+    return sp.csr_matrix((vals, (rows, cols)), shape=(idx.size, idx.size))
+
+
+@pytest.mark.parametrize("op", ["A", "M"])
+@pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
+def test_matrix_free_equals_rowwise_assembly(op, bc):
+    """Row-by-row sparse assembly of section 2.4 (and of M_h with the shift
+    (1 + 0.5i) k^2 of section 3.3 in the volume term only) against the
+    matrix-free apply of Algorithm 2."""
+    shape = (4 + 1, 3 + 2, 7)
+    lvl = _random_level(shape, bc, seed=5)
+    shift = 1.0 if op == "A" else (1 + 0.5j)
+    A = rowwise_assembly(lvl, shift)
     rng = np.random.default_rng(6)
-    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
-    y = O.apply_A(x, lvl)
+    x = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * O.unknown_mask(shape, bc)
+    y = O.apply_A(x, lvl) if op == "A" else O.apply_M(x, lvl)
     assert np.abs(A @ x.ravel() - y.ravel()).max() <= 1e-13 * np.abs(y).max()
+
+
+@pytest.mark.parametrize("beta", [(1.0, -0.5), (1.0, -1.0), (0.7, 0.3)])
+def test_diag_M_equals_rowwise_diagonal(beta):
+    """The Jacobi diagonal D = diag(M_h) (section 3.4.1) against the diagonal of the
+    row-wise assembled M_h: on a Sommerfeld grid every node kind occurs (interior,
+    faces n_j = 1, edges n_j = 2, corners n_j = 3), each with its -2ik/h per
+    missing neighbour; Dirichlet interior rows have no boundary term."""
+    b1, b2 = beta
+    shift = complex(b1, -b2)
+    shape = (5, 6, 7)
+    for bc in (SOMMERFELD, DIRICHLET):
+        lvl = _random_level(shape, bc, seed=9)
+        ref = rowwise_assembly(lvl, shift).diagonal().reshape(shape)
+        d = O.diag_M(lvl, b1, b2)
+        mask = O.unknown_mask(shape, bc)
+        assert np.abs(d[mask] - ref[mask]).max() <= 1e-14 * np.abs(ref[mask]).max()
+        if bc == SOMMERFELD:
+            nj = boundary_directions(shape)
+            assert {0, 1, 2, 3} <= set(np.unique(nj))
+            # the boundary term is what separates the node kinds: with it removed
+            # (or its sign flipped) every boundary row would differ
+            plain = 6.0 / lvl.h**2 - shift * lvl.k**2
+            assert np.all(np.abs(d - plain)[nj > 0] > 1.0 / lvl.h)
 
 
 def test_single_precision_apply_tracks_double():
