@@ -1,37 +1,43 @@
 """Benchmark: DoF-iterations/s of CSLP-preconditioned Bi-CGSTAB on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
-                    [--workload wedge|cube513|batched|beta2_sweep|closedoff129]
+                    [--workload cube513|wedge|batched|beta2_sweep|closedoff129]
 
 One step = one complete solve to ||b - A x|| / ||b|| <= 1e-6 of the workload
 (model and sources resident in HBM before the timed region).  The default
-workload is the three-layer wedge, 129 x 129 x 257 nodes (4,276,737
-unknowns, h = 4.6875 m, f = 10 Hz, first-order Sommerfeld boundaries, one
-point source at the centre of the top face).  ``value`` is the mixed-precision
-solve (complex64 V-cycle inside complex128 Bi-CGSTAB); the plain complex128
-solve is timed the same way and reported under ``fp64``.
+workload is the constant-k unit cube on 513^3 nodes (135,005,697 unknowns,
+h = 1/512, k = 160 so kh = 0.3125, first-order Sommerfeld boundaries, 8
+multigrid levels down to 5^3, one point source at the centre node): at 2.16 GB
+per complex128 vector nothing of a step stays in the 256 MB Infinity Cache.
+``value`` is the mixed-precision solve (complex64 V-cycle inside complex128
+Bi-CGSTAB), K timed solves after W warm-up solves; the plain complex128 solve
+is timed the same way (on the cube at most 5 timed solves after at most one
+warm-up: its step count is deterministic) and reported under ``fp64``.
 
 DoF-iterations/s = unknowns x Bi-CGSTAB iterations (half step = 0.5, summed
 over right-hand sides) / solve time.
 
 ``roofline`` reports the kernel with the largest share of an iteration.  After
-the timed solves the same number of solves of the same workload run with the
-library's event tracing on: HIP events on the solver's stream around every
-fine-level launch of every step (the steps launched directly instead of
-replayed as a graph; only check windows in which every right-hand side kept
-iterating count).  Each step of those solves also brackets one launch of the
-operator apply with every workgroup gated off: the average of that bracket
-(``event_bracket_ms``, the event pair's dispatch and completion latency) is
-subtracted from each kernel's average bracketed duration (``avg_ms_bracketed``)
-to give ``avg_ms``, the kernel's own duration.  ``achieved`` = the kernel's
-algorithmic bytes per launch / ``avg_ms``, against 8 TB/s HBM3E peak;
-``launches`` is the number of launches behind the average.
+the timed solves a few more solves of the same workload (2 on the cube, else K)
+run with the library's event tracing on: HIP events on the solver's stream
+around every fine-level launch of every step (the steps launched directly
+instead of replayed as a graph; only check windows in which every right-hand
+side kept iterating count).  ``avg_ms`` is the kernel's average event-bracketed
+duration over those launches (``launches`` of them), nothing subtracted, so it
+is comparable with the per-dispatch mean of a rocprofv3 kernel trace of the
+same command; ``event_bracket_ms`` (events around one launch whose workgroups
+all exit at once) is reported beside it as the bracket's own cost.
+``achieved`` = the kernel's algorithmic bytes per launch / ``avg_ms``, against
+8 TB/s HBM3E peak.
 ``hbm_per_iteration``: the algorithmic bytes of one whole Bi-CGSTAB step as
 built (every kernel of KERNELS, the coarse multigrid levels at 1/7 of the
 level-0 passes) per DoF, times DoF x iterations / solve time: the whole
 iteration's HBM rate, beside the dominant kernel's.
-``cpu_baseline`` times the CPU oracle on a bounded sample (a few Bi-CGSTAB
-steps of the same workload) on the host.
+``cpu_baseline`` times the CPU oracle on a bounded sample of the workload on
+the host (NumPy, BLAS held to one thread), set-up excluded: one complex128
+Bi-CGSTAB step of the 513^3 cube itself (8 steps of the wedge).  If the host
+lacks the free memory (about 400 B per node), the sample is the largest
+2^j + 1 cube with the same kh that fits, and ``sample`` says so.
 
 ``variants`` (wedge workload): the same solves with the paper's other
 solver settings, both precisions, timed the same way: Bi-CGSTAB with one
@@ -264,30 +270,65 @@ def kernel_roofline(solver, nrhs, prec_idx, n_nodes, x, solves):
     """Per-kernel average launch duration inside real solves of the workload:
     `solves` solves with the library's event tracing on (HIP events on the
     solver's stream around every fine-level launch, steps launched directly
-    instead of replayed as a graph), then algorithmic bytes / duration."""
+    instead of replayed as a graph), then algorithmic bytes / duration.  The
+    durations are the event-bracketed averages as measured; the bracket's own
+    cost (events around a launch whose workgroups all exit at once) is
+    returned beside them, not subtracted."""
     solver.set_option("trace", 1)
     for _ in range(solves):
         solver.solve(rtol=1e-6, out=x)
     ms, cnt = solver.kernel_times()
     solver.set_option("trace", 0)
-    bracket = ms[6]  # events around an empty launch: the bracket's own cost
+    bracket = ms[6]
     rows = {}
     for kid, (name, per_iter, nbytes) in KERNELS.items():
         algo = nbytes[prec_idx] * n_nodes * nrhs
-        net = ms[kid] - bracket
-        rows[name] = {"ms": net, "ms_bracketed": ms[kid], "launches": cnt[kid], "per_iter": per_iter,
-                      "bytes": int(algo), "GBs": algo / (net * 1e-3) / 1e9 if net > 0 else None}
+        rows[name] = {"ms": ms[kid], "launches": cnt[kid], "per_iter": per_iter,
+                      "bytes": int(algo), "GBs": algo / (ms[kid] * 1e-3) / 1e9 if ms[kid] > 0 else None}
     dom = max(rows, key=lambda k: rows[k]["ms"] * rows[k]["per_iter"])
     return dom, rows, bracket
 
 
+# the oracle's peak host memory per node during one Bi-CGSTAB step (complex128
+# Krylov vectors, the multigrid levels and NumPy's temporaries: 292 B measured
+# on a 257^3 cube), with a margin
+ORACLE_BYTES_PER_NODE = 400
+# largest cube the oracle sample runs on (one complex128 step of the oracle
+# grows linearly with the nodes: 0.7 s at 129^3, 5.7 s at 257^3 on a 16-core
+# host of the GPU machine, so about 46 s at 513^3)
+ORACLE_MAX_CUBE = 513
+
+
 def cpu_baseline(wl, nodes, n_iter):
+    """The CPU oracle on a bounded sample of the workload: n_iter complex128
+    Bi-CGSTAB steps (set-up excluded), BLAS held to one thread.  For a cube
+    larger than ORACLE_MAX_CUBE, or than the host's free memory holds, the
+    sample is the largest 2^j + 1 cube below it with the same kh, boundary
+    condition and centre source (one level fewer per halving); the oracle's
+    time per DoF-iteration does not depend on the grid size."""
     import oracle as O
+    import workloads as W
     from oracle.discretization import Level
     from oracle.multigrid import build_hierarchy, vcycle
 
     from threadpoolctl import threadpool_limits
 
+    note = ""
+    if wl.shape[0] == wl.shape[1] == wl.shape[2] and wl.shape[0] > 65 and np.all(wl.k == wl.k.flat[0]):
+        import psutil
+
+        avail = psutil.virtual_memory().available
+        n, levels = wl.shape[0], wl.n_levels
+        kh = float(wl.k.flat[0]) * wl.h
+        while n > 65 and (n > ORACLE_MAX_CUBE or n ** 3 * ORACLE_BYTES_PER_NODE > avail):
+            n, levels = (n - 1) // 2 + 1, levels - 1
+        if n != wl.shape[0]:
+            note = (f"; sample on the {n}^3 cube with the same kh = {kh:g}, boundary condition and centre "
+                    f"source ({levels} levels) in place of {wl.shape[0]}^3, where one oracle step takes "
+                    f"about {(wl.shape[0] - 1) ** 3 // (n - 1) ** 3} times as long "
+                    f"(host memory free: {avail / 2**30:.0f} GiB)")
+            wl = W.constant_cube(n, kh * (n - 1), wl.bc, n_levels=levels)
+            nodes = wl.sources
     lvl = Level(wl.shape, wl.h, wl.k, wl.bc)
     hier = build_hierarchy(wl.k, wl.h, wl.bc, n_levels=wl.n_levels)
     b = O.point_source_rhs(wl.shape, wl.h, nodes[:1])[0]
@@ -298,8 +339,8 @@ def cpu_baseline(wl, nodes, n_iter):
         O.bicgstab(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, fixed_iterations=n_iter)
         dt = time.perf_counter() - t0
     return {"value": dof(wl) * n_iter / dt, "unit": "DoF-iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_iter} complex128 Bi-CGSTAB steps of the same workload, one source, "
-                      f"NumPy/SciPy single thread on the host ({dt:.1f} s)"}
+            "sample": f"{n_iter} complex128 Bi-CGSTAB step(s) of {wl.name}, one source, NumPy/SciPy "
+                      f"single thread on a host of {os.cpu_count()} cores ({dt:.1f} s){note}"}
 
 
 def beta2_sweep(args, wl, nodes, desc):
@@ -379,7 +420,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="wedge", choices=["wedge", "cube513", "batched", "beta2_sweep", "closedoff129"])
+    ap.add_argument("--workload", default="cube513",
+                    choices=["cube513", "wedge", "batched", "beta2_sweep", "closedoff129"])
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the F-cycle and IDR(4) solves of the wedge")
     ap.add_argument("--cycle", default="V", choices=["V", "F"],
@@ -388,8 +430,14 @@ def main():
                     help="Krylov method of the headline solves (default bicgstab; idrs = IDR(4); gmres = full GMRES)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=8)
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=None,
+                    help="oracle Bi-CGSTAB steps of the cpu_baseline sample (default 1 on the cube, 8 otherwise)")
+    ap.add_argument("--trace-solves", type=int, default=None,
+                    help="event-traced solves behind the roofline (default 2 on the cube, else --steps)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch shapes with hh_autotune first (default for --workload batched)")
+    ap.add_argument("--autotune-cache", default=None,
+                    help="JSON cache file of hh_autotune (read first, updated after measuring)")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 1 GiB device buffer 3 times (reference kernel for HBM counters)")
@@ -422,29 +470,37 @@ def main():
     n_nodes = int(np.prod(wl.shape))
     k = torch.from_numpy(wl.k).cuda()
 
+    tuned = {}
+
     def make(prec, method=None, cycle=None):
         s = Solver(wl.shape, wl.h, bc=wl.bc, prec=prec, n_levels=wl.n_levels, nrhs_max=nrhs,
                    cycle=cycle or args.cycle, method=method or args.method)
         s.set_model(k)
         s.set_point_sources(nodes)
-        if args.autotune:
-            s.autotune(nrhs)
+        if args.autotune or args.workload == "batched":
+            tuned[prec] = s.autotune(args.autotune_cache)
         return s
 
-    log = (lambda *a: print(*a, file=sys.stderr, flush=True)) if args.verbose else (lambda *a: None)
+    # progress lines on stderr (stdout carries only the result line)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     results = {}
     solutions = {}
+    cube = args.workload == "cube513"
+    traced = args.trace_solves if args.trace_solves is not None else (2 if cube else max(1, args.steps))
     for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
         s = make(prec)
-        x, stats, times, iters = run_solves(s, args.steps, args.warmup)
+        # the cube's FP64 comparison: at most 5 timed solves after at most one
+        # warm-up (its step count is deterministic), to keep the GPU time short
+        reps, warm = ((min(args.steps, 5), min(args.warmup, 1)) if cube and prec == "fp64"
+                      else (args.steps, args.warmup))
+        x, stats, times, iters = run_solves(s, reps, warm)
         t = float(np.sum(times))
         it = float(np.mean(iters))
         # the library's own true residual ||b - A x|| / ||b|| after the solve (the
         # GPU tests hold it to the oracle's operator within 1e-9)
         rel = [s_.relres_true for s_ in stats]
         if args.method == "bicgstab":
-            dom, rows, bracket = kernel_roofline(s, nrhs, 0 if prec == "fp64" else 1, n_nodes, x,
-                                                 max(1, args.steps))
+            dom, rows, bracket = kernel_roofline(s, nrhs, 0 if prec == "fp64" else 1, n_nodes, x, traced)
         else:  # the library's in-solve kernel tracing covers the Bi-CGSTAB step only
             dom, rows, bracket = None, {}, None
         bpd = step_bytes_per_dof(0 if prec == "fp64" else 1)
@@ -453,7 +509,8 @@ def main():
             "hbm_per_iteration": {"bytes_per_dof": round(bpd, 1), "GBs": step_gbs,
                                   "frac": step_gbs / HBM_PEAK_GBS} if args.method == "bicgstab" else None,
             "value": dof(wl) * float(np.sum(iters)) / t,
-            "ms_per_step": 1e3 * t / args.steps,
+            "ms_per_step": 1e3 * t / reps,
+            "steps": reps, "warmup": warm,
             "iterations": it,
             "matvecs": int(sum(st.matvecs for st in stats)),
             "relres_true_max": max(rel),
@@ -461,7 +518,8 @@ def main():
             "block": s.get_option("block"), "zb": s.get_option("zb"),
             "dominant": dom, "kernels": rows, "event_bracket_ms": bracket,
         }
-        log(prec, json.dumps(results[prec]))
+        log(prec, json.dumps(results[prec]) if args.verbose else
+            f"{results[prec]['ms_per_step']:.1f} ms per solve, {it} steps")
         s.close()
         solutions[prec] = x
         del x
@@ -502,8 +560,8 @@ def main():
         roofline = {"bound": "hbm", "kernel": dom, "achieved": row["GBs"], "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": row["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
                     "algorithmic_bytes_per_launch": row["bytes"], "avg_ms": row["ms"],
-                    "avg_ms_bracketed": row["ms_bracketed"], "event_bracket_ms": head["event_bracket_ms"],
-                    "launches": row["launches"], "frac_of_streaming_reference": row["GBs"] / ref["GBs"]}
+                    "event_bracket_ms": head["event_bracket_ms"], "launches": row["launches"],
+                    "traced_solves": traced, "frac_of_streaming_reference": row["GBs"] / ref["GBs"]}
     line = {
         "metric": METRIC,
         "value": head["value"],
@@ -531,6 +589,7 @@ def main():
     if "fp64" in results:
         f = results["fp64"]
         line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "iterations": f["iterations"],
+                        "steps": f["steps"], "warmup": f["warmup"],
                         "hbm_per_iteration": f["hbm_per_iteration"],
                         "relres_true_max": f["relres_true_max"], "dominant": f["dominant"],
                         "kernels": {k_: {"ms": v["ms"], "GBs": v["GBs"] and round(v["GBs"], 1)}
@@ -540,10 +599,16 @@ def main():
                                                / (head["ms_per_step"] / head["iterations"]))
     if ref_err is not None:
         line["error_vs_fp64_reference"] = ref_err
+    if tuned:
+        line["autotuned_shapes"] = tuned
     if fres is not None:
         line["variants"] = fres
-    if not args.no_cpu and args.workload != "cube513":
-        line["cpu_baseline"] = cpu_baseline(wl, nodes, args.cpu_iters)
+    if not args.no_cpu:
+        log("cpu_baseline: timing the oracle")
+        del k
+        torch.cuda.empty_cache()
+        n_iter = args.cpu_iters if args.cpu_iters is not None else (1 if cube else 8)
+        line["cpu_baseline"] = cpu_baseline(wl, nodes, n_iter)
     print(json.dumps(line), flush=True)
 
 
