@@ -478,7 +478,8 @@ def main():
         s.set_model(k)
         s.set_point_sources(nodes)
         if args.autotune or args.workload == "batched":
-            tuned[prec] = s.autotune(args.autotune_cache)
+            shapes = s.autotune(args.autotune_cache)
+            tuned.setdefault(prec, shapes)  # the timed solves' shapes
         return s
 
     # progress lines on stderr (stdout carries only the result line)

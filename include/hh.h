@@ -79,6 +79,10 @@ typedef struct {
     double beta1;     /* CSLP: M = -Laplace - (beta1 - beta2 i) k^2 ; paper default 1 */
     double beta2;     /* paper default -0.5 (section 3.3) */
     double omega;     /* damped-Jacobi weight, paper value 0.8 (section 3.4.1) */
+    int nu_pre;       /* damped-Jacobi sweeps before the coarse-grid correction (nu_1 of
+                         Algorithm 1); the paper uses 1 and 1 is the only value the fused
+                         passes implement: any other is HH_ERR_ARG */
+    int nu_post;      /* sweeps after it (nu_2 of Algorithm 1); likewise only 1 */
     int n_levels;     /* multigrid levels incl. the finest; 0 = coarsen while the
                          next grid keeps >= 3 nodes on every axis.  (n_d - 1) must
                          be divisible by 2^(n_levels-1) on every axis. */
@@ -94,10 +98,14 @@ typedef struct {
     double relres_true; /* ||b - A x|| / ||b|| recomputed at exit */
     int status;         /* hh_status of this right-hand side */
     int restarts;       /* restarts after a true-residual check missed rtol */
+    double ms;          /* duration of the whole hh_solve call on the context stream
+                           (HIP events around all of its device work), in milliseconds;
+                           the same for every right-hand side of the call */
 } hh_stats;
 
 /* Fill *cfg with the paper's defaults (beta1 = 1, beta2 = -0.5, omega = 0.8,
- * Sommerfeld, FP64, n_levels = 0, nrhs_max = 1) for an nx x ny x nz grid. */
+ * nu_pre = nu_post = 1, Sommerfeld, FP64, n_levels = 0, nrhs_max = 1) for an
+ * nx x ny x nz grid. */
 void hh_default_config(hh_config* cfg, int nx, int ny, int nz, double h);
 
 /* Validate cfg, allocate every device buffer for up to nrhs_max right-hand sides
@@ -129,6 +137,13 @@ hh_status hh_level_shape(const hh_ctx* ctx, int l, int* nx, int* ny, int* nz, in
  * inverse.  HH_ERR_NUMERIC if k holds NaN/Inf or a negative value, or if the
  * coarsest M is singular. */
 hh_status hh_set_model(hh_ctx* ctx, const double* k);
+
+/* The same model given as squared slowness s = 1/c^2 (device array (nz, ny, nx)
+ * of doubles, read once) at angular frequency omega: k_j = omega sqrt(s_j)
+ * (section 2: k = 2 pi f / c) is formed on the device, then everything
+ * hh_set_model does follows.  HH_ERR_ARG for omega <= 0 or non-finite,
+ * HH_ERR_NUMERIC if s holds NaN/Inf or a negative value. */
+hh_status hh_set_model_slowness2(hh_ctx* ctx, const double* s, double omega);
 
 /* Copy nrhs right-hand sides (nrhs, nz, ny, nx) complex128 into the context. */
 hh_status hh_set_sources(hh_ctx* ctx, const void* b, int nrhs);
@@ -214,6 +229,19 @@ hh_status hh_set_shadow(hh_ctx* ctx, const void* P, int s);
  * level's multigrid down / up pass, 0 = automatic), "zb_down:<l>" / "zb_up:<l>"
  * (the same for level l, 0 <= l < n_levels - 1; levels run by the single-workgroup
  * tail kernel ignore it).  A level outside that range is HH_ERR_ARG.
+ * "dn_region:<l>" (fine region nodes staged per workgroup by the down pass from
+ * level l when it runs one coarse plane per workgroup: 256, 512 or 1280;
+ * 0 = automatic, the default; the result does not depend on it).
+ * "coarse_solver" (0 = exact: the dense inverse of the coarsest M, default;
+ * 1 = the paper's iterative coarsest solve (end of section 3.4.5, section 4.2):
+ * full GMRES on the coarsest M without preconditioner from a zero initial
+ * guess to relative residual 10^-"coarse_tol_e" (default 11, the paper's 1e-11,
+ * section 5; 1..15), complex128 in both precisions, one workgroup per
+ * right-hand side; the fused passes then run down to the coarsest level;
+ * allocates (coarse_m + 2) coarsest-grid vectors per right-hand side;
+ * HH_ERR_ARG for a coarsest grid of more than 8192 nodes), "coarse_m"
+ * (Arnoldi steps per GMRES cycle, 1..100, default 100), "coarse_cycles"
+ * (cycles, i.e. restarts + 1, at most; 1..1000, default 10).
  * "cycle" (0 = V(1,1)-cycle, default; 1 = F(1,1)-cycle, section 3.4.5, which
  * visits level l >= 1 l + 1 times per application instead of once and adds one
  * residual pass on each level from 1 to the second coarsest; other values are
@@ -231,7 +259,11 @@ hh_status hh_set_shadow(hh_ctx* ctx, const void* P, int s);
  * launched directly and not timed.
  * hh_get_option also reports "n_levels", "coarse_unknowns", "tail_first" (first
  * level run by the tail kernel, or the coarsest level when the multi-workgroup
- * coarsest solve is in use) and the z-planes in use under the same names. */
+ * coarsest solve is in use), "autotune_source" (0 = no hh_autotune call yet,
+ * 1 = shapes taken from the cache file, 2 = measured), "coarse_steps" (Arnoldi
+ * steps of the last coarse GMRES solve, the largest over the right-hand sides;
+ * waits for the stream) and the shapes in use
+ * under the same names ("dn_region:<l>" then gives the region in use). */
 hh_status hh_set_option(hh_ctx* ctx, const char* name, long long value);
 hh_status hh_get_option(const hh_ctx* ctx, const char* name, long long* value);
 
@@ -265,13 +297,29 @@ hh_status hh_time_kernel(hh_ctx* ctx, int which, int nrhs, int reps, float* ms_a
  * of 7 entries. */
 hh_status hh_kernel_times(const hh_ctx* ctx, double* ms_avg, long long* launches);
 
-/* Sweep the workgroup shape of the fine-grid stencil and Krylov kernels
- * (lanes 128 / 256 / 512 x z-planes 2 / 4 / 8; default 256 x 4) and keep the
- * fastest: each shape runs the first Bi-CGSTAB steps of the current sources
- * (nrhs of them must be set) from a fresh start, replayed as a graph and timed
- * with HIP events on the context stream.  Leaves the iterate undefined; the
- * next hh_solve starts afresh. */
-hh_status hh_autotune(hh_ctx* ctx, int nrhs);
+/* Pick the launch shapes of the solve by timing it: the lanes of
+ * the flat Krylov kernels (128 / 256 / 512) with the z-planes per workgroup of
+ * the operator apply (2 / 4 / 8), then, level by level, the z-planes per
+ * workgroup of every fused multigrid down pass (1, 2, 4, 8, 16) and up pass
+ * (2, 4, 8, 16 where the built-in rule marches over several planes; a level
+ * where the rule runs the one-plane form keeps it, since the two forms round
+ * some nodes differently) and the region of the one-plane down passes
+ * (256 / 512 / 1280 fine nodes).  Each
+ * candidate runs the first Bi-CGSTAB steps of the current sources (set by
+ * hh_set_*sources; all of them) from a fresh start, replayed as a graph and
+ * timed with HIP events on the context stream; a candidate replaces the
+ * current choice only when it is at least 1 % faster (coordinate descent from
+ * the built-in rule).  The multigrid shapes it picks do not change any result
+ * bit; the flat-kernel shape changes the rounding of the inner products only.
+ * cache_json_path (may be NULL: no cache): a JSON object file mapping a key
+ * made of the device architecture, grid, boundary condition, precision,
+ * right-hand-side count, cycle and level count to the chosen shapes; an entry
+ * for this context's key is applied without measuring, a new one is added and
+ * the file rewritten (written to "<path>.tmp", then renamed).  HH_ERR_ARG if
+ * the file exists but is not such an object or an entry holds a shape outside
+ * the sets above; HH_ERR_STATE without sources.  Leaves the iterate undefined;
+ * the next hh_solve starts afresh. */
+hh_status hh_autotune(hh_ctx* ctx, const char* cache_json_path);
 
 #ifdef __cplusplus
 }

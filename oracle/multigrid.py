@@ -21,8 +21,11 @@ Readings where the paper is silent (also in the design notes):
   domain takes the value of its mirror image (even reflection), so constants
   are preserved; Dirichlet coarse boundary nodes are not unknowns (zero);
 * zero initial guess on every level, so one V-cycle is a fixed linear map;
-* coarsest level: solved exactly (sparse LU of the rediscretised M), in place
-  of the paper's GMRES to 1e-11 -- the two agree to about 1e-11;
+* coarsest level: solved exactly (sparse LU of the rediscretised M) by
+  default, or, as the paper does (end of section 3.4.5, section 4.2 and the
+  coarse stopping criterion of section 5), by full GMRES without
+  preconditioning from a zero initial guess to relative residual 1e-11
+  (``coarse="gmres"``), always in complex128; the two agree to about 1e-11;
 * level count: coarsen while the next level keeps at least 3 nodes per axis,
   or a given count, or (``paper17``) while every axis has more than 17 nodes,
   which reproduces the paper's 17^3 and 41 x 41 x 13 coarsest grids.
@@ -43,6 +46,7 @@ from .discretization import (
     diag_M,
     unknown_mask,
 )
+from .krylov import gmres
 
 
 def coarsen_shape(shape):
@@ -87,6 +91,10 @@ class Hierarchy:
     coarse_lu: object = None
     coarse_mask: np.ndarray = None
     diags: list = field(default_factory=list)
+    coarse: str = "exact"          # coarsest solve: "exact" (sparse LU) or "gmres"
+    coarse_tol: float = 1e-11      # relative residual of the coarsest GMRES
+    coarse_maxit: int = 200        # Arnoldi steps of the coarsest GMRES (no restart)
+    coarse_level64: Level = None   # the coarsest level in double precision (for GMRES)
 
     @property
     def coarsest(self):
@@ -100,19 +108,25 @@ def _level_in_precision(lvl: Level, dtype):
 
 
 def build_hierarchy(k, h, bc, n_levels=0, rule="min3", beta1=1.0, beta2=-0.5,
-                    omega=0.8, dtype=np.complex128) -> Hierarchy:
+                    omega=0.8, dtype=np.complex128, coarse="exact", coarse_tol=1e-11,
+                    coarse_maxit=200) -> Hierarchy:
     """Levels by injection of k, then a sparse LU of the coarsest M.
 
     dtype complex64 gives the mixed-precision variant: k^2, M, D and the
-    coarse factorisation in single precision.
+    coarse factorisation in single precision.  coarse="gmres" solves the
+    coarsest level by full GMRES in complex128 instead (see coarse_gmres).
     """
+    if coarse not in ("exact", "gmres"):
+        raise ValueError("coarse must be 'exact' or 'gmres'")
     shapes = level_shapes(k.shape, n_levels, rule)
     levels = [Level(shapes[0], h, np.asarray(k, dtype=np.float64), bc)]
     for s in shapes[1:]:
         prev = levels[-1]
         levels.append(Level(s, prev.h * 2.0, prev.k[::2, ::2, ::2].copy(), bc))
+    coarsest64 = levels[-1]
     levels = [_level_in_precision(lv, dtype) for lv in levels]
-    hier = Hierarchy(levels, beta1, beta2, omega, dtype)
+    hier = Hierarchy(levels, beta1, beta2, omega, dtype, coarse=coarse, coarse_tol=coarse_tol,
+                     coarse_maxit=coarse_maxit, coarse_level64=coarsest64)
     hier.diags = [diag_M(lv, beta1, beta2, dtype) for lv in levels]
     hier.coarse_mask = unknown_mask(hier.coarsest.shape, bc)
     hier.coarse_lu = _factor_coarsest(hier)
@@ -146,8 +160,31 @@ def _factor_coarsest(hier: Hierarchy):
     return splu(_assemble_coarsest(hier))
 
 
+def coarse_gmres(b, hier: Hierarchy):
+    """The paper's coarsest-grid solve: full GMRES on M_c (no preconditioner,
+    no restart), zero initial guess, stopped when the relative residual
+    ||b - M_c e|| / ||b|| (the Arnoldi estimate |g_{j+1}| / ||b||) reaches
+    hier.coarse_tol, or after hier.coarse_maxit steps.  Always complex128 (the
+    operator from the double-precision k of the coarsest level); one
+    right-hand side (nz, ny, nx).  Returns (e, Arnoldi steps)."""
+    lvl = hier.coarse_level64
+    mask = hier.coarse_mask
+    b64 = np.asarray(b, dtype=np.complex128) * mask
+
+    def apply(x):
+        return apply_M(x * mask, lvl, hier.beta1, hier.beta2) * mask
+
+    res = gmres(apply, lambda v: v, b64, tol=hier.coarse_tol, maxit=hier.coarse_maxit)
+    return res.x * mask, res.iterations
+
+
 def coarse_solve(b, hier: Hierarchy):
-    """e = M_c^{-1} b exactly on the coarsest level (unknown nodes only)."""
+    """e = M_c^{-1} b on the coarsest level (unknown nodes only): exactly, or
+    by coarse_gmres when the hierarchy was built with coarse="gmres"."""
+    if hier.coarse == "gmres":
+        if b.ndim == 3:
+            return coarse_gmres(b, hier)[0].astype(hier.dtype)
+        return np.stack([coarse_gmres(b[r], hier)[0] for r in range(b.shape[0])]).astype(hier.dtype)
     mask = hier.coarse_mask
     e = np.zeros_like(b)
     flat_b = b.reshape(b.shape[:-3] + (-1,))
@@ -273,7 +310,7 @@ def vcycle_mixed_entry(b, hier32: Hierarchy):
 
 
 __all__ = [
-    "Hierarchy", "build_hierarchy", "level_shapes", "coarsen_shape", "coarse_solve",
+    "Hierarchy", "build_hierarchy", "level_shapes", "coarsen_shape", "coarse_solve", "coarse_gmres",
     "jacobi_sweep", "restrict_fw", "prolong_trilinear", "vcycle", "fcycle", "vcycle_mixed_entry",
     "SOMMERFELD", "DIRICHLET",
 ]

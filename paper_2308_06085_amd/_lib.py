@@ -29,7 +29,7 @@ PREC = {"fp64": 0, "mixed": 1}
 # every symbol include/hh.h declares
 EXPORTS = [
     "hh_default_config", "hh_create", "hh_destroy", "hh_last_error", "hh_level_shape",
-    "hh_set_model", "hh_set_sources", "hh_set_point_sources", "hh_solve",
+    "hh_set_model", "hh_set_model_slowness2", "hh_set_sources", "hh_set_point_sources", "hh_solve",
     "hh_apply_operator", "hh_apply_shifted", "hh_apply_vcycle", "hh_adjoint_rhs",
     "hh_grad_slowness2", "hh_set_shadow", "hh_set_option", "hh_get_option", "hh_time_kernel", "hh_kernel_times",
     "hh_autotune",
@@ -43,6 +43,7 @@ class Config(C.Structure):
         ("bc", C.c_int),
         ("beta1", C.c_double), ("beta2", C.c_double),
         ("omega", C.c_double),
+        ("nu_pre", C.c_int), ("nu_post", C.c_int),
         ("n_levels", C.c_int),
         ("prec", C.c_int),
         ("nrhs_max", C.c_int),
@@ -57,6 +58,7 @@ class Stats(C.Structure):
         ("relres_true", C.c_double),
         ("status", C.c_int),
         ("restarts", C.c_int),
+        ("ms", C.c_double),
     ]
 
 
@@ -87,6 +89,7 @@ def load(path: str = LIB_PATH):
         "hh_last_error": (C.c_char_p, [vp]),
         "hh_level_shape": (ip, [vp, ip, C.POINTER(ip), C.POINTER(ip), C.POINTER(ip), C.POINTER(ip)]),
         "hh_set_model": (ip, [vp, vp]),
+        "hh_set_model_slowness2": (ip, [vp, vp, dp]),
         "hh_set_sources": (ip, [vp, vp, ip]),
         "hh_set_point_sources": (ip, [vp, C.POINTER(ip), ip]),
         "hh_solve": (ip, [vp, vp, dp, ip, ip, C.POINTER(Stats)]),
@@ -100,7 +103,7 @@ def load(path: str = LIB_PATH):
         "hh_get_option": (ip, [vp, C.c_char_p, C.POINTER(C.c_longlong)]),
         "hh_time_kernel": (ip, [vp, ip, ip, ip, C.POINTER(C.c_float)]),
         "hh_kernel_times": (ip, [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
-        "hh_autotune": (ip, [vp, ip]),
+        "hh_autotune": (ip, [vp, C.c_char_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -33,4 +33,30 @@ void launch_coarse_gemv(hipStream_t s, int nnode, int n_unk, const int* unk_of, 
                         const c128* minv, const cx<R>* b, cx<R>* e, c128* part, int nrhs, const RhsState* st,
                         int gate);
 
+// The paper's iterative coarsest solve (option "coarse_solver" = 1): full
+// GMRES on M_c, no preconditioner, x0 = 0, to ||b - M_c e|| <= tol ||b||, one
+// 1024-lane workgroup per right-hand side (see hh_coarse_gmres.hip).
+constexpr int COARSE_GMRES_MAX_NODES = 8192;  // coarsest-grid nodes
+constexpr int COARSE_GMRES_MAX_M = 100;       // Arnoldi steps per cycle
+struct CoarseGmres {
+    Geo g;                // the coarsest level
+    double sr, si;        // shift: M_c = -Laplace - (sr + i si) k^2, sr = beta1, si = -beta2
+    double ih2, two_over_h;
+    const double* k;      // wavenumber at the coarsest nodes (device)
+    int m;                // Arnoldi steps per cycle, 1 .. COARSE_GMRES_MAX_M
+    int cycles;           // cycles (restarts + 1) at most
+    double tol;           // relative residual
+    c128* V;              // device, (m + 2) g.n complex128 per right-hand side (basis, x)
+    int* steps;           // device, nrhs entries: Arnoldi steps of the last solve (may be null)
+};
+// LDS bytes of the kernel for m steps, and the attribute call that allows them
+size_t coarse_gmres_lds_bytes(int m);
+bool coarse_gmres_allow_lds(size_t bytes);
+// e = M_c^-1 b (to the tolerance) on the coarsest level for every right-hand
+// side the gate admits; b and e hold nrhs slices of g.n nodes in the
+// multigrid precision, the solve itself runs in complex128.
+template <typename R>
+void launch_coarse_gmres(hipStream_t s, int bc, const CoarseGmres& D, const cx<R>* b, cx<R>* e, int nrhs,
+                         const RhsState* st, int gate);
+
 }  // namespace hh

@@ -77,10 +77,12 @@ void launch_init(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs,
 struct MgParams {
     double beta1, beta2, omega;
 };
+// reg: fine region nodes a workgroup of a one-plane pass (zbc = 1) stages,
+// 256, 512 or 1280; 0 = chosen by dn_region().  Ignored when zbc > 1.
 template <typename TB, typename R>
 void launch_mg_down(hipStream_t s, int bc, const Geo& gf, const Geo& gc, int zbc, int nrhs,
                     const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
-                    cx<R>* bc_out, const RhsState* st, int gate);
+                    cx<R>* bc_out, const RhsState* st, int gate, int reg = 0);
 template <typename TB, typename R, typename TO>
 void launch_mg_up(hipStream_t s, int bc, const Geo& g, const Geo& gc, int zb, int nrhs,
                   const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
@@ -91,6 +93,9 @@ template <typename R>
 void launch_mg_resid(hipStream_t s, int bc, const Geo& g, int nrhs, cx<R>* b, const cx<R>* e, const R* k2l,
                      const MgParams& P, const RhsState* st, int gate);
 int mg_down_blocks(const Geo& gc, int zbc);
+// region of the down pass into a coarse grid gc: the automatic choice for
+// (zbc, nrhs), or `want` (256, 512, 1280) where it applies (zbc = 1)
+int mg_down_region(const Geo& gc, int zbc, int nrhs, int want);
 int mg_up_blocks(const Geo& g, int zb);
 
 // The trailing (smallest) levels of the hierarchy, run by one workgroup per
@@ -140,6 +145,8 @@ void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const doub
                      long long nblk, long long nblk_max, double tol);
 
 void launch_model_check(hipStream_t s, long long n, const double* k, double* k2, double* kb, int* bad);
+// k = omega sqrt(s) (s = squared slowness); bad counts invalid entries
+void launch_model_from_slowness2(hipStream_t s, long long n, const double* s2, double omega, double* k, int* bad);
 void launch_inject(hipStream_t s, const Geo& gf, const Geo& gc, const double* kf, double* kc);
 template <typename R>
 void launch_level_k2(hipStream_t s, long long n, const double* k, R* k2);

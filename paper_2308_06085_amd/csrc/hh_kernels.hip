@@ -569,6 +569,20 @@ __global__ void k_model_check(long long n, const double* __restrict__ k, double*
     }
 }
 
+// k = omega sqrt(s) from the squared slowness s = 1/c^2 (k = 2 pi f / c);
+// NaN/Inf or negative s, or a non-finite product, counts as bad
+__global__ void k_model_from_slowness2(long long n, const double* __restrict__ s2, double omega,
+                                       double* __restrict__ k, int* __restrict__ bad) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double v = s2[i];
+        const bool ok = isfinite(v) && v >= 0.0;
+        const double kv = ok ? omega * sqrt(v) : 0.0;
+        if (!ok || !isfinite(kv)) atomicAdd(bad, 1);
+        k[i] = kv;
+    }
+}
+
 // k_{l+1}(I) = k_l(2I)  (injection)
 __global__ void k_inject(Geo gf, Geo gc, const double* __restrict__ kf, double* __restrict__ kc) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < gc.n;
@@ -789,6 +803,10 @@ void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const doub
 void launch_model_check(hipStream_t s, long long n, const double* k, double* k2, double* kb, int* bad) {
     hipLaunchKernelGGL(k_model_check, dim3(flat_blocks(n, 256, 8192)), dim3(256), 0, s, n, k, k2, kb,
                        bad);
+}
+void launch_model_from_slowness2(hipStream_t s, long long n, const double* s2, double omega, double* k, int* bad) {
+    hipLaunchKernelGGL(k_model_from_slowness2, dim3(flat_blocks(n, 256, 8192)), dim3(256), 0, s, n, s2, omega,
+                       k, bad);
 }
 void launch_inject(hipStream_t s, const Geo& gf, const Geo& gc, const double* kf, double* kc) {
     hipLaunchKernelGGL(k_inject, dim3(flat_blocks(gc.n, 256, 8192)), dim3(256), 0, s, gf, gc, kf, kc);

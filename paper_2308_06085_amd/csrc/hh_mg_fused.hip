@@ -617,11 +617,17 @@ int dn_region(const Geo& gc, int zbc, int nrhs) {
     return best;
 }
 
+int mg_down_region(const Geo& gc, int zbc, int nrhs, int want) {
+    if (zbc != 1) return DN_REGION;
+    if (want == 256 || want == 512 || want == DN_REGION) return want;
+    return dn_region(gc, zbc, nrhs);
+}
+
 template <typename TB, typename R>
 void launch_mg_down(hipStream_t s, int bc, const Geo& gf, const Geo& gc, int zbc, int nrhs,
                     const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
-                    cx<R>* bc_out, const RhsState* st, int gate) {
-    const int reg = dn_region(gc, zbc, nrhs);
+                    cx<R>* bc_out, const RhsState* st, int gate, int reg_want) {
+    const int reg = mg_down_region(gc, zbc, nrhs, reg_want);
     const TileShape T = dn_tile_shape(gc.nx, gc.ny, reg);
     dim3 grid(T.ntx * T.nty, (gc.nz + zbc - 1) / zbc, nrhs);
 #define HH_DOWN(BCV, ONEV, REGV)                                                                                \
@@ -695,7 +701,7 @@ template void launch_mg_resid<float>(hipStream_t, int, const Geo&, int, c64*, co
 #define HH_INST_F(TB, R, TO)                                                                           \
     template void launch_mg_down<TB, R>(hipStream_t, int, const Geo&, const Geo&, int, int, const cx<TB>*, \
                                         long long, const R*, const MgParams&, cx<R>*, const RhsState*,   \
-                                        int);                                                             \
+                                        int, int);                                                        \
     template void launch_mg_up<TB, R, TO>(hipStream_t, int, const Geo&, const Geo&, int, int,              \
                                           const cx<TB>*, long long, const R*, const MgParams&,            \
                                           const cx<R>*, cx<TO>*, long long, const RhsState*, int, bool);

@@ -18,6 +18,7 @@
 #include "hh_coarse.h"
 #include "hh_kernels.h"
 #include "hh_krylov.h"
+#include "hh_tune_cache.h"
 
 using namespace hh;
 
@@ -48,6 +49,7 @@ struct LevelBuf {
     Launch L;
     int zb_down = 4;      // coarse planes per workgroup of the fused down kernel into this level's child
     int zb_up = 8;        // fine planes per workgroup of the fused up kernel on this level
+    int dn_reg = 0;       // fine region nodes per workgroup of a one-plane down pass (0 = automatic)
     double* k = nullptr;  // wavenumber at the nodes of this level
     void* k2l = nullptr;  // k^2 in the multigrid precision
     void* b = nullptr;    // right-hand side (levels >= 1)
@@ -88,6 +90,16 @@ struct hh_ctx {
     int n_unk = 0;
     bool coarse_gemv = false;  // coarsest solve by launch_coarse_gemv instead of the tail kernel
     c128* cg_part = nullptr;   // its per-chunk row sums
+    // coarsest solve by GMRES (option "coarse_solver" = 1, the paper's choice):
+    // the fused passes run down to the coarsest level, launch_coarse_gmres solves it
+    int coarse_solver = 0;
+    bool coarse_iter = false;
+    int cgm_m = COARSE_GMRES_MAX_M;  // Arnoldi steps per cycle
+    int cgm_tol_e = 11;              // relative residual 10^-cgm_tol_e
+    int cgm_cycles = 10;             // cycles (restarts + 1) at most
+    int cgm_alloc_m = 0;
+    c128* cgm_V = nullptr;           // (cgm_m + 2) coarse vectors per right-hand side
+    int* cgm_steps = nullptr;        // Arnoldi steps of the last coarse solve per right-hand side
     // state
     bool model_set = false;
     int nrhs_cur = 0;
@@ -116,6 +128,9 @@ struct hh_ctx {
     // z-planes per workgroup of each level's multigrid passes set by the caller
     // (0 = automatic); indexed by level, grown on demand
     std::vector<int> zb_down_set, zb_up_set;
+    // down-pass regions set by the caller (0 = automatic), indexed by level
+    std::vector<int> dn_reg_set;
+    int autotune_source = 0;  // 0 = not tuned, 1 = shapes from the cache file, 2 = measured
     size_t tail_lds_cap = 65536;
     float last_ms = 0.f;
     // in-solve kernel timing (option "trace"): HIP events around the fine-level
@@ -181,7 +196,8 @@ Launch level_launch(const Geo& g, const Launch& base) {
         zb = (int)std::min<long long>(std::max<long long>(want, 1), 32);
     }
     zb = std::max(1, std::min(zb, g.nz));
-    while (tiles * ((g.nz + zb - 1) / zb) > NBLK_CAP) ++zb;
+    // bounded at zb = nz: hh_create rejects planes whose tiles alone exceed NBLK_CAP
+    while (zb < g.nz && tiles * ((g.nz + zb - 1) / zb) > NBLK_CAP) ++zb;
     L.zb = zb;
     return L;
 }
@@ -205,6 +221,7 @@ void free_all(hh_ctx* c) {
     c->idr_graphs.clear();
     for (void* q : {(void*)c->idr_G, (void*)c->idr_U, (void*)c->idr_P, (void*)c->idr_st}) (void)hipFree(q);
     for (void* q : {(void*)c->gm_V, (void*)c->gm_part, (void*)c->gm_st}) (void)hipFree(q);
+    for (void* q : {(void*)c->cgm_V, (void*)c->cgm_steps}) (void)hipFree(q);
     for (auto& L : c->lv) {
         (void)hipFree(L.k);
         (void)hipFree(L.k2l);
@@ -290,6 +307,13 @@ int pick_zb(F blocks, int want) {
 // levels' LDS arrays fit the budget; level 0 always stays with the fused passes.
 void choose_tail(hh_ctx* c) {
     const int L = (int)c->lv.size();
+    c->coarse_iter = c->coarse_solver == 1;
+    if (c->coarse_iter) {
+        // the coarsest level alone is the "tail": solved by GMRES
+        c->coarse_gemv = false;
+        c->tail_first = L - 1;
+        return;
+    }
     const size_t per_node = c->mixed ? 4 * sizeof(c64) + sizeof(float) : 4 * sizeof(c128) + sizeof(double);
     long long total = 0;
     int first = L - 1;
@@ -307,6 +331,42 @@ void choose_tail(hh_ctx* c) {
         total += c->lv[first].g.n;
     }
     c->tail_first = first;
+}
+
+// Coarse GMRES buffers for m Arnoldi steps per cycle; grown only.
+hh_status cgm_alloc(hh_ctx* c, int m) {
+    if (!coarse_gmres_allow_lds(coarse_gmres_lds_bytes(m)))
+        return fail(c, HH_ERR_HIP, "the coarse GMRES kernel cannot get %zu bytes of LDS", coarse_gmres_lds_bytes(m));
+    if (m <= c->cgm_alloc_m) return HH_OK;
+    invalidate_graphs(c);  // captured cycles hold the old buffer's address
+    for (void* q : {(void*)c->cgm_V, (void*)c->cgm_steps}) (void)hipFree(q);
+    c->cgm_V = nullptr;
+    c->cgm_steps = nullptr;
+    c->cgm_alloc_m = 0;
+    const size_t n = (size_t)c->lv.back().g.n;
+    const size_t R = (size_t)c->cfg.nrhs_max;
+    CHK(dalloc(c, &c->cgm_V, sizeof(c128) * (size_t)(m + 2) * n * R));
+    CHK(dalloc(c, &c->cgm_steps, sizeof(int) * R));
+    HIPCHK(c, hipMemset(c->cgm_steps, 0, sizeof(int) * R));
+    c->cgm_alloc_m = m;
+    return HH_OK;
+}
+
+CoarseGmres cgm_desc(const hh_ctx* c) {
+    CoarseGmres D{};
+    const LevelBuf& B = c->lv.back();
+    D.g = B.g;
+    D.sr = c->cfg.beta1;
+    D.si = -c->cfg.beta2;
+    D.ih2 = 1.0 / (B.g.h * B.g.h);
+    D.two_over_h = 2.0 / B.g.h;
+    D.k = B.k;
+    D.m = c->cgm_m;
+    D.cycles = c->cgm_cycles;
+    D.tol = std::pow(10.0, -(double)c->cgm_tol_e);
+    D.V = c->cgm_V;
+    D.steps = c->cgm_steps;
+    return D;
 }
 
 TailDesc tail_desc(hh_ctx* c) {
@@ -350,6 +410,7 @@ void apply_launch(hh_ctx* c) {
             c->lv[l].zb_down = std::min(c->zb_down_set[l], c->lv[l + 1].g.nz);
         if (l < c->zb_up_set.size() && c->zb_up_set[l] > 0)
             c->lv[l].zb_up = std::min(c->zb_up_set[l], c->lv[l].g.nz);
+        c->lv[l].dn_reg = l < c->dn_reg_set.size() ? c->dn_reg_set[l] : 0;
     }
     c->L0 = c->lv[0].L;
     c->nblk0 = nblk_of(c->lv[0].g, c->L0);
@@ -377,7 +438,7 @@ struct CycleOps {
         LevelBuf& a = c->lv[l];
         LevelBuf& n = c->lv[l + 1];
         launch_mg_down<R, R>(s, c->cfg.bc, a.g, n.g, a.zb_down, nrhs, C(a.b), a.g.n, K(a.k2l), P(), C(n.b), st,
-                             gate);
+                             gate, a.dn_reg);
     }
     // e_l = post-smoothed (W b_l + P e_{l+1}); with acc added to e_l
     void up(int l, bool acc) const {
@@ -388,6 +449,12 @@ struct CycleOps {
     }
     void tail(const TailProg& prog) const {
         const int T = c->tail_first;
+        if (c->coarse_iter) {
+            // the coarsest level alone, solved by GMRES (V and F alike there)
+            const LevelBuf& cl = c->lv[T];
+            launch_coarse_gmres<R>(s, c->cfg.bc, cgm_desc(c), C(cl.b), C(cl.e), nrhs, st, gate);
+            return;
+        }
         if (c->coarse_gemv) {
             // the tail is the coarsest level alone, where V and F are the exact solve
             const LevelBuf& cl = c->lv[T];
@@ -432,7 +499,7 @@ void enqueue_cycle_t(hh_ctx* c, hipStream_t s, int nrhs, const cx<TB>* bin, cx<T
     // down: one fused pass per level writes the next level's right-hand side
     if (ev_down) (void)hipEventRecord(ev_down[0], s);
     launch_mg_down<TB, R>(s, bc, f.g, c->lv[1].g, f.zb_down, nrhs, bin, f.g.n, ops.K(f.k2l), ops.P(),
-                          ops.C(c->lv[1].b), st, gate);
+                          ops.C(c->lv[1].b), st, gate, f.dn_reg);
     if (ev_down) (void)hipEventRecord(ev_down[1], s);
     // the coarse-grid solve: one V-cycle on level 1, or the F-cycle's
     if (c->cycle == 1) ops.fcoarse(1);
@@ -922,6 +989,7 @@ hh_status finish_solve(hh_ctx* c, void* x, int nrhs, hipEvent_t e0, hipEvent_t e
             o.relres_true = S.bnorm2 > 0.0 ? std::sqrt(S.true_rnorm2 / S.bnorm2) : 0.0;
             o.status = sr;
             o.restarts = S.restarts;
+            o.ms = ms;
         }
         if (worst == HH_OK && sr != HH_OK) worst = sr;
     }
@@ -948,6 +1016,8 @@ void hh_default_config(hh_config* cfg, int nx, int ny, int nz, double h) {
     cfg->beta1 = 1.0;
     cfg->beta2 = -0.5;
     cfg->omega = 0.8;
+    cfg->nu_pre = 1;
+    cfg->nu_post = 1;
     cfg->n_levels = 0;
     cfg->prec = HH_PREC_FP64;
     cfg->nrhs_max = 1;
@@ -969,6 +1039,10 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
     if (cfg->nrhs_max < 1 || cfg->nrhs_max > NRHS_LIMIT)
         return fail(nullptr, HH_ERR_ARG, "nrhs_max must be in 1..%d", NRHS_LIMIT);
     if (!(cfg->omega > 0.0 && cfg->omega <= 1.0)) return fail(nullptr, HH_ERR_ARG, "omega must be in (0, 1]");
+    if (cfg->nu_pre != 1 || cfg->nu_post != 1)
+        return fail(nullptr, HH_ERR_ARG,
+                    "nu_pre = %d, nu_post = %d: the fused multigrid passes implement one pre- and one "
+                    "post-smoothing sweep (nu_pre = nu_post = 1) only", cfg->nu_pre, cfg->nu_post);
     // level shapes
     std::vector<Geo> shapes;
     shapes.push_back(make_geo(cfg->nx, cfg->ny, cfg->nz, cfg->h));
@@ -989,6 +1063,14 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
         }
     }
     if (shapes.size() < 2) return fail(nullptr, HH_ERR_ARG, "grid cannot be coarsened (need at least 2 levels)");
+    {
+        // one reduction partial per operator-apply workgroup: the x-y tiles of a
+        // plane must stay within NBLK_CAP even with the whole z-range in one workgroup
+        const TileShape T = ap_tile_shape(cfg->nx, cfg->ny);
+        if ((long long)T.ntx * T.nty > NBLK_CAP)
+            return fail(nullptr, HH_ERR_ARG, "an x-y plane of %d x %d nodes needs %lld tiles of the operator "
+                        "apply (at most %lld)", cfg->nx, cfg->ny, (long long)T.ntx * T.nty, NBLK_CAP);
+    }
 
     hh_ctx* c = new hh_ctx();
     c->cfg = *cfg;
@@ -1113,14 +1195,17 @@ hh_status hh_level_shape(const hh_ctx* ctx, int l, int* nx, int* ny, int* nz, in
     return HH_OK;
 }
 
-hh_status hh_set_model(hh_ctx* c, const double* k) {
-    if (!c || !k) return c ? fail(c, HH_ERR_ARG, "null k") : HH_ERR_ARG;
-    c->model_set = false;
-    HIPCHK(c, hipStreamSynchronize(c->stream));  // no pending solve still reads the old model
+}  // extern "C"
+
+namespace {
+
+// The model set-up shared by hh_set_model and hh_set_model_slowness2: k is a
+// device array of the finest level's wavenumbers (possibly lv[0].k itself).
+hh_status set_model_from(hh_ctx* c, const double* k) {
     LevelBuf& f = c->lv[0];
     HIPCHK(c, hipMemsetAsync(c->bad, 0, sizeof(int), c->stream));
     launch_model_check(c->stream, f.g.n, k, c->k2, c->kb, c->bad);
-    HIPCHK(c, hipMemcpyAsync(f.k, k, sizeof(double) * f.g.n, hipMemcpyDeviceToDevice, c->stream));
+    if (k != f.k) HIPCHK(c, hipMemcpyAsync(f.k, k, sizeof(double) * f.g.n, hipMemcpyDeviceToDevice, c->stream));
     for (size_t l = 1; l < c->lv.size(); ++l)
         launch_inject(c->stream, c->lv[l - 1].g, c->lv[l].g, c->lv[l - 1].k, c->lv[l].k);
     for (auto& B : c->lv) {
@@ -1134,6 +1219,34 @@ hh_status hh_set_model(hh_ctx* c, const double* k) {
     CHK(build_coarse(c));
     c->model_set = true;
     return HH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hh_status hh_set_model(hh_ctx* c, const double* k) {
+    if (!c || !k) return c ? fail(c, HH_ERR_ARG, "null k") : HH_ERR_ARG;
+    c->model_set = false;
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // no pending solve still reads the old model
+    return set_model_from(c, k);
+}
+
+hh_status hh_set_model_slowness2(hh_ctx* c, const double* s2, double omega) {
+    if (!c || !s2) return c ? fail(c, HH_ERR_ARG, "null s") : HH_ERR_ARG;
+    if (!(omega > 0.0) || !std::isfinite(omega)) return fail(c, HH_ERR_ARG, "omega must be finite and > 0");
+    c->model_set = false;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    LevelBuf& f = c->lv[0];
+    HIPCHK(c, hipMemsetAsync(c->bad, 0, sizeof(int), c->stream));
+    launch_model_from_slowness2(c->stream, f.g.n, s2, omega, f.k, c->bad);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->bad_host, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (*c->bad_host)
+        return fail(c, HH_ERR_NUMERIC, "s holds %d NaN/Inf or negative values (or omega sqrt(s) overflows)",
+                    *c->bad_host);
+    return set_model_from(c, f.k);
 }
 
 hh_status hh_set_sources(hh_ctx* c, const void* b, int nrhs) {
@@ -1366,6 +1479,31 @@ hh_status hh_set_option(hh_ctx* c, const char* name, long long value) {
         if (value != 0 && value != 1) return fail(c, HH_ERR_ARG, "cycle must be 0 (V-cycle) or 1 (F-cycle)");
         c->cycle = (int)value;
         invalidate_graphs(c);
+    } else if (n == "coarse_solver") {
+        if (value != 0 && value != 1) return fail(c, HH_ERR_ARG, "coarse_solver must be 0 (exact) or 1 (GMRES)");
+        if (value == 1) {
+            if (c->lv.back().g.n > COARSE_GMRES_MAX_NODES)
+                return fail(c, HH_ERR_ARG, "the coarsest grid has %lld nodes; its GMRES solve takes at most %d",
+                            c->lv.back().g.n, COARSE_GMRES_MAX_NODES);
+            CHK(cgm_alloc(c, c->cgm_m));
+        }
+        c->coarse_solver = (int)value;
+        choose_tail(c);
+        apply_launch(c);
+    } else if (n == "coarse_m") {
+        if (value < 1 || value > COARSE_GMRES_MAX_M)
+            return fail(c, HH_ERR_ARG, "coarse_m must be in 1..%d", COARSE_GMRES_MAX_M);
+        if (c->coarse_solver == 1) CHK(cgm_alloc(c, (int)value));
+        c->cgm_m = (int)value;
+        invalidate_graphs(c);
+    } else if (n == "coarse_tol_e") {
+        if (value < 1 || value > 15) return fail(c, HH_ERR_ARG, "coarse_tol_e must be in 1..15");
+        c->cgm_tol_e = (int)value;
+        invalidate_graphs(c);
+    } else if (n == "coarse_cycles") {
+        if (value < 1 || value > 1000) return fail(c, HH_ERR_ARG, "coarse_cycles must be in 1..1000");
+        c->cgm_cycles = (int)value;
+        invalidate_graphs(c);
     } else if (n == "block") {
         if (value != 64 && value != 128 && value != 256 && value != 512)
             return fail(c, HH_ERR_ARG, "block must be 64, 128, 256 or 512");
@@ -1374,6 +1512,19 @@ hh_status hh_set_option(hh_ctx* c, const char* name, long long value) {
     } else if (n == "zb") {
         if (value < 0 || value > 1024) return fail(c, HH_ERR_ARG, "zb must be in 0..1024");
         c->base.zb = (int)value;
+        apply_launch(c);
+    } else if (n.rfind("dn_region:", 0) == 0) {
+        const std::string rest = n.substr(10);
+        if (rest.empty() || rest.size() > 3 || rest.find_first_not_of("0123456789") != std::string::npos)
+            return fail(c, HH_ERR_ARG, "unknown option '%s'", name);
+        const int level = std::atoi(rest.c_str());
+        if (level >= (int)c->lv.size() - 1)
+            return fail(c, HH_ERR_ARG, "%s: level %d has no down pass (levels 0..%d)", name, level,
+                        (int)c->lv.size() - 2);
+        if (value != 0 && value != 256 && value != 512 && value != 1280)
+            return fail(c, HH_ERR_ARG, "%s must be 0, 256, 512 or 1280", name);
+        if ((int)c->dn_reg_set.size() <= level) c->dn_reg_set.resize(level + 1, 0);
+        c->dn_reg_set[level] = (int)value;
         apply_launch(c);
     } else if (n.rfind("zb_down", 0) == 0 || n.rfind("zb_up", 0) == 0) {
         // "zb_down" / "zb_up" (finest level) or "zb_down:<level>" / "zb_up:<level>"
@@ -1416,6 +1567,31 @@ hh_status hh_get_option(const hh_ctx* c, const char* name, long long* value) {
         }
         if (level >= (int)c->lv.size() - 1) return HH_ERR_ARG;
         *value = down ? c->lv[level].zb_down : c->lv[level].zb_up;
+    }
+    else if (n.rfind("dn_region:", 0) == 0) {
+        const std::string rest = n.substr(10);
+        if (rest.empty() || rest.size() > 3 || rest.find_first_not_of("0123456789") != std::string::npos)
+            return HH_ERR_ARG;
+        const int level = std::atoi(rest.c_str());
+        if (level >= (int)c->lv.size() - 1) return HH_ERR_ARG;
+        *value = mg_down_region(c->lv[level + 1].g, c->lv[level].zb_down, std::max(1, c->nrhs_cur),
+                                c->lv[level].dn_reg);
+    }
+    else if (n == "autotune_source") *value = c->autotune_source;
+    else if (n == "coarse_solver") *value = c->coarse_solver;
+    else if (n == "coarse_m") *value = c->cgm_m;
+    else if (n == "coarse_tol_e") *value = c->cgm_tol_e;
+    else if (n == "coarse_cycles") *value = c->cgm_cycles;
+    else if (n == "coarse_steps") {
+        // Arnoldi steps of the last coarse GMRES solve, the largest over the right-hand sides
+        *value = 0;
+        if (c->cgm_steps) {
+            std::vector<int> st(c->cfg.nrhs_max);
+            if (hipStreamSynchronize(c->stream) != hipSuccess ||
+                hipMemcpy(st.data(), c->cgm_steps, sizeof(int) * st.size(), hipMemcpyDeviceToHost) != hipSuccess)
+                return HH_ERR_HIP;
+            for (int v : st) *value = std::max<long long>(*value, v);
+        }
     }
     else if (n == "tail_first") *value = c->tail_first;
     else if (n == "check_every") *value = c->check_every;
@@ -1468,7 +1644,8 @@ void launch_one_fine(hh_ctx* c, int which, int nrhs) {
                                 NBLK_CAP, F);
             break;
         case 2:
-            launch_mg_down<R, R>(s, bc, g, g1, f.zb_down, nrhs, pin, g.n, k2l, P, C(c->lv[1].b), c->st, ST_RUN);
+            launch_mg_down<R, R>(s, bc, g, g1, f.zb_down, nrhs, pin, g.n, k2l, P, C(c->lv[1].b), c->st, ST_RUN,
+                                 f.dn_reg);
             break;
         case 3:
             launch_mg_up<R, R, R>(s, bc, g, g1, f.zb_up, nrhs, pin, g.n, k2l, P, C(c->lv[1].e), phat, g.n,
@@ -1533,29 +1710,63 @@ hh_status hh_kernel_times(const hh_ctx* c, double* ms_avg, long long* launches) 
     return HH_OK;
 }
 
-hh_status hh_autotune(hh_ctx* c, int nrhs) {
+hh_status hh_autotune(hh_ctx* c, const char* cache_json_path) {
+    if (!c) return HH_ERR_ARG;
+    if (c->nrhs_cur < 1) return fail(c, HH_ERR_STATE, "autotune needs the right-hand sides set");
+    const int nrhs = c->nrhs_cur;
     CHK(check_ready(c, nrhs));
-    if (c->nrhs_cur < nrhs) return fail(c, HH_ERR_STATE, "autotune needs %d right-hand sides set", nrhs);
-    // Each candidate shape runs the first steps of a solve of the current
-    // sources (a fresh start, graph replay) and is timed with HIP events on
-    // the context stream: kernels see the data flow and cache state of a
-    // solve, not a repeated launch on warm inputs.
-    constexpr int kSteps = 8, kWarm = 2;
-    const int blocks[] = {128, 256, 512};
-    const int zbs[] = {2, 4, 8};
+    const int T = c->tail_first;  // levels 0 .. T - 1 run the fused passes
+    std::map<std::string, TuneEntry> cache;
+    std::string key;
+    if (cache_json_path) {
+        std::string err;
+        if (!tune_cache_read(cache_json_path, cache, err)) return fail(c, HH_ERR_ARG, "%s", err.c_str());
+        hipDeviceProp_t prop;
+        HIPCHK(c, hipGetDeviceProperties(&prop, c->device));
+        char buf[256];
+        const Geo& g = c->lv[0].g;
+        std::snprintf(buf, sizeof(buf), "%s|%dx%dx%d|%s|%s|nrhs%d|%s|levels%d", prop.gcnArchName, g.nx, g.ny,
+                      g.nz, c->cfg.bc == HH_BC_SOMMERFELD ? "sommerfeld" : "dirichlet",
+                      c->mixed ? "mixed" : "fp64", nrhs, c->cycle ? "F" : "V", (int)c->lv.size());
+        key = buf;
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            const TuneEntry& e = it->second;
+            auto in = [](int v, std::initializer_list<int> ok) {
+                return std::find(ok.begin(), ok.end(), v) != ok.end();
+            };
+            bool valid = in(e.block, {64, 128, 256, 512}) && e.zb >= 1 && e.zb <= 1024 &&
+                         (int)e.zb_down.size() == T && (int)e.zb_up.size() == T && (int)e.dn_region.size() == T;
+            for (int l = 0; valid && l < T; ++l)
+                valid = in(e.zb_down[l], {1, 2, 4, 8, 16}) && in(e.zb_up[l], {1, 2, 4, 8, 16}) &&
+                        in(e.dn_region[l], {0, 256, 512, 1280});
+            if (!valid) return fail(c, HH_ERR_ARG, "%s: the entry for %s holds a shape outside the tuned sets",
+                                    cache_json_path, key.c_str());
+            c->base.block = e.block;
+            c->base.zb = e.zb;
+            c->zb_down_set.assign(e.zb_down.begin(), e.zb_down.end());
+            c->zb_up_set.assign(e.zb_up.begin(), e.zb_up.end());
+            c->dn_reg_set.assign(e.dn_region.begin(), e.dn_region.end());
+            apply_launch(c);
+            c->autotune_source = 1;
+            return HH_OK;
+        }
+    }
+    // Each candidate runs the first steps of a solve of the current sources (a
+    // fresh start, graph replay) timed with HIP events on the context stream:
+    // kernels see the data flow and cache state of a solve, not a repeated
+    // launch on warm inputs.  The best of two timings counts.
+    constexpr int kSteps = 8, kWarm = 2, kRepeat = 2;
     const Geo& g = c->lv[0].g;
-    Launch best = c->base;
-    float best_ms = 1e30f;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    for (int b : blocks)
-        for (int z : zbs) {
-            c->base.block = b;
-            c->base.zb = z;
-            apply_launch(c);
-            hipGraphExec_t exec = nullptr;
-            CHK(get_graph(c, nrhs, &exec));
+    auto time_steps = [&](float* out) -> hh_status {
+        apply_launch(c);
+        hipGraphExec_t exec = nullptr;
+        CHK(get_graph(c, nrhs, &exec));
+        float best = 1e30f;
+        for (int rep = 0; rep < kRepeat; ++rep) {
             // tolerance 0: no right-hand side stops within the few steps timed
             launch_fill_status(c->stream, nrhs, c->st, ST_RUN, 2 * (kSteps + kWarm + 1));
             launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v,
@@ -1568,15 +1779,81 @@ hh_status hh_autotune(hh_ctx* c, int nrhs) {
             HIPCHK(c, hipEventSynchronize(e1));
             float ms = 0.f;
             HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = c->base;
-            }
+            best = std::min(best, ms / kSteps);
         }
+        *out = best;
+        return HH_OK;
+    };
+    // start from the built-in rule: flat shape 256 x 4, multigrid shapes automatic
+    c->base.block = 256;
+    c->base.zb = 4;
+    c->zb_down_set.assign(T, 0);
+    c->zb_up_set.assign(T, 0);
+    c->dn_reg_set.assign(T, 0);
+    float cur = 0.f;
+    hh_status st = time_steps(&cur);
+    const float def_ms = cur;
+    // a candidate replaces the current choice only when >= 1 % faster
+    auto try_set = [&](int* slot, int value) -> hh_status {
+        const int keep = *slot;
+        if (value == keep) return HH_OK;
+        *slot = value;
+        float ms = 0.f;
+        CHK(time_steps(&ms));
+        if (ms < 0.99f * cur) cur = ms;
+        else *slot = keep;
+        return HH_OK;
+    };
+    // the effective (rule-chosen) values are the starting point of each level
+    apply_launch(c);
+    for (int l = 0; st == HH_OK && l < T; ++l) {
+        c->zb_down_set[l] = c->lv[l].zb_down;
+        c->zb_up_set[l] = c->lv[l].zb_up;
+    }
+    for (int b : {128, 256, 512})
+        for (int z : {2, 4, 8}) {
+            if (st != HH_OK) break;
+            if (b == c->base.block && z == c->base.zb) continue;
+            const Launch keep = c->base;
+            c->base.block = b;
+            c->base.zb = z;
+            float ms = 0.f;
+            st = time_steps(&ms);
+            if (st == HH_OK && ms < 0.99f * cur) cur = ms;
+            else c->base = keep;
+        }
+    for (int l = 0; st == HH_OK && l < T; ++l) {
+        const int ncz = c->lv[l + 1].g.nz, nz = c->lv[l].g.nz;
+        for (int z : {1, 2, 4, 8, 16})
+            if (st == HH_OK && z <= ncz) st = try_set(&c->zb_down_set[l], z);
+        if (st == HH_OK && c->zb_down_set[l] == 1)
+            for (int reg : {256, 512, 1280})
+                if (st == HH_OK) st = try_set(&c->dn_reg_set[l], reg);
+        // the up pass's one-plane form (1 plane per workgroup) rounds some
+        // nodes differently from its marching form (> 1 plane): the tuner
+        // keeps the form the rule chose, so the cycle's output stays the same
+        if (c->zb_up_set[l] > 1)
+            for (int z : {2, 4, 8, 16})
+                if (st == HH_OK && z <= nz) st = try_set(&c->zb_up_set[l], z);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    c->base = best;
     apply_launch(c);
+    if (st != HH_OK) return st;
+    c->autotune_source = 2;
+    if (cache_json_path) {
+        TuneEntry e;
+        e.block = c->base.block;
+        e.zb = c->base.zb;
+        e.zb_down.assign(c->zb_down_set.begin(), c->zb_down_set.begin() + T);
+        e.zb_up.assign(c->zb_up_set.begin(), c->zb_up_set.begin() + T);
+        e.dn_region.assign(c->dn_reg_set.begin(), c->dn_reg_set.begin() + T);
+        e.step_ms = cur;
+        e.default_step_ms = def_ms;
+        cache[key] = e;
+        std::string err;
+        if (!tune_cache_write(cache_json_path, cache, err)) return fail(c, HH_ERR_ARG, "%s", err.c_str());
+    }
     return HH_OK;
 }
 

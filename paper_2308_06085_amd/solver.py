@@ -45,6 +45,7 @@ class SolveStats:
     relres_true: float
     status: str
     restarts: int
+    ms: float = 0.0  # device time of the whole solve call
 
 
 class Solver:
@@ -84,6 +85,7 @@ class Solver:
         self.ctx = ctx
         self.nrhs = 0
         self._k = None
+        self.model_version = 0  # counts set_model calls (HelmholtzSolve reuses a model it set)
         if cycle not in ("V", "F"):
             self.close()
             raise ValueError(f"cycle must be 'V' or 'F', not {cycle!r}")
@@ -145,6 +147,15 @@ class Solver:
         _require(k, torch.float64, self.shape, "k")
         check(self.lib.hh_set_model(self.ctx, _ptr(k)), self.ctx)
         self._k = k
+        self.model_version += 1
+
+    def set_model_slowness2(self, s: torch.Tensor, omega: float):
+        """The model as squared slowness s = 1/c^2, float64 (nz, ny, nx) on the
+        device, at angular frequency omega: the library forms k = omega sqrt(s)."""
+        _require(s, torch.float64, self.shape, "s")
+        check(self.lib.hh_set_model_slowness2(self.ctx, _ptr(s), float(omega)), self.ctx)
+        self._k = None
+        self.model_version += 1
 
     def set_sources(self, b: torch.Tensor):
         """Right-hand sides, complex128 (nrhs, nz, ny, nx) or (nz, ny, nx)."""
@@ -187,7 +198,7 @@ class Solver:
         allow = () if raise_on_fail else (4, 5, 6)
         check(status, self.ctx, allow=allow)
         stats = [SolveStats(s.iterations, s.matvecs, s.relres, s.relres_true,
-                            _lib.STATUS_NAMES.get(s.status, str(s.status)), s.restarts) for s in st]
+                            _lib.STATUS_NAMES.get(s.status, str(s.status)), s.restarts, s.ms) for s in st]
         return out, stats
 
     def _apply(self, fn, x):
@@ -239,9 +250,24 @@ class Solver:
         check(self.lib.hh_kernel_times(self.ctx, ms, n), self.ctx)
         return list(ms), list(n)
 
-    def autotune(self, nrhs: int = 1):
-        check(self.lib.hh_autotune(self.ctx, int(nrhs)), self.ctx)
-        return self.get_option("block"), self.get_option("zb")
+    def autotune(self, cache_path: str | None = None) -> dict:
+        """Pick the launch shapes by timing the first steps of a solve of the
+        current sources (``hh_autotune``); with ``cache_path`` a JSON cache file
+        is read first and updated after measuring.  Returns the shapes in use."""
+        path = None if cache_path is None else str(cache_path).encode()
+        check(self.lib.hh_autotune(self.ctx, path), self.ctx)
+        return self.launch_shapes()
+
+    def launch_shapes(self) -> dict:
+        """The launch shapes in use: flat-kernel lanes, operator-apply z-planes,
+        and per multigrid level with fused passes the down / up z-planes and the
+        down-pass region."""
+        levels = self.get_option("tail_first")
+        return {"block": self.get_option("block"), "zb": self.get_option("zb"),
+                "zb_down": [self.get_option(f"zb_down:{l}") for l in range(levels)],
+                "zb_up": [self.get_option(f"zb_up:{l}") for l in range(levels)],
+                "dn_region": [self.get_option(f"dn_region:{l}") for l in range(levels)],
+                "autotune_source": self.get_option("autotune_source")}
 
 
 class HelmholtzSolve(torch.autograd.Function):
@@ -259,11 +285,12 @@ class HelmholtzSolve(torch.autograd.Function):
     def forward(ctx, s, b, omega, solver: Solver, rtol=1e-10, maxit=2000):
         if isinstance(b, torch.Tensor) and b.requires_grad:
             raise NotImplementedError("HelmholtzSolve differentiates with respect to s only")
-        k = float(omega) * torch.sqrt(s)
-        solver.set_model(k.contiguous())
+        s = s.detach().contiguous()
+        solver.set_model_slowness2(s, float(omega))
         solver.set_sources(b.contiguous())
         u, stats = solver.solve(rtol=rtol, maxit=maxit, raise_on_fail=True)
         ctx.solver, ctx.omega, ctx.rtol, ctx.maxit = solver, float(omega), rtol, maxit
+        ctx.model_version = solver.model_version
         ctx.save_for_backward(s, u)
         return u
 
@@ -271,7 +298,10 @@ class HelmholtzSolve(torch.autograd.Function):
     def backward(ctx, grad_u):
         s, u = ctx.saved_tensors
         solver = ctx.solver
-        solver.set_model((ctx.omega * torch.sqrt(s)).contiguous())
+        # the model (hierarchy and coarsest inverse) of the forward solve is
+        # still set unless the solver was given another one in between
+        if solver.model_version != ctx.model_version:
+            solver.set_model_slowness2(s, ctx.omega)
         rhs = solver.adjoint_rhs(grad_u.contiguous())
         solver.set_sources(rhs)
         w, _ = solver.solve(rtol=ctx.rtol, maxit=ctx.maxit, raise_on_fail=True)

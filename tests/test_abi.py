@@ -44,9 +44,12 @@ def test_config_struct_layout_matches_header():
     from paper_2308_06085_amd._lib import Config, Stats
 
     assert [f for f, _ in Config._fields_] == ["nx", "ny", "nz", "h", "bc", "beta1", "beta2",
-                                               "omega", "n_levels", "prec", "nrhs_max"]
-    assert ctypes.sizeof(Config) == 72
-    assert ctypes.sizeof(Stats) == 40
+                                               "omega", "nu_pre", "nu_post", "n_levels", "prec",
+                                               "nrhs_max"]
+    assert ctypes.sizeof(Config) == 80
+    assert [f for f, _ in Stats._fields_] == ["iterations", "matvecs", "relres", "relres_true",
+                                              "status", "restarts", "ms"]
+    assert ctypes.sizeof(Stats) == 48
 
 
 def test_default_config_and_create_validation_without_gpu():
@@ -60,7 +63,30 @@ def test_default_config_and_create_validation_without_gpu():
     lib.hh_default_config(ctypes.byref(cfg), 33, 33, 65, 0.5)
     assert (cfg.nx, cfg.ny, cfg.nz, cfg.h) == (33, 33, 65, 0.5)
     assert (cfg.beta1, cfg.beta2, cfg.omega, cfg.bc) == (1.0, -0.5, 0.8, 1)
-    cfg.nx = 32  # even: rejected before any device call
+    assert (cfg.nu_pre, cfg.nu_post) == (1, 1)
     ctx = ctypes.c_void_p()
+    for nu in ((2, 1), (1, 0), (0, 1)):
+        # only one pre- and one post-smoothing sweep: rejected before any device call
+        cfg.nu_pre, cfg.nu_post = nu
+        assert lib.hh_create(ctypes.byref(cfg), None, ctypes.byref(ctx)) == 1
+        assert b"nu_pre" in lib.hh_last_error(None)
+    cfg.nu_pre = cfg.nu_post = 1
+    cfg.nx = 32  # even: rejected before any device call
     assert lib.hh_create(ctypes.byref(cfg), None, ctypes.byref(ctx)) == 1
     assert b"odd" in lib.hh_last_error(None)
+
+
+def test_create_rejects_planes_beyond_the_partial_sum_capacity():
+    """An x-y plane whose operator-apply tiles alone exceed the reduction
+    capacity is an argument error, found on the host before any device call."""
+    if not os.path.exists(LIB):
+        pytest.skip("libhh.so not built")
+    from paper_2308_06085_amd import _lib
+
+    lib = _lib.load()
+    cfg = _lib.Config()
+    lib.hh_default_config(ctypes.byref(cfg), 8193, 8193, 5, 1.0)
+    ctx = ctypes.c_void_p()
+    assert lib.hh_create(ctypes.byref(cfg), None, ctypes.byref(ctx)) == 1
+    assert b"tiles" in lib.hh_last_error(None)
+

@@ -1,0 +1,188 @@
+"""The paper's coarsest-grid solve on the GPU (option "coarse_solver" = 1):
+full GMRES on the coarsest M without preconditioner, from zero, to relative
+residual 1e-11 (end of section 3.4.5, section 4.2, coarse stopping criterion of
+section 5), one workgroup per right-hand side.
+
+Parity: V- and F-cycles against the oracle's cycles with the same GMRES
+coarsest solve (1e-10 in complex128, 1e-5 in complex64) on coarsest grids of
+27 to 4913 nodes; the Arnoldi step count of one coarse solve against the
+oracle's (the same Krylov process; the GPU orthogonalises by classical
+Gram-Schmidt applied twice, the oracle by modified Gram-Schmidt); the Table 1
+counts of section 5.1.3 with this coarsest solve; batched equals single.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle.discretization import DIRICHLET, SOMMERFELD, Level, apply_M, diag_M, unknown_mask
+from oracle.multigrid import build_hierarchy, coarse_gmres, fcycle, restrict_fw, vcycle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _solver(shape, h, bc, **kw):
+    from paper_2308_06085_amd import Solver
+
+    s = Solver(shape, h, bc=bc, **kw)
+    s.set_option("coarse_solver", 1)
+    return s
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+# (shape, bc, n_levels): coarsest 17^3 (Dirichlet 3375 unknowns, Sommerfeld
+# 4913), a 9 x 9 x 17 coarsest grid under three levels, and the default
+# hierarchy down to 3 x 3 x 5
+CASES = [((33, 33, 33), DIRICHLET, 2, 2), ((33, 33, 33), SOMMERFELD, 2, 1), ((33, 33, 65), SOMMERFELD, 3, 2),
+         ((17, 33, 33), DIRICHLET, 0, 3)]
+
+
+@pytest.mark.parametrize("shape,bc,n_levels,nrhs", CASES)
+def test_cycles_with_coarse_gmres_match_the_oracle(shape, bc, n_levels, nrhs):
+    h = 1.0 / (max(shape) - 1)
+    k = np.random.default_rng(81).uniform(20.0, 40.0, shape)
+    r = W.random_complex((nrhs,) + shape, seed=82) * unknown_mask(shape, bc)
+    h64 = build_hierarchy(k, h, bc, n_levels=n_levels, coarse="gmres")
+    h32 = build_hierarchy(k, h, bc, n_levels=n_levels, coarse="gmres", dtype=np.complex64)
+    for cyc, fn in (("V", vcycle), ("F", fcycle)):
+        ref64 = fn(r, h64)
+        ref32 = fn(r.astype(np.complex64), h32).astype(np.complex128)
+        for prec, ref, tol in (("fp64", ref64, 1e-10), ("mixed", ref32, 1e-5)):
+            s = _solver(shape, h, bc, n_levels=n_levels, nrhs_max=nrhs, prec=prec, cycle=cyc)
+            assert s.get_option("tail_first") == len(h64.levels) - 1
+            assert s.level_shapes() == [lv.shape for lv in h64.levels]
+            s.set_model(dev(k))
+            z = host(s.apply_vcycle(dev(r)))
+            assert relerr(z, ref) <= tol, (shape, bc, cyc, prec, relerr(z, ref))
+            s.close()
+
+
+@pytest.mark.parametrize("bc", [DIRICHLET, SOMMERFELD])
+def test_coarse_gmres_step_count_matches_the_oracle(bc):
+    """Two levels: the coarse right-hand side of one V-cycle is R(r - M W r)
+    on the fine grid; the GPU's Arnoldi steps for it equal the oracle's for
+    the same right-hand side within one step."""
+    shape, h = (33, 33, 33), 1 / 32
+    k = np.full(shape, 40.0)
+    r = W.random_complex(shape, seed=83) * unknown_mask(shape, bc)
+    hier = build_hierarchy(k, h, bc, n_levels=2, coarse="gmres")
+    lvl = hier.levels[0]
+    u1 = (hier.omega / diag_M(lvl)) * r
+    bcoarse = restrict_fw(r - apply_M(u1, lvl), bc) * unknown_mask(hier.coarsest.shape, bc)
+    _, steps = coarse_gmres(bcoarse, hier)
+    s = _solver(shape, h, bc, n_levels=2)
+    s.set_model(dev(k))
+    z = host(s.apply_vcycle(dev(r)))[0]
+    assert relerr(z, vcycle(r, hier)) <= 1e-10
+    gpu_steps = s.get_option("coarse_steps")
+    print(f"coarse GMRES steps ({bc}): GPU {gpu_steps}, oracle {steps}")
+    assert abs(gpu_steps - steps) <= 1, (gpu_steps, steps)
+    s.close()
+
+
+def test_coarse_gmres_options_and_restarts():
+    """A cycle of m = 8 Arnoldi steps with restarts reaches the same coarse
+    solution as full GMRES; a looser tolerance takes fewer steps; invalid
+    values and a coarsest grid beyond 8192 nodes are argument errors."""
+    from paper_2308_06085_amd._lib import HHError
+
+    shape, h, bc = (33, 33, 33), 1 / 32, SOMMERFELD
+    k = np.random.default_rng(84).uniform(20.0, 40.0, shape)
+    r = dev(W.random_complex(shape, seed=85))
+    s = _solver(shape, h, bc, n_levels=2)
+    s.set_model(dev(k))
+    z_full = host(s.apply_vcycle(r))
+    full_steps = s.get_option("coarse_steps")
+    s.set_option("coarse_m", 8)
+    s.set_option("coarse_cycles", 200)
+    z_restart = host(s.apply_vcycle(r))
+    assert relerr(z_restart, z_full) <= 1e-9
+    assert s.get_option("coarse_steps") > full_steps
+    s.set_option("coarse_m", 100)
+    s.set_option("coarse_tol_e", 4)
+    host(s.apply_vcycle(r))
+    assert s.get_option("coarse_steps") < full_steps
+    for opt, bad in (("coarse_m", 0), ("coarse_m", 101), ("coarse_tol_e", 16), ("coarse_solver", 2)):
+        with pytest.raises(HHError):
+            s.set_option(opt, bad)
+    s.close()
+    from paper_2308_06085_amd import Solver
+
+    big = Solver((65, 65, 65), 1 / 64, bc=SOMMERFELD, n_levels=3)   # 17^3 coarsest: fine
+    big.set_option("coarse_solver", 1)
+    big.close()
+    too_big = Solver((129, 129, 129), 1 / 128, bc=SOMMERFELD, n_levels=3)   # 33^3 = 35937 nodes
+    with pytest.raises(HHError, match="8192"):
+        too_big.set_option("coarse_solver", 1)
+    too_big.close()
+
+
+@pytest.mark.parametrize("method", ["gmres", "bicgstab", "idrs"])
+def test_paper_table1_counts_with_the_coarse_gmres(method):
+    """Table 1 (section 5.1.3) with the paper's own coarsest solve: closed-off
+    65^3, k = 40, 17^3 coarsest grid solved by GMRES to 1e-11, FP64: GMRES
+    within one step of the printed 145, Bi-CGSTAB and IDR(4) inside the band
+    of the printed partitions."""
+    with open(os.path.join(GOLDEN, "table1_bicgstab_matvec.json")) as f:
+        gold = json.load(f)
+    n, kk = gold["problem"]["n"], gold["problem"]["k"]
+    lvl, b, uex = O.closed_off_problem(n, kk)
+    s = _solver(lvl.shape, lvl.h, DIRICHLET, n_levels=3, method=method)
+    assert s.level_shapes()[-1] == (17, 17, 17)
+    s.set_model(dev(np.full(lvl.shape, kk)))
+    s.set_sources(dev(b))
+    x, st = s.solve(rtol=gold["problem"]["tol"], maxit=1000)
+    x = host(x)[0]
+    assert st[0].status == "HH_OK"
+    true_rel = np.linalg.norm(b - O.apply_A(x, lvl)) / np.linalg.norm(b)
+    assert true_rel <= (1e-5 if method == "gmres" else gold["problem"]["tol"])
+    assert np.abs(x - uex).max() < 2e-3
+    mv = st[0].matvecs
+    print(f"Table 1 with the coarse GMRES, {method}: {mv} matvecs, coarse steps {s.get_option('coarse_steps')}")
+    if method == "gmres":
+        assert abs(mv - 145) <= 1, mv
+    else:
+        key = "bicgstab" if method == "bicgstab" else "idr4"
+        assert 0.8 * min(gold[key]) <= mv <= 1.15 * max(gold[key]), mv
+    s.close()
+
+
+def test_coarse_gmres_batched_equals_single_solves():
+    """Two right-hand sides that stop at different steps: each equals its
+    single solve bit for bit (each right-hand side's coarse GMRES runs in its
+    own workgroup with a fixed summation order)."""
+    n, kk = 33, 20.0
+    lvl, b0, _ = O.closed_off_problem(n, kk)
+    b1 = O.point_source_rhs(lvl.shape, lvl.h, [(16, 16, 16)])[0]
+    b = np.stack([b0, b1])
+    s = _solver(lvl.shape, lvl.h, DIRICHLET, n_levels=2, nrhs_max=2)
+    s.set_model(dev(np.full(lvl.shape, kk)))
+    s.set_sources(dev(b))
+    xb, stb = s.solve(rtol=1e-8)
+    xb = host(xb)
+    assert all(t.status == "HH_OK" for t in stb)
+    assert all(np.linalg.norm(b[r] - O.apply_A(xb[r], lvl)) <= 1e-8 * np.linalg.norm(b[r]) for r in range(2))
+    assert stb[0].iterations != stb[1].iterations
+    for r in range(2):
+        s.set_sources(dev(b[r]))
+        x1, st1 = s.solve(rtol=1e-8)
+        assert np.array_equal(host(x1)[0], xb[r]) and st1[0].iterations == stb[r].iterations, r
+    s.close()

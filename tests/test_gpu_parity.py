@@ -429,10 +429,13 @@ def test_launch_shape_options_and_autotune():
         s.set_option("zb", zb)
         x, st = s.solve(rtol=1e-7)
         assert st[0].status == "HH_OK" and st[0].relres_true <= 1e-7
-    block, zb = s.autotune(1)
-    assert block in (128, 256, 512) and zb in (2, 4, 8)
+    shapes = s.autotune()
+    assert shapes["block"] in (128, 256, 512) and shapes["zb"] in (2, 4, 8)
+    assert shapes["autotune_source"] == 2 and len(shapes["zb_down"]) == first_tail
     x, st = s.solve(rtol=1e-7)
     assert st[0].status == "HH_OK" and st[0].relres_true <= 1e-7
+    # the tuned multigrid shapes leave the cycle's output unchanged bit for bit
+    assert np.array_equal(host(s.apply_vcycle(r)), z_ref)
 
 
 def test_resume_from_initial_guess():

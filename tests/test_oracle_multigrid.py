@@ -369,3 +369,50 @@ def test_fcycle_contraction_between_w_and_v_for_k0():
     assert rw <= rf + 1e-3 and rf < rv, (rw, rf, rv)
     rf17 = _contraction_of(fcycle, 17)
     assert rf <= rf17 + 0.05, (rf17, rf)
+
+
+@pytest.mark.parametrize("bc", [DIRICHLET, SOMMERFELD])
+def test_coarse_gmres_reaches_the_exact_coarse_solution(bc):
+    """The paper's coarsest-grid solve (full GMRES to relative residual 1e-11,
+    end of section 3.4.5 and section 5) against the sparse LU solve of the same
+    coarsest M: on the 17^3 coarsest grid of the closed-off configuration
+    (k = 40, h = 1/16 there) and a heterogeneous k, the GMRES result lies
+    within the residual bound times a small condition number of the exact
+    solution, and its true residual meets 1e-11."""
+    from oracle.discretization import apply_M
+    from oracle.multigrid import coarse_gmres, coarse_solve
+
+    for k in (np.full((33, 33, 33), 40.0), np.random.default_rng(3).uniform(20.0, 60.0, (33, 33, 33))):
+        exact = build_hierarchy(k, 1 / 32, bc, n_levels=2)
+        itv = build_hierarchy(k, 1 / 32, bc, n_levels=2, coarse="gmres")
+        assert exact.coarsest.shape == (17, 17, 17)
+        mask = unknown_mask((17, 17, 17), bc)
+        rng = np.random.default_rng(4)
+        b = (rng.standard_normal((17, 17, 17)) + 1j * rng.standard_normal((17, 17, 17))) * mask
+        e_lu = coarse_solve(b, exact)
+        e_gm, steps = coarse_gmres(b, itv)
+        assert 10 <= steps <= 200
+        res = np.linalg.norm((b - apply_M(e_gm, itv.coarsest)) * mask) / np.linalg.norm(b)
+        assert res <= 1.5e-11, res
+        assert np.linalg.norm(e_gm - e_lu) / np.linalg.norm(e_lu) <= 1e-9
+        assert np.all(e_gm[~mask.astype(bool)] == 0)
+
+
+@pytest.mark.parametrize("bc", [DIRICHLET, SOMMERFELD])
+def test_cycles_with_coarse_gmres_equal_cycles_with_the_exact_coarse_solve(bc):
+    """V- and F-cycles whose coarsest level is solved by GMRES to 1e-11 agree
+    with the exact-solve cycles to about that tolerance (three levels down to
+    9^3, two right-hand sides; the mixed form solves its coarsest level in
+    complex128 too)."""
+    shape = (33, 33, 33)
+    k = np.random.default_rng(5).uniform(4.0, 12.0, shape)
+    rng = np.random.default_rng(6)
+    r = (rng.standard_normal((2,) + shape) + 1j * rng.standard_normal((2,) + shape)) * unknown_mask(shape, bc)
+    for dtype, tol in ((np.complex128, 1e-10), (np.complex64, 1e-5)):
+        exact = build_hierarchy(k, 1 / 32, bc, n_levels=3, dtype=dtype)
+        itv = build_hierarchy(k, 1 / 32, bc, n_levels=3, dtype=dtype, coarse="gmres")
+        for cyc in (vcycle, fcycle):
+            za = cyc(r.astype(dtype), exact)
+            zb = cyc(r.astype(dtype), itv)
+            assert zb.dtype == dtype
+            assert np.abs(zb - za).max() <= tol * np.abs(za).max(), (dtype, cyc.__name__)

@@ -379,3 +379,16 @@ def test_paper_table1_gmres_matvecs_exact():
     assert set(gold["gmres"]) == {145}
     assert res.matvecs == 145
     assert np.abs(res.x - uex).max() < 2e-3
+
+
+def test_paper_table1_gmres_matvecs_exact_with_the_coarse_gmres():
+    """Table 1 again with the paper's own coarsest solve (full GMRES to 1e-11
+    on the 17^3 grid instead of the exact solve): still exactly 145 matvecs."""
+    with open(os.path.join(GOLDEN, "table1_bicgstab_matvec.json")) as f:
+        gold = json.load(f)
+    lvl, b, uex = O.closed_off_problem(gold["problem"]["n"], gold["problem"]["k"])
+    hier = build_hierarchy(lvl.k, lvl.h, lvl.bc, rule="paper17", coarse="gmres")
+    res = O.gmres(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, tol=gold["problem"]["tol"])
+    assert res.status == O.Status.OK
+    assert res.matvecs == 145 == gold["gmres"][0]
+    assert np.abs(res.x - uex).max() < 2e-3
