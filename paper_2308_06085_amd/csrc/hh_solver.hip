@@ -335,8 +335,11 @@ void choose_tail(hh_ctx* c) {
 
 // Coarse GMRES buffers for m Arnoldi steps per cycle; grown only.
 hh_status cgm_alloc(hh_ctx* c, int m) {
-    if (!coarse_gmres_allow_lds(coarse_gmres_lds_bytes(m)))
-        return fail(c, HH_ERR_HIP, "the coarse GMRES kernel cannot get %zu bytes of LDS", coarse_gmres_lds_bytes(m));
+    // the kernels' LDS limit is process-wide: allow the largest m's needs, so
+    // contexts with different m never lower it under one another
+    const size_t lds = coarse_gmres_lds_bytes(COARSE_GMRES_MAX_M);
+    if (!coarse_gmres_allow_lds(lds))
+        return fail(c, HH_ERR_HIP, "the coarse GMRES kernel cannot get %zu bytes of LDS", lds);
     if (m <= c->cgm_alloc_m) return HH_OK;
     invalidate_graphs(c);  // captured cycles hold the old buffer's address
     for (void* q : {(void*)c->cgm_V, (void*)c->cgm_steps}) (void)hipFree(q);
