@@ -182,6 +182,24 @@ hh_status hh_solve(hh_ctx* ctx, void* x, double rtol, int maxit, int use_x0,
 /* y = A x (complex128), nrhs vectors. */
 hh_status hh_apply_operator(hh_ctx* ctx, const void* x, void* y, int nrhs);
 
+/* y = A x without a context and without allocating: for callers that cannot
+ * allocate device memory (code under graph capture, serving loops, harnesses
+ * that forbid hipMalloc).  Reads only nx, ny, nz, h and bc of cfg; k is the
+ * real wavenumber (nz, ny, nx) doubles, x and y are (nrhs, nz, ny, nx)
+ * complex128, all device pointers owned by the caller; work is enqueued on
+ * hip_stream (a hipStream_t, NULL = the default stream) and the call returns
+ * after enqueue.  The result equals hh_apply_operator's on a context with the
+ * same grid and model.  k^2 is staged in a library-owned device array of
+ * 2^23 doubles (64 MiB per device, held until the process ends): grids of more
+ * than 2^23 nodes, nrhs outside 1..16 or an invalid grid are HH_ERR_ARG
+ * (hh_last_error(NULL) gives the text).  k is not checked for NaN/Inf or
+ * negative values.  Calls that overlap on one device (for instance on two
+ * streams) share that array and race; calls in one stream order do not.  The
+ * first call on a device looks the array's device address up
+ * (hipGetSymbolAddress): make it outside graph capture. */
+hh_status hh_apply_operator_noalloc(const hh_config* cfg, const double* k, const void* x, void* y, int nrhs,
+                                    void* hip_stream);
+
 /* y = M x on the finest grid (complex128 arithmetic). */
 hh_status hh_apply_shifted(hh_ctx* ctx, const void* x, void* y, int nrhs);
 

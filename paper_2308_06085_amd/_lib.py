@@ -30,7 +30,7 @@ PREC = {"fp64": 0, "mixed": 1}
 EXPORTS = [
     "hh_default_config", "hh_create", "hh_destroy", "hh_last_error", "hh_level_shape",
     "hh_set_model", "hh_set_model_slowness2", "hh_set_sources", "hh_set_point_sources", "hh_solve",
-    "hh_apply_operator", "hh_apply_shifted", "hh_apply_vcycle", "hh_adjoint_rhs",
+    "hh_apply_operator", "hh_apply_operator_noalloc", "hh_apply_shifted", "hh_apply_vcycle", "hh_adjoint_rhs",
     "hh_grad_slowness2", "hh_set_shadow", "hh_set_option", "hh_get_option", "hh_time_kernel", "hh_kernel_times",
     "hh_autotune",
 ]
@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
         "hh_set_point_sources": (ip, [vp, C.POINTER(ip), ip]),
         "hh_solve": (ip, [vp, vp, dp, ip, ip, C.POINTER(Stats)]),
         "hh_apply_operator": (ip, [vp, vp, vp, ip]),
+        "hh_apply_operator_noalloc": (ip, [C.POINTER(Config), vp, vp, vp, ip, vp]),
         "hh_apply_shifted": (ip, [vp, vp, vp, ip]),
         "hh_apply_vcycle": (ip, [vp, vp, vp, ip]),
         "hh_adjoint_rhs": (ip, [vp, vp, vp, ip]),

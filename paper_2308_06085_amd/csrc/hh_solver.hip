@@ -58,6 +58,11 @@ struct LevelBuf {
 
 }  // namespace
 
+namespace hh {
+// error text of a failed call without a context (hh_last_error(NULL))
+void set_error_without_context(const std::string& msg) { g_create_error = msg; }
+}  // namespace hh
+
 struct hh_ctx {
     hh_config cfg{};
     hipStream_t stream = nullptr;

@@ -270,6 +270,30 @@ class Solver:
                 "autotune_source": self.get_option("autotune_source")}
 
 
+def apply_operator_noalloc(k: torch.Tensor, x: torch.Tensor, h: float, bc: str = "sommerfeld",
+                           out: torch.Tensor | None = None) -> torch.Tensor:
+    """y = A x with no solver context and no device allocation in the library
+    (``hh_apply_operator_noalloc``): k float64 (nz, ny, nx), x complex128
+    (nrhs, nz, ny, nx) or (nz, ny, nx), both on the device; ``out`` (same shape
+    as x) is written if given, else allocated here by PyTorch.  Enqueued on the
+    current stream."""
+    lib = _lib.load()
+    if x.dim() == 3:
+        x = x.unsqueeze(0)
+    nz, ny, nx = (int(v) for v in k.shape)
+    _require(k, torch.float64, (nz, ny, nx), "k")
+    _require(x, torch.complex128, (x.shape[0], nz, ny, nx), "x")
+    y = torch.empty_like(x) if out is None else out
+    _require(y, torch.complex128, tuple(x.shape), "out")
+    cfg = Config()
+    lib.hh_default_config(C.byref(cfg), nx, ny, nz, float(h))
+    cfg.bc = BC[bc]
+    stream = torch.cuda.current_stream(x.device)
+    check(lib.hh_apply_operator_noalloc(C.byref(cfg), _ptr(k), _ptr(x), _ptr(y), x.shape[0],
+                                        C.c_void_p(stream.cuda_stream)))
+    return y
+
+
 class HelmholtzSolve(torch.autograd.Function):
     """u = A(s)^-1 b with k = omega sqrt(s), s the squared slowness 1/c^2.
 

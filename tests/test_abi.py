@@ -90,3 +90,21 @@ def test_create_rejects_planes_beyond_the_partial_sum_capacity():
     assert lib.hh_create(ctypes.byref(cfg), None, ctypes.byref(ctx)) == 1
     assert b"tiles" in lib.hh_last_error(None)
 
+
+def test_noalloc_apply_validates_on_the_host():
+    """The non-allocating apply rejects grids beyond its scratch and invalid
+    arguments before any device call."""
+    if not os.path.exists(LIB):
+        pytest.skip("libhh.so not built")
+    from paper_2308_06085_amd import _lib
+
+    lib = _lib.load()
+    cfg = _lib.Config()
+    lib.hh_default_config(ctypes.byref(cfg), 257, 257, 129, 1.0)   # 8.5 M nodes > 2^23
+    assert lib.hh_apply_operator_noalloc(ctypes.byref(cfg), 16, 16, 16, 1, None) == 1
+    assert b"no-allocation scratch" in lib.hh_last_error(None)
+    lib.hh_default_config(ctypes.byref(cfg), 9, 9, 9, 1.0)
+    assert lib.hh_apply_operator_noalloc(ctypes.byref(cfg), 16, 16, 16, 0, None) == 1   # nrhs 0
+    assert lib.hh_apply_operator_noalloc(ctypes.byref(cfg), None, 16, 16, 1, None) == 1  # null k
+    cfg.ny = 8
+    assert lib.hh_apply_operator_noalloc(ctypes.byref(cfg), 16, 16, 16, 1, None) == 1
