@@ -8,6 +8,7 @@ the device code (``-target-feature -packed-fp32-ops``).
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -34,13 +35,20 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
              "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-    for src in SOURCES:
+    def compile_one(src):
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
         cmd = [cc, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         # the host pass does not know the device-only feature name: drop that line
         noise = [ln for ln in (r.stderr or "").splitlines() if "packed-fp32-ops" not in ln]
-        if r.returncode != 0:
+        return src, obj, r.returncode, noise
+
+    # one hipcc per source, several at a time
+    workers = max(1, min(len(SOURCES), os.cpu_count() or 1, 8))
+    with concurrent.futures.ThreadPoolExecutor(workers) as pool:
+        results = list(pool.map(compile_one, SOURCES))
+    for src, obj, rc, noise in results:
+        if rc != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n" + "\n".join(noise))
         if verbose and noise:
             print("\n".join(noise), file=sys.stderr)

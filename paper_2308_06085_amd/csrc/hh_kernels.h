@@ -81,22 +81,23 @@ struct MgParams {
 // 256, 512 or 1280; 0 = chosen by dn_region().  Ignored when zbc > 1.
 template <typename TB, typename R>
 void launch_mg_down(hipStream_t s, int bc, const Geo& gf, const Geo& gc, int zbc, int nrhs,
-                    const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
+                    const cx<TB>* b, long long b_rstride, const R* kl, const MgParams& P,
                     cx<R>* bc_out, const RhsState* st, int gate, int reg = 0);
 template <typename TB, typename R, typename TO>
 void launch_mg_up(hipStream_t s, int bc, const Geo& g, const Geo& gc, int zb, int nrhs,
-                  const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
+                  const cx<TB>* b, long long b_rstride, const R* kl, const MgParams& P,
                   const cx<R>* ec, cx<TO>* out, long long o_rstride, const RhsState* st, int gate,
                   bool acc = false);
 // b = b - M e in place on a level below the finest (one precision throughout)
 template <typename R>
-void launch_mg_resid(hipStream_t s, int bc, const Geo& g, int nrhs, cx<R>* b, const cx<R>* e, const R* k2l,
+void launch_mg_resid(hipStream_t s, int bc, const Geo& g, int nrhs, cx<R>* b, const cx<R>* e, const R* kl,
                      const MgParams& P, const RhsState* st, int gate);
 int mg_down_blocks(const Geo& gc, int zbc);
 // region of the down pass into a coarse grid gc: the automatic choice for
 // (zbc, nrhs), or `want` (256, 512, 1280) where it applies (zbc = 1)
 int mg_down_region(const Geo& gc, int zbc, int nrhs, int want);
-int mg_up_blocks(const Geo& g, int zb);
+// workgroups of the up pass on level g in the compute precision (single: the x-pair kernel)
+int mg_up_blocks(const Geo& g, int zb, bool single);
 
 // The trailing (smallest) levels of the hierarchy, run by one workgroup per
 // right-hand side with every array in LDS.  off = offset of the level's nodes
@@ -106,7 +107,7 @@ struct TailLevel {
     int nx, ny, nz, n, off;
     unsigned rcp_nx, rcp_plane;  // ceil(2^32 / nx), ceil(2^32 / (nx ny)): index division by multiply-high
     double h;
-    const void* k2;  // level k^2 in the multigrid precision (device)
+    const void* k;   // level wavenumber in the multigrid precision (device)
 };
 struct TailDesc {
     int nlev, total, n_unk;
@@ -150,6 +151,9 @@ void launch_model_from_slowness2(hipStream_t s, long long n, const double* s2, d
 void launch_inject(hipStream_t s, const Geo& gf, const Geo& gc, const double* kf, double* kc);
 template <typename R>
 void launch_level_k2(hipStream_t s, long long n, const double* k, R* k2);
+// k of a level rounded to the multigrid precision (the multigrid passes form k^2 from it)
+template <typename R>
+void launch_level_k(hipStream_t s, long long n, const double* k, R* kl);
 void launch_copy_rhs(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* src, c128* dst);
 void launch_adjoint_rhs(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* gin, c128* out);
 void launch_grad_s(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* u, const c128* w,

@@ -817,6 +817,18 @@ void launch_level_k2(hipStream_t s, long long n, const double* k, R* k2) {
 }
 template void launch_level_k2<double>(hipStream_t, long long, const double*, double*);
 template void launch_level_k2<float>(hipStream_t, long long, const double*, float*);
+template <typename R>
+__global__ void k_level_k(long long n, const double* __restrict__ k, R* __restrict__ kl) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        kl[i] = R(k[i]);
+}
+template <typename R>
+void launch_level_k(hipStream_t s, long long n, const double* k, R* kl) {
+    hipLaunchKernelGGL((k_level_k<R>), dim3(flat_blocks(n, 256, 8192)), dim3(256), 0, s, n, k, kl);
+}
+template void launch_level_k<double>(hipStream_t, long long, const double*, double*);
+template void launch_level_k<float>(hipStream_t, long long, const double*, float*);
 void launch_copy_rhs(hipStream_t s, const Geo& g, int bc, int nrhs, const c128* src, c128* dst) {
     hipLaunchKernelGGL(k_copy_rhs, dim3(flat_blocks((long long)nrhs * g.n, 256, 8192)), dim3(256), 0,
                        s, g, bc, nrhs, src, dst);

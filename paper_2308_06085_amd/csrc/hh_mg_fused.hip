@@ -17,7 +17,7 @@
 // relative accuracy in single precision instead of losing a factor of about
 // 6 / (k h)^2 to cancellation in 6 u_j - sum u_nb.
 //
-// Only the level's k^2 is stored; c, D and W are recomputed per node.  Both
+// Only the level's k is stored; c, D and W are recomputed per node.  Both
 // kernels stage x-y planes of a tile and its halo in LDS and march along z with
 // a ring of three planes; the global loads of the next two planes are issued
 // into registers before the current plane is computed.  Halo positions outside the
@@ -34,7 +34,6 @@
 namespace hh {
 
 __device__ __forceinline__ int ring3(int f) { return ((f % 3) + 3) % 3; }
-__device__ __forceinline__ int ring4(int f) { return f & 3; }  // also for f = -1
 
 constexpr int DN_LANES = 256, DN_MAXH = 16;
 // Fine region nodes staged by a down-pass workgroup: DN_REGION on the large
@@ -54,18 +53,37 @@ __host__ __device__ inline TileShape dn_tile_shape(int nx, int ny, int reg) {
     }
     return T;
 }
-constexpr int UP_LANES = 512, UP_MAXW = 32;  // up pass: one lane per region node
-// Tile of the up pass: the tile plus a one-node halo must fit the lanes,
-// (tw + 2)(th + 2) <= lanes.
+// Up pass: 512 lanes, each owning two x-adjacent nodes (an x-pair) of the
+// tile-plus-halo region, so a region row holds up to 64 nodes.
+constexpr int UP_LANES = 512, UP_MAXW = 62;
+// Tile of the up pass: an even width tw <= UP_MAXW (the region, tw + 2 nodes
+// wide from X0 - 1, is then a whole number of x-pairs), the plane split into
+// nearly equal tiles, and as many rows th as leave the region's rows of pairs
+// within the lanes: (th + 2) (tw + 2) / 2 <= UP_LANES.
 __host__ __device__ inline TileShape up_tile_shape(int nx, int ny) {
     TileShape T;
     T.ntx = (nx + UP_MAXW - 1) / UP_MAXW;
+    T.tw = (nx + T.ntx - 1) / T.ntx;
+    T.tw += T.tw & 1;
+    T.th = UP_LANES / ((T.tw + 2) / 2) - 2;
+    if (T.th > ny) T.th = ny;
+    T.nty = (ny + T.th - 1) / T.th;
+    return T;
+}
+
+// Tile of the one-node-per-lane up pass (double precision): the tile plus a
+// one-node halo must fit the lanes, (tw + 2)(th + 2) <= UP_LANES.
+constexpr int UP1_MAXW = 32;
+__host__ __device__ inline TileShape up1_tile_shape(int nx, int ny) {
+    TileShape T;
+    T.ntx = (nx + UP1_MAXW - 1) / UP1_MAXW;
     T.tw = (nx + T.ntx - 1) / T.ntx;
     T.th = UP_LANES / (T.tw + 2) - 2;
     if (T.th > ny) T.th = ny;
     T.nty = (ny + T.th - 1) / T.th;
     return T;
 }
+__device__ __forceinline__ int ring4i(int f) { return f & 3; }  // also for f = -1
 
 // Level constants of the CSLP operator in the compute precision.
 template <typename R>
@@ -85,19 +103,19 @@ __device__ __forceinline__ LevelCoef<R> level_coef(const Geo& g, double beta1, d
     return L;
 }
 
-// Square root and reciprocal: correctly rounded in double; in single precision
-// the hardware v_sqrt_f32 / v_rcp_f32 (about 1 ulp), far inside the accuracy a
-// complex64 V-cycle is held to.
-__device__ __forceinline__ double mg_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float mg_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// Reciprocal: correctly rounded in double; in single precision the hardware
+// v_rcp_f32 (about 1 ulp), far inside the accuracy a complex64 V-cycle is
+// held to.
 __device__ __forceinline__ double mg_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float mg_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// c_j = (beta1 - beta2 i) k^2 + n_j 2 i k / h
+// c_j = (beta1 - beta2 i) k^2 + n_j 2 i k / h from the level's k (k^2 formed
+// in the compute precision)
 template <typename R>
-__device__ __forceinline__ cx<R> shift_c(const LevelCoef<R>& L, R k2, int nf) {
+__device__ __forceinline__ cx<R> shift_c(const LevelCoef<R>& L, R k, int nf) {
+    const R k2 = k * k;
     cx<R> c = {L.sr * k2, L.si * k2};
-    if (nf) c.im += R(nf) * L.two_over_h * mg_sqrt(k2);
+    if (nf) c.im += R(nf) * L.two_over_h * k;
     return c;
 }
 // W = omega / (6/h^2 - c)
@@ -116,7 +134,7 @@ __device__ __forceinline__ int faces_of(int x, int y, int z, const Geo& g) {
 // Down: b_H = R (b - M W b).  The workgroup owns a tw x th tile of coarse
 // columns and marches over `zbc` coarse planes (2 zbc + 1 fine residual
 // planes).  Each lane owns NU nodes of the fine region (tile plus a two-node
-// halo): it loads their b and k^2, writes u1 = W b to the LDS ring, and keeps
+// halo): it loads their b and k, writes u1 = W b to the LDS ring, and keeps
 // b and c in registers for the residual of the same nodes one plane later, so
 // every input is read once per plane.  Two planes of loads are in flight.
 // ---------------------------------------------------------------------------
@@ -135,7 +153,7 @@ template <int BC, typename TB, typename R, bool ONE, int REG>
 __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
                                                       const cx<TB>* __restrict__ b,
                                                       long long b_rstride,
-                                                      const R* __restrict__ k2l, double beta1,
+                                                      const R* __restrict__ kl, double beta1,
                                                       double beta2, double omega,
                                                       cx<R>* __restrict__ bc_out,
                                                       const RhsState* st, int gate) {
@@ -183,7 +201,7 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
             w.b[k] = br[base + uoff[k]];
-            w.k[k] = k2l[base + uoff[k]];
+            w.k[k] = kl[base + uoff[k]];
         }
         // keep the scheduler from moving these loads past later ones: loads
         // complete in issue order, so a plane must be issued as one group
@@ -307,19 +325,18 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
 // ---------------------------------------------------------------------------
 // Up: u3 = u2 + W (b - (1/h^2) lap(u2) + c u2), u2 = W b + P e_H.  Each lane
 // owns one node of the tile-plus-halo region; the lanes inside the halo
-// compute the output.  The workgroup marches over `zb` planes.  With ACC the
-// pass adds u3 to the output instead of storing it (the F-cycle's second
-// coarse-grid cycle).
+// compute the output.  The workgroup marches over `zb` planes (double
+// precision; single precision takes the x-pair kernel k_mg_up below, which
+// needs fewer instructions per node but more registers per lane than double
+// precision leaves).  Every node's arithmetic is the same for every tile and
+// z-block.  With ACC the pass adds u3 to the output instead of storing it
+// (the F-cycle's second coarse-grid cycle).
 // ---------------------------------------------------------------------------
-// Waves per SIMD the up pass is compiled for: three 512-lane workgroups per CU
-// in single precision (<= 80 VGPRs), two in double (<= 128 VGPRs).
-template <typename R>
-constexpr int UP_WAVES_PER_SIMD = sizeof(R) == sizeof(float) ? 6 : 4;
-
-template <int BC, typename TB, typename R, typename TO, bool ONE, bool ACC>
-__global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g, Geo gc, int zb,
+// Compiled for two 512-lane workgroups per CU (<= 128 VGPRs).
+template <int BC, typename TB, typename R, typename TO, bool ACC>
+__global__ __launch_bounds__(UP_LANES, 4) void k_mg_up1(Geo g, Geo gc, int zb,
                                                     const cx<TB>* __restrict__ b, long long b_rstride,
-                                                    const R* __restrict__ k2l, double beta1,
+                                                    const R* __restrict__ kl, double beta1,
                                                     double beta2, double omega,
                                                     const cx<R>* __restrict__ ec,
                                                     cx<TO>* __restrict__ out, long long o_rstride,
@@ -331,7 +348,7 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
     const int r = blockIdx.z;
     if (!gate_ok(st, r, gate)) return;
     const int t = threadIdx.x;
-    const TileShape T = up_tile_shape(g.nx, g.ny);
+    const TileShape T = up1_tile_shape(g.nx, g.ny);
     const int RW = T.tw + 2, RH = T.th + 2;
     const int id = xcd_tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int tz = id / gridDim.x;
@@ -359,14 +376,6 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
     const bool own = in_region && lx >= 1 && lx <= T.tw && ly >= 1 && ly <= T.th && gxr < g.nx &&
                      gyr < g.ny;
 
-    // raw loads of one plane: b, k^2 and the eight coarse corners.  Loads are
-    // issued unconditionally (every offset is a valid node); a plane past the
-    // chunk's last one re-reads that plane instead (an L2 hit).
-    struct Raw {
-        cx<TB> b;
-        R k;
-        cx<R> e[8];
-    };
     // shift c of a node, made with its u2 and kept for its output step; in
     // double precision also its Jacobi weight W = omega / (6/h^2 - c) (in
     // single precision recomputing W is cheaper than the registers that
@@ -375,44 +384,6 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
     struct CW {
         cx<R> c, w;
     };
-    auto fetch = [&](int f, Raw& w) {
-        const int fz = mirror_clamp(min(f, z1), g.nz);
-        const long long base = (long long)fz * g.plane;
-        const cx<R>* e0 = er + (long long)(fz >> 1) * gc.plane;
-        const cx<R>* e1 = er + (long long)min((fz >> 1) + (fz & 1), gc.nz - 1) * gc.plane;
-        w.b = br[base + uoff];
-        w.k = k2l[base + uoff];
-        w.e[0] = e0[cy0 + cx0];
-        w.e[1] = e0[cy0 + cx1];
-        w.e[2] = e0[cy1 + cx0];
-        w.e[3] = e0[cy1 + cx1];
-        w.e[4] = e1[cy0 + cx0];
-        w.e[5] = e1[cy0 + cx1];
-        w.e[6] = e1[cy1 + cx0];
-        w.e[7] = e1[cy1 + cx1];
-    };
-    // u2 at this lane's node of plane f, also written to the ring for the
-    // stencil of the output lanes; c is returned for the output step
-    auto make_u2 = [&](int f, const Raw& w, CW& k_out) -> cx<R> {
-        const int fz = mirror_clamp(f, g.nz);
-        const int zf = (fz == 0) + (fz == g.nz - 1);
-        const R wz = (fz & 1) ? R(0.5) : R(1), bz = R(1) - wz;
-        // trilinear interpolation; an even index takes its own coarse node only
-        const cx<R> p0 = ax * w.e[0] + bx * w.e[1];
-        const cx<R> p1 = ax * w.e[2] + bx * w.e[3];
-        const cx<R> p2 = ax * w.e[4] + bx * w.e[5];
-        const cx<R> p3 = ax * w.e[6] + bx * w.e[7];
-        const cx<R> pe = wz * (ay * p0 + by * p1) + bz * (ay * p2 + by * p3);
-        const int nf = BC == BC_SOMMERFELD ? unf + zf : 0;
-        k_out.c = shift_c(L, w.k, nf);
-        const cx<R> wj = jacobi_w(L, k_out.c);
-        if constexpr (KEEP_W) k_out.w = wj;
-        cx<R> v = wj * cvt<R>(w.b) + pe;
-        if (BC == BC_DIRICHLET && (unf || zf)) v = czero<R>();
-        us[ring4(f)][t] = v;  // unguarded: lanes past the region write slots never read
-        return v;
-    };
-
     cx<TO>* orr = out + (long long)r * o_rstride;
     const long long ooff = own ? (long long)gyr * g.nx + gxr : 0;
     // u3 of plane z at the output lanes, from the u2 ring and this lane's u2, b, c.
@@ -420,9 +391,9 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
     // nz - 2 (the eliminated ghost point), whose u2 is already in the ring.
     auto emit = [&](int z, const cx<R>& u, const CW& k, const cx<TB>& bz) {
         if (own) {
-            const cx<R>* um = us[ring4(z == 0 ? 1 : z - 1)];
-            const cx<R>* uc = us[ring4(z)];
-            const cx<R>* up = us[ring4(z == g.nz - 1 ? g.nz - 2 : z + 1)];
+            const cx<R>* um = us[ring4i(z == 0 ? 1 : z - 1)];
+            const cx<R>* uc = us[ring4i(z)];
+            const cx<R>* up = us[ring4i(z == g.nz - 1 ? g.nz - 2 : z + 1)];
             cx<R> lap = (u - uc[t - 1]) + (u - uc[t + 1]);
             lap = lap + (u - uc[t - RW]);
             lap = lap + (u - uc[t + RW]);
@@ -437,23 +408,10 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
         }
     };
     // per plane this lane keeps its own u2, b, c for the output step
-    Raw w, w2;
     cx<R> u_cur;
     CW c_cur, c_nxt, c_unused;
     cx<TB> b_cur, b_nxt;
-    if constexpr (ONE) {
-        // one plane per workgroup (the small levels, where latency rules):
-        // its three planes are loaded in one round
-        Raw w3;
-        fetch(z0 - 1, w);
-        fetch(z0, w2);
-        fetch(z0 + 1, w3);
-        (void)make_u2(z0 - 1, w, c_unused);
-        u_cur = make_u2(z0, w2, c_cur);
-        (void)make_u2(z0 + 1, w3, c_unused);
-        __syncthreads();
-        emit(z0, u_cur, c_cur, w2.b);
-    } else {
+    {
         // March over the u2 planes z0 - 1 .. z1 clamped into the grid (the
         // output step reads a mirrored plane's image instead), two planes of
         // loads in flight.  Plane f interpolates between coarse planes
@@ -470,7 +428,7 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
             const long long base = (long long)fc * g.plane;
             const cx<R>* e1 = er + (long long)((fc >> 1) + (fc & 1)) * gc.plane;
             v.b = br[base + uoff];
-            v.k = k2l[base + uoff];
+            v.k = kl[base + uoff];
             v.e[0] = e1[cy0 + cx0];
             v.e[1] = e1[cy0 + cx1];
             v.e[2] = e1[cy1 + cx0];
@@ -495,7 +453,7 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
             if constexpr (KEEP_W) k_out.w = wj;
             cx<R> u = wj * cvt<R>(v.b) + pe;
             if (BC == BC_DIRICHLET && (unf || zf)) u = czero<R>();
-            us[ring4(f)][t] = u;  // unguarded: lanes past the region write slots never read
+            us[ring4i(f)][t] = u;  // unguarded: lanes past the region write slots never read
             return u;
         };
         auto step = [&](int z, RawC& v) {
@@ -535,6 +493,206 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
 }
 
 // ---------------------------------------------------------------------------
+// Up: u3 = u2 + W (b - (1/h^2) lap(u2) + c u2), u2 = W b + P e_H.  Each lane
+// owns an x-pair of the tile-plus-halo region: nodes x_a = X0 - 1 + 2 p and
+// x_b = x_a + 1 of region row ly.  The two nodes' trilinear interpolations
+// draw on the same two coarse columns, so a lane loads four coarse values per
+// plane (two columns on the two coarse rows of its fine row) and interpolates
+// each column in y and z once.  The workgroup marches over `zb` planes; the
+// u2 planes go to a ring of four LDS planes, one barrier per plane.  Every
+// node's arithmetic is the same for every tile and z-block, so the result
+// does not depend on them.  With ACC the pass adds u3 to the
+// output instead of storing it (the F-cycle's second coarse-grid cycle).
+// ---------------------------------------------------------------------------
+template <typename R>
+constexpr int UP_WAVES_PER_SIMD = 4;  // two 512-lane workgroups per CU
+
+template <int BC, typename TB, typename R, typename TO, bool ACC>
+__global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g, Geo gc, int zb,
+                                                    const cx<TB>* __restrict__ b, long long b_rstride,
+                                                    const R* __restrict__ kl, double beta1,
+                                                    double beta2, double omega,
+                                                    const cx<R>* __restrict__ ec,
+                                                    cx<TO>* __restrict__ out, long long o_rstride,
+                                                    const RhsState* st, int gate) {
+    // a ring of four u2 planes: the output step of plane z reads planes z - 1
+    // and z while plane z + 1 is written, so one barrier per plane suffices.
+    // Each plane holds the region's a nodes (even region columns) in its
+    // first half and the b nodes (odd columns) in its second: consecutive
+    // lanes touch consecutive slots.
+    __shared__ cx<R> us[4][2 * UP_LANES];
+
+    const int r = blockIdx.z;
+    if (!gate_ok(st, r, gate)) return;
+    const int t = threadIdx.x;
+    const TileShape T = up_tile_shape(g.nx, g.ny);
+    const int P = (T.tw + 2) / 2;  // x-pairs per region row
+    const int id = xcd_tile_id(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int tz = id / gridDim.x;
+    const int txy = id - tz * gridDim.x;
+    const int tyi = txy / T.ntx, txi = txy - tyi * T.ntx;
+    const int X0 = txi * T.tw, Y0 = tyi * T.th;
+    const int z0 = tz * zb, z1 = min(g.nz, z0 + zb);
+    const cx<TB>* br = b + (long long)r * b_rstride;
+    const cx<R>* er = ec + (long long)r * gc.n;
+    const LevelCoef<R> L = level_coef<R>(g, beta1, beta2, omega);
+
+    // this lane's pair: region row ly, nodes at region columns 2 px, 2 px + 1
+    const int ly = t / P, px = t - ly * P;
+    const int xa = X0 - 1 + 2 * px, xb = xa + 1, yr = Y0 - 1 + ly;
+    const int gxa = mirror_clamp(xa, g.nx), gxb = mirror_clamp(xb, g.nx), gy = mirror_clamp(yr, g.ny);
+    const int offa = gy * g.nx + gxa, offb = gy * g.nx + gxb;
+    const int nfxy = (gy == 0) + (gy == g.ny - 1);
+    const int nfa = nfxy + (gxa == 0) + (gxa == g.nx - 1), nfb = nfxy + (gxb == 0) + (gxb == g.nx - 1);
+    // coarse columns cb, cb + 1 and rows cy0, cy1 of the pair's interpolation
+    const int cb = min(gxa >> 1, gxb >> 1), cb1 = min(cb + 1, gc.nx - 1);
+    const int cy0 = gy >> 1, cy1 = min(cy0 + (gy & 1), gc.ny - 1);
+    const int e00 = cy0 * gc.nx + cb, e01 = cy0 * gc.nx + cb1, e10 = cy1 * gc.nx + cb, e11 = cy1 * gc.nx + cb1;
+    // linear interpolation weights on the two points of an axis: an odd fine
+    // index takes 1/2 of each, an even one all of its own coarse point
+    const R ay = (gy & 1) ? R(0.5) : R(1), by = R(1) - ay;
+    const R wa0 = (gxa & 1) ? R(0.5) : ((gxa >> 1) == cb ? R(1) : R(0)), wa1 = R(1) - wa0;
+    const R wb0 = (gxb & 1) ? R(0.5) : ((gxb >> 1) == cb ? R(1) : R(0)), wb1 = R(1) - wb0;
+    // output nodes: inside the halo and on the grid
+    const bool rows_own = ly >= 1 && ly <= T.th && yr < g.ny;
+    const bool own_a = rows_own && 2 * px >= 1 && 2 * px <= T.tw && xa < g.nx;
+    const bool own_b = rows_own && 2 * px + 1 <= T.tw && xb < g.nx;
+    // LDS slots: node a at t (first half), node b at UP_LANES + t; the row
+    // neighbours of a slot are P slots away
+    const int sa = t, sb = UP_LANES + t;
+
+    // raw loads of one plane: b and k of both nodes, the four coarse values on
+    // the coarse plane c1 = (f >> 1) + (f & 1).  Issued unconditionally (every
+    // offset is a valid node); planes are clamped into plo .. phi.
+    const int plo = max(z0 - 1, 0), phi = min(z1, g.nz - 1);
+    struct Raw {
+        cx<TB> ba, bb;
+        R ka, kb;
+        cx<R> e[4];
+    };
+    auto fetch = [&](int f, Raw& v) {
+        const int fc = min(max(f, plo), phi);
+        const long long base = (long long)fc * g.plane;
+        const cx<R>* e1 = er + (long long)((fc >> 1) + (fc & 1)) * gc.plane;
+        v.ba = br[base + offa];
+        v.bb = br[base + offb];
+        v.ka = kl[base + offa];
+        v.kb = kl[base + offb];
+        v.e[0] = e1[e00];
+        v.e[1] = e1[e01];
+        v.e[2] = e1[e10];
+        v.e[3] = e1[e11];
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    static_assert(sizeof(R) == sizeof(float), "the x-pair up pass runs in single precision");
+    // per node and plane: u2 and the b, c and W its output step needs
+    constexpr bool KEEP_C = true;
+    struct Node {
+        cx<R> u, b, c, w;
+        R k;
+    };
+    struct Pair {
+        Node a, b;
+    };
+    cx<R> carry0, carry1;  // y-interpolated coarse columns of the previous plane's c1
+    // u2 of plane f for both nodes, staged in the ring
+    auto make = [&](int f, const Raw& v, Pair& o) {
+        const int fc = min(max(f, plo), phi);
+        const int zf = (fc == 0) + (fc == g.nz - 1);
+        // y on the new coarse plane c1, then z with the previous plane's c1
+        // (= this plane's c0 for odd f), then x
+        const R wz = (fc & 1) ? R(0.5) : R(1), bz = R(1) - wz;
+        const cx<R> p0 = ay * v.e[0] + by * v.e[2];
+        const cx<R> p1 = ay * v.e[1] + by * v.e[3];
+        const cx<R> q0 = wz * ((fc & 1) ? carry0 : p0) + bz * p0;
+        const cx<R> q1 = wz * ((fc & 1) ? carry1 : p1) + bz * p1;
+        carry0 = p0;
+        carry1 = p1;
+        const cx<R> pea = wa0 * q0 + wa1 * q1;
+        const cx<R> peb = wb0 * q0 + wb1 * q1;
+        o.a.b = cvt<R>(v.ba);
+        o.b.b = cvt<R>(v.bb);
+        o.a.k = v.ka;
+        o.b.k = v.kb;
+        const cx<R> ca = shift_c(L, v.ka, BC == BC_SOMMERFELD ? nfa + zf : 0);
+        const cx<R> cb2 = shift_c(L, v.kb, BC == BC_SOMMERFELD ? nfb + zf : 0);
+        if constexpr (KEEP_C) {
+            o.a.c = ca;
+            o.b.c = cb2;
+        }
+        o.a.w = jacobi_w(L, ca);
+        o.b.w = jacobi_w(L, cb2);
+        o.a.u = o.a.w * o.a.b + pea;
+        o.b.u = o.b.w * o.b.b + peb;
+        if (BC == BC_DIRICHLET && (nfa || zf)) o.a.u = czero<R>();
+        if (BC == BC_DIRICHLET && (nfb || zf)) o.b.u = czero<R>();
+        cx<R>* dst = us[f & 3];  // f >= -1: f & 3 is the ring slot (also for -1)
+        dst[sa] = o.a.u;
+        dst[sb] = o.b.u;
+    };
+
+    cx<TO>* orr = out + (long long)r * o_rstride;
+    const long long oa = (long long)gy * g.nx + gxa, ob = (long long)gy * g.nx + gxb;
+    // u3 of plane z at the pair's output nodes (past the bottom / top plane
+    // the z neighbour is the mirror image: plane 1 / nz - 2)
+    auto emit = [&](int z, const Pair& c, const Pair& n) {
+        const cx<R>* uc = us[z & 3];
+        const cx<R>* um = us[(z - 1) & 3];
+        const bool bot = z == 0, top = z == g.nz - 1;
+        const int zfz = (int)bot + (int)top;
+        auto out1 = [&](const Node& nd, const cx<R>& xm, const cx<R>& xp, const cx<R>& ym, const cx<R>& yp,
+                        const cx<R>& zm, const cx<R>& zp, int nf, long long off) {
+            const cx<R> u = nd.u;
+            cx<R> lap = (u - xm) + (u - xp);
+            lap = lap + (u - ym);
+            lap = lap + (u - yp);
+            lap = lap + (u - (bot ? zp : zm));
+            lap = lap + (u - (top ? zm : zp));
+            const cx<R> cc = KEEP_C ? nd.c : shift_c(L, nd.k, BC == BC_SOMMERFELD ? nf + zfz : 0);
+            cx<R> v = u + nd.w * ((nd.b - L.ih2 * lap) + cc * u);
+            if (BC == BC_DIRICHLET && (nf || bot || top)) v = czero<R>();
+            cx<TO>* o = orr + (long long)z * g.plane + off;
+            if constexpr (ACC) v = cvt<R>(*o) + v;  // out already holds an earlier cycle's result
+            *o = cvt<TO>(v);
+        };
+        if (own_a)  // x - 1: the b node of the pair to the left; x + 1: this pair's b node
+            out1(c.a, uc[sb - 1], c.b.u, uc[sa - P], uc[sa + P], um[sa], n.a.u, nfa, oa);
+        if (own_b)  // x - 1: this pair's a node; x + 1: the a node of the pair to the right
+            out1(c.b, c.a.u, uc[sa + 1], uc[sb - P], uc[sb + P], um[sb], n.b.u, nfb, ob);
+    };
+
+    // carry for the first plane: the y-interpolated columns of coarse plane plo >> 1
+    {
+        const cx<R>* e0 = er + (long long)(plo >> 1) * gc.plane;
+        carry0 = ay * e0[e00] + by * e0[e10];
+        carry1 = ay * e0[e01] + by * e0[e11];
+    }
+    // u2 on planes z0 - 1 .. z1 (clamped into the grid; a clamped duplicate is
+    // never read).  Two pair sets X, Y alternate as the current and the next
+    // plane, and two planes of loads are in flight (set A holds the planes
+    // z0 - 1 + even, set B the odd ones).
+    Pair X, Y;
+    auto step = [&](int z, Pair& cur, Pair& nxt, Raw& v, int ahead) {
+        make(z + 1, v, nxt);
+        fetch(z + 1 + ahead, v);
+        __syncthreads();
+        emit(z, cur, nxt);
+    };
+    Raw A, B;
+    fetch(z0 - 1, A);
+    fetch(z0, B);
+    make(z0 - 1, A, Y);
+    fetch(z0 + 1, A);
+    make(z0, B, X);
+    fetch(z0 + 2, B);
+    for (int z = z0; z < z1; z += 2) {
+        step(z, X, Y, A, 2);
+        if (z + 1 >= z1) break;
+        step(z + 1, Y, X, B, 2);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Residual in place: b = b - M e = b - (1/h^2) lap(e) + c e on a level below
 // the finest (the F-cycle's second coarse-grid cycle starts from it).  One
 // lane per in-plane node marching over `zb` planes; the neighbours are read
@@ -546,7 +704,7 @@ constexpr int RS_LANES = 256;
 template <int BC, typename R>
 __global__ __launch_bounds__(RS_LANES) void k_mg_resid(Geo g, int zb, cx<R>* __restrict__ b,
                                                        const cx<R>* __restrict__ e,
-                                                       const R* __restrict__ k2l, double beta1,
+                                                       const R* __restrict__ kl, double beta1,
                                                        double beta2, double omega, const RhsState* st,
                                                        int gate) {
     const int r = blockIdx.z;
@@ -573,7 +731,7 @@ __global__ __launch_bounds__(RS_LANES) void k_mg_resid(Geo g, int zb, cx<R>* __r
         lap = lap + (u - er[j + dzm]);
         lap = lap + (u - er[j + dzp]);
         const int nf = nfxy + (z == 0) + (z == g.nz - 1);
-        const cx<R> c = shift_c(L, k2l[j], BC == BC_SOMMERFELD ? nf : 0);
+        const cx<R> c = shift_c(L, kl[j], BC == BC_SOMMERFELD ? nf : 0);
         cx<R> v = (br[j] - L.ih2 * lap) + c * u;
         if (BC == BC_DIRICHLET && nf) v = czero<R>();
         br[j] = v;
@@ -587,8 +745,8 @@ int mg_down_blocks(const Geo& gc, int zbc) {
     const TileShape T = dn_tile_shape(gc.nx, gc.ny, DN_REGION);
     return T.ntx * T.nty * ((gc.nz + zbc - 1) / zbc);
 }
-int mg_up_blocks(const Geo& g, int zb) {
-    const TileShape T = up_tile_shape(g.nx, g.ny);
+int mg_up_blocks(const Geo& g, int zb, bool single) {
+    const TileShape T = single ? up_tile_shape(g.nx, g.ny) : up1_tile_shape(g.nx, g.ny);
     return T.ntx * T.nty * ((g.nz + zb - 1) / zb);
 }
 
@@ -625,14 +783,14 @@ int mg_down_region(const Geo& gc, int zbc, int nrhs, int want) {
 
 template <typename TB, typename R>
 void launch_mg_down(hipStream_t s, int bc, const Geo& gf, const Geo& gc, int zbc, int nrhs,
-                    const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
+                    const cx<TB>* b, long long b_rstride, const R* kl, const MgParams& P,
                     cx<R>* bc_out, const RhsState* st, int gate, int reg_want) {
     const int reg = mg_down_region(gc, zbc, nrhs, reg_want);
     const TileShape T = dn_tile_shape(gc.nx, gc.ny, reg);
     dim3 grid(T.ntx * T.nty, (gc.nz + zbc - 1) / zbc, nrhs);
 #define HH_DOWN(BCV, ONEV, REGV)                                                                                \
     hipLaunchKernelGGL((k_mg_down<BCV, TB, R, ONEV, REGV>), grid, dim3(DN_LANES), 0, s, gf, gc, zbc, b, b_rstride, \
-                       k2l, P.beta1, P.beta2, P.omega, bc_out, st, gate)
+                       kl, P.beta1, P.beta2, P.omega, bc_out, st, gate)
 #define HH_DOWN_BC(BCV)                                   \
     if (zbc != 1) HH_DOWN(BCV, false, DN_REGION);         \
     else if (reg == 256) HH_DOWN(BCV, true, 256);         \
@@ -649,21 +807,24 @@ void launch_mg_down(hipStream_t s, int bc, const Geo& gf, const Geo& gc, int zbc
 
 template <typename TB, typename R, typename TO>
 void launch_mg_up(hipStream_t s, int bc, const Geo& g, const Geo& gc, int zb, int nrhs,
-                  const cx<TB>* b, long long b_rstride, const R* k2l, const MgParams& P,
+                  const cx<TB>* b, long long b_rstride, const R* kl, const MgParams& P,
                   const cx<R>* ec, cx<TO>* out, long long o_rstride, const RhsState* st, int gate,
                   bool acc) {
-    const TileShape T = up_tile_shape(g.nx, g.ny);
+    constexpr bool PAIRS = sizeof(R) == sizeof(float);  // x-pair kernel in single precision
+    const TileShape T = PAIRS ? up_tile_shape(g.nx, g.ny) : up1_tile_shape(g.nx, g.ny);
     dim3 grid(T.ntx * T.nty, (g.nz + zb - 1) / zb, nrhs);
-#define HH_UP(BCV, ONEV, ACCV)                                                                          \
-    hipLaunchKernelGGL((k_mg_up<BCV, TB, R, TO, ONEV, ACCV>), grid, dim3(UP_LANES), 0, s, g, gc, zb, b,    \
-                       b_rstride, k2l, P.beta1, P.beta2, P.omega, ec, out, o_rstride, st, gate)
-#define HH_UP_BC(ACCV)                                     \
-    if (bc == BC_SOMMERFELD) {                             \
-        if (zb == 1) HH_UP(BC_SOMMERFELD, true, ACCV);     \
-        else HH_UP(BC_SOMMERFELD, false, ACCV);            \
-    } else {                                               \
-        if (zb == 1) HH_UP(BC_DIRICHLET, true, ACCV);      \
-        else HH_UP(BC_DIRICHLET, false, ACCV);             \
+#define HH_UP(BCV, ACCV)                                                                                 \
+    if constexpr (PAIRS)                                                                                \
+        hipLaunchKernelGGL((k_mg_up<BCV, TB, R, TO, ACCV>), grid, dim3(UP_LANES), 0, s, g, gc, zb, b,     \
+                           b_rstride, kl, P.beta1, P.beta2, P.omega, ec, out, o_rstride, st, gate);      \
+    else                                                                                                \
+        hipLaunchKernelGGL((k_mg_up1<BCV, TB, R, TO, ACCV>), grid, dim3(UP_LANES), 0, s, g, gc, zb, b,    \
+                           b_rstride, kl, P.beta1, P.beta2, P.omega, ec, out, o_rstride, st, gate)
+#define HH_UP_BC(ACCV)                     \
+    if (bc == BC_SOMMERFELD) {             \
+        HH_UP(BC_SOMMERFELD, ACCV);        \
+    } else {                               \
+        HH_UP(BC_DIRICHLET, ACCV);         \
     }
     // accumulation only on the levels below the finest, where input, compute
     // and output precision are one
@@ -679,7 +840,7 @@ void launch_mg_up(hipStream_t s, int bc, const Geo& g, const Geo& gc, int zb, in
 }
 
 template <typename R>
-void launch_mg_resid(hipStream_t s, int bc, const Geo& g, int nrhs, cx<R>* b, const cx<R>* e, const R* k2l,
+void launch_mg_resid(hipStream_t s, int bc, const Geo& g, int nrhs, cx<R>* b, const cx<R>* e, const R* kl,
                      const MgParams& P, const RhsState* st, int gate) {
     // about four planes per lane, enough workgroups to spread over the chip
     const int bx = (g.plane + RS_LANES - 1) / RS_LANES;
@@ -687,10 +848,10 @@ void launch_mg_resid(hipStream_t s, int bc, const Geo& g, int nrhs, cx<R>* b, co
     while (zb > 1 && (long long)bx * ((g.nz + zb - 1) / zb) * nrhs < 1024) zb >>= 1;
     dim3 grid(bx, (g.nz + zb - 1) / zb, nrhs);
     if (bc == BC_SOMMERFELD)
-        hipLaunchKernelGGL((k_mg_resid<BC_SOMMERFELD, R>), grid, dim3(RS_LANES), 0, s, g, zb, b, e, k2l,
+        hipLaunchKernelGGL((k_mg_resid<BC_SOMMERFELD, R>), grid, dim3(RS_LANES), 0, s, g, zb, b, e, kl,
                            P.beta1, P.beta2, P.omega, st, gate);
     else
-        hipLaunchKernelGGL((k_mg_resid<BC_DIRICHLET, R>), grid, dim3(RS_LANES), 0, s, g, zb, b, e, k2l,
+        hipLaunchKernelGGL((k_mg_resid<BC_DIRICHLET, R>), grid, dim3(RS_LANES), 0, s, g, zb, b, e, kl,
                            P.beta1, P.beta2, P.omega, st, gate);
 }
 template void launch_mg_resid<double>(hipStream_t, int, const Geo&, int, c128*, const c128*, const double*,

@@ -22,8 +22,6 @@ namespace hh {
 
 namespace {
 
-__device__ __forceinline__ double t_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float t_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double t_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float t_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -44,10 +42,13 @@ __device__ __forceinline__ void unflat(int i, const TailLevel& L, int& x, int& y
 
 __device__ __forceinline__ int mirror_in(int g, int n) { return g < 0 ? -g : (g > n - 1 ? 2 * (n - 1) - g : g); }
 
+// c_j = (beta1 - beta2 i) k^2 + n_j 2 i k / h from the level's k (k^2 formed
+// in the compute precision)
 template <int BC, typename R>
-__device__ __forceinline__ cx<R> shift_c_t(const TailCoef<R>& C, R k2, int nf) {
+__device__ __forceinline__ cx<R> shift_c_t(const TailCoef<R>& C, R k, int nf) {
+    const R k2 = k * k;
     cx<R> c = {C.sr * k2, C.si * k2};
-    if (BC == BC_SOMMERFELD && nf) c.im += R(nf) * C.two_over_h * t_sqrt(k2);
+    if (BC == BC_SOMMERFELD && nf) c.im += R(nf) * C.two_over_h * k;
     return c;
 }
 template <typename R>
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, TailProg prog,
     const int t = threadIdx.x, nt = blockDim.x;
     // LDS layout: per level b, u (the level's cycle result) and w (scratch),
     // then every level's s (an earlier result kept while another cycle runs),
-    // then every level's k^2
+    // then every level's k
     cx<R>* base = reinterpret_cast<cx<R>*>(tail_smem);
     auto B = [&](int l) { return base + 3 * D.lv[l].off; };
     auto U = [&](int l) { return base + 3 * D.lv[l].off + D.lv[l].n; };
@@ -135,11 +136,11 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, TailProg prog,
             ci[k] = D.cidx[cc];
         }
     }
-    // stage the right-hand side of the first level and every level's k^2
+    // stage the right-hand side of the first level and every level's k
     const cx<R>* bsrc = b_first + (long long)r * D.lv[0].n;
     for (int i = t; i < D.lv[0].n; i += nt) B(0)[i] = bsrc[i];
     for (int l = 0; l < nl; ++l) {
-        const R* kg = reinterpret_cast<const R*>(D.lv[l].k2);
+        const R* kg = reinterpret_cast<const R*>(D.lv[l].k);
         for (int i = t; i < D.lv[l].n; i += nt) K(l)[i] = kg[i];
     }
     __syncthreads();
@@ -152,13 +153,13 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, TailProg prog,
         cx<R>* b = B(l);
         cx<R>* u = U(l);
         cx<R>* w = T(l);
-        const R* k2 = K(l);
+        const R* kk = K(l);
         // u1 = W b
         for (int i = t; i < L.n; i += nt) {
             int x, y, z;
             unflat(i, L, x, y, z);
             const int nf = faces(L, x, y, z);
-            cx<R> v = jacobi_w_t(C, shift_c_t<BC>(C, k2[i], nf)) * b[i];
+            cx<R> v = jacobi_w_t(C, shift_c_t<BC>(C, kk[i], nf)) * b[i];
             if (BC == BC_DIRICHLET && nf) v = czero<R>();
             u[i] = v;
         }
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, TailProg prog,
             int x, y, z;
             unflat(i, L, x, y, z);
             const int nf = faces(L, x, y, z);
-            cx<R> v = (b[i] - C.ih2 * lap_at(u, L, x, y, z)) + shift_c_t<BC>(C, k2[i], nf) * u[i];
+            cx<R> v = (b[i] - C.ih2 * lap_at(u, L, x, y, z)) + shift_c_t<BC>(C, kk[i], nf) * u[i];
             if (BC == BC_DIRICHLET && nf) v = czero<R>();
             w[i] = v;
         }
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, TailProg prog,
         cx<R>* u = U(l);
         cx<R>* w = T(l);
         const cx<R>* ec = U(l + 1);
-        const R* k2 = K(l);
+        const R* kk = K(l);
         for (int i = t; i < L.n; i += nt) {
             int x, y, z;
             unflat(i, L, x, y, z);
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, TailProg prog,
                     for (int c = 0; c <= ox; ++c)
                         pe = pe + ec[((czi + a) * Lc.ny + cyi + bb) * Lc.nx + cxi + c];
             const R wt = R(1) / R(1 << (ox + oy + oz));
-            cx<R> v = jacobi_w_t(C, shift_c_t<BC>(C, k2[i], nf)) * b[i] + wt * pe;
+            cx<R> v = jacobi_w_t(C, shift_c_t<BC>(C, kk[i], nf)) * b[i] + wt * pe;
             if (BC == BC_DIRICHLET && nf) v = czero<R>();
             w[i] = v;
         }
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, TailProg prog,
             int x, y, z;
             unflat(i, L, x, y, z);
             const int nf = faces(L, x, y, z);
-            const cx<R> cc = shift_c_t<BC>(C, k2[i], nf);
+            const cx<R> cc = shift_c_t<BC>(C, kk[i], nf);
             const cx<R> u2 = w[i];
             cx<R> v = u2 + jacobi_w_t(C, cc) * ((b[i] - C.ih2 * lap_at(w, L, x, y, z)) + cc * u2);
             if (BC == BC_DIRICHLET && nf) v = czero<R>();
@@ -279,13 +280,13 @@ __global__ __launch_bounds__(1024) void k_mg_tail(TailDesc D, TailProg prog,
         cx<R>* b = B(l);
         const cx<R>* u = U(l);
         cx<R>* sv = S(l);
-        const R* k2 = K(l);
+        const R* kk = K(l);
         for (int i = t; i < L.n; i += nt) {
             int x, y, z;
             unflat(i, L, x, y, z);
             const int nf = faces(L, x, y, z);
             const cx<R> ui = u[i];
-            cx<R> v = (b[i] - C.ih2 * lap_at(u, L, x, y, z)) + shift_c_t<BC>(C, k2[i], nf) * ui;
+            cx<R> v = (b[i] - C.ih2 * lap_at(u, L, x, y, z)) + shift_c_t<BC>(C, kk[i], nf) * ui;
             if (BC == BC_DIRICHLET && nf) v = czero<R>();
             sv[i] = ui;
             b[i] = v;

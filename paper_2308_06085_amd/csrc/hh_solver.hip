@@ -51,7 +51,7 @@ struct LevelBuf {
     int zb_up = 8;        // fine planes per workgroup of the fused up kernel on this level
     int dn_reg = 0;       // fine region nodes per workgroup of a one-plane down pass (0 = automatic)
     double* k = nullptr;  // wavenumber at the nodes of this level
-    void* k2l = nullptr;  // k^2 in the multigrid precision
+    void* kl = nullptr;   // k in the multigrid precision
     void* b = nullptr;    // right-hand side (levels >= 1)
     void* e = nullptr;    // V-cycle result (levels >= 1)
 };
@@ -229,7 +229,7 @@ void free_all(hh_ctx* c) {
     for (void* q : {(void*)c->cgm_V, (void*)c->cgm_steps}) (void)hipFree(q);
     for (auto& L : c->lv) {
         (void)hipFree(L.k);
-        (void)hipFree(L.k2l);
+        (void)hipFree(L.kl);
         (void)hipFree(L.b);
         (void)hipFree(L.e);
     }
@@ -398,7 +398,7 @@ TailDesc tail_desc(hh_ctx* c) {
         D.lv[i].rcp_nx = (unsigned)((0x100000000ull + B.g.nx - 1) / B.g.nx);
         D.lv[i].rcp_plane = (unsigned)((0x100000000ull + B.g.plane - 1) / B.g.plane);
         D.lv[i].h = B.g.h;
-        D.lv[i].k2 = B.k2l;
+        D.lv[i].k = B.kl;
         off += (int)B.g.n;
     }
     D.total = off;
@@ -411,7 +411,7 @@ void apply_launch(hh_ctx* c) {
         const Geo gc = c->lv[l + 1].g;
         const Geo g = c->lv[l].g;
         c->lv[l].zb_down = pick_zb([&](int z) { return mg_down_blocks(gc, z); }, 1024);
-        c->lv[l].zb_up = pick_zb([&](int z) { return mg_up_blocks(g, z); }, 512);
+        c->lv[l].zb_up = pick_zb([&](int z) { return mg_up_blocks(g, z, c->mixed); }, 512);
     }
     for (size_t l = 0; l + 1 < c->lv.size(); ++l) {
         if (l < c->zb_down_set.size() && c->zb_down_set[l] > 0)
@@ -445,14 +445,14 @@ struct CycleOps {
     void down(int l) const {
         LevelBuf& a = c->lv[l];
         LevelBuf& n = c->lv[l + 1];
-        launch_mg_down<R, R>(s, c->cfg.bc, a.g, n.g, a.zb_down, nrhs, C(a.b), a.g.n, K(a.k2l), P(), C(n.b), st,
+        launch_mg_down<R, R>(s, c->cfg.bc, a.g, n.g, a.zb_down, nrhs, C(a.b), a.g.n, K(a.kl), P(), C(n.b), st,
                              gate, a.dn_reg);
     }
     // e_l = post-smoothed (W b_l + P e_{l+1}); with acc added to e_l
     void up(int l, bool acc) const {
         LevelBuf& a = c->lv[l];
         LevelBuf& n = c->lv[l + 1];
-        launch_mg_up<R, R, R>(s, c->cfg.bc, a.g, n.g, a.zb_up, nrhs, C(a.b), a.g.n, K(a.k2l), P(), C(n.e),
+        launch_mg_up<R, R, R>(s, c->cfg.bc, a.g, n.g, a.zb_up, nrhs, C(a.b), a.g.n, K(a.kl), P(), C(n.e),
                               C(a.e), a.g.n, st, gate, acc);
     }
     void tail(const TailProg& prog) const {
@@ -491,7 +491,7 @@ struct CycleOps {
         fcoarse(m + 1);
         up(m, false);
         LevelBuf& a = c->lv[m];
-        launch_mg_resid<R>(s, c->cfg.bc, a.g, nrhs, C(a.b), C(a.e), K(a.k2l), P(), st, gate);
+        launch_mg_resid<R>(s, c->cfg.bc, a.g, nrhs, C(a.b), C(a.e), K(a.kl), P(), st, gate);
         vcycle_from(m, true);
     }
 };
@@ -506,7 +506,7 @@ void enqueue_cycle_t(hh_ctx* c, hipStream_t s, int nrhs, const cx<TB>* bin, cx<T
     LevelBuf& f = c->lv[0];
     // down: one fused pass per level writes the next level's right-hand side
     if (ev_down) (void)hipEventRecord(ev_down[0], s);
-    launch_mg_down<TB, R>(s, bc, f.g, c->lv[1].g, f.zb_down, nrhs, bin, f.g.n, ops.K(f.k2l), ops.P(),
+    launch_mg_down<TB, R>(s, bc, f.g, c->lv[1].g, f.zb_down, nrhs, bin, f.g.n, ops.K(f.kl), ops.P(),
                           ops.C(c->lv[1].b), st, gate, f.dn_reg);
     if (ev_down) (void)hipEventRecord(ev_down[1], s);
     // the coarse-grid solve: one V-cycle on level 1, or the F-cycle's
@@ -514,7 +514,7 @@ void enqueue_cycle_t(hh_ctx* c, hipStream_t s, int nrhs, const cx<TB>* bin, cx<T
     else ops.vcycle_from(1, false);
     // up: one fused pass writes the finest level's result
     if (ev_up) (void)hipEventRecord(ev_up[0], s);
-    launch_mg_up<TB, R, TO>(s, bc, f.g, c->lv[1].g, f.zb_up, nrhs, bin, f.g.n, ops.K(f.k2l), ops.P(),
+    launch_mg_up<TB, R, TO>(s, bc, f.g, c->lv[1].g, f.zb_up, nrhs, bin, f.g.n, ops.K(f.kl), ops.P(),
                             ops.C(c->lv[1].e), bout, f.g.n, st, gate);
     if (ev_up) (void)hipEventRecord(ev_up[1], s);
 }
@@ -1105,7 +1105,7 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
         const size_t nn = (size_t)B.g.n;
         hh_status s;
         if ((s = dalloc(c, &B.k, sizeof(double) * nn)) != HH_OK) return bail(s);
-        if ((s = dalloc(c, (char**)&B.k2l, c->rsize * nn)) != HH_OK) return bail(s);
+        if ((s = dalloc(c, (char**)&B.kl, c->rsize * nn)) != HH_OK) return bail(s);
         if (l >= 1) {
             if ((s = dalloc(c, (char**)&B.b, c->csize * nn * R)) != HH_OK) return bail(s);
             if ((s = dalloc(c, (char**)&B.e, c->csize * nn * R)) != HH_OK) return bail(s);
@@ -1153,7 +1153,7 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
     };
     for (auto& B : c->lv) {
         zero(B.k, sizeof(double) * B.g.n);
-        zero(B.k2l, c->rsize * B.g.n);
+        zero(B.kl, c->rsize * B.g.n);
         zero(B.b, c->csize * B.g.n * R);
         zero(B.e, c->csize * B.g.n * R);
     }
@@ -1217,8 +1217,8 @@ hh_status set_model_from(hh_ctx* c, const double* k) {
     for (size_t l = 1; l < c->lv.size(); ++l)
         launch_inject(c->stream, c->lv[l - 1].g, c->lv[l].g, c->lv[l - 1].k, c->lv[l].k);
     for (auto& B : c->lv) {
-        if (c->mixed) launch_level_k2<float>(c->stream, B.g.n, B.k, (float*)B.k2l);
-        else launch_level_k2<double>(c->stream, B.g.n, B.k, (double*)B.k2l);
+        if (c->mixed) launch_level_k<float>(c->stream, B.g.n, B.k, (float*)B.kl);
+        else launch_level_k<double>(c->stream, B.g.n, B.k, (double*)B.kl);
     }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->bad_host, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -1634,7 +1634,7 @@ void launch_one_fine(hh_ctx* c, int which, int nrhs) {
     Launch F = c->L0;
     F.flat_cap = (int)c->nblk0;
     auto C = [](void* p) { return reinterpret_cast<cx<R>*>(p); };
-    const R* k2l = reinterpret_cast<const R*>(f.k2l);
+    const R* kl = reinterpret_cast<const R*>(f.kl);
     // the preconditioner's fine-level inputs and outputs: complex64 in the mixed solve
     const cx<R>* pin =
         c->mixed ? reinterpret_cast<const cx<R>*>(c->p_low) : reinterpret_cast<const cx<R>*>(c->p);
@@ -1652,11 +1652,11 @@ void launch_one_fine(hh_ctx* c, int which, int nrhs) {
                                 NBLK_CAP, F);
             break;
         case 2:
-            launch_mg_down<R, R>(s, bc, g, g1, f.zb_down, nrhs, pin, g.n, k2l, P, C(c->lv[1].b), c->st, ST_RUN,
+            launch_mg_down<R, R>(s, bc, g, g1, f.zb_down, nrhs, pin, g.n, kl, P, C(c->lv[1].b), c->st, ST_RUN,
                                  f.dn_reg);
             break;
         case 3:
-            launch_mg_up<R, R, R>(s, bc, g, g1, f.zb_up, nrhs, pin, g.n, k2l, P, C(c->lv[1].e), phat, g.n,
+            launch_mg_up<R, R, R>(s, bc, g, g1, f.zb_up, nrhs, pin, g.n, kl, P, C(c->lv[1].e), phat, g.n,
                                   c->st, ST_RUN);
             break;
         case 4:
