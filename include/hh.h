@@ -318,11 +318,8 @@ hh_status hh_kernel_times(const hh_ctx* ctx, double* ms_avg, long long* launches
 /* Pick the launch shapes of the solve by timing it: the lanes of
  * the flat Krylov kernels (128 / 256 / 512) with the z-planes per workgroup of
  * the operator apply (2 / 4 / 8), then, level by level, the z-planes per
- * workgroup of every fused multigrid down pass (1, 2, 4, 8, 16) and up pass
- * (2, 4, 8, 16 where the built-in rule marches over several planes; a level
- * where the rule runs the one-plane form keeps it, since the two forms round
- * some nodes differently) and the region of the one-plane down passes
- * (256 / 512 / 1280 fine nodes).  Each
+ * workgroup of every fused multigrid down and up pass (1, 2, 4, 8, 16) and the
+ * region of the one-plane down passes (256 / 512 / 1280 fine nodes).  Each
  * candidate runs the first Bi-CGSTAB steps of the current sources (set by
  * hh_set_*sources; all of them) from a fresh start, replayed as a graph and
  * timed with HIP events on the context stream; a candidate replaces the

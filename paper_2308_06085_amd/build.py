@@ -4,7 +4,8 @@
 
 Compiles every HIP source under ``csrc/`` with hipcc for gfx950 into one
 shared library next to this file.  Packed FP32 instructions are disabled in
-the device code (``-target-feature -packed-fp32-ops``).
+the device code (``-target-feature -packed-fp32-ops``); the multigrid passes
+(``hh_mg_fused.hip``) are compiled with ``-ffp-contract=off``.
 """
 from __future__ import annotations
 
@@ -19,6 +20,10 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhh.so")
 SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
 ARCH = os.environ.get("HH_OFFLOAD_ARCH", "gfx950")
+# The multigrid passes are compiled without implicit multiply-add contraction:
+# they write their fused multiply-adds out, so every inlined copy of a loop
+# body rounds alike and the results do not depend on z-blocks or regions.
+EXTRA_FLAGS = {"hh_mg_fused.hip": ["-ffp-contract=off"]}
 
 
 def hipcc() -> str:
@@ -37,7 +42,7 @@ def build(verbose: bool = False) -> str:
              "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
     def compile_one(src):
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [cc, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *flags, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         # the host pass does not know the device-only feature name: drop that line
         noise = [ln for ln in (r.stderr or "").splitlines() if "packed-fp32-ops" not in ln]

@@ -103,6 +103,38 @@ __device__ __forceinline__ LevelCoef<R> level_coef(const Geo& g, double beta1, d
     return L;
 }
 
+// Fused multiply-adds are written out: this file is compiled without implicit
+// contraction (-ffp-contract=off), so every rounding is fixed by the source
+// and is the same in every inlined copy of a loop body -- the passes' results
+// do not depend on their z-blocks or regions.
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// a b + c (complex)
+template <typename R>
+__device__ __forceinline__ cx<R> cfma(const cx<R>& a, const cx<R>& b, const cx<R>& c) {
+    return {fmar(a.re, b.re, fmar(-a.im, b.im, c.re)), fmar(a.re, b.im, fmar(a.im, b.re, c.im))};
+}
+// a b (complex)
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(const cx<R>& a, const cx<R>& b) {
+    return {fmar(a.re, b.re, -(a.im * b.im)), fmar(a.re, b.im, a.im * b.re)};
+}
+// s a + c (s real)
+template <typename R>
+__device__ __forceinline__ cx<R> sfma(R s, const cx<R>& a, const cx<R>& c) {
+    return {fmar(s, a.re, c.re), fmar(s, a.im, c.im)};
+}
+// s a + t b (s, t real)
+template <typename R>
+__device__ __forceinline__ cx<R> lerp2(R s, const cx<R>& a, R t, const cx<R>& b) {
+    return sfma(s, a, t * b);
+}
+// the residual of M at a node, b - (1/h^2) lap + c u
+template <typename R>
+__device__ __forceinline__ cx<R> mresid(const cx<R>& b, R ih2, const cx<R>& lap, const cx<R>& c, const cx<R>& u) {
+    return cfma(c, u, sfma(-ih2, lap, b));
+}
+
 // Reciprocal: correctly rounded in double; in single precision the hardware
 // v_rcp_f32 (about 1 ulp), far inside the accuracy a complex64 V-cycle is
 // held to.
@@ -115,14 +147,14 @@ template <typename R>
 __device__ __forceinline__ cx<R> shift_c(const LevelCoef<R>& L, R k, int nf) {
     const R k2 = k * k;
     cx<R> c = {L.sr * k2, L.si * k2};
-    if (nf) c.im += R(nf) * L.two_over_h * k;
+    if (nf) c.im = fmar(R(nf) * L.two_over_h, k, c.im);
     return c;
 }
 // W = omega / (6/h^2 - c)
 template <typename R>
 __device__ __forceinline__ cx<R> jacobi_w(const LevelCoef<R>& L, cx<R> c) {
     const R dr = L.six_ih2 - c.re, di = -c.im;
-    const R s = L.omega * mg_rcp(dr * dr + di * di);
+    const R s = L.omega * mg_rcp(fmar(dr, dr, di * di));
     return {dr * s, -di * s};
 }
 
@@ -218,7 +250,7 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
             const int nf = BC == BC_SOMMERFELD ? unf[k] + zf : 0;
             const cx<R> c = shift_c(L, w.k[k], nf);
             const cx<R> bb = cvt<R>(w.b[k]);
-            cx<R> v = jacobi_w(L, c) * bb;
+            cx<R> v = cmul(jacobi_w(L, c), bb);
             if (BC == BC_DIRICHLET && (ubnd[k] || zf)) v = czero<R>();
             // unguarded: idx < NU * DN_LANES = REG, and slots past the
             // region are never read (a guard would sink the loads into it)
@@ -242,7 +274,7 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
                 lap = lap + (u - uc[c + RW]);
                 lap = lap + (u - um[c]);
                 lap = lap + (u - up[c]);
-                rs[c] = (kp.b[k] - L.ih2 * lap) + kp.c[k] * u;
+                rs[c] = mresid(kp.b[k], L.ih2, lap, kp.c[k], u);
             }
         }
     };
@@ -400,7 +432,7 @@ __global__ __launch_bounds__(UP_LANES, 4) void k_mg_up1(Geo g, Geo gc, int zb,
             lap = lap + (u - um[t]);
             lap = lap + (u - up[t]);
             const cx<R> wj = KEEP_W ? k.w : jacobi_w(L, k.c);
-            cx<R> v = u + wj * ((cvt<R>(bz) - L.ih2 * lap) + k.c * u);
+            cx<R> v = cfma(wj, mresid(cvt<R>(bz), L.ih2, lap, k.c, u), u);
             if (BC == BC_DIRICHLET && (unf || z == 0 || z == g.nz - 1)) v = czero<R>();
             cx<TO>* o = orr + (long long)z * g.plane + ooff;
             if constexpr (ACC) v = cvt<R>(*o) + v;  // out already holds an earlier cycle's result
@@ -435,9 +467,9 @@ __global__ __launch_bounds__(UP_LANES, 4) void k_mg_up1(Geo g, Geo gc, int zb,
             v.e[3] = e1[cy1 + cx1];
         };
         auto interp = [&](const cx<R>(&e)[4]) -> cx<R> {
-            const cx<R> p0 = ax * e[0] + bx * e[1];
-            const cx<R> p1 = ax * e[2] + bx * e[3];
-            return ay * p0 + by * p1;
+            const cx<R> p0 = lerp2(ax, e[0], bx, e[1]);
+            const cx<R> p1 = lerp2(ax, e[2], bx, e[3]);
+            return lerp2(ay, p0, by, p1);
         };
         cx<R> carry;  // in-plane interpolation on the previous plane's c1
         auto make_c = [&](int f, const RawC& v, CW& k_out) -> cx<R> {
@@ -445,13 +477,13 @@ __global__ __launch_bounds__(UP_LANES, 4) void k_mg_up1(Geo g, Geo gc, int zb,
             const int zf = (fc == 0) + (fc == g.nz - 1);
             const R wz = (fc & 1) ? R(0.5) : R(1), bz = R(1) - wz;
             const cx<R> pn = interp(v.e);
-            const cx<R> pe = wz * ((fc & 1) ? carry : pn) + bz * pn;
+            const cx<R> pe = lerp2(wz, (fc & 1) ? carry : pn, bz, pn);
             carry = pn;
             const int nf = BC == BC_SOMMERFELD ? unf + zf : 0;
             k_out.c = shift_c(L, v.k, nf);
             const cx<R> wj = jacobi_w(L, k_out.c);
             if constexpr (KEEP_W) k_out.w = wj;
-            cx<R> u = wj * cvt<R>(v.b) + pe;
+            cx<R> u = cfma(wj, cvt<R>(v.b), pe);
             if (BC == BC_DIRICHLET && (unf || zf)) u = czero<R>();
             us[ring4i(f)][t] = u;  // unguarded: lanes past the region write slots never read
             return u;
@@ -602,14 +634,14 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
         // y on the new coarse plane c1, then z with the previous plane's c1
         // (= this plane's c0 for odd f), then x
         const R wz = (fc & 1) ? R(0.5) : R(1), bz = R(1) - wz;
-        const cx<R> p0 = ay * v.e[0] + by * v.e[2];
-        const cx<R> p1 = ay * v.e[1] + by * v.e[3];
-        const cx<R> q0 = wz * ((fc & 1) ? carry0 : p0) + bz * p0;
-        const cx<R> q1 = wz * ((fc & 1) ? carry1 : p1) + bz * p1;
+        const cx<R> p0 = lerp2(ay, v.e[0], by, v.e[2]);
+        const cx<R> p1 = lerp2(ay, v.e[1], by, v.e[3]);
+        const cx<R> q0 = lerp2(wz, (fc & 1) ? carry0 : p0, bz, p0);
+        const cx<R> q1 = lerp2(wz, (fc & 1) ? carry1 : p1, bz, p1);
         carry0 = p0;
         carry1 = p1;
-        const cx<R> pea = wa0 * q0 + wa1 * q1;
-        const cx<R> peb = wb0 * q0 + wb1 * q1;
+        const cx<R> pea = lerp2(wa0, q0, wa1, q1);
+        const cx<R> peb = lerp2(wb0, q0, wb1, q1);
         o.a.b = cvt<R>(v.ba);
         o.b.b = cvt<R>(v.bb);
         o.a.k = v.ka;
@@ -622,8 +654,8 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
         }
         o.a.w = jacobi_w(L, ca);
         o.b.w = jacobi_w(L, cb2);
-        o.a.u = o.a.w * o.a.b + pea;
-        o.b.u = o.b.w * o.b.b + peb;
+        o.a.u = cfma(o.a.w, o.a.b, pea);
+        o.b.u = cfma(o.b.w, o.b.b, peb);
         if (BC == BC_DIRICHLET && (nfa || zf)) o.a.u = czero<R>();
         if (BC == BC_DIRICHLET && (nfb || zf)) o.b.u = czero<R>();
         cx<R>* dst = us[f & 3];  // f >= -1: f & 3 is the ring slot (also for -1)
@@ -649,7 +681,7 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
             lap = lap + (u - (bot ? zp : zm));
             lap = lap + (u - (top ? zm : zp));
             const cx<R> cc = KEEP_C ? nd.c : shift_c(L, nd.k, BC == BC_SOMMERFELD ? nf + zfz : 0);
-            cx<R> v = u + nd.w * ((nd.b - L.ih2 * lap) + cc * u);
+            cx<R> v = cfma(nd.w, mresid(nd.b, L.ih2, lap, cc, u), u);
             if (BC == BC_DIRICHLET && (nf || bot || top)) v = czero<R>();
             cx<TO>* o = orr + (long long)z * g.plane + off;
             if constexpr (ACC) v = cvt<R>(*o) + v;  // out already holds an earlier cycle's result
@@ -664,8 +696,8 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
     // carry for the first plane: the y-interpolated columns of coarse plane plo >> 1
     {
         const cx<R>* e0 = er + (long long)(plo >> 1) * gc.plane;
-        carry0 = ay * e0[e00] + by * e0[e10];
-        carry1 = ay * e0[e01] + by * e0[e11];
+        carry0 = lerp2(ay, e0[e00], by, e0[e10]);
+        carry1 = lerp2(ay, e0[e01], by, e0[e11]);
     }
     // u2 on planes z0 - 1 .. z1 (clamped into the grid; a clamped duplicate is
     // never read).  Two pair sets X, Y alternate as the current and the next
@@ -732,7 +764,7 @@ __global__ __launch_bounds__(RS_LANES) void k_mg_resid(Geo g, int zb, cx<R>* __r
         lap = lap + (u - er[j + dzp]);
         const int nf = nfxy + (z == 0) + (z == g.nz - 1);
         const cx<R> c = shift_c(L, kl[j], BC == BC_SOMMERFELD ? nf : 0);
-        cx<R> v = (br[j] - L.ih2 * lap) + c * u;
+        cx<R> v = mresid(br[j], L.ih2, lap, c, u);
         if (BC == BC_DIRICHLET && nf) v = czero<R>();
         br[j] = v;
     }

@@ -1837,12 +1837,8 @@ hh_status hh_autotune(hh_ctx* c, const char* cache_json_path) {
         if (st == HH_OK && c->zb_down_set[l] == 1)
             for (int reg : {256, 512, 1280})
                 if (st == HH_OK) st = try_set(&c->dn_reg_set[l], reg);
-        // the up pass's one-plane form (1 plane per workgroup) rounds some
-        // nodes differently from its marching form (> 1 plane): the tuner
-        // keeps the form the rule chose, so the cycle's output stays the same
-        if (c->zb_up_set[l] > 1)
-            for (int z : {2, 4, 8, 16})
-                if (st == HH_OK && z <= nz) st = try_set(&c->zb_up_set[l], z);
+        for (int z : {1, 2, 4, 8, 16})
+            if (st == HH_OK && z <= nz) st = try_set(&c->zb_up_set[l], z);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -40,14 +40,11 @@ def test_autotune_cache_roundtrip(tmp_path, prec, nrhs):
     s.set_point_sources(nodes)
     z_default = host(s.apply_vcycle(r))
     assert s.get_option("autotune_source") == 0
-    default_up = s.launch_shapes()["zb_up"]
     tuned = s.autotune(cache)
     assert tuned["autotune_source"] == 2
     levels = s.get_option("tail_first")
     assert len(tuned["zb_down"]) == len(tuned["zb_up"]) == len(tuned["dn_region"]) == levels
     assert all(z in (1, 2, 4, 8, 16) for z in tuned["zb_down"] + tuned["zb_up"])
-    # the up pass keeps the rule's form (one plane or marching) on every level
-    assert [z == 1 for z in tuned["zb_up"]] == [z == 1 for z in default_up]
     assert all(g in (256, 512, 1280) for g in tuned["dn_region"])
     # the tuned multigrid shapes change no bit of the cycle
     assert np.array_equal(host(s.apply_vcycle(r)), z_default)

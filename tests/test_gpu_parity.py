@@ -412,11 +412,12 @@ def test_launch_shape_options_and_autotune():
     assert 1 <= first_tail < nlev
     r = dev(W.random_complex(wl.shape, seed=3)).unsqueeze(0)
     z_ref = host(s.apply_vcycle(r))
-    for l in range(first_tail):
-        for opt in (f"zb_down:{l}", f"zb_up:{l}"):
-            s.set_option(opt, 1)
-            assert s.get_option(opt) == 1
-    assert np.array_equal(host(s.apply_vcycle(r)), z_ref)
+    for zb in (1, 2, 3, 16):
+        # every z-block of every level's passes gives the same bits
+        for l in range(first_tail):
+            for opt in (f"zb_down:{l}", f"zb_up:{l}"):
+                s.set_option(opt, zb)
+        assert np.array_equal(host(s.apply_vcycle(r)), z_ref), zb
     with pytest.raises(HHError):
         s.set_option(f"zb_down:{nlev - 1}", 2)   # the coarsest level has no pass
     with pytest.raises(HHError):
