@@ -84,7 +84,7 @@ METRIC = "DoF-iterations/s of CSLP-Bi-CGSTAB, mixed vs FP64 at 1e-6 rel residual
 # Kernel ids of hh_time_kernel, launches per Bi-CGSTAB step and algorithmic
 # bytes per fine-grid node per right-hand side for (fp64, mixed) precision:
 # every array the kernel must read or write once (complex128 16 B, complex64
-# 8 B, real k^2 8 B for the operator, k^2 in the multigrid precision for the
+# 8 B, real k^2 8 B for the operator, k in the multigrid precision for the
 # multigrid passes, coarse-grid arrays 1/8 of a fine one).  In the mixed solve
 # the preconditioner's inputs (complex64 copies of p and s, written by the p
 # and s updates) and outputs p_hat, s_hat are complex64.
@@ -109,16 +109,16 @@ def step_bytes_per_dof(prec_idx: int) -> float:
 
 # HBM traffic per launch, FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scale factors
 # from a 1 GiB reference copy) from two rocprofv3 --pmc runs of
-# `bench.py --steps 1 --warmup 0 --no-cpu --no-fp64 --no-variants --copy-calibration`
-# (profiles/wedge_129x129x257_solve.md).  Valid only for the kernel sources it
-# was measured on (kernel_source_sha); otherwise reported as null.
+# `bench.py --steps 1 --warmup 0 --no-cpu --no-fp64 --copy-calibration`
+# (profiles/cube513_hbm_traffic.md).  Valid only for the kernel sources it was
+# measured on (kernel_source_sha); otherwise reported as null.
 TRAFFIC = {
-    ("apply_A+dots", "wedge", "mixed"): (214.3e6, "3589f48a6f9934f1"),
-    ("update_xr+dots", "wedge", "mixed"): (479.6e6, "3589f48a6f9934f1"),
-    ("mg_down_L0", "wedge", "mixed"): (74.1e6, "3589f48a6f9934f1"),
-    ("mg_up_L0", "wedge", "mixed"): (99.2e6, "3589f48a6f9934f1"),
-    ("p_update", "wedge", "mixed"): (307.9e6, "3589f48a6f9934f1"),
-    ("s_update+dot", "wedge", "mixed"): (239.7e6, "3589f48a6f9934f1"),
+    ("update_xr+dots", "cube513", "mixed"): (15127.2e6, "ad04d4bb9999cb49"),
+    ("apply_A+dots", "cube513", "mixed"): (6774.2e6, "ad04d4bb9999cb49"),
+    ("mg_down_L0", "cube513", "mixed"): (2301.7e6, "ad04d4bb9999cb49"),
+    ("mg_up_L0", "cube513", "mixed"): (3217.6e6, "ad04d4bb9999cb49"),
+    ("p_update", "cube513", "mixed"): (9720.3e6, "ad04d4bb9999cb49"),
+    ("s_update+dot", "cube513", "mixed"): (7562.7e6, "ad04d4bb9999cb49"),
 }
 
 
