@@ -98,6 +98,9 @@ int mg_down_blocks(const Geo& gc, int zbc);
 int mg_down_region(const Geo& gc, int zbc, int nrhs, int want);
 // workgroups of the up pass on level g in the compute precision (single: the x-pair kernel)
 int mg_up_blocks(const Geo& g, int zb, bool single);
+// whether every tile of the single-precision (x-pair) up pass on level g
+// (coarse grid gc) reads a coarse window of at most one node per lane
+bool mg_up_windows_fit(const Geo& g, const Geo& gc);
 
 // The trailing (smallest) levels of the hierarchy, run by one workgroup per
 // right-hand side with every array in LDS.  off = offset of the level's nodes

@@ -85,6 +85,28 @@ __host__ __device__ inline TileShape up1_tile_shape(int nx, int ny) {
 }
 __device__ __forceinline__ int ring4i(int f) { return f & 3; }  // also for f = -1
 
+// Coarse nodes an x-pair up-pass tile interpolates from: a window of cw x ch nodes of
+// one coarse plane starting at (cx0, cy0).  A region node at fine (x, y) of the
+// tile (or the mirror image of a halo position) reads coarse columns x >> 1 and
+// x >> 1 + 1 (clamped), so the window spans (X0 - 1) >> 1 .. (X0 + tw) >> 1 + 1
+// and likewise in y.  Region positions past the grid's far end that are
+// neither output nor halo of an output may fall outside; their coarse indices
+// are clamped into the window (their results are never used).  The window is
+// staged in LDS one node per lane, so cw ch <= UP_LANES is required (checked
+// on the host for every level by mg_up_windows_fit).
+struct CoarseWin {
+    int cx0, cy0, cw, ch;
+};
+__host__ __device__ inline CoarseWin up_coarse_window(int X0, int Y0, int tw, int th, int gcnx, int gcny) {
+    CoarseWin W;
+    W.cx0 = X0 >= 1 ? (X0 - 1) >> 1 : 0;
+    W.cy0 = Y0 >= 1 ? (Y0 - 1) >> 1 : 0;
+    const int xe = ((X0 + tw) >> 1) + 1, ye = ((Y0 + th) >> 1) + 1;
+    W.cw = (xe < gcnx - 1 ? xe : gcnx - 1) - W.cx0 + 1;
+    W.ch = (ye < gcny - 1 ? ye : gcny - 1) - W.cy0 + 1;
+    return W;
+}
+
 // Level constants of the CSLP operator in the compute precision.
 template <typename R>
 struct LevelCoef {
@@ -447,36 +469,40 @@ __global__ __launch_bounds__(UP_LANES, 4) void k_mg_up1(Geo g, Geo gc, int zb,
         // March over the u2 planes z0 - 1 .. z1 clamped into the grid (the
         // output step reads a mirrored plane's image instead), two planes of
         // loads in flight.  Plane f interpolates between coarse planes
-        // c0 = f >> 1 and c1 = c0 + (f & 1): only c1 is loaded, the in-plane
-        // interpolation on c0 is the previous plane's (the same plane for even f).
+        // c0 = f >> 1 and c1 = c0 + (f & 1).  The in-plane interpolation on
+        // c0 is the previous plane's, and for even f c1 = c0: only odd planes
+        // load coarse values (a branch on the plane, the same for every lane).
         const int plo = max(z0 - 1, 0), phi = min(z1, g.nz - 1);
+        auto clampz = [&](int f) { return min(max(f, plo), phi); };
         struct RawC {
             cx<TB> b;
             R k;
-            cx<R> e[4];
+            cx<R> e[4];  // the four corners on c1, odd planes only
         };
         auto fetch_c = [&](int f, RawC& v) {
-            const int fc = min(max(f, plo), phi);
+            const int fc = clampz(f);
             const long long base = (long long)fc * g.plane;
-            const cx<R>* e1 = er + (long long)((fc >> 1) + (fc & 1)) * gc.plane;
             v.b = br[base + uoff];
             v.k = kl[base + uoff];
-            v.e[0] = e1[cy0 + cx0];
-            v.e[1] = e1[cy0 + cx1];
-            v.e[2] = e1[cy1 + cx0];
-            v.e[3] = e1[cy1 + cx1];
+            if (fc & 1) {
+                const cx<R>* e1 = er + (long long)((fc >> 1) + 1) * gc.plane;
+                v.e[0] = e1[cy0 + cx0];
+                v.e[1] = e1[cy0 + cx1];
+                v.e[2] = e1[cy1 + cx0];
+                v.e[3] = e1[cy1 + cx1];
+            }
         };
-        auto interp = [&](const cx<R>(&e)[4]) -> cx<R> {
-            const cx<R> p0 = lerp2(ax, e[0], bx, e[1]);
-            const cx<R> p1 = lerp2(ax, e[2], bx, e[3]);
+        auto interp = [&](const cx<R>& e00, const cx<R>& e01, const cx<R>& e10, const cx<R>& e11) -> cx<R> {
+            const cx<R> p0 = lerp2(ax, e00, bx, e01);
+            const cx<R> p1 = lerp2(ax, e10, bx, e11);
             return lerp2(ay, p0, by, p1);
         };
         cx<R> carry;  // in-plane interpolation on the previous plane's c1
         auto make_c = [&](int f, const RawC& v, CW& k_out) -> cx<R> {
-            const int fc = min(max(f, plo), phi);
+            const int fc = clampz(f);
             const int zf = (fc == 0) + (fc == g.nz - 1);
             const R wz = (fc & 1) ? R(0.5) : R(1), bz = R(1) - wz;
-            const cx<R> pn = interp(v.e);
+            const cx<R> pn = (fc & 1) ? interp(v.e[0], v.e[1], v.e[2], v.e[3]) : carry;
             const cx<R> pe = lerp2(wz, (fc & 1) ? carry : pn, bz, pn);
             carry = pn;
             const int nf = BC == BC_SOMMERFELD ? unf + zf : 0;
@@ -500,17 +526,13 @@ __global__ __launch_bounds__(UP_LANES, 4) void k_mg_up1(Geo g, Geo gc, int zb,
         };
         // set A holds the planes z0 - 1 + even, set B the odd ones
         RawC A, B;
-        cx<R> e_first[4];  // coarse plane c0 of the first plane
-        {
-            const cx<R>* e0 = er + (long long)(plo >> 1) * gc.plane;
-            e_first[0] = e0[cy0 + cx0];
-            e_first[1] = e0[cy0 + cx1];
-            e_first[2] = e0[cy1 + cx0];
-            e_first[3] = e0[cy1 + cx1];
-        }
         fetch_c(z0 - 1, A);
         fetch_c(z0, B);
-        carry = interp(e_first);
+        {
+            // the in-plane interpolation on coarse plane c0 of the first plane
+            const cx<R>* e0 = er + (long long)(plo >> 1) * gc.plane;
+            carry = interp(e0[cy0 + cx0], e0[cy0 + cx1], e0[cy1 + cx0], e0[cy1 + cx1]);
+        }
         (void)make_c(z0 - 1, A, c_unused);
         fetch_c(z0 + 1, A);
         b_cur = B.b;
@@ -528,12 +550,14 @@ __global__ __launch_bounds__(UP_LANES, 4) void k_mg_up1(Geo g, Geo gc, int zb,
 // Up: u3 = u2 + W (b - (1/h^2) lap(u2) + c u2), u2 = W b + P e_H.  Each lane
 // owns an x-pair of the tile-plus-halo region: nodes x_a = X0 - 1 + 2 p and
 // x_b = x_a + 1 of region row ly.  The two nodes' trilinear interpolations
-// draw on the same two coarse columns, so a lane loads four coarse values per
-// plane (two columns on the two coarse rows of its fine row) and interpolates
-// each column in y and z once.  The workgroup marches over `zb` planes; the
-// u2 planes go to a ring of four LDS planes, one barrier per plane.  Every
-// node's arithmetic is the same for every tile and z-block, so the result
-// does not depend on them.  With ACC the pass adds u3 to the
+// draw on the same two coarse columns (two columns on the two coarse rows of
+// its fine row), so a lane interpolates each column in y and z once.  The
+// coarse values come from LDS: every second fine plane starts a new coarse
+// plane, whose window for the tile is loaded one node per lane a plane ahead
+// and staged before the barrier that precedes its use.  The workgroup marches
+// over `zb` planes; the u2 planes go to a ring of four LDS planes, one barrier
+// per plane.  Every node's arithmetic is the same for every tile and z-block,
+// so the result does not depend on them.  With ACC the pass adds u3 to the
 // output instead of storing it (the F-cycle's second coarse-grid cycle).
 // ---------------------------------------------------------------------------
 template <typename R>
@@ -553,6 +577,8 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
     // first half and the b nodes (odd columns) in its second: consecutive
     // lanes touch consecutive slots.
     __shared__ cx<R> us[4][2 * UP_LANES];
+    // the tile's coarse window of one coarse plane (see up_coarse_window)
+    __shared__ cx<R> cs[UP_LANES];
 
     const int r = blockIdx.z;
     if (!gate_ok(st, r, gate)) return;
@@ -592,29 +618,44 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
     // LDS slots: node a at t (first half), node b at UP_LANES + t; the row
     // neighbours of a slot are P slots away
     const int sa = t, sb = UP_LANES + t;
+    // the coarse window: lane t stages window node t; the pair's four corners
+    // as window slots (clamped: lanes whose nodes lie outside are never used)
+    const CoarseWin win = up_coarse_window(X0, Y0, T.tw, T.th, gc.nx, gc.ny);
+    const bool stager = t < win.cw * win.ch;
+    const int soff = (win.cy0 + min(t / win.cw, win.ch - 1)) * gc.nx + win.cx0 + t % win.cw;
+    auto wslot = [&](int cyy, int cxx) {
+        return min(max(cyy - win.cy0, 0), win.ch - 1) * win.cw + min(max(cxx - win.cx0, 0), win.cw - 1);
+    };
+    const int s00 = wslot(cy0, cb), s01 = wslot(cy0, cb1), s10 = wslot(cy1, cb), s11 = wslot(cy1, cb1);
 
-    // raw loads of one plane: b and k of both nodes, the four coarse values on
-    // the coarse plane c1 = (f >> 1) + (f & 1).  Issued unconditionally (every
-    // offset is a valid node); planes are clamped into plo .. phi.
+    // raw loads of one plane: b and k of both nodes and, when plane f + 1 is
+    // odd, this lane's window node of its coarse plane c1 = (f + 1) / 2 + 1
+    // (plane f interpolates between coarse planes c0 = f >> 1 and
+    // c1 = c0 + (f & 1); even planes reuse the previous plane's in-plane
+    // interpolation).  Issued unconditionally within the plane (every offset
+    // is a valid node); planes are clamped into plo .. phi.
     const int plo = max(z0 - 1, 0), phi = min(z1, g.nz - 1);
+    auto clampz = [&](int f) { return min(max(f, plo), phi); };
     struct Raw {
         cx<TB> ba, bb;
         R ka, kb;
-        cx<R> e[4];
+        cx<R> ce;
     };
     auto fetch = [&](int f, Raw& v) {
-        const int fc = min(max(f, plo), phi);
+        const int fc = clampz(f), fn = clampz(f + 1);
         const long long base = (long long)fc * g.plane;
-        const cx<R>* e1 = er + (long long)((fc >> 1) + (fc & 1)) * gc.plane;
         v.ba = br[base + offa];
         v.bb = br[base + offb];
         v.ka = kl[base + offa];
         v.kb = kl[base + offb];
-        v.e[0] = e1[e00];
-        v.e[1] = e1[e01];
-        v.e[2] = e1[e10];
-        v.e[3] = e1[e11];
+        if (fn & 1) v.ce = er[(long long)((fn >> 1) + 1) * gc.plane + soff];
         __builtin_amdgcn_sched_barrier(0);
+    };
+    // stage the window of plane f's c1 (from the set fetched for f - 1) when
+    // f is odd and not a clamped repeat of f - 1
+    auto stage_at = [&](int f) { return (clampz(f) & 1) && clampz(f) != clampz(f - 1); };
+    auto stage = [&](const Raw& v) {
+        if (stager) cs[t] = v.ce;
     };
     static_assert(sizeof(R) == sizeof(float), "the x-pair up pass runs in single precision");
     // per node and plane: u2 and the b, c and W its output step needs
@@ -629,13 +670,13 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
     cx<R> carry0, carry1;  // y-interpolated coarse columns of the previous plane's c1
     // u2 of plane f for both nodes, staged in the ring
     auto make = [&](int f, const Raw& v, Pair& o) {
-        const int fc = min(max(f, plo), phi);
+        const int fc = clampz(f);
         const int zf = (fc == 0) + (fc == g.nz - 1);
-        // y on the new coarse plane c1, then z with the previous plane's c1
-        // (= this plane's c0 for odd f), then x
+        // y on the new coarse plane c1 (for even f the previous plane's), then
+        // z with the previous plane's c1 (= this plane's c0 for odd f), then x
         const R wz = (fc & 1) ? R(0.5) : R(1), bz = R(1) - wz;
-        const cx<R> p0 = lerp2(ay, v.e[0], by, v.e[2]);
-        const cx<R> p1 = lerp2(ay, v.e[1], by, v.e[3]);
+        const cx<R> p0 = (fc & 1) ? lerp2(ay, cs[s00], by, cs[s10]) : carry0;
+        const cx<R> p1 = (fc & 1) ? lerp2(ay, cs[s01], by, cs[s11]) : carry1;
         const cx<R> q0 = lerp2(wz, (fc & 1) ? carry0 : p0, bz, p0);
         const cx<R> q1 = lerp2(wz, (fc & 1) ? carry1 : p1, bz, p1);
         carry0 = p0;
@@ -706,6 +747,7 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
     Pair X, Y;
     auto step = [&](int z, Pair& cur, Pair& nxt, Raw& v, int ahead) {
         make(z + 1, v, nxt);
+        if (stage_at(z + 2)) stage(v);
         fetch(z + 1 + ahead, v);
         __syncthreads();
         emit(z, cur, nxt);
@@ -713,9 +755,18 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
     Raw A, B;
     fetch(z0 - 1, A);
     fetch(z0, B);
+    if ((plo & 1) && stager) cs[t] = er[(long long)((plo >> 1) + 1) * gc.plane + soff];
+    // the window is read only by odd planes and written only for an odd plane
+    // when the plane before it (even) is made: a barrier between each write
+    // and its reads, and between the reads and the next write
+    __syncthreads();
     make(z0 - 1, A, Y);
+    if (stage_at(z0)) stage(A);
+    __syncthreads();
     fetch(z0 + 1, A);
     make(z0, B, X);
+    if (stage_at(z0 + 1)) stage(B);
+    __syncthreads();
     fetch(z0 + 2, B);
     for (int z = z0; z < z1; z += 2) {
         step(z, X, Y, A, 2);
@@ -780,6 +831,15 @@ int mg_down_blocks(const Geo& gc, int zbc) {
 int mg_up_blocks(const Geo& g, int zb, bool single) {
     const TileShape T = single ? up_tile_shape(g.nx, g.ny) : up1_tile_shape(g.nx, g.ny);
     return T.ntx * T.nty * ((g.nz + zb - 1) / zb);
+}
+bool mg_up_windows_fit(const Geo& g, const Geo& gc) {
+    const TileShape T = up_tile_shape(g.nx, g.ny);
+    for (int ty = 0; ty < T.nty; ++ty)
+        for (int tx = 0; tx < T.ntx; ++tx) {
+            const CoarseWin W = up_coarse_window(tx * T.tw, ty * T.th, T.tw, T.th, gc.nx, gc.ny);
+            if (W.cw < 1 || W.ch < 1 || W.cw * W.ch > UP_LANES) return false;
+        }
+    return true;
 }
 
 // Region of the down pass.  The z-marching pass (zbc > 1, the large levels)

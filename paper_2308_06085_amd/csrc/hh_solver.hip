@@ -1071,6 +1071,10 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
         }
     }
     if (shapes.size() < 2) return fail(nullptr, HH_ERR_ARG, "grid cannot be coarsened (need at least 2 levels)");
+    for (size_t l = 0; l + 1 < shapes.size(); ++l)
+        if (!mg_up_windows_fit(shapes[l], shapes[l + 1]))
+            return fail(nullptr, HH_ERR_ARG, "level %zu (%d x %d x %d): an up-pass tile reads more coarse nodes "
+                        "than it has lanes", l, shapes[l].nx, shapes[l].ny, shapes[l].nz);
     {
         // one reduction partial per operator-apply workgroup: the x-y tiles of a
         // plane must stay within NBLK_CAP even with the whole z-range in one workgroup
