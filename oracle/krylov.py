@@ -68,11 +68,16 @@ def _norm(a):
 
 
 def bicgstab(apply_A, precond, b, x0=None, tol=1e-6, maxit=1000, max_restarts=5,
-             breakdown_tol=1e-300, fixed_iterations=None) -> SolveResult:
+             breakdown_tol=1e-300, fixed_iterations=None, shadow_dtype=None) -> SolveResult:
     """Solve A x = b.  ``apply_A`` and ``precond`` map arrays of b's shape.
 
     fixed_iterations : run exactly this many full steps with no stopping test
                        (used to compare iterates).
+    shadow_dtype     : None keeps r_hat = r (the standard choice); a dtype
+                       such as complex64 takes r_hat = r rounded to it (then
+                       widened back), the shadow vector of a solve whose
+                       preconditioner runs in that precision.  Bi-CGSTAB
+                       admits any fixed r_hat with <r_hat, r> != 0.
     """
     b = np.asarray(b)
     bnorm = _norm(b)
@@ -87,7 +92,7 @@ def bicgstab(apply_A, precond, b, x0=None, tol=1e-6, maxit=1000, max_restarts=5,
     relres = np.inf
     while True:
         r = b - apply_A(x) if (x0 is not None or restarts > 0) else b.copy()
-        r_hat = r.copy()
+        r_hat = r.copy() if shadow_dtype is None else r.astype(shadow_dtype).astype(r.dtype)
         rho_old = alpha = omega = 1.0 + 0j
         p = np.zeros_like(b)
         v = np.zeros_like(b)

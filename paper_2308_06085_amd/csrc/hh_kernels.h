@@ -68,9 +68,10 @@ void launch_apply(hipStream_t s, int bc, int mode, const Geo& g, const Launch& L
 void launch_apply_p(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs, int ns, const c128* x,
                     c128* y, const double* k2, const double* kb, const c64* P, double* part,
                     long long nblk_max, const RhsState* st, int gate);
+// rhat: the shadow residual, complex64 when rhat_low (the mixed solve), else complex128
 void launch_init(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs, const c128* b,
-                 c128* x, c128* r, c128* rhat, c128* p, c128* v, const double* k2, const double* kb,
-                 int use_x0, double* part, long long nblk_max, const RhsState* st, int gate);
+                 c128* x, c128* r, void* rhat, bool rhat_low, c128* p, c128* v, const double* k2,
+                 const double* kb, int use_x0, double* part, long long nblk_max, const RhsState* st, int gate);
 
 // CSLP parameters of the multigrid kernels: M = -Laplace - (beta1 - beta2 i) k^2,
 // damped-Jacobi weight omega.
@@ -143,7 +144,7 @@ void launch_s_update(hipStream_t s, long long n, int nrhs, c128* sv, const c128*
 // p_hat, s_hat: complex128, or complex64 from a single-precision preconditioner
 template <typename TH>
 void launch_update_xr(hipStream_t s, long long n, int nrhs, c128* x, c128* r, const cx<TH>* ph,
-                      const cx<TH>* sh, const c128* sv, const c128* t, const c128* rhat,
+                      const cx<TH>* sh, const c128* sv, const c128* t, const cx<TH>* rhat,
                       const RhsState* st, double* part, long long nblk_max, const Launch& L);
 void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const double* part,
                      long long nblk, long long nblk_max, double tol);

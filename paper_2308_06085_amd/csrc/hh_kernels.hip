@@ -249,7 +249,8 @@ __global__ __launch_bounds__(1024) void k_finalize(int mode, RhsState* st, const
 // the single-precision preconditioner's outputs, complex64 (converted exactly
 // on load).  MODE selects the fused epilogue:
 //   OP_PLAIN : y = Op x
-//   OP_V     : y = A x, partials Re/Im sum conj(rhat) y          (slot V)
+//   OP_V     : y = A x, partials Re/Im sum conj(rhat) y          (slot V);
+//              rhat (aux) is stored in the input's precision
 //   OP_T     : y = A x, partials Re/Im sum conj(y) s, sum |y|^2   (slot T)
 //   OP_P     : y = A x, partials Re/Im sum conj(p_i) y for the NS complex64
 //              shadow vectors p_i of IDR(s) (rows 0 .. 2 NS - 1; aux points
@@ -336,7 +337,8 @@ __global__ __launch_bounds__(AP_LANES) void k_apply(Geo g, int zb, const cx<TX>*
         const double kbv = kb[nf ? idx : 0];
         c128 aux_v = czero<double>();
         c64 pv[MODE == OP_P ? NS : 1];
-        if (MODE == OP_V || MODE == OP_T) aux_v = aux[roff + idx];
+        if (MODE == OP_V) aux_v = cvt<double>(reinterpret_cast<const cx<TX>*>(aux)[roff + idx]);
+        if (MODE == OP_T) aux_v = aux[roff + idx];
         if constexpr (MODE == OP_P) {
 #pragma unroll
             for (int a = 0; a < NS; ++a) pv[a] = pshadow[(long long)a * g.n + idx];
@@ -395,13 +397,15 @@ __global__ __launch_bounds__(AP_LANES) void k_apply(Geo g, int zb, const cx<TX>*
 }
 
 // ---------------------------------------------------------------------------
-// Start of a (re)start: r = b - A x (use_x0) or r = b (x := 0); r_hat = r;
-// p = v = 0; partials ||r||^2, Re/Im r_hat^H r (= ||r||^2, 0), ||b||^2 (slot R).
+// Start of a (re)start: r = b - A x (use_x0) or r = b (x := 0); r_hat = r
+// stored in precision TS (complex64 in the mixed solve: the shadow vector is
+// then r rounded to complex64); p = v = 0; partials ||r||^2,
+// Re/Im r_hat^H r (= ||r||^2, 0 when TS is double), ||b||^2 (slot R).
 // ---------------------------------------------------------------------------
-template <int BC>
+template <int BC, typename TS>
 __global__ __launch_bounds__(AP_LANES) void k_init(Geo g, int zb, const c128* __restrict__ b,
                                               c128* __restrict__ x, c128* __restrict__ rr,
-                                              c128* __restrict__ rhat, c128* __restrict__ p,
+                                              cx<TS>* __restrict__ rhat, c128* __restrict__ p,
                                               c128* __restrict__ v, const double* __restrict__ k2,
                                               const double* __restrict__ kb, int use_x0,
                                               double* __restrict__ part, long long nblk_max,
@@ -459,12 +463,19 @@ __global__ __launch_bounds__(AP_LANES) void k_init(Geo g, int zb, const c128* __
                 x[roff + idx] = czero<double>();
             }
             rr[roff + idx] = res;
-            rhat[roff + idx] = res;
+            const cx<TS> rh = cvt<TS>(res);
+            rhat[roff + idx] = rh;
             p[roff + idx] = czero<double>();
             v[roff + idx] = czero<double>();
             const double n2 = abs2(res);
             acc[0] += n2;
-            acc[1] += n2;
+            if constexpr (sizeof(TS) == sizeof(double)) {
+                acc[1] += n2;
+            } else {
+                const c128 d = cdot(cvt<double>(rh), res);
+                acc[1] += d.re;
+                acc[2] += d.im;
+            }
             acc[3] += abs2(bv);
             xm = xc;
             xc = xp;
@@ -519,7 +530,7 @@ __global__ __launch_bounds__(512) void k_s_update(long long n, c128* __restrict_
 }
 
 // Iterating right-hand sides: x += alpha p_hat + omega s_hat; r = s - omega t;
-// partials ||r||^2, r_hat^H r.  Right-hand sides that stopped at the half step:
+// partials ||r||^2, r_hat^H r (p_hat, s_hat and r_hat in precision TH).  Right-hand sides that stopped at the half step:
 // x += alpha p_hat (the next FIN_RHO marks them converged).
 template <typename TH>
 __global__ __launch_bounds__(512) void k_update_xr(long long n, c128* __restrict__ x,
@@ -528,7 +539,7 @@ __global__ __launch_bounds__(512) void k_update_xr(long long n, c128* __restrict
                                                    const cx<TH>* __restrict__ sh,
                                                    const c128* __restrict__ s,
                                                    const c128* __restrict__ t,
-                                                   const c128* __restrict__ rhat, const RhsState* st,
+                                                   const cx<TH>* __restrict__ rhat, const RhsState* st,
                                                    double* __restrict__ part, long long nblk_max) {
     const int r = blockIdx.z;
     const int status = st[r].status;
@@ -548,7 +559,7 @@ __global__ __launch_bounds__(512) void k_update_xr(long long n, c128* __restrict
         c128 rv = s[off + i] - om * t[off + i];
         rr[off + i] = rv;
         acc[0] += abs2(rv);
-        c128 d = cdot(rhat[off + i], rv);
+        c128 d = cdot(cvt<double>(rhat[off + i]), rv);
         acc[1] += d.re;
         acc[2] += d.im;
     }
@@ -756,15 +767,20 @@ template void launch_apply<float>(hipStream_t, int, int, const Geo&, const Launc
                                   double*, long long, const RhsState*, int);
 
 void launch_init(hipStream_t s, int bc, const Geo& g, const Launch& L, int nrhs, const c128* b,
-                 c128* x, c128* r, c128* rhat, c128* p, c128* v, const double* k2, const double* kb,
-                 int use_x0, double* part, long long nblk_max, const RhsState* st, int gate) {
+                 c128* x, c128* r, void* rhat, bool rhat_low, c128* p, c128* v, const double* k2,
+                 const double* kb, int use_x0, double* part, long long nblk_max, const RhsState* st, int gate) {
     dim3 grid = grid_fine(g, L, nrhs);
-    if (bc == BC_SOMMERFELD)
-        hipLaunchKernelGGL((k_init<BC_SOMMERFELD>), grid, dim3(AP_LANES), 0, s, g, L.zb, b, x, r, rhat,
-                           p, v, k2, kb, use_x0, part, nblk_max, st, gate);
-    else
-        hipLaunchKernelGGL((k_init<BC_DIRICHLET>), grid, dim3(AP_LANES), 0, s, g, L.zb, b, x, r, rhat,
-                           p, v, k2, kb, use_x0, part, nblk_max, st, gate);
+#define HH_INIT(BCV, TSV)                                                                                     \
+    hipLaunchKernelGGL((k_init<BCV, TSV>), grid, dim3(AP_LANES), 0, s, g, L.zb, b, x, r,                     \
+                       reinterpret_cast<cx<TSV>*>(rhat), p, v, k2, kb, use_x0, part, nblk_max, st, gate)
+    if (bc == BC_SOMMERFELD) {
+        if (rhat_low) HH_INIT(BC_SOMMERFELD, float);
+        else HH_INIT(BC_SOMMERFELD, double);
+    } else {
+        if (rhat_low) HH_INIT(BC_DIRICHLET, float);
+        else HH_INIT(BC_DIRICHLET, double);
+    }
+#undef HH_INIT
 }
 
 void launch_p_update(hipStream_t s, long long n, int nrhs, c128* p, const c128* r, const c128* v,
@@ -784,7 +800,7 @@ void launch_s_update(hipStream_t s, long long n, int nrhs, c128* sv, const c128*
 }
 template <typename TH>
 void launch_update_xr(hipStream_t s, long long n, int nrhs, c128* x, c128* r, const cx<TH>* ph,
-                      const cx<TH>* sh, const c128* sv, const c128* t, const c128* rhat,
+                      const cx<TH>* sh, const c128* sv, const c128* t, const cx<TH>* rhat,
                       const RhsState* st, double* part, long long nblk_max, const Launch& L) {
     hipLaunchKernelGGL(k_update_xr<TH>, dim3(L.flat_cap, 1, nrhs), dim3(L.block), 0, s, n, x, r, ph, sh, sv,
                        t, rhat, st, part, nblk_max);
@@ -793,7 +809,7 @@ template void launch_update_xr<double>(hipStream_t, long long, int, c128*, c128*
                                        const c128*, const c128*, const c128*, const RhsState*, double*,
                                        long long, const Launch&);
 template void launch_update_xr<float>(hipStream_t, long long, int, c128*, c128*, const c64*, const c64*,
-                                      const c128*, const c128*, const c128*, const RhsState*, double*,
+                                      const c128*, const c128*, const c64*, const RhsState*, double*,
                                       long long, const Launch&);
 void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const double* part,
                      long long nblk, long long nblk_max, double tol) {

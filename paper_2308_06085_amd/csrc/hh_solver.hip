@@ -81,7 +81,8 @@ struct hh_ctx {
     c128 *bsrc = nullptr, *xk = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr,
          *s = nullptr, *t = nullptr, *ph = nullptr, *sh = nullptr;
     // single-precision preconditioner: complex64 copies of p and s (its inputs);
-    // ph / sh then hold its complex64 outputs
+    // ph / sh then hold its complex64 outputs, and rhat the complex64 shadow
+    // residual (r0 rounded to complex64)
     c64 *p_low = nullptr, *s_low = nullptr;
     RhsState* st = nullptr;
     RhsState* st_host = nullptr;  // pinned
@@ -578,7 +579,8 @@ void enqueue_iteration_t(hh_ctx* c, hipStream_t s, int nrhs, cx<TH>* ph, cx<TH>*
     mark(TL_APPLY_T, 1);
     launch_finalize(s, FIN_OMEGA, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
     mark(TL_UPDATE_XR, 0);
-    launch_update_xr<TH>(s, n, nrhs, c->xk, c->r, ph, sh, c->s, c->t, c->rhat, c->st, c->part, NBLK_CAP, F);
+    launch_update_xr<TH>(s, n, nrhs, c->xk, c->r, ph, sh, c->s, c->t, reinterpret_cast<const cx<TH>*>(c->rhat),
+                         c->st, c->part, NBLK_CAP, F);
     mark(TL_UPDATE_XR, 1);
 }
 
@@ -866,8 +868,8 @@ hh_status run_idr(hh_ctx* c, int nrhs, int maxit) {
             if (++guard > 2LL * (maxit + 8) * (MAX_RESTARTS + 1)) return fail(c, HH_ERR_STATE, "driver did not terminate");
             continue;
         }
-        launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->k2,
-                    c->kb, 1, c->part, NBLK_CAP, c->st, GATE_FINISHED);
+        launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->mixed, c->p, c->v,
+                    c->k2, c->kb, 1, c->part, NBLK_CAP, c->st, GATE_FINISHED);
         launch_finalize(c->stream, FIN_TRUE, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, 0.0);
         HIPCHK(c, hipGetLastError());
         CHK(read_states(c, nrhs));
@@ -948,8 +950,8 @@ hh_status run_gmres(hh_ctx* c, int nrhs, int maxit, double rtol, int use_x0) {
         CHK(read_states(c, nrhs));
         if (j == M) {
             // full basis: restart the iterating ones from the updated x
-            launch_init(s, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->k2, c->kb, 1,
-                        c->part, NBLK_CAP, st, ST_RUN);
+            launch_init(s, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->mixed, c->p, c->v,
+                        c->k2, c->kb, 1, c->part, NBLK_CAP, st, ST_RUN);
             start(2);
             HIPCHK(c, hipGetLastError());
             CHK(read_states(c, nrhs));
@@ -958,8 +960,8 @@ hh_status run_gmres(hh_ctx* c, int nrhs, int maxit, double rtol, int use_x0) {
         if (++guard > 4LL * (maxit + 8) * (MAX_RESTARTS + 1)) return fail(c, HH_ERR_STATE, "driver did not terminate");
     }
     // the true residual of every solution (GMRES stops on the preconditioned one)
-    launch_init(s, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->k2, c->kb, 1, c->part,
-                NBLK_CAP, st, GATE_FINISHED);
+    launch_init(s, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->mixed, c->p, c->v, c->k2,
+                c->kb, 1, c->part, NBLK_CAP, st, GATE_FINISHED);
     launch_finalize(s, FIN_TRUE_RECORD, nrhs, st, c->part, c->nblk0, NBLK_CAP, 0.0);
     HIPCHK(c, hipGetLastError());
     CHK(read_states(c, nrhs));
@@ -1335,8 +1337,8 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
     HIPCHK(c, hipEventRecord(e0, c->stream));
     if (use_x0) HIPCHK(c, hipMemcpyAsync(c->xk, x, bytes, hipMemcpyDeviceToDevice, c->stream));
     launch_fill_status(c->stream, nrhs, c->st, ST_RUN, 2 * maxit);
-    launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->k2,
-                c->kb, use_x0, c->part, NBLK_CAP, c->st, ST_RUN);
+    launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->mixed, c->p, c->v,
+                c->k2, c->kb, use_x0, c->part, NBLK_CAP, c->st, ST_RUN);
     launch_finalize(c->stream, FIN_INIT, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, rtol);
     HIPCHK(c, hipGetLastError());
     CHK(read_states(c, nrhs));
@@ -1402,8 +1404,8 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
         // every right-hand side stopped: recompute the true residual b - A x;
         // a converged one whose true residual misses rtol restarts from x
         if (any_half) launch_finalize(c->stream, FIN_RHO, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, rtol);
-        launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->k2,
-                    c->kb, 1, c->part, NBLK_CAP, c->st, GATE_FINISHED);
+        launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->mixed, c->p, c->v,
+                    c->k2, c->kb, 1, c->part, NBLK_CAP, c->st, GATE_FINISHED);
         launch_finalize(c->stream, FIN_TRUE, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, rtol);
         HIPCHK(c, hipGetLastError());
         CHK(read_states(c, nrhs));
@@ -1652,7 +1654,8 @@ void launch_one_fine(hh_ctx* c, int which, int nrhs) {
                          NBLK_CAP, c->st, ST_RUN);
             break;
         case 1:
-            launch_update_xr<R>(s, g.n, nrhs, c->xk, c->r, phat, shat, c->s, c->t, c->rhat, c->st, c->part,
+            launch_update_xr<R>(s, g.n, nrhs, c->xk, c->r, phat, shat, c->s, c->t,
+                                reinterpret_cast<const cx<R>*>(c->rhat), c->st, c->part,
                                 NBLK_CAP, F);
             break;
         case 2:
@@ -1781,8 +1784,8 @@ hh_status hh_autotune(hh_ctx* c, const char* cache_json_path) {
         for (int rep = 0; rep < kRepeat; ++rep) {
             // tolerance 0: no right-hand side stops within the few steps timed
             launch_fill_status(c->stream, nrhs, c->st, ST_RUN, 2 * (kSteps + kWarm + 1));
-            launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v,
-                        c->k2, c->kb, 0, c->part, NBLK_CAP, c->st, ST_RUN);
+            launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->mixed, c->p,
+                        c->v, c->k2, c->kb, 0, c->part, NBLK_CAP, c->st, ST_RUN);
             launch_finalize(c->stream, FIN_INIT, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, 0.0);
             for (int k = 0; k < kWarm; ++k) HIPCHK(c, hipGraphLaunch(exec, c->stream));
             HIPCHK(c, hipEventRecord(e0, c->stream));

@@ -246,6 +246,28 @@ def test_idr1_with_r0_shadow_equals_bicgstab():
         assert np.abs(ri.x - rb.x).max() <= 1e-11 * np.abs(rb.x).max(), j
 
 
+def test_complex64_shadow_equals_idr1_with_that_shadow():
+    """Bi-CGSTAB with r_hat = r_0 rounded to complex64 (the mixed solve's
+    shadow vector) is IDR(1) with that shadow vector: the same 2j-product
+    iterates.  The rounding is visible (the iterate differs from the r_hat = r_0
+    one) and the solve still reaches the tolerance on its true residual."""
+    lvl, hier, b = _problem(17, SOMMERFELD, seed=3)
+    A = lambda x: O.apply_A(x, lvl)  # noqa: E731
+    K = lambda r: vcycle(r, hier)  # noqa: E731
+    p32 = b.astype(np.complex64).astype(np.complex128)
+    assert np.abs(p32 - b).max() > 0
+    for j in (1, 2, 5):
+        ri = O.idrs(A, K, b, p32[None], kappa=0.0, fixed_steps=2 * j)
+        rb = O.bicgstab(A, K, b, fixed_iterations=j, shadow_dtype=np.complex64)
+        # agreement to rounding (about 1e-16); an unrounded shadow is 5e-12 off
+        assert np.abs(ri.x - rb.x).max() <= 1e-13 * np.abs(rb.x).max(), j
+    r64 = O.bicgstab(A, K, b, fixed_iterations=2)
+    r32 = O.bicgstab(A, K, b, fixed_iterations=2, shadow_dtype=np.complex64)
+    assert np.abs(r32.x - r64.x).max() > 1e-14 * np.abs(r64.x).max()
+    res = O.bicgstab(A, K, b, tol=1e-8, shadow_dtype=np.complex64)
+    assert res.status == O.Status.OK and res.relres_true <= 1e-8
+
+
 def test_idrs_biorthogonality_and_true_residual():
     """IDR(4) invariants after every update of r: r = b - A x; after inner step k
     r is orthogonal to p_1..p_k; g_k is orthogonal to p_1..p_{k-1}; the small
