@@ -111,17 +111,18 @@ def step_bytes_per_dof(prec_idx: int) -> float:
 
 
 # HBM traffic per launch, FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scale factors
-# from a 1 GiB reference copy) from two rocprofv3 --pmc runs of
+# from a 1 GiB reference copy; the operator apply's entry is the mean of its
+# two launches per step) from two rocprofv3 --pmc runs of
 # `bench.py --steps 1 --warmup 0 --no-cpu --no-fp64 --copy-calibration`
 # (profiles/cube513_hbm_traffic.md).  Valid only for the kernel sources it was
 # measured on (kernel_source_sha); otherwise reported as null.
 TRAFFIC = {
-    ("update_xr+dots", "cube513", "mixed"): (15127.2e6, "ad04d4bb9999cb49"),
-    ("apply_A+dots", "cube513", "mixed"): (6774.2e6, "ad04d4bb9999cb49"),
-    ("mg_down_L0", "cube513", "mixed"): (2301.7e6, "ad04d4bb9999cb49"),
-    ("mg_up_L0", "cube513", "mixed"): (3217.6e6, "ad04d4bb9999cb49"),
-    ("p_update", "cube513", "mixed"): (9720.3e6, "ad04d4bb9999cb49"),
-    ("s_update+dot", "cube513", "mixed"): (7562.7e6, "ad04d4bb9999cb49"),
+    ("update_xr+dots", "cube513", "mixed"): (14047.3e6, "386748f5da0ff30c"),
+    ("apply_A+dots", "cube513", "mixed"): (6240.0e6, "386748f5da0ff30c"),
+    ("mg_down_L0", "cube513", "mixed"): (2301.1e6, "386748f5da0ff30c"),
+    ("mg_up_L0", "cube513", "mixed"): (3223.4e6, "386748f5da0ff30c"),
+    ("p_update", "cube513", "mixed"): (9720.4e6, "386748f5da0ff30c"),
+    ("s_update+dot", "cube513", "mixed"): (7562.5e6, "386748f5da0ff30c"),
 }
 
 

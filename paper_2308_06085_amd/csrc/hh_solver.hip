@@ -211,6 +211,13 @@ Launch level_launch(const Geo& g, const Launch& base) {
 template <typename T>
 hh_status dalloc(hh_ctx* c, T** p, size_t bytes) {
     void* q = nullptr;
+    // a request beyond the device's free memory fails here, with the sizes
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && bytes > free_b) {
+        *p = nullptr;
+        return fail(c, HH_ERR_OOM, "%zu bytes requested, %zu of %zu bytes free on the device", bytes, free_b,
+                    total_b);
+    }
     hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
     if (e != hipSuccess) {
         *p = nullptr;

@@ -4,7 +4,10 @@
   one V-cycle and one F-cycle against the oracle element by element on the
   whole grid; FP64 and mixed Bi-CGSTAB solves, and mixed IDR(4) and GMRES
   solves, checked by the true residual under the oracle's operator; the mixed
-  solution against a tight FP64 solve.
+  solution against a tight FP64 solve; FP64 and mixed solves to 1e-10 against
+  the oracle's solve to 1e-10 at 2066 sampled nodes (tests/golden).
+* the wedge at half resolution (65 x 65 x 129, 5 Hz): FP64 and mixed solves
+  to 1e-10 against the oracle's solve to 1e-10 at every node.
 * the same wedge with 16 seeded top-face sources, one batched mixed solve:
   every right-hand side's true residual under the oracle's operator.
 * 513^3 cube, k = 160, 8 levels: the operator on z-slabs against the oracle,
@@ -14,6 +17,9 @@
 * adjoint workload, 65^3 smoothed-noise model: the autograd gradient against
   the oracle's adjoint gradient and central finite differences on 20 directions.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -73,8 +79,21 @@ def _true_relres(wl, x, nodes):
             for r in range(len(nodes))]
 
 
+def _golden_wedge():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "wedge_solution_samples.json")
+    with open(path) as f:
+        g = json.load(f)
+    return np.array(g["index"]), np.array(g["re"]) + 1j * np.array(g["im"]), g
+
+
 def test_wedge_solves_fp64_and_mixed(wedge):
+    """Solves to 1e-6 (true residual under the oracle's operator), and solves to
+    1e-10 against the oracle's own solve to 1e-10 (stored at a seeded sample of
+    nodes by tests/golden/make_wedge_solution.py): within 1e-6 of its largest
+    value at every sample, and its 2-norm to 1e-6."""
     wl = wedge
+    idx, ref, g = _golden_wedge()
+    assert g["problem"]["shape"] == list(wl.shape) and g["problem"]["source"] == list(wl.sources[0])
     sols = {}
     for prec in ("fp64", "mixed"):
         s = _solver(wl, prec=prec)
@@ -86,14 +105,38 @@ def test_wedge_solves_fp64_and_mixed(wedge):
         assert st[0].status == "HH_OK" and rel <= 1e-6, (prec, rel, st[0])
         assert abs(st[0].relres_true - rel) <= 1e-9
         sols[prec] = x[0]
+        xt, stt = s.solve(rtol=1e-10)
+        xt = host(xt)[0]
+        assert stt[0].status == "HH_OK" and stt[0].relres_true <= 1e-10, (prec, stt[0])
+        assert np.abs(xt.ravel()[idx] - ref).max() <= 1e-6 * g["max_abs"], prec
+        assert abs(np.linalg.norm(xt) - g["norm2"]) <= 1e-6 * g["norm2"], prec
         if prec == "fp64":
-            xt, stt = s.solve(rtol=1e-10)
-            sols["tight"] = host(xt)[0]
+            sols["tight"] = xt
         s.close()
     err = {p: np.linalg.norm(sols[p] - sols["tight"]) / np.linalg.norm(sols["tight"])
            for p in ("fp64", "mixed")}
     # both stop at the same residual; their errors are of the same size
     assert err["mixed"] <= 10 * err["fp64"] + 1e-7, err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_half_wedge_tight_solution_against_oracle(prec):
+    """The wedge at half resolution (65 x 65 x 129 nodes, 5 Hz: the same kh),
+    solved to relative residual 1e-10 on both sides: the GPU solution equals
+    the oracle's at every node to 1e-6 of its largest value."""
+    wl = W.wedge(5.0, 65, 65, 129)
+    lvl = Level(wl.shape, wl.h, wl.k, wl.bc)
+    hier = build_hierarchy(wl.k, wl.h, wl.bc, n_levels=wl.n_levels)
+    b = O.point_source_rhs(wl.shape, wl.h, wl.sources)[0]
+    ref = O.bicgstab(lambda v: O.apply_A(v, lvl), lambda r: vcycle(r, hier), b, tol=1e-10)
+    assert ref.status == O.Status.OK
+    s = _solver(wl, prec=prec)
+    s.set_model(dev(wl.k))
+    s.set_point_sources(wl.sources)
+    x, st = s.solve(rtol=1e-10)
+    assert st[0].status == "HH_OK" and st[0].relres_true <= 1e-10
+    assert relerr(host(x)[0], ref.x) <= 1e-6
+    s.close()
 
 
 def test_wedge_batched_sixteen_sources(wedge):

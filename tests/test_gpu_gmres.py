@@ -192,3 +192,27 @@ def test_zero_and_mixed_batch_for_idrs_and_gmres(method):
     s.set_sources(dev(b))
     x1, st1 = s.solve(rtol=1e-7)
     assert np.array_equal(host(x1)[0], x[1]) and st1[0].iterations == st[1].iterations
+
+
+def test_gmres_basis_beyond_device_memory_is_an_error():
+    """Full GMRES keeps gmres_m + 1 complex128 vectors per right-hand side.  On
+    the 513^3 cube the default 200 steps would need 201 x 2.16 GB, more than
+    the device holds: switching to GMRES fails with HH_ERR_OOM, the context
+    keeps its method, and a basis that fits is then accepted."""
+    from paper_2308_06085_amd._lib import HHError
+
+    n = 513
+    s = _solver((n, n, n), 1.0 / (n - 1), SOMMERFELD, n_levels=8)
+    try:
+        need = 201 * 16 * n**3
+        free, _ = torch.cuda.mem_get_info()
+        assert need > free
+        with pytest.raises(HHError) as err:
+            s.set_option("method", 2)
+        assert err.value.status == 3 and "bytes requested" in str(err.value)
+        assert s.get_option("method") == 0
+        s.set_option("gmres_m", 8)
+        s.set_option("method", 2)
+        assert s.get_option("method") == 2 and s.get_option("gmres_m") == 8
+    finally:
+        s.close()
