@@ -15,6 +15,29 @@ __device__ __forceinline__ bool gate_ok(const RhsState* st, int r, int gate) {
 template <typename R>
 __device__ __forceinline__ cx<R> czero() { return cx<R>{R(0), R(0)}; }
 
+// Streaming access: loads and stores with the non-temporal hint, for data a
+// kernel touches once (the Krylov vectors in the update kernels).  Measured on
+// the 513^3 cube: the x / r update 2.87 -> 2.57 ms, the p update 1.96 -> 1.84
+// ms, the s update 1.44 -> 1.38 ms against plain loads and stores.
+typedef double hh_d2 __attribute__((ext_vector_type(2)));
+typedef float hh_f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ c128 ld_stream(const c128* p) {
+    const hh_d2 v = __builtin_nontemporal_load(reinterpret_cast<const hh_d2*>(p));
+    return {v.x, v.y};
+}
+__device__ __forceinline__ c64 ld_stream(const c64* p) {
+    const hh_f2 v = __builtin_nontemporal_load(reinterpret_cast<const hh_f2*>(p));
+    return {v.x, v.y};
+}
+__device__ __forceinline__ void st_stream(c128* p, const c128& a) {
+    const hh_d2 v = {a.re, a.im};
+    __builtin_nontemporal_store(v, reinterpret_cast<hh_d2*>(p));
+}
+__device__ __forceinline__ void st_stream(c64* p, const c64& a) {
+    const hh_f2 v = {a.re, a.im};
+    __builtin_nontemporal_store(v, reinterpret_cast<hh_f2*>(p));
+}
+
 // Deterministic block reduction of NT doubles: butterfly within each 64-lane
 // wavefront, then wavefront partials summed by thread 0 in wave order.  The
 // result goes to out[t * stride] for t < NT.

@@ -488,6 +488,7 @@ __global__ __launch_bounds__(AP_LANES) void k_init(Geo g, int zb, const c128* __
 // ---------------------------------------------------------------------------
 // Krylov vector updates (complex128), grid-stride over nodes with exactly the
 // fine-grid kernels' workgroup count per right-hand side: gridDim = (nblk, 1, nrhs).
+// Every vector is read and written once per launch, with streaming loads and stores.
 // ---------------------------------------------------------------------------
 template <bool LOW>
 __global__ __launch_bounds__(512) void k_p_update(long long n, c128* __restrict__ p,
@@ -500,9 +501,10 @@ __global__ __launch_bounds__(512) void k_p_update(long long n, c128* __restrict_
     const long long off = (long long)r * n;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        const c128 pv = rr[off + i] + beta * (p[off + i] - om * v[off + i]);
-        p[off + i] = pv;
-        if (LOW) p_low[off + i] = cvt<float>(pv);
+        const c128 pv =
+            ld_stream(&rr[off + i]) + beta * (ld_stream(&p[off + i]) - om * ld_stream(&v[off + i]));
+        st_stream(&p[off + i], pv);
+        if (LOW) st_stream(&p_low[off + i], cvt<float>(pv));
     }
 }
 
@@ -521,9 +523,9 @@ __global__ __launch_bounds__(512) void k_s_update(long long n, c128* __restrict_
     double acc[1] = {0.0};
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        c128 sv = rr[off + i] - al * v[off + i];
-        s[off + i] = sv;
-        if (LOW) s_low[off + i] = cvt<float>(sv);
+        c128 sv = ld_stream(&rr[off + i]) - al * ld_stream(&v[off + i]);
+        st_stream(&s[off + i], sv);
+        if (LOW) st_stream(&s_low[off + i], cvt<float>(sv));
         acc[0] += abs2(sv);
     }
     block_sum_store<1>(acc, part + part_index(r, SLOT_T, 3, nblk_max) + blockIdx.x, nblk_max);
@@ -555,11 +557,12 @@ __global__ __launch_bounds__(512) void k_update_xr(long long n, c128* __restrict
     double acc[3] = {0.0, 0.0, 0.0};
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        x[off + i] = x[off + i] + al * cvt<double>(ph[off + i]) + om * cvt<double>(sh[off + i]);
-        c128 rv = s[off + i] - om * t[off + i];
-        rr[off + i] = rv;
+        st_stream(&x[off + i], ld_stream(&x[off + i]) + al * cvt<double>(ld_stream(&ph[off + i])) +
+                                   om * cvt<double>(ld_stream(&sh[off + i])));
+        c128 rv = ld_stream(&s[off + i]) - om * ld_stream(&t[off + i]);
+        st_stream(&rr[off + i], rv);
         acc[0] += abs2(rv);
-        c128 d = cdot(cvt<double>(rhat[off + i]), rv);
+        c128 d = cdot(cvt<double>(ld_stream(&rhat[off + i])), rv);
         acc[1] += d.re;
         acc[2] += d.im;
     }
