@@ -90,10 +90,13 @@ METRIC = "DoF-iterations/s of CSLP-Bi-CGSTAB, mixed vs FP64 at 1e-6 rel residual
 # and s updates), its outputs p_hat, s_hat and the shadow residual r_hat are
 # complex64.  The operator apply's figure is the mean of its two launches per
 # step: v = A p_hat with r_hat^H v (FP64 56 B, mixed 40 B) and t = A s_hat with
-# t^H s, t^H t (FP64 56 B, mixed 48 B: s stays complex128).
+# t^H s, t^H t (FP64 56 B, mixed 48 B: s stays complex128).  The x / r update
+# alternates: an even step reads s, t, r_hat and writes r (FP64 64 B, mixed
+# 56 B); an odd step also reads x and both steps' p_hat, s_hat and writes x
+# (FP64 160 B, mixed 120 B); its figure is the mean of the two.
 KERNELS = {
     0: ("apply_A+dots", 2, (16 + 8 + 16 + 16, 8 + 8 + (8 + 16) / 2 + 16)),
-    1: ("update_xr+dots", 1, (6 * 16 + 2 * 16, 3 * 16 + 3 * 8 + 2 * 16)),
+    1: ("update_xr+dots", 1, ((64 + 160) / 2, (56 + 120) / 2)),
     2: ("mg_down_L0", 2, (16 + 8 + 16 / 8, 8 + 4 + 8 / 8)),
     3: ("mg_up_L0", 2, (16 + 8 + 16 / 8 + 16, 8 + 4 + 8 / 8 + 8)),
     4: ("p_update", 1, (4 * 16, 4 * 16 + 8)),

@@ -72,8 +72,11 @@ enum RhsStatus : int {
 
 struct RhsState {
     c128 rho, alpha, omega, beta;
+    // the solution update of an even step, x += alpha_d p_hat + omega_d s_hat,
+    // waits for the odd step that follows (pend = 1 while it is outstanding)
+    c128 alpha_d, omega_d;
     double bnorm2, rnorm2, snorm2, rhat_norm2, tol2, true_rnorm2;
-    int status, iters2, maxit2, matvecs, restarts, pad_;
+    int status, iters2, maxit2, matvecs, restarts, pend;
 };
 
 // Reduction slots (each holds `nterm` doubles per block per right-hand side).

@@ -52,7 +52,17 @@ enum OpMode : int { OP_PLAIN = 0, OP_V = 1, OP_T = 2, OP_P = 3 };
 // partial sums beside those of t = A s_hat, so one finalize serves both.
 // FIN_TRUE_RECORD: the true residual only, no restart (GMRES stops on the
 // preconditioned residual)
-enum FinMode : int { FIN_INIT = 0, FIN_RHO = 1, FIN_ALPHA = 2, FIN_OMEGA = 4, FIN_TRUE = 5, FIN_TRUE_RECORD = 6 };
+// FIN_RHO_DEFER: FIN_RHO at the start of an odd step, which also records the
+// even step's solution update as outstanding (alpha_d, omega_d, pend)
+enum FinMode : int {
+    FIN_INIT = 0,
+    FIN_RHO = 1,
+    FIN_ALPHA = 2,
+    FIN_OMEGA = 4,
+    FIN_TRUE = 5,
+    FIN_TRUE_RECORD = 6,
+    FIN_RHO_DEFER = 7
+};
 constexpr int GATE_ALL = -1;       // act on every right-hand side
 constexpr int GATE_FINISHED = -2;  // act on right-hand sides that stopped iterating
 
@@ -143,9 +153,15 @@ void launch_s_update(hipStream_t s, long long n, int nrhs, c128* sv, const c128*
                      c64* s_low, const RhsState* st, double* part, long long nblk_max, const Launch& L);
 // p_hat, s_hat: complex128, or complex64 from a single-precision preconditioner
 template <typename TH>
-void launch_update_xr(hipStream_t s, long long n, int nrhs, c128* x, c128* r, const cx<TH>* ph,
-                      const cx<TH>* sh, const c128* sv, const c128* t, const cx<TH>* rhat,
-                      const RhsState* st, double* part, long long nblk_max, const Launch& L);
+void launch_update_xr(hipStream_t s, bool odd, long long n, int nrhs, c128* x, c128* r, const cx<TH>* ph,
+                      const cx<TH>* sh, const cx<TH>* php, const cx<TH>* shp, const c128* sv, const c128* t,
+                      const cx<TH>* rhat, const RhsState* st, double* part, long long nblk_max,
+                      const Launch& L);
+// x += alpha_d p_hat' + omega_d s_hat' for the stopped right-hand sides with an
+// outstanding even-step update (before the true residual of a solve)
+template <typename TH>
+void launch_flush_x(hipStream_t s, long long n, int nrhs, c128* x, const cx<TH>* php, const cx<TH>* shp,
+                    const RhsState* st, const Launch& L);
 void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const double* part,
                      long long nblk, long long nblk_max, double tol);
 

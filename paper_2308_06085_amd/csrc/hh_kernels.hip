@@ -117,6 +117,7 @@ __device__ void fin_update(int mode, RhsState& S, const double* s, double tol) {
             S.matvecs = 1;
             S.restarts = 0;
             S.true_rnorm2 = 0.0;
+            S.pend = 0;
             if (!isfinite(s[0]) || !isfinite(s[3])) S.status = ST_NUMERIC;
             else if (s[3] == 0.0 || s[0] <= S.tol2) S.status = ST_CONV;
             return;
@@ -126,6 +127,7 @@ __device__ void fin_update(int mode, RhsState& S, const double* s, double tol) {
             return;
         case FIN_TRUE:
             S.true_rnorm2 = s[0];
+            S.pend = 0;  // applied by the flush before the true residual
             if (!isfinite(s[0])) {
                 S.status = ST_NUMERIC;
             } else if (status == ST_CONV && S.bnorm2 > 0.0 && s[0] > S.tol2 && S.iters2 < S.maxit2 &&
@@ -141,7 +143,17 @@ __device__ void fin_update(int mode, RhsState& S, const double* s, double tol) {
                 S.restarts += 1;
             }
             return;
+        case FIN_RHO_DEFER:
         case FIN_RHO: {
+            if (mode == FIN_RHO_DEFER && status == ST_RUN) {
+                // the even step just finished left x += alpha p_hat + omega s_hat
+                // to the odd step (or to the flush, if this right-hand side stops here)
+                S.alpha_d = S.alpha;
+                S.omega_d = S.omega;
+                S.pend = 1;
+            } else {
+                S.pend = 0;  // consumed by the odd step's x / r update
+            }
             if (status == ST_HALF) {
                 // the half step has added alpha p_hat to x: this right-hand side is done
                 S.status = ST_CONV;
@@ -193,14 +205,15 @@ __device__ __forceinline__ int fin_slot(int mode) {
     switch (mode) {
         case FIN_ALPHA: return SLOT_V;
         case FIN_OMEGA: return SLOT_T;
-        default: return SLOT_R;
+        default: return SLOT_R;  // FIN_INIT, FIN_RHO, FIN_RHO_DEFER, FIN_TRUE*
     }
 }
 __device__ __forceinline__ int fin_terms(int mode) {
     switch (mode) {
         case FIN_ALPHA: return 2;
         case FIN_OMEGA: return 4;
-        case FIN_RHO: return 3;
+        case FIN_RHO:
+        case FIN_RHO_DEFER: return 3;
         case FIN_TRUE:
         case FIN_TRUE_RECORD: return 1;
         default: return 4;
@@ -226,7 +239,8 @@ __global__ __launch_bounds__(1024) void k_finalize(int mode, RhsState* st, const
     switch (mode) {
         case FIN_TRUE:
         case FIN_TRUE_RECORD: act = status != ST_RUN && status != ST_IDLE && status != ST_HALF; break;
-        case FIN_RHO: act = status == ST_RUN || status == ST_HALF; break;
+        case FIN_RHO:
+        case FIN_RHO_DEFER: act = status == ST_RUN || status == ST_HALF; break;
         default: act = status == ST_RUN; break;
     }
     if (!act) return;
@@ -531,14 +545,22 @@ __global__ __launch_bounds__(512) void k_s_update(long long n, c128* __restrict_
     block_sum_store<1>(acc, part + part_index(r, SLOT_T, 3, nblk_max) + blockIdx.x, nblk_max);
 }
 
-// Iterating right-hand sides: x += alpha p_hat + omega s_hat; r = s - omega t;
-// partials ||r||^2, r_hat^H r (p_hat, s_hat and r_hat in precision TH).  Right-hand sides that stopped at the half step:
-// x += alpha p_hat (the next FIN_RHO marks them converged).
-template <typename TH>
+// Iterating right-hand sides: r = s - omega t and the partials ||r||^2,
+// r_hat^H r (p_hat, s_hat and r_hat in precision TH).  The solution is
+// updated every second step: an even step (ODD false) leaves its
+// x += alpha p_hat + omega s_hat outstanding (the next FIN_RHO_DEFER records
+// it), and the odd step adds both steps' terms, reading p_hat' and s_hat' of
+// the even step from their own buffers (php, shp), so x is read and written
+// once per two steps.  Right-hand sides that stopped at the half step add
+// alpha p_hat (and an outstanding update) to x; the next FIN_RHO marks them
+// converged.
+template <typename TH, bool ODD>
 __global__ __launch_bounds__(512) void k_update_xr(long long n, c128* __restrict__ x,
                                                    c128* __restrict__ rr,
                                                    const cx<TH>* __restrict__ ph,
                                                    const cx<TH>* __restrict__ sh,
+                                                   const cx<TH>* __restrict__ php,
+                                                   const cx<TH>* __restrict__ shp,
                                                    const c128* __restrict__ s,
                                                    const c128* __restrict__ t,
                                                    const cx<TH>* __restrict__ rhat, const RhsState* st,
@@ -547,18 +569,27 @@ __global__ __launch_bounds__(512) void k_update_xr(long long n, c128* __restrict
     const int status = st[r].status;
     if (status != ST_RUN && status != ST_HALF) return;
     const c128 al = st[r].alpha, om = st[r].omega;
+    const bool pend = ODD && st[r].pend;
+    const c128 ald = st[r].alpha_d, omd = st[r].omega_d;
     const long long off = (long long)r * n;
+    // x plus the outstanding update of the even step, if any
+    auto x_pend = [&](long long k) -> c128 {
+        c128 xv = ld_stream(&x[k]);
+        if (pend) xv = xv + ald * cvt<double>(ld_stream(&php[k])) + omd * cvt<double>(ld_stream(&shp[k]));
+        return xv;
+    };
     if (status == ST_HALF) {
         for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
              i += (long long)gridDim.x * blockDim.x)
-            x[off + i] = x[off + i] + al * cvt<double>(ph[off + i]);
+            st_stream(&x[off + i], x_pend(off + i) + al * cvt<double>(ld_stream(&ph[off + i])));
         return;
     }
     double acc[3] = {0.0, 0.0, 0.0};
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        st_stream(&x[off + i], ld_stream(&x[off + i]) + al * cvt<double>(ld_stream(&ph[off + i])) +
-                                   om * cvt<double>(ld_stream(&sh[off + i])));
+        if (ODD)
+            st_stream(&x[off + i], x_pend(off + i) + al * cvt<double>(ld_stream(&ph[off + i])) +
+                                       om * cvt<double>(ld_stream(&sh[off + i])));
         c128 rv = ld_stream(&s[off + i]) - om * ld_stream(&t[off + i]);
         st_stream(&rr[off + i], rv);
         acc[0] += abs2(rv);
@@ -567,6 +598,25 @@ __global__ __launch_bounds__(512) void k_update_xr(long long n, c128* __restrict
         acc[2] += d.im;
     }
     block_sum_store<3>(acc, part + part_index(r, SLOT_R, 0, nblk_max) + blockIdx.x, nblk_max);
+}
+
+// The outstanding even-step update of right-hand sides that stopped after an
+// even step (pend set, status neither iterating nor at the half step):
+// x += alpha_d p_hat' + omega_d s_hat'.  FIN_TRUE, which follows the true
+// residual, clears pend.
+template <typename TH>
+__global__ __launch_bounds__(512) void k_flush_x(long long n, c128* __restrict__ x,
+                                                 const cx<TH>* __restrict__ php,
+                                                 const cx<TH>* __restrict__ shp, const RhsState* st) {
+    const int r = blockIdx.z;
+    const int status = st[r].status;
+    if (!st[r].pend || status == ST_RUN || status == ST_HALF || status == ST_IDLE) return;
+    const c128 ald = st[r].alpha_d, omd = st[r].omega_d;
+    const long long off = (long long)r * n;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        st_stream(&x[off + i], ld_stream(&x[off + i]) + ald * cvt<double>(ld_stream(&php[off + i])) +
+                                   omd * cvt<double>(ld_stream(&shp[off + i])));
 }
 
 // ---------------------------------------------------------------------------
@@ -690,6 +740,7 @@ __global__ void k_fill_status(int n, RhsState* st, int status, int maxit2, doubl
     if (r < n) {
         st[r].status = status;
         st[r].maxit2 = maxit2;
+        st[r].pend = 0;
         if (tol2 < 0.0) st[r].tol2 = tol2;
     }
 }
@@ -802,18 +853,33 @@ void launch_s_update(hipStream_t s, long long n, int nrhs, c128* sv, const c128*
                            nblk_max);
 }
 template <typename TH>
-void launch_update_xr(hipStream_t s, long long n, int nrhs, c128* x, c128* r, const cx<TH>* ph,
-                      const cx<TH>* sh, const c128* sv, const c128* t, const cx<TH>* rhat,
-                      const RhsState* st, double* part, long long nblk_max, const Launch& L) {
-    hipLaunchKernelGGL(k_update_xr<TH>, dim3(L.flat_cap, 1, nrhs), dim3(L.block), 0, s, n, x, r, ph, sh, sv,
-                       t, rhat, st, part, nblk_max);
+void launch_update_xr(hipStream_t s, bool odd, long long n, int nrhs, c128* x, c128* r, const cx<TH>* ph,
+                      const cx<TH>* sh, const cx<TH>* php, const cx<TH>* shp, const c128* sv, const c128* t,
+                      const cx<TH>* rhat, const RhsState* st, double* part, long long nblk_max,
+                      const Launch& L) {
+    const dim3 grid(L.flat_cap, 1, nrhs);
+    if (odd)
+        hipLaunchKernelGGL((k_update_xr<TH, true>), grid, dim3(L.block), 0, s, n, x, r, ph, sh, php, shp, sv, t,
+                           rhat, st, part, nblk_max);
+    else
+        hipLaunchKernelGGL((k_update_xr<TH, false>), grid, dim3(L.block), 0, s, n, x, r, ph, sh, php, shp, sv,
+                           t, rhat, st, part, nblk_max);
 }
-template void launch_update_xr<double>(hipStream_t, long long, int, c128*, c128*, const c128*, const c128*,
-                                       const c128*, const c128*, const c128*, const RhsState*, double*,
-                                       long long, const Launch&);
-template void launch_update_xr<float>(hipStream_t, long long, int, c128*, c128*, const c64*, const c64*,
-                                      const c128*, const c128*, const c64*, const RhsState*, double*,
-                                      long long, const Launch&);
+template <typename TH>
+void launch_flush_x(hipStream_t s, long long n, int nrhs, c128* x, const cx<TH>* php, const cx<TH>* shp,
+                    const RhsState* st, const Launch& L) {
+    hipLaunchKernelGGL(k_flush_x<TH>, dim3(L.flat_cap, 1, nrhs), dim3(L.block), 0, s, n, x, php, shp, st);
+}
+template void launch_update_xr<double>(hipStream_t, bool, long long, int, c128*, c128*, const c128*,
+                                       const c128*, const c128*, const c128*, const c128*, const c128*,
+                                       const c128*, const RhsState*, double*, long long, const Launch&);
+template void launch_update_xr<float>(hipStream_t, bool, long long, int, c128*, c128*, const c64*, const c64*,
+                                      const c64*, const c64*, const c128*, const c128*, const c64*,
+                                      const RhsState*, double*, long long, const Launch&);
+template void launch_flush_x<double>(hipStream_t, long long, int, c128*, const c128*, const c128*,
+                                     const RhsState*, const Launch&);
+template void launch_flush_x<float>(hipStream_t, long long, int, c128*, const c64*, const c64*,
+                                    const RhsState*, const Launch&);
 void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const double* part,
                      long long nblk, long long nblk_max, double tol) {
     hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(1024), 0, s, mode, st, part, nblk, nblk_max, tol);

@@ -80,6 +80,9 @@ struct hh_ctx {
     double* kb = nullptr;
     c128 *bsrc = nullptr, *xk = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr,
          *s = nullptr, *t = nullptr, *ph = nullptr, *sh = nullptr;
+    // p_hat, s_hat of the odd steps (ph, sh hold the even steps'): the even
+    // step's pair stays until the odd step's x update has added it
+    c128 *ph2 = nullptr, *sh2 = nullptr;
     // single-precision preconditioner: complex64 copies of p and s (its inputs);
     // ph / sh then hold its complex64 outputs, and rhat the complex64 shadow
     // residual (r0 rounded to complex64)
@@ -243,7 +246,7 @@ void free_all(hh_ctx* c) {
     }
     c->lv.clear();
     void* ptrs[] = {c->k2, c->kb, c->bsrc, c->xk, c->r, c->rhat, c->p, c->v, c->s, c->t,
-                    c->ph, c->sh, c->p_low, c->s_low, c->st, c->part, c->bad, c->cidx, c->unk_of, c->minv,
+                    c->ph, c->sh, c->ph2, c->sh2, c->p_low, c->s_low, c->st, c->part, c->bad, c->cidx, c->unk_of, c->minv,
                     c->cg_part};
     for (void* q : ptrs) (void)hipFree(q);
     if (c->st_host) (void)hipHostFree(c->st_host);
@@ -541,15 +544,15 @@ void enqueue_cycle(hh_ctx* c, hipStream_t s, int nrhs, const c128* bin, c128* bo
 // entry, and its output is a complex64 value either way.
 // ev (may be null): NTRACE_LAUNCH event pairs recorded around the traced launches
 template <typename TH>
-void enqueue_iteration_t(hh_ctx* c, hipStream_t s, int nrhs, cx<TH>* ph, cx<TH>* sh, c64* p_low,
-                         c64* s_low, hipEvent_t* ev) {
+void enqueue_iteration_t(hh_ctx* c, hipStream_t s, int nrhs, bool odd, cx<TH>* ph, cx<TH>* sh,
+                         const cx<TH>* php, const cx<TH>* shp, c64* p_low, c64* s_low, hipEvent_t* ev) {
     const Geo& g = c->lv[0].g;
     const long long n = g.n;
     const long long nb = c->nblk0;
     const int bc = c->cfg.bc;
     Launch F = c->L0;
     F.flat_cap = (int)nb;  // flat kernels use exactly nblk0 workgroups: same partial count
-    launch_finalize(s, FIN_RHO, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
+    launch_finalize(s, odd ? FIN_RHO_DEFER : FIN_RHO, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
     constexpr bool low = sizeof(TH) == sizeof(float);
     auto E = [&](int launch) -> hipEvent_t* { return ev ? ev + 2 * launch : nullptr; };
     auto mark = [&](int launch, int end) {
@@ -586,20 +589,37 @@ void enqueue_iteration_t(hh_ctx* c, hipStream_t s, int nrhs, cx<TH>* ph, cx<TH>*
     mark(TL_APPLY_T, 1);
     launch_finalize(s, FIN_OMEGA, nrhs, c->st, c->part, nb, NBLK_CAP, 0.0);
     mark(TL_UPDATE_XR, 0);
-    launch_update_xr<TH>(s, n, nrhs, c->xk, c->r, ph, sh, c->s, c->t, reinterpret_cast<const cx<TH>*>(c->rhat),
-                         c->st, c->part, NBLK_CAP, F);
+    launch_update_xr<TH>(s, odd, n, nrhs, c->xk, c->r, ph, sh, php, shp, c->s, c->t,
+                         reinterpret_cast<const cx<TH>*>(c->rhat), c->st, c->part, NBLK_CAP, F);
     mark(TL_UPDATE_XR, 1);
 }
 
 // One Bi-CGSTAB step for all right-hand sides still iterating (device-side
 // scalars).  A right-hand side that meets the tolerance at the half step gets
 // x += alpha p_hat in the x / r update and is marked converged by the next FIN_RHO.
-void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs, hipEvent_t* ev = nullptr) {
+// Steps alternate between even (odd = false: p_hat, s_hat in ph, sh; x not
+// touched) and odd (p_hat, s_hat in ph2, sh2; x gets both steps' updates).
+void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs, bool odd, hipEvent_t* ev = nullptr) {
+    c128* ph = odd ? c->ph2 : c->ph;
+    c128* sh = odd ? c->sh2 : c->sh;
     if (c->mixed)
-        enqueue_iteration_t<float>(c, s, nrhs, reinterpret_cast<c64*>(c->ph), reinterpret_cast<c64*>(c->sh),
+        enqueue_iteration_t<float>(c, s, nrhs, odd, reinterpret_cast<c64*>(ph), reinterpret_cast<c64*>(sh),
+                                   reinterpret_cast<const c64*>(c->ph), reinterpret_cast<const c64*>(c->sh),
                                    c->p_low, c->s_low, ev);
     else
-        enqueue_iteration_t<double>(c, s, nrhs, c->ph, c->sh, nullptr, nullptr, ev);
+        enqueue_iteration_t<double>(c, s, nrhs, odd, ph, sh, c->ph, c->sh, nullptr, nullptr, ev);
+}
+
+// The outstanding even-step updates of the right-hand sides that stopped.
+void enqueue_flush_x(hh_ctx* c, hipStream_t s, int nrhs) {
+    Launch F = c->L0;
+    F.flat_cap = (int)c->nblk0;
+    const long long n = c->lv[0].g.n;
+    if (c->mixed)
+        launch_flush_x<float>(s, n, nrhs, c->xk, reinterpret_cast<const c64*>(c->ph),
+                              reinterpret_cast<const c64*>(c->sh), c->st, F);
+    else
+        launch_flush_x<double>(s, n, nrhs, c->xk, c->ph, c->sh, c->st, F);
 }
 
 // One IDR(s) cycle (s inner steps and the reduction step) for every
@@ -684,7 +704,8 @@ hh_status get_graph(hh_ctx* c, int nrhs, hipGraphExec_t* out) {
     }
     hipGraph_t graph = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
-    enqueue_iteration(c, c->cap, nrhs);
+    enqueue_iteration(c, c->cap, nrhs, false);
+    enqueue_iteration(c, c->cap, nrhs, true);
     hipError_t le = hipGetLastError();
     hipError_t ee = hipStreamEndCapture(c->cap, &graph);
     if (le != hipSuccess) return fail(c, HH_ERR_HIP, "launch during capture: %s", hipGetErrorString(le));
@@ -1125,7 +1146,8 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
         }
     }
     const size_t n0 = (size_t)shapes[0].n;
-    c128** vecs[] = {&c->bsrc, &c->xk, &c->r, &c->rhat, &c->p, &c->v, &c->s, &c->t, &c->ph, &c->sh};
+    c128** vecs[] = {&c->bsrc, &c->xk, &c->r, &c->rhat, &c->p, &c->v, &c->s, &c->t, &c->ph, &c->sh, &c->ph2,
+                     &c->sh2};
     for (c128** q : vecs) {
         hh_status s = dalloc(c, q, sizeof(c128) * n0 * R);
         if (s != HH_OK) return bail(s);
@@ -1364,8 +1386,10 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
     hipGraphExec_t exec = nullptr;
     if (c->use_graph && !c->trace) CHK(get_graph(c, nrhs, &exec));
     const size_t ev_per_step = 2 * NTRACE_LAUNCH;
+    // steps between host checks: whole even/odd pairs (the graph holds one pair)
+    const int pairs = (c->check_every + 1) / 2, window = 2 * pairs;
     if (c->trace)
-        while (c->tev.size() < ev_per_step * (size_t)c->check_every) {
+        while (c->tev.size() < ev_per_step * (size_t)window) {
             // no system-scope fence at record: the events only bracket kernels
             // on this stream, and a fence per record would lengthen every bracket
             hipEvent_t e;
@@ -1386,16 +1410,18 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
         }
         if (any_run) {
             const bool full_before = all_running();
-            for (int k = 0; k < c->check_every; ++k) {
-                if (exec) HIPCHK(c, hipGraphLaunch(exec, c->stream));
-                else enqueue_iteration(c, c->stream, nrhs, c->trace ? &c->tev[ev_per_step * k] : nullptr);
+            if (exec) {
+                for (int k = 0; k < pairs; ++k) HIPCHK(c, hipGraphLaunch(exec, c->stream));
+            } else {
+                for (int k = 0; k < window; ++k)
+                    enqueue_iteration(c, c->stream, nrhs, k & 1, c->trace ? &c->tev[ev_per_step * k] : nullptr);
             }
             HIPCHK(c, hipGetLastError());
             CHK(read_states(c, nrhs));
             if (c->trace && full_before && all_running()) {
                 // every right-hand side iterated through the whole window: each
                 // traced launch did its full work
-                for (int k = 0; k < c->check_every; ++k)
+                for (int k = 0; k < window; ++k)
                     for (int l = 0; l < NTRACE_LAUNCH; ++l) {
                         float ms = 0.f;
                         hipEvent_t* e = &c->tev[ev_per_step * k + 2 * l];
@@ -1411,6 +1437,7 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
         // every right-hand side stopped: recompute the true residual b - A x;
         // a converged one whose true residual misses rtol restarts from x
         if (any_half) launch_finalize(c->stream, FIN_RHO, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, rtol);
+        enqueue_flush_x(c, c->stream, nrhs);
         launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->mixed, c->p, c->v,
                     c->k2, c->kb, 1, c->part, NBLK_CAP, c->st, GATE_FINISHED);
         launch_finalize(c->stream, FIN_TRUE, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, rtol);
@@ -1661,7 +1688,8 @@ void launch_one_fine(hh_ctx* c, int which, int nrhs) {
                          NBLK_CAP, c->st, ST_RUN);
             break;
         case 1:
-            launch_update_xr<R>(s, g.n, nrhs, c->xk, c->r, phat, shat, c->s, c->t,
+            // the odd step's form (x += alpha p_hat + omega s_hat; nothing outstanding)
+            launch_update_xr<R>(s, true, g.n, nrhs, c->xk, c->r, phat, shat, phat, shat, c->s, c->t,
                                 reinterpret_cast<const cx<R>*>(c->rhat), c->st, c->part,
                                 NBLK_CAP, F);
             break;
@@ -1777,8 +1805,9 @@ hh_status hh_autotune(hh_ctx* c, const char* cache_json_path) {
     // Each candidate runs the first steps of a solve of the current sources (a
     // fresh start, graph replay) timed with HIP events on the context stream:
     // kernels see the data flow and cache state of a solve, not a repeated
-    // launch on warm inputs.  The best of two timings counts.
-    constexpr int kSteps = 8, kWarm = 2, kRepeat = 2;
+    // launch on warm inputs.  The best of two timings counts.  The graph holds
+    // one even/odd pair of steps: 8 steps timed after 2 warm-up steps.
+    constexpr int kPairs = 4, kWarm = 1, kRepeat = 2;
     const Geo& g = c->lv[0].g;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
@@ -1790,18 +1819,18 @@ hh_status hh_autotune(hh_ctx* c, const char* cache_json_path) {
         float best = 1e30f;
         for (int rep = 0; rep < kRepeat; ++rep) {
             // tolerance 0: no right-hand side stops within the few steps timed
-            launch_fill_status(c->stream, nrhs, c->st, ST_RUN, 2 * (kSteps + kWarm + 1));
+            launch_fill_status(c->stream, nrhs, c->st, ST_RUN, 4 * (kPairs + kWarm + 1));
             launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->mixed, c->p,
                         c->v, c->k2, c->kb, 0, c->part, NBLK_CAP, c->st, ST_RUN);
             launch_finalize(c->stream, FIN_INIT, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, 0.0);
             for (int k = 0; k < kWarm; ++k) HIPCHK(c, hipGraphLaunch(exec, c->stream));
             HIPCHK(c, hipEventRecord(e0, c->stream));
-            for (int k = 0; k < kSteps; ++k) HIPCHK(c, hipGraphLaunch(exec, c->stream));
+            for (int k = 0; k < kPairs; ++k) HIPCHK(c, hipGraphLaunch(exec, c->stream));
             HIPCHK(c, hipEventRecord(e1, c->stream));
             HIPCHK(c, hipEventSynchronize(e1));
             float ms = 0.f;
             HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-            best = std::min(best, ms / kSteps);
+            best = std::min(best, ms / (2 * kPairs));
         }
         *out = best;
         return HH_OK;
