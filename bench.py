@@ -114,18 +114,19 @@ def step_bytes_per_dof(prec_idx: int) -> float:
 
 
 # HBM traffic per launch, FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scale factors
-# from a 1 GiB reference copy; the operator apply's entry is the mean of its
-# two launches per step) from two rocprofv3 --pmc runs of
+# from a 1 GiB reference copy; the operator apply's entry is the mean of its two
+# launches in a step, the x / r update's the mean of its even- and odd-step
+# launches) from two rocprofv3 --pmc runs of
 # `bench.py --steps 1 --warmup 0 --no-cpu --no-fp64 --copy-calibration`
 # (profiles/cube513_hbm_traffic.md).  Valid only for the kernel sources it was
 # measured on (kernel_source_sha); otherwise reported as null.
 TRAFFIC = {
-    ("update_xr+dots", "cube513", "mixed"): (14047.3e6, "386748f5da0ff30c"),
-    ("apply_A+dots", "cube513", "mixed"): (6240.0e6, "386748f5da0ff30c"),
-    ("mg_down_L0", "cube513", "mixed"): (2301.1e6, "386748f5da0ff30c"),
-    ("mg_up_L0", "cube513", "mixed"): (3223.4e6, "386748f5da0ff30c"),
-    ("p_update", "cube513", "mixed"): (9720.4e6, "386748f5da0ff30c"),
-    ("s_update+dot", "cube513", "mixed"): (7562.5e6, "386748f5da0ff30c"),
+    ("update_xr+dots", "cube513", "mixed"): (11886.4e6, "0c2f0ec5782ea0dc"),
+    ("apply_A+dots", "cube513", "mixed"): (6243.2e6, "0c2f0ec5782ea0dc"),
+    ("mg_down_L0", "cube513", "mixed"): (2282.1e6, "0c2f0ec5782ea0dc"),
+    ("mg_up_L0", "cube513", "mixed"): (3228.4e6, "0c2f0ec5782ea0dc"),
+    ("p_update", "cube513", "mixed"): (9720.4e6, "0c2f0ec5782ea0dc"),
+    ("s_update+dot", "cube513", "mixed"): (7562.3e6, "0c2f0ec5782ea0dc"),
 }
 
 
