@@ -16,9 +16,12 @@ template <typename R>
 __device__ __forceinline__ cx<R> czero() { return cx<R>{R(0), R(0)}; }
 
 // Streaming access: loads and stores with the non-temporal hint, for data a
-// kernel touches once (the Krylov vectors in the update kernels).  Measured on
-// the 513^3 cube: the x / r update 2.87 -> 2.57 ms, the p update 1.96 -> 1.84
-// ms, the s update 1.44 -> 1.38 ms against plain loads and stores.
+// kernel touches once (the Krylov vectors in the update kernels of
+// Bi-CGSTAB, IDR(s) and GMRES).  Measured on the 513^3 cube: the x / r update
+// 2.87 -> 2.57 ms, the p update 1.96 -> 1.84 ms, the s update 1.44 -> 1.38 ms
+// against plain loads and stores; on the wedge IDR(4) 35.7 -> 34.4 ms and
+// GMRES 252 -> 238 ms per solve.  The stencil kernels, whose halos are
+// re-read through the caches, are slower with them.
 typedef double hh_d2 __attribute__((ext_vector_type(2)));
 typedef float hh_f2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ c128 ld_stream(const c128* p) {

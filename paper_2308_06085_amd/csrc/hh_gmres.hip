@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_gm_dots(long long n, int j, const c128*
 #pragma unroll
         for (int q = 0; q < GM_GROUP; ++q)
             if (i0 + q <= j) {
-                const c128 d = cdot(V[(i0 + q) * rsv + off + x], wv);
+                const c128 d = cdot(ld_stream(&V[(i0 + q) * rsv + off + x]), wv);
                 acc[2 * q] += d.re;
                 acc[2 * q + 1] += d.im;
             }
@@ -112,9 +112,9 @@ __global__ __launch_bounds__(256) void k_gm_axpy(long long n, int j, const c128*
     double acc[1] = {0.0};
     for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n;
          x += (long long)gridDim.x * blockDim.x) {
-        c128 a = w_in[off + x];
-        for (int i = 0; i <= j; ++i) a = a - coef[i] * V[i * rsv + off + x];
-        w_out[off + x] = a;
+        c128 a = ld_stream(&w_in[off + x]);
+        for (int i = 0; i <= j; ++i) a = a - coef[i] * ld_stream(&V[i * rsv + off + x]);
+        st_stream(&w_out[off + x], a);
         if (NORM) acc[0] += abs2(a);
     }
     if (NORM) {
@@ -190,9 +190,9 @@ __global__ __launch_bounds__(256) void k_gm_xupdate(long long n, c128* __restric
     const long long off = (long long)r * n;
     for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n;
          x += (long long)gridDim.x * blockDim.x) {
-        c128 a = xk[off + x];
-        for (int i = 0; i < m; ++i) a = a + y[i] * V[i * rsv + off + x];
-        xk[off + x] = a;
+        c128 a = ld_stream(&xk[off + x]);
+        for (int i = 0; i < m; ++i) a = a + y[i] * ld_stream(&V[i * rsv + off + x]);
+        st_stream(&xk[off + x], a);
     }
 }
 

@@ -69,12 +69,12 @@ __global__ __launch_bounds__(512) void k_idr_v(long long n, int k, const c128* _
     const long long off = (long long)r * n;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        c128 a = rr[off + i];
+        c128 a = ld_stream(&rr[off + i]);
 #pragma unroll
         for (int j = 0; j < IDR_SMAX; ++j)
-            if (j >= k && j < s) a = a - cj[j] * G[j * rsj + off + i];
-        if (LOW) v_low[off + i] = cvt<float>(a);
-        else v[off + i] = a;
+            if (j >= k && j < s) a = a - cj[j] * ld_stream(&G[j * rsj + off + i]);
+        if (LOW) st_stream(&v_low[off + i], cvt<float>(a));
+        else st_stream(&v[off + i], a);
     }
 }
 
@@ -95,11 +95,11 @@ __global__ __launch_bounds__(512) void k_idr_u(long long n, int k, c128* __restr
     c128* uk = U + k * rsj + off;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        c128 a = om * cvt<double>(vh[off + i]);
+        c128 a = om * cvt<double>(ld_stream(&vh[off + i]));
 #pragma unroll
         for (int j = 0; j < IDR_SMAX; ++j)
-            if (j >= k && j < s) a = a + cj[j] * U[j * rsj + off + i];
-        uk[i] = a;
+            if (j >= k && j < s) a = a + cj[j] * ld_stream(&U[j * rsj + off + i]);
+        st_stream(&uk[i], a);
     }
 }
 
@@ -131,25 +131,25 @@ __global__ __launch_bounds__(512) void k_idr_update(long long n, int k, c128* __
     double acc[1] = {0.0};
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        c128 g = gk[i], u = uk[i];
+        c128 g = ld_stream(&gk[i]), u = ld_stream(&uk[i]);
 #pragma unroll
         for (int j = 0; j < IDR_SMAX; ++j)
             if (j < k) {
-                g = g - a[j] * G[j * rsj + off + i];
-                u = u - a[j] * U[j * rsj + off + i];
+                g = g - a[j] * ld_stream(&G[j * rsj + off + i]);
+                u = u - a[j] * ld_stream(&U[j * rsj + off + i]);
             }
-        gk[i] = g;
-        uk[i] = u;
-        const c128 rv = rr[off + i] - beta * g;
-        rr[off + i] = rv;
-        x[off + i] = x[off + i] + beta * u;
+        st_stream(&gk[i], g);
+        st_stream(&uk[i], u);
+        const c128 rv = ld_stream(&rr[off + i]) - beta * g;
+        st_stream(&rr[off + i], rv);
+        st_stream(&x[off + i], ld_stream(&x[off + i]) + beta * u);
         acc[0] += abs2(rv);
         c128 nv = rv;
 #pragma unroll
         for (int j = 0; j < IDR_SMAX; ++j)
-            if (j > k && j < sn) nv = nv - cn[j] * G[j * rsj + off + i];
-        if (LOW) v_low[off + i] = cvt<float>(nv);
-        else v[off + i] = nv;
+            if (j > k && j < sn) nv = nv - cn[j] * ld_stream(&G[j * rsj + off + i]);
+        if (LOW) st_stream(&v_low[off + i], cvt<float>(nv));
+        else st_stream(&v[off + i], nv);
     }
     block_sum_store<1>(acc, part + idr_row(r, IDR_ROW_RN, nblk_max) + blockIdx.x, nblk_max);
 }
@@ -171,12 +171,12 @@ __global__ __launch_bounds__(512) void k_idr_xr(long long n, c128* __restrict__ 
     for (int q = 0; q < 2 * NS; ++q) acc[q] = 0.0;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        x[off + i] = x[off + i] + om * cvt<double>(vh[off + i]);
-        const c128 rv = rr[off + i] - om * t[off + i];
-        rr[off + i] = rv;
+        st_stream(&x[off + i], ld_stream(&x[off + i]) + om * cvt<double>(ld_stream(&vh[off + i])));
+        const c128 rv = ld_stream(&rr[off + i]) - om * ld_stream(&t[off + i]);
+        st_stream(&rr[off + i], rv);
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-            const c128 d = cdot(cvt<double>(P[q * n + i]), rv);
+            const c128 d = cdot(cvt<double>(ld_stream(&P[q * n + i])), rv);
             acc[2 * q] += d.re;
             acc[2 * q + 1] += d.im;
         }

@@ -269,6 +269,31 @@ def test_fixed_iteration_iterates(steps):
     assert relerr(host(x)[0], ref.x) <= 1e-9
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_check_window_does_not_change_the_solution(prec):
+    """The solve updates x every second step and replays an even/odd pair of
+    steps per graph launch, so host checks every 1 or 3 steps round up to whole
+    pairs; steps after a right-hand side stops are gated off, so the window
+    changes neither the solution (bit for bit) nor the step count.  Two
+    right-hand sides stop at different steps."""
+    shape = (17, 17, 33)
+    h = 1 / 16
+    k = hetero_k(shape, 11, 6.0, 14.0)
+    s = _solver(shape, h, SOMMERFELD, prec=prec, nrhs_max=2)
+    s.set_model(dev(k))
+    b = np.stack([O.point_source_rhs(shape, h, [(8, 8, 16)])[0], W.random_complex(shape, seed=29)])
+    s.set_sources(dev(b))
+    ref, st_ref = s.solve(rtol=1e-6)
+    ref = host(ref)
+    assert st_ref[0].iterations != st_ref[1].iterations
+    for ce in (1, 3, 4):
+        s.set_option("check_every", ce)
+        x, st = s.solve(rtol=1e-6)
+        assert np.array_equal(host(x), ref), ce
+        assert [t.iterations for t in st] == [t.iterations for t in st_ref], ce
+    s.close()
+
+
 @pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
 @pytest.mark.parametrize("steps", [1, 2, 5])
 def test_fixed_iteration_iterates_mixed(bc, steps):
