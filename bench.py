@@ -82,10 +82,11 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "DoF-iterations/s of CSLP-Bi-CGSTAB, mixed vs FP64 at 1e-6 rel residual; %HBM"
 
 # Kernel ids of hh_time_kernel, launches per Bi-CGSTAB step and algorithmic
-# bytes per fine-grid node per right-hand side for (fp64, mixed) precision:
-# every array the kernel must read or write once (complex128 16 B, complex64
-# 8 B, real k^2 8 B for the operator, k in the multigrid precision for the
-# multigrid passes, coarse-grid arrays 1/8 of a fine one).  In the mixed solve
+# bytes per fine-grid node for (fp64, mixed) precision: every array the kernel
+# must read or write once (complex128 16 B, complex64 8 B, real k^2 8 B for the
+# operator, k in the multigrid precision for the multigrid passes, coarse-grid
+# arrays 1/8 of a fine one), split into the bytes of each right-hand side and
+# the bytes all right-hand sides of a batch share (k^2, k: read once per launch).  In the mixed solve
 # the preconditioner's inputs (complex64 copies of p and s, written by the p
 # and s updates), its outputs p_hat, s_hat and the shadow residual r_hat are
 # complex64.  The operator apply's figure is the mean of its two launches per
@@ -94,23 +95,37 @@ METRIC = "DoF-iterations/s of CSLP-Bi-CGSTAB, mixed vs FP64 at 1e-6 rel residual
 # alternates: an even step reads s, t, r_hat and writes r (FP64 64 B, mixed
 # 56 B); an odd step also reads x and both steps' p_hat, s_hat and writes x
 # (FP64 160 B, mixed 120 B); its figure is the mean of the two.
-KERNELS = {
-    0: ("apply_A+dots", 2, (16 + 8 + 16 + 16, 8 + 8 + (8 + 16) / 2 + 16)),
-    1: ("update_xr+dots", 1, ((64 + 160) / 2, (56 + 120) / 2)),
-    2: ("mg_down_L0", 2, (16 + 8 + 16 / 8, 8 + 4 + 8 / 8)),
-    3: ("mg_up_L0", 2, (16 + 8 + 16 / 8 + 16, 8 + 4 + 8 / 8 + 8)),
-    4: ("p_update", 1, (4 * 16, 4 * 16 + 8)),
-    5: ("s_update+dot", 1, (3 * 16, 3 * 16 + 8)),
+KERNELS = {  # id: (name, launches per step, per-RHS (fp64, mixed), shared (fp64, mixed))
+    0: ("apply_A+dots", 2, (16 + 16 + 16, 8 + (8 + 16) / 2 + 16), (8, 8)),
+    1: ("update_xr+dots", 1, ((64 + 160) / 2, (56 + 120) / 2), (0, 0)),
+    2: ("mg_down_L0", 2, (16 + 16 / 8, 8 + 8 / 8), (8, 4)),
+    3: ("mg_up_L0", 2, (16 + 16 / 8 + 16, 8 + 8 / 8 + 8), (8, 4)),
+    4: ("p_update", 1, (4 * 16, 4 * 16 + 8), (0, 0)),
+    5: ("s_update+dot", 1, (3 * 16, 3 * 16 + 8), (0, 0)),
 }
+
+
+def kernel_bytes(kid: int, prec_idx: int, nrhs: int = 1) -> float:
+    """Algorithmic bytes per fine node of one launch of kernel `kid` for
+    `nrhs` right-hand sides."""
+    _, _, rhs, shared = KERNELS[kid]
+    return nrhs * rhs[prec_idx] + shared[prec_idx]
+
 
 # Coarse multigrid levels per preconditioner application: the level-0 pass
 # bytes (down + up) times sum_{l>=1} 8^-l = 1/7; two applications per step.
-def step_bytes_per_dof(prec_idx: int) -> float:
-    """Algorithmic bytes per DoF of one Bi-CGSTAB step as built: every level-0
-    kernel of KERNELS times its launches per step, plus the coarse levels."""
-    total = sum(per * nb[prec_idx] for _, per, nb in KERNELS.values())
-    mg = KERNELS[2][2][prec_idx] + KERNELS[3][2][prec_idx]
+def step_bytes(prec_idx: int, nrhs: int = 1) -> float:
+    """Algorithmic bytes per fine node of one Bi-CGSTAB step for `nrhs`
+    iterating right-hand sides as built: every level-0 kernel of KERNELS times
+    its launches per step, plus the coarse levels."""
+    total = sum(KERNELS[k][1] * kernel_bytes(k, prec_idx, nrhs) for k in KERNELS)
+    mg = kernel_bytes(2, prec_idx, nrhs) + kernel_bytes(3, prec_idx, nrhs)
     return total + 2 * mg / 7.0
+
+
+def step_bytes_per_dof(prec_idx: int) -> float:
+    """Algorithmic bytes per DoF of one single-source Bi-CGSTAB step."""
+    return step_bytes(prec_idx, 1)
 
 
 # HBM traffic per launch, FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scale factors
@@ -289,8 +304,8 @@ def kernel_roofline(solver, nrhs, prec_idx, n_nodes, x, solves):
     solver.set_option("trace", 0)
     bracket = ms[6]
     rows = {}
-    for kid, (name, per_iter, nbytes) in KERNELS.items():
-        algo = nbytes[prec_idx] * n_nodes * nrhs
+    for kid, (name, per_iter, _, _) in KERNELS.items():
+        algo = kernel_bytes(kid, prec_idx, nrhs) * n_nodes
         rows[name] = {"ms": ms[kid], "launches": cnt[kid], "per_iter": per_iter,
                       "bytes": int(algo), "GBs": algo / (ms[kid] * 1e-3) / 1e9 if ms[kid] > 0 else None}
     dom = max(rows, key=lambda k: rows[k]["ms"] * rows[k]["per_iter"])
@@ -512,8 +527,13 @@ def main():
             dom, rows, bracket = kernel_roofline(s, nrhs, 0 if prec == "fp64" else 1, n_nodes, x, traced)
         else:  # the library's in-solve kernel tracing covers the Bi-CGSTAB step only
             dom, rows, bracket = None, {}, None
-        bpd = step_bytes_per_dof(0 if prec == "fp64" else 1)
-        step_gbs = bpd * dof(wl) * float(np.sum(iters)) / t / 1e9
+        # bytes of the solves: every right-hand side's own bytes per step it
+        # iterated, the shared k^2 / k bytes once per step of the longest one
+        pi = 0 if prec == "fp64" else 1
+        per_rhs, shared = step_bytes(pi, 1) - step_bytes(pi, 0), step_bytes(pi, 0)
+        solve_bytes = n_nodes * (per_rhs * float(np.sum(iters)) + shared * reps * max(s_.iterations for s_ in stats))
+        bpd = solve_bytes / (dof(wl) * float(np.sum(iters)))
+        step_gbs = solve_bytes / t / 1e9
         results[prec] = {
             "hbm_per_iteration": {"bytes_per_dof": round(bpd, 1), "GBs": step_gbs,
                                   "frac": step_gbs / HBM_PEAK_GBS} if args.method == "bicgstab" else None,
