@@ -659,10 +659,8 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
     };
     static_assert(sizeof(R) == sizeof(float), "the x-pair up pass runs in single precision");
     // per node and plane: u2 and the b, c and W its output step needs
-    constexpr bool KEEP_C = true;
     struct Node {
         cx<R> u, b, c, w;
-        R k;
     };
     struct Pair {
         Node a, b;
@@ -685,16 +683,10 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
         const cx<R> peb = lerp2(wb0, q0, wb1, q1);
         o.a.b = cvt<R>(v.ba);
         o.b.b = cvt<R>(v.bb);
-        o.a.k = v.ka;
-        o.b.k = v.kb;
-        const cx<R> ca = shift_c(L, v.ka, BC == BC_SOMMERFELD ? nfa + zf : 0);
-        const cx<R> cb2 = shift_c(L, v.kb, BC == BC_SOMMERFELD ? nfb + zf : 0);
-        if constexpr (KEEP_C) {
-            o.a.c = ca;
-            o.b.c = cb2;
-        }
-        o.a.w = jacobi_w(L, ca);
-        o.b.w = jacobi_w(L, cb2);
+        o.a.c = shift_c(L, v.ka, BC == BC_SOMMERFELD ? nfa + zf : 0);
+        o.b.c = shift_c(L, v.kb, BC == BC_SOMMERFELD ? nfb + zf : 0);
+        o.a.w = jacobi_w(L, o.a.c);
+        o.b.w = jacobi_w(L, o.b.c);
         o.a.u = cfma(o.a.w, o.a.b, pea);
         o.b.u = cfma(o.b.w, o.b.b, peb);
         if (BC == BC_DIRICHLET && (nfa || zf)) o.a.u = czero<R>();
@@ -712,7 +704,6 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
         const cx<R>* uc = us[z & 3];
         const cx<R>* um = us[(z - 1) & 3];
         const bool bot = z == 0, top = z == g.nz - 1;
-        const int zfz = (int)bot + (int)top;
         auto out1 = [&](const Node& nd, const cx<R>& xm, const cx<R>& xp, const cx<R>& ym, const cx<R>& yp,
                         const cx<R>& zm, const cx<R>& zp, int nf, long long off) {
             const cx<R> u = nd.u;
@@ -721,8 +712,7 @@ __global__ __launch_bounds__(UP_LANES, UP_WAVES_PER_SIMD<R>) void k_mg_up(Geo g,
             lap = lap + (u - yp);
             lap = lap + (u - (bot ? zp : zm));
             lap = lap + (u - (top ? zm : zp));
-            const cx<R> cc = KEEP_C ? nd.c : shift_c(L, nd.k, BC == BC_SOMMERFELD ? nf + zfz : 0);
-            cx<R> v = cfma(nd.w, mresid(nd.b, L.ih2, lap, cc, u), u);
+            cx<R> v = cfma(nd.w, mresid(nd.b, L.ih2, lap, nd.c, u), u);
             if (BC == BC_DIRICHLET && (nf || bot || top)) v = czero<R>();
             cx<TO>* o = orr + (long long)z * g.plane + off;
             if constexpr (ACC) v = cvt<R>(*o) + v;  // out already holds an earlier cycle's result
