@@ -237,8 +237,9 @@ hh_status hh_grad_slowness2(hh_ctx* ctx, const void* u, const void* w, const dou
  * HH_ERR_ARG for a null P or s outside 1..8. */
 hh_status hh_set_shadow(hh_ctx* ctx, const void* P, int s);
 
-/* Options: "graph" (1 = replay each Bi-CGSTAB step as a captured hipGraph,
- * default 1), "check_every" (steps between host convergence checks, default 4),
+/* Options: "graph" (1 = replay Bi-CGSTAB steps as a captured hipGraph of one
+ * even and one odd step, default 1), "check_every" (steps between host
+ * convergence checks, default 4; Bi-CGSTAB rounds it up to an even number),
  * "block" (threads per workgroup of the flat Krylov vector kernels: 64, 128,
  * 256, 512; default 256), "zb" (z-planes per workgroup of the operator apply and
  * the start-residual kernel, whose workgroups are 256-node x-y tiles; default 4,
@@ -290,7 +291,9 @@ hh_status hh_get_option(const hh_ctx* ctx, const char* name, long long* value);
  * workgroup shape), on the context's scratch vectors, and return the average
  * duration in milliseconds measured with HIP events on that stream.
  * which: 0 = t = A s_hat with the fused partial dot products, 1 = the Krylov
- * x / r update with its dot products, 2 = fused multigrid down pass on the
+ * x / r update with its dot products in the form of an odd step with nothing
+ * outstanding (x += alpha p_hat + omega s_hat, r = s - omega t; the solve
+ * updates x every second step), 2 = fused multigrid down pass on the
  * finest level (smoother + residual + restriction), 3 = fused up pass on the
  * finest level (prolongation + correction + post-smoother), 4 = p update,
  * 5 = s update with ||s||^2.
@@ -302,11 +305,12 @@ hh_status hh_time_kernel(hh_ctx* ctx, int which, int nrhs, int reps, float* ms_a
  * resets the sums) every following hh_solve launches its steps directly
  * (no graph replay) with HIP events on the context stream around the
  * fine-level kernels of each step that runs; "trace" 0 returns to graph
- * replay.  Only check windows (check_every steps) through which every
+ * replay.  Only check windows (check_every steps rounded up to an even
+ * number) through which every
  * right-hand side kept iterating are counted, so each counted launch did the
  * full work of all right-hand sides.  hh_kernel_times returns, per kernel id
  * of hh_time_kernel (0 = the operator apply with its dot products, both
- * launches of a step; 1 = x / r update; 2 / 3 = finest-level multigrid
+ * launches of a step; 1 = x / r update, even and odd steps alike; 2 / 3 = finest-level multigrid
  * down / up pass, both V-cycles; 4 = p update; 5 = s update) and id 6 (an
  * extra launch of the operator apply per step with every workgroup gated off:
  * what the event bracket around one launch adds to a kernel's own duration),
