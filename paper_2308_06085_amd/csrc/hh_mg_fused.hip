@@ -8,6 +8,9 @@
 // Down (Algorithm 1 steps 1-3: zero initial guess, one damped-Jacobi sweep,
 // residual, full-weighting restriction of section 3.4.2):
 //   u1 = W b,   r = b - (1/h^2) lap(u1) + c u1,   b_H = R r.
+// Since D u1 = omega b, the residual is r = (1 - omega) b + (1/h^2) sum_nb u1_nb:
+// the node's own u1 and c drop out, and every term has the size of b (no
+// cancellation to guard against, unlike the up pass's residual of u2).
 // Up (Algorithm 1 steps 5-7: trilinear prolongation of section 3.4.3,
 // correction, one damped-Jacobi sweep):
 //   u2 = W b + P e_H,   u3 = u2 + W (b - (1/h^2) lap(u2) + c u2).
@@ -157,10 +160,16 @@ __device__ __forceinline__ cx<R> mresid(const cx<R>& b, R ih2, const cx<R>& lap,
     return cfma(c, u, sfma(-ih2, lap, b));
 }
 
-// Reciprocal: correctly rounded in double; in single precision the hardware
-// v_rcp_f32 (about 1 ulp), far inside the accuracy a complex64 V-cycle is
-// held to.
-__device__ __forceinline__ double mg_rcp(double x) { return 1.0 / x; }
+// Reciprocal of |D|^2, a positive normal number far from both ends of the
+// range: in single precision the hardware v_rcp_f32 (about 1 ulp), far inside
+// the accuracy a complex64 V-cycle is held to; in double precision v_rcp_f64
+// refined by two Newton steps y += y (1 - x y), about 1 ulp as well, instead
+// of the correctly rounded division's scaling and fix-up sequence.
+__device__ __forceinline__ double mg_rcp(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fmar(y, fmar(-x, y, 1.0), y);
+    return fmar(y, fmar(-x, y, 1.0), y);
+}
 __device__ __forceinline__ float mg_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // c_j = (beta1 - beta2 i) k^2 + n_j 2 i k / h from the level's k (k^2 formed
@@ -189,8 +198,9 @@ __device__ __forceinline__ int faces_of(int x, int y, int z, const Geo& g) {
 // columns and marches over `zbc` coarse planes (2 zbc + 1 fine residual
 // planes).  Each lane owns NU nodes of the fine region (tile plus a two-node
 // halo): it loads their b and k, writes u1 = W b to the LDS ring, and keeps
-// b and c in registers for the residual of the same nodes one plane later, so
-// every input is read once per plane.  Two planes of loads are in flight.
+// (1 - omega) b in registers for the residual of the same nodes one plane
+// later, so every input is read once per plane.  Two planes of loads are in
+// flight.
 // ---------------------------------------------------------------------------
 template <typename TB, typename R, int NU>
 struct DownRaw {
@@ -199,8 +209,7 @@ struct DownRaw {
 };
 template <typename R, int NU>
 struct DownKeep {
-    cx<R> b[NU];
-    cx<R> c[NU];
+    cx<R> b[NU];  // (1 - omega) b
 };
 
 template <int BC, typename TB, typename R, bool ONE, int REG>
@@ -261,7 +270,8 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
         // complete in issue order, so a plane must be issued as one group
         __builtin_amdgcn_sched_barrier(0);
     };
-    // u1 = W b to the ring; b and c kept for this plane's residual
+    // u1 = W b to the ring; (1 - omega) b kept for this plane's residual
+    const R omc = R(1.0 - omega);
     auto commit = [&](int f, const DownRaw<TB, R, NU>& w, DownKeep<R, NU>& kp) {
         const int fz = mirror_clamp(f, gf.nz);
         const int zf = (fz == 0) + (fz == gf.nz - 1);
@@ -277,11 +287,12 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
             // unguarded: idx < NU * DN_LANES = REG, and slots past the
             // region are never read (a guard would sink the loads into it)
             dst[idx] = v;
-            kp.b[k] = bb;
-            kp.c[k] = c;
+            kp.b[k] = {omc * bb.re, omc * bb.im};
         }
     };
-    // r = b - (1/h^2) lap(u1) + c u1 on the region's inner nodes
+    // r = (1 - omega) b + (1/h^2) sum_nb u1_nb on the region's inner nodes (on
+    // a Dirichlet boundary node, where u1 is held at zero, this is not its
+    // residual; such nodes feed only coarse boundary nodes, whose output is zero)
     auto residual = [&](int f, const DownKeep<R, NU>& kp) {
         const cx<R>* um = u1s[ring3(f - 1)];
         const cx<R>* uc = u1s[ring3(f)];
@@ -290,13 +301,12 @@ __global__ __launch_bounds__(DN_LANES) void k_mg_down(Geo gf, Geo gc, int zbc,
         for (int k = 0; k < NU; ++k) {
             if (uin[k]) {
                 const int c = t + k * DN_LANES;
-                const cx<R> u = uc[c];
-                cx<R> lap = (u - uc[c - 1]) + (u - uc[c + 1]);
-                lap = lap + (u - uc[c - RW]);
-                lap = lap + (u - uc[c + RW]);
-                lap = lap + (u - um[c]);
-                lap = lap + (u - up[c]);
-                rs[c] = mresid(kp.b[k], L.ih2, lap, kp.c[k], u);
+                cx<R> nb = uc[c - 1] + uc[c + 1];
+                nb = nb + uc[c - RW];
+                nb = nb + uc[c + RW];
+                nb = nb + um[c];
+                nb = nb + up[c];
+                rs[c] = sfma(L.ih2, nb, kp.b[k]);
             }
         }
     };
