@@ -1,8 +1,10 @@
-"""Writes wedge_step_counts.json: the oracle's Bi-CGSTAB step counts on the
-wedge problem (129 x 129 x 257 nodes, 10 Hz, Sommerfeld) to relative residual
-1e-6, for the 16 seeded top-face sources of the batched workload and the
-single source at the centre of the top face, with the complex128 V-cycle
-(FP64) and with the complex64 V-cycle and shadow residual (mixed).
+"""Writes the oracle's Bi-CGSTAB step counts to relative residual 1e-6 on a
+wedge problem (Sommerfeld), for 16 seeded top-face sources and the single
+source at the centre of the top face, with the complex128 V-cycle (FP64) and
+with the complex64 V-cycle and shadow residual (mixed):
+
+    wedge10      129 x 129 x 257 nodes, 10 Hz (kh up to 0.20)  -> wedge_step_counts.json
+    halfwedge14   65 x  65 x 129 nodes, 14 Hz (kh up to 0.55)  -> half_wedge_14hz_step_counts.json
 
 Bi-CGSTAB's step count on this indefinite problem reacts to roundings far
 below the solution's accuracy: two preconditioners that differ by 1e-7 in
@@ -11,7 +13,7 @@ many sources is what a change of precision actually moves, so the file keeps
 every count and their means.  Calls only the oracle and the seeded input
 generators; the 34 solves run in worker processes.
 
-    python tests/golden/make_wedge_step_counts.py [workers]
+    python tests/golden/make_wedge_step_counts.py [wedge10|halfwedge14] [workers]
 """
 import json
 import os
@@ -32,11 +34,22 @@ from oracle.multigrid import build_hierarchy, vcycle  # noqa: E402
 N_SOURCES = 16
 SOURCE_SEED = 4
 RTOL = 1e-6
+MAXIT = 1000
+# name: (frequency in Hz, (nx, ny, nz), output file)
+CONFIGS = {
+    "wedge10": (10.0, (129, 129, 257), "wedge_step_counts.json"),
+    "halfwedge14": (14.0, (65, 65, 129), "half_wedge_14hz_step_counts.json"),
+}
+
+
+def _workload(name):
+    freq, (nx, ny, nz), _ = CONFIGS[name]
+    return W.wedge(freq, nx, ny, nz)
 
 
 def _count(job):
-    prec, src = job
-    wl = W.wedge(10.0)
+    name, prec, src = job
+    wl = _workload(name)
     lvl = Level(wl.shape, wl.h, wl.k, wl.bc)
     if prec == "mixed":
         hier = build_hierarchy(wl.k, wl.h, wl.bc, n_levels=wl.n_levels, dtype=np.complex64)
@@ -47,21 +60,24 @@ def _count(job):
         precond = lambda r: vcycle(r, hier)  # noqa: E731
         shadow = None
     b = O.point_source_rhs(wl.shape, wl.h, [src])[0]
-    res = O.bicgstab(lambda x: O.apply_A(x, lvl), precond, b, tol=RTOL, shadow_dtype=shadow)
-    assert res.status == O.Status.OK and res.relres_true <= RTOL, (prec, src, res.status)
+    res = O.bicgstab(lambda x: O.apply_A(x, lvl), precond, b, tol=RTOL, maxit=MAXIT, shadow_dtype=shadow)
+    assert res.status == O.Status.OK and res.relres_true <= RTOL, (name, prec, src, res.status)
     return res.iterations
 
 
 def main():
-    workers = int(sys.argv[1]) if len(sys.argv) > 1 else 4
-    wl = W.wedge(10.0)
-    sources = [tuple(int(v) for v in s) for s in W.batched_wedge_sources(N_SOURCES, seed=SOURCE_SEED)]
+    name = sys.argv[1] if len(sys.argv) > 1 else "wedge10"
+    workers = int(sys.argv[2]) if len(sys.argv) > 2 else 4
+    freq, (nx, ny, _), fname = CONFIGS[name]
+    wl = _workload(name)
+    sources = [tuple(int(v) for v in s)
+               for s in W.batched_wedge_sources(N_SOURCES, seed=SOURCE_SEED, nx=nx, ny=ny)]
     single = tuple(int(v) for v in wl.sources[0])
-    jobs = [(p, s) for p in ("mixed", "fp64") for s in sources + [single]]
+    jobs = [(name, p, s) for p in ("mixed", "fp64") for s in sources + [single]]
     t0 = time.time()
     with Pool(workers) as pool:
         counts = pool.map(_count, jobs, chunksize=1)
-    out = {"problem": {"workload": "wedge", "freq": 10.0, "shape": list(wl.shape), "h": wl.h, "bc": wl.bc,
+    out = {"problem": {"workload": "wedge", "freq": freq, "shape": list(wl.shape), "h": wl.h, "bc": wl.bc,
                        "rtol": RTOL, "sources": [list(s) for s in sources], "source_seed": SOURCE_SEED,
                        "single_source": list(single)},
            "seconds": round(time.time() - t0, 1)}
@@ -69,7 +85,7 @@ def main():
     for i, prec in enumerate(("mixed", "fp64")):
         c = counts[i * n:(i + 1) * n]
         out[prec] = {"steps": c[:-1], "mean": float(np.mean(c[:-1])), "single": c[-1]}
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "wedge_step_counts.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), fname)
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")

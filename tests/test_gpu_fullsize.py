@@ -11,7 +11,7 @@
 * the same wedge with 16 seeded top-face sources, one batched mixed solve:
   every right-hand side's true residual under the oracle's operator; the mean
   step count over the 16 sources, mixed and FP64, against the oracle's
-  (tests/golden).
+  (tests/golden), here and on the half-resolution wedge at 14 Hz.
 * 513^3 cube, k = 160, 8 levels: the operator on z-slabs against the oracle,
   and the solve's true residual accumulated slab by slab with the oracle's operator.
 * V- and F-cycles on 513 x 513 planes (the cube's in-plane tiling) against
@@ -160,30 +160,34 @@ def test_wedge_batched_sixteen_sources(wedge):
     assert np.array_equal(host(x1)[0], x[5]) and st1[0].iterations == st[5].iterations
 
 
-def test_wedge_step_counts_match_oracle_on_average(wedge):
-    """Bi-CGSTAB steps to 1e-6 on the wedge, averaged over the 16 seeded
-    top-face sources (one batched solve per precision): within 5 % of the
-    oracle's averages with the same preconditioner precisions (complex128
-    V-cycle; complex64 V-cycle and shadow residual), stored by
-    tests/golden/make_wedge_step_counts.py.  The count of one source reacts
-    to roundings far below the solution's accuracy (the oracle's own counts
-    spread from 45 to 58.5 steps over these sources), so single sources are
-    not compared; a systematic loss of preconditioner accuracy moves the
-    average."""
-    wl = wedge
-    with open(os.path.join(os.path.dirname(__file__), "golden", "wedge_step_counts.json")) as f:
+@pytest.mark.parametrize("golden,freq,dims", [("wedge_step_counts.json", 10.0, (129, 129, 257)),
+                                              ("half_wedge_14hz_step_counts.json", 14.0, (65, 65, 129))])
+def test_wedge_step_counts_match_oracle_on_average(golden, freq, dims):
+    """Bi-CGSTAB steps to 1e-6 averaged over 16 seeded top-face sources (one
+    batched solve per precision): within 5 % of the oracle's averages with the
+    same preconditioner precisions (complex128 V-cycle; complex64 V-cycle and
+    shadow residual), stored by tests/golden/make_wedge_step_counts.py; on the
+    10 Hz wedge and on the half-resolution wedge at 14 Hz, whose kh of 0.55
+    costs the complex64 cycle a third more steps in the oracle.  The count of
+    one source reacts to roundings far below the solution's accuracy (the
+    oracle's own counts spread by about 7 % over the sources), so single
+    sources are not compared; a systematic loss of preconditioner accuracy
+    moves the average."""
+    wl = W.wedge(freq, *dims)
+    with open(os.path.join(os.path.dirname(__file__), "golden", golden)) as f:
         g = json.load(f)
     assert g["problem"]["shape"] == list(wl.shape) and g["problem"]["rtol"] == 1e-6
     nodes = [tuple(n) for n in g["problem"]["sources"]]
-    assert nodes == [tuple(int(v) for v in n) for n in W.batched_wedge_sources(16, seed=g["problem"]["source_seed"])]
+    assert nodes == [tuple(int(v) for v in n)
+                     for n in W.batched_wedge_sources(16, seed=g["problem"]["source_seed"], nx=dims[0], ny=dims[1])]
     for prec in ("fp64", "mixed"):
         s = _solver(wl, prec=prec, nrhs_max=16)
         s.set_model(dev(wl.k))
         s.set_point_sources(nodes)
-        _, st = s.solve(rtol=1e-6)
+        _, st = s.solve(rtol=1e-6, maxit=1000)
         assert all(t.status == "HH_OK" for t in st), [t.status for t in st]
         mean = sum(t.iterations for t in st) / len(st)
-        print(prec, "GPU mean steps", mean, "oracle", g[prec]["mean"], flush=True)
+        print(golden, prec, "GPU mean steps", mean, "oracle", g[prec]["mean"], flush=True)
         assert abs(mean - g[prec]["mean"]) <= 0.05 * g[prec]["mean"], (prec, mean, g[prec]["mean"])
         s.close()
 
