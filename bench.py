@@ -136,12 +136,12 @@ def step_bytes_per_dof(prec_idx: int) -> float:
 # (profiles/cube513_hbm_traffic.md).  Valid only for the kernel sources it was
 # measured on (kernel_source_sha); otherwise reported as null.
 TRAFFIC = {
-    ("update_xr+dots", "cube513", "mixed"): (11886.4e6, "356c4cb4ca1d1427"),
-    ("apply_A+dots", "cube513", "mixed"): (6243.2e6, "356c4cb4ca1d1427"),
-    ("mg_down_L0", "cube513", "mixed"): (2314.3e6, "356c4cb4ca1d1427"),
-    ("mg_up_L0", "cube513", "mixed"): (3227.7e6, "356c4cb4ca1d1427"),
-    ("p_update", "cube513", "mixed"): (9720.4e6, "356c4cb4ca1d1427"),
-    ("s_update+dot", "cube513", "mixed"): (7562.3e6, "356c4cb4ca1d1427"),
+    ("update_xr+dots", "cube513", "mixed"): (11886.4e6, "bdf21719b2142df3"),
+    ("apply_A+dots", "cube513", "mixed"): (6241.9e6, "bdf21719b2142df3"),
+    ("mg_down_L0", "cube513", "mixed"): (2313.0e6, "bdf21719b2142df3"),
+    ("mg_up_L0", "cube513", "mixed"): (3226.4e6, "bdf21719b2142df3"),
+    ("p_update", "cube513", "mixed"): (9720.4e6, "bdf21719b2142df3"),
+    ("s_update+dot", "cube513", "mixed"): (7562.3e6, "bdf21719b2142df3"),
 }
 
 

@@ -97,7 +97,11 @@ typedef struct {
     double relres;      /* recursive residual norm / ||b|| at exit */
     double relres_true; /* ||b - A x|| / ||b|| recomputed at exit */
     int status;         /* hh_status of this right-hand side */
-    int restarts;       /* restarts after a true-residual check missed rtol */
+    int restarts;       /* restarts of Bi-CGSTAB from the current x: after a
+                           true-residual check missed rtol (at most 5), and with
+                           option "restart_decade" each time the residual fell
+                           below another power of ten of ||b||; each costs one
+                           product with A (counted in matvecs) */
     double ms;          /* duration of the whole hh_solve call on the context stream
                            (HIP events around all of its device work), in milliseconds;
                            the same for every right-hand side of the call */
@@ -240,6 +244,13 @@ hh_status hh_set_shadow(hh_ctx* ctx, const void* P, int s);
 /* Options: "graph" (1 = replay Bi-CGSTAB steps as a captured hipGraph of one
  * even and one odd step, default 1), "check_every" (steps between host
  * convergence checks, default 4; Bi-CGSTAB rounds it up to an even number),
+ * "restart_decade" (1 = Bi-CGSTAB restarts from the current x each time the
+ * recursive residual falls below the next power of ten of ||b|| (0.1, 0.01,
+ * ...): true residual r = b - A x, shadow residual r_hat = r, fresh
+ * recurrences; the right-hand side waits for the next host check, at most
+ * check_every steps.  Default 1 in the mixed form, whose complex64
+ * preconditioner is not exactly linear: without restarts Bi-CGSTAB can stall
+ * where the FP64 solve converges.  0 = the plain method, the FP64 default),
  * "block" (threads per workgroup of the flat Krylov vector kernels: 64, 128,
  * 256, 512; default 256), "zb" (z-planes per workgroup of the operator apply and
  * the start-residual kernel, whose workgroups are 256-node x-y tiles; default 4,

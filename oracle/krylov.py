@@ -68,7 +68,8 @@ def _norm(a):
 
 
 def bicgstab(apply_A, precond, b, x0=None, tol=1e-6, maxit=1000, max_restarts=5,
-             breakdown_tol=1e-300, fixed_iterations=None, shadow_dtype=None) -> SolveResult:
+             breakdown_tol=1e-300, fixed_iterations=None, shadow_dtype=None,
+             restart_decade=False) -> SolveResult:
     """Solve A x = b.  ``apply_A`` and ``precond`` map arrays of b's shape.
 
     fixed_iterations : run exactly this many full steps with no stopping test
@@ -78,6 +79,13 @@ def bicgstab(apply_A, precond, b, x0=None, tol=1e-6, maxit=1000, max_restarts=5,
                        widened back), the shadow vector of a solve whose
                        preconditioner runs in that precision.  Bi-CGSTAB
                        admits any fixed r_hat with <r_hat, r> != 0.
+    restart_decade   : restart from the current x (true residual, new shadow
+                       residual, fresh recurrences) each time ||r|| / ||b||
+                       falls below the next power of ten (0.1, 0.01, ...),
+                       also with fixed_iterations; each restart counts one
+                       product with A.  Not part of the paper's method: the
+                       policy of the mixed form, whose rounded preconditioner
+                       is not exactly linear.
     """
     b = np.asarray(b)
     bnorm = _norm(b)
@@ -88,15 +96,27 @@ def bicgstab(apply_A, precond, b, x0=None, tol=1e-6, maxit=1000, max_restarts=5,
     iters = 0.0
     matvecs = 1                      # initial residual, paper convention
     restarts = 0
+    decades = 0
     status = Status.NOT_CONVERGED
     relres = np.inf
+    next_decade = 0.1
+    if restart_decade and x0 is not None:
+        r0 = _norm(b - apply_A(x)) / bnorm
+        while next_decade >= r0:
+            next_decade *= 0.1
     while True:
-        r = b - apply_A(x) if (x0 is not None or restarts > 0) else b.copy()
+        r = b - apply_A(x) if (x0 is not None or restarts > 0 or decades > 0) else b.copy()
         r_hat = r.copy() if shadow_dtype is None else r.astype(shadow_dtype).astype(r.dtype)
         rho_old = alpha = omega = 1.0 + 0j
         p = np.zeros_like(b)
         v = np.zeros_like(b)
         converged = False
+        decade = False
+        if decades > 0 and _norm(r) / bnorm <= tol and fixed_iterations is None:
+            # the true residual at a restart already meets the tolerance
+            relres = _norm(r) / bnorm
+            status = Status.OK
+            break
         while iters < maxit or fixed_iterations is not None:
             if fixed_iterations is not None and iters >= fixed_iterations:
                 break
@@ -142,7 +162,17 @@ def bicgstab(apply_A, precond, b, x0=None, tol=1e-6, maxit=1000, max_restarts=5,
             if abs(omega) <= breakdown_tol:
                 status = Status.BREAKDOWN
                 break
+            limit = fixed_iterations if fixed_iterations is not None else maxit
+            if restart_decade and relres <= next_decade and iters < limit:
+                while next_decade >= relres:
+                    next_decade *= 0.1
+                decade = True
+                break
             rho_old = rho
+        if decade:
+            decades += 1
+            matvecs += 1
+            continue
         if fixed_iterations is not None:
             status = Status.OK
             break

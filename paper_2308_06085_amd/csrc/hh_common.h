@@ -67,7 +67,8 @@ enum RhsStatus : int {
     ST_BREAK = 3,    // breakdown
     ST_MAXIT = 4,    // iteration limit
     ST_NUMERIC = 5,  // NaN / Inf
-    ST_IDLE = 6      // slot not in use
+    ST_IDLE = 6,     // slot not in use
+    ST_RESTART = 7   // stopped for a restart from x: the residual fell below the next power of ten
 };
 
 struct RhsState {
@@ -76,7 +77,12 @@ struct RhsState {
     // waits for the odd step that follows (pend = 1 while it is outstanding)
     c128 alpha_d, omega_d;
     double bnorm2, rnorm2, snorm2, rhat_norm2, tol2, true_rnorm2;
-    int status, iters2, maxit2, matvecs, restarts, pend;
+    // ||r||^2 at which the next restart from x is due (restarts at every power
+    // of ten of ||r|| / ||b||; 0 = none)
+    double next2;
+    // restarts: after a true-residual check missed rtol (at most 5);
+    // decades: at a power of ten of the residual
+    int status, iters2, maxit2, matvecs, restarts, pend, decades;
 };
 
 // Reduction slots (each holds `nterm` doubles per block per right-hand side).

@@ -61,7 +61,9 @@ enum FinMode : int {
     FIN_OMEGA = 4,
     FIN_TRUE = 5,
     FIN_TRUE_RECORD = 6,
-    FIN_RHO_DEFER = 7
+    FIN_RHO_DEFER = 7,
+    FIN_INIT_DECADE = 8,  // FIN_INIT with restarts from x at every power of ten of the residual
+    FIN_RESTART = 9       // restart from x the right-hand sides stopped for it (true residual in slot R)
 };
 constexpr int GATE_ALL = -1;       // act on every right-hand side
 constexpr int GATE_FINISHED = -2;  // act on right-hand sides that stopped iterating
@@ -158,10 +160,11 @@ void launch_update_xr(hipStream_t s, bool odd, long long n, int nrhs, c128* x, c
                       const cx<TH>* rhat, const RhsState* st, double* part, long long nblk_max,
                       const Launch& L);
 // x += alpha_d p_hat' + omega_d s_hat' for the stopped right-hand sides with an
-// outstanding even-step update (before the true residual of a solve)
+// outstanding even-step update (before the true residual of a solve or of a
+// restart); only >= 0 restricts it to the right-hand sides with that status
 template <typename TH>
 void launch_flush_x(hipStream_t s, long long n, int nrhs, c128* x, const cx<TH>* php, const cx<TH>* shp,
-                    const RhsState* st, const Launch& L);
+                    const RhsState* st, const Launch& L, int only = -1);
 void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const double* part,
                      long long nblk, long long nblk_max, double tol);
 

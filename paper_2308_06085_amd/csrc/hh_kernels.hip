@@ -105,6 +105,7 @@ __device__ void fin_update(int mode, RhsState& S, const double* s, double tol) {
     const int status = S.status;
     switch (mode) {
         case FIN_INIT:
+        case FIN_INIT_DECADE:
             S.bnorm2 = s[3];
             S.rnorm2 = s[0];
             S.rhat_norm2 = s[0];
@@ -118,8 +119,39 @@ __device__ void fin_update(int mode, RhsState& S, const double* s, double tol) {
             S.restarts = 0;
             S.true_rnorm2 = 0.0;
             S.pend = 0;
+            S.decades = 0;
+            // the first restart when ||r|| / ||b|| < 0.1, then below 0.01, ...
+            S.next2 = 0.0;
+            if (mode == FIN_INIT_DECADE) {
+                S.next2 = 0.01 * s[3];
+                while (S.next2 > 0.0 && S.next2 >= s[0]) S.next2 *= 0.01;
+            }
             if (!isfinite(s[0]) || !isfinite(s[3])) S.status = ST_NUMERIC;
             else if (s[3] == 0.0 || s[0] <= S.tol2) S.status = ST_CONV;
+            return;
+        case FIN_RESTART:
+            // a right-hand side stopped at a power of ten: s[0] is its true
+            // ||b - A x||^2 from the start kernel, which has also set r_hat = r
+            // and p = v = 0; the next step's rho finalize takes rho from there
+            S.true_rnorm2 = s[0];
+            S.pend = 0;  // applied by the flush before the start kernel
+            if (!isfinite(s[0])) {
+                S.status = ST_NUMERIC;
+                return;
+            }
+            S.rnorm2 = s[0];
+            if (s[0] <= S.tol2) {
+                S.status = ST_CONV;
+                return;
+            }
+            S.status = ST_RUN;
+            S.rhat_norm2 = s[0];
+            S.rho = mk(1.0, 0.0);
+            S.alpha = mk(1.0, 0.0);
+            S.omega = mk(1.0, 0.0);
+            S.beta = mk(0.0, 0.0);
+            S.matvecs += 1;
+            S.decades += 1;
             return;
         case FIN_TRUE_RECORD:
             S.true_rnorm2 = s[0];
@@ -168,6 +200,13 @@ __device__ void fin_update(int mode, RhsState& S, const double* s, double tol) {
             if (rn2 <= S.tol2) { S.status = ST_CONV; return; }
             if (abs2(S.omega) <= tiny * tiny) { S.status = ST_BREAK; return; }
             if (S.iters2 >= S.maxit2) { S.status = ST_MAXIT; return; }
+            if (rn2 <= S.next2) {
+                // restart from x, due at the next power of ten below this residual
+                S.status = ST_RESTART;
+                do S.next2 *= 0.01;
+                while (S.next2 >= rn2);
+                return;
+            }
             if (sqrt(abs2(rho_new)) <= tiny * sqrt(S.rhat_norm2) * sqrt(rn2)) { S.status = ST_BREAK; return; }
             S.beta = cdiv(rho_new, S.rho) * cdiv(S.alpha, S.omega);
             S.rho = rho_new;
@@ -215,7 +254,8 @@ __device__ __forceinline__ int fin_terms(int mode) {
         case FIN_RHO:
         case FIN_RHO_DEFER: return 3;
         case FIN_TRUE:
-        case FIN_TRUE_RECORD: return 1;
+        case FIN_TRUE_RECORD:
+        case FIN_RESTART: return 1;
         default: return 4;
     }
 }
@@ -241,6 +281,7 @@ __global__ __launch_bounds__(1024) void k_finalize(int mode, RhsState* st, const
         case FIN_TRUE_RECORD: act = status != ST_RUN && status != ST_IDLE && status != ST_HALF; break;
         case FIN_RHO:
         case FIN_RHO_DEFER: act = status == ST_RUN || status == ST_HALF; break;
+        case FIN_RESTART: act = status == ST_RESTART; break;
         default: act = status == ST_RUN; break;
     }
     if (!act) return;
@@ -607,10 +648,12 @@ __global__ __launch_bounds__(512) void k_update_xr(long long n, c128* __restrict
 template <typename TH>
 __global__ __launch_bounds__(512) void k_flush_x(long long n, c128* __restrict__ x,
                                                  const cx<TH>* __restrict__ php,
-                                                 const cx<TH>* __restrict__ shp, const RhsState* st) {
+                                                 const cx<TH>* __restrict__ shp, const RhsState* st,
+                                                 int only) {
     const int r = blockIdx.z;
     const int status = st[r].status;
     if (!st[r].pend || status == ST_RUN || status == ST_HALF || status == ST_IDLE) return;
+    if (only >= 0 && status != only) return;
     const c128 ald = st[r].alpha_d, omd = st[r].omega_d;
     const long long off = (long long)r * n;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -867,8 +910,9 @@ void launch_update_xr(hipStream_t s, bool odd, long long n, int nrhs, c128* x, c
 }
 template <typename TH>
 void launch_flush_x(hipStream_t s, long long n, int nrhs, c128* x, const cx<TH>* php, const cx<TH>* shp,
-                    const RhsState* st, const Launch& L) {
-    hipLaunchKernelGGL(k_flush_x<TH>, dim3(L.flat_cap, 1, nrhs), dim3(L.block), 0, s, n, x, php, shp, st);
+                    const RhsState* st, const Launch& L, int only) {
+    hipLaunchKernelGGL(k_flush_x<TH>, dim3(L.flat_cap, 1, nrhs), dim3(L.block), 0, s, n, x, php, shp, st,
+                       only);
 }
 template void launch_update_xr<double>(hipStream_t, bool, long long, int, c128*, c128*, const c128*,
                                        const c128*, const c128*, const c128*, const c128*, const c128*,
@@ -877,9 +921,9 @@ template void launch_update_xr<float>(hipStream_t, bool, long long, int, c128*, 
                                       const c64*, const c64*, const c128*, const c128*, const c64*,
                                       const RhsState*, double*, long long, const Launch&);
 template void launch_flush_x<double>(hipStream_t, long long, int, c128*, const c128*, const c128*,
-                                     const RhsState*, const Launch&);
+                                     const RhsState*, const Launch&, int);
 template void launch_flush_x<float>(hipStream_t, long long, int, c128*, const c64*, const c64*,
-                                    const RhsState*, const Launch&);
+                                    const RhsState*, const Launch&, int);
 void launch_finalize(hipStream_t s, int mode, int nrhs, RhsState* st, const double* part,
                      long long nblk, long long nblk_max, double tol) {
     hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(1024), 0, s, mode, st, part, nblk, nblk_max, tol);

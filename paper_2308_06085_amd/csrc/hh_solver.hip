@@ -116,6 +116,9 @@ struct hh_ctx {
     int check_every = 4;
     std::map<int, hipGraphExec_t> graphs;
     int tail_first = 0;   // first level run by the single-workgroup tail kernel
+    // Bi-CGSTAB restarts from x at every power of ten of the residual
+    // (option "restart_decade"; on by default in the mixed form)
+    int restart_decade = 0;
     int cycle = 0;        // preconditioner cycle: 0 = V-cycle, 1 = F-cycle
     // Krylov method: 0 = Bi-CGSTAB, 1 = IDR(s), 2 = full GMRES
     int method = 0;
@@ -610,16 +613,17 @@ void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs, bool odd, hipEvent_t*
         enqueue_iteration_t<double>(c, s, nrhs, odd, ph, sh, c->ph, c->sh, nullptr, nullptr, ev);
 }
 
-// The outstanding even-step updates of the right-hand sides that stopped.
-void enqueue_flush_x(hh_ctx* c, hipStream_t s, int nrhs) {
+// The outstanding even-step updates of the right-hand sides that stopped
+// (only >= 0: of those with that status).
+void enqueue_flush_x(hh_ctx* c, hipStream_t s, int nrhs, int only = -1) {
     Launch F = c->L0;
     F.flat_cap = (int)c->nblk0;
     const long long n = c->lv[0].g.n;
     if (c->mixed)
         launch_flush_x<float>(s, n, nrhs, c->xk, reinterpret_cast<const c64*>(c->ph),
-                              reinterpret_cast<const c64*>(c->sh), c->st, F);
+                              reinterpret_cast<const c64*>(c->sh), c->st, F, only);
     else
-        launch_flush_x<double>(s, n, nrhs, c->xk, c->ph, c->sh, c->st, F);
+        launch_flush_x<double>(s, n, nrhs, c->xk, c->ph, c->sh, c->st, F, only);
 }
 
 // One IDR(s) cycle (s inner steps and the reduction step) for every
@@ -1026,7 +1030,7 @@ hh_status finish_solve(hh_ctx* c, void* x, int nrhs, hipEvent_t e0, hipEvent_t e
             o.relres = S.bnorm2 > 0.0 ? std::sqrt(S.rnorm2 / S.bnorm2) : 0.0;
             o.relres_true = S.bnorm2 > 0.0 ? std::sqrt(S.true_rnorm2 / S.bnorm2) : 0.0;
             o.status = sr;
-            o.restarts = S.restarts;
+            o.restarts = S.restarts + S.decades;
             o.ms = ms;
         }
         if (worst == HH_OK && sr != HH_OK) worst = sr;
@@ -1119,6 +1123,7 @@ hh_status hh_create(const hh_config* cfg, void* hip_stream, hh_ctx** out) {
     c->cfg.n_levels = (int)shapes.size();
     c->stream = (hipStream_t)hip_stream;
     c->mixed = cfg->prec == HH_PREC_MIXED;
+    c->restart_decade = c->mixed ? 1 : 0;
     c->csize = c->mixed ? sizeof(c64) : sizeof(c128);
     c->rsize = c->mixed ? sizeof(float) : sizeof(double);
     (void)hipGetDevice(&c->device);
@@ -1368,7 +1373,8 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
     launch_fill_status(c->stream, nrhs, c->st, ST_RUN, 2 * maxit);
     launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->mixed, c->p, c->v,
                 c->k2, c->kb, use_x0, c->part, NBLK_CAP, c->st, ST_RUN);
-    launch_finalize(c->stream, FIN_INIT, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, rtol);
+    launch_finalize(c->stream, c->method == 0 && c->restart_decade ? FIN_INIT_DECADE : FIN_INIT, nrhs, c->st,
+                    c->part, c->nblk0, NBLK_CAP, rtol);
     HIPCHK(c, hipGetLastError());
     CHK(read_states(c, nrhs));
     // b = 0: the solution is x = 0
@@ -1403,6 +1409,19 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
     };
     int guard = 0;
     while (true) {
+        bool any_restart = false;
+        for (int r = 0; r < nrhs; ++r) any_restart |= c->st_host[r].status == ST_RESTART;
+        if (any_restart) {
+            // right-hand sides whose residual fell below the next power of ten:
+            // their outstanding x update, then r = b - A x, r_hat = r, p = v = 0,
+            // and a fresh start of the recurrences (the others wait unchanged)
+            enqueue_flush_x(c, c->stream, nrhs, ST_RESTART);
+            launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->mixed, c->p,
+                        c->v, c->k2, c->kb, 1, c->part, NBLK_CAP, c->st, ST_RESTART);
+            launch_finalize(c->stream, FIN_RESTART, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, rtol);
+            HIPCHK(c, hipGetLastError());
+            CHK(read_states(c, nrhs));
+        }
         bool any_run = false, any_half = false;
         for (int r = 0; r < nrhs; ++r) {
             any_run |= c->st_host[r].status == ST_RUN;
@@ -1490,6 +1509,9 @@ hh_status hh_set_option(hh_ctx* c, const char* name, long long value) {
     } else if (n == "check_every") {
         if (value < 1 || value > 1000) return fail(c, HH_ERR_ARG, "check_every must be in 1..1000");
         c->check_every = (int)value;
+    } else if (n == "restart_decade") {
+        if (value != 0 && value != 1) return fail(c, HH_ERR_ARG, "restart_decade must be 0 or 1");
+        c->restart_decade = (int)value;
     } else if (n == "trace") {
         c->trace = value != 0;
         for (int k = 0; k < NTRACE_KERNEL; ++k) {
@@ -1643,6 +1665,7 @@ hh_status hh_get_option(const hh_ctx* c, const char* name, long long* value) {
     }
     else if (n == "tail_first") *value = c->tail_first;
     else if (n == "check_every") *value = c->check_every;
+    else if (n == "restart_decade") *value = c->restart_decade;
     else if (n == "trace") *value = c->trace;
     else if (n == "cycle") *value = c->cycle;
     else if (n == "method") *value = c->method;

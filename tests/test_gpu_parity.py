@@ -294,13 +294,20 @@ def test_check_window_does_not_change_the_solution(prec):
     s.close()
 
 
-@pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
-@pytest.mark.parametrize("steps", [1, 2, 5])
-def test_fixed_iteration_iterates_mixed(bc, steps):
+@pytest.mark.parametrize("bc,steps,restart",
+                         [(bc, st, rs) for bc in (SOMMERFELD, DIRICHLET) for st in (1, 2, 5) for rs in (0, 1)]
+                         + [(SOMMERFELD, 9, 1)])
+def test_fixed_iteration_iterates_mixed(bc, steps, restart):
     """The mixed solve (complex64 V-cycle and shadow residual r_hat = r_0
     rounded to complex64, complex128 Krylov vectors) against the oracle's
     Bi-CGSTAB with the same precisions: fixed-step iterates agree to the
-    complex64 V-cycle's tolerance."""
+    complex64 V-cycle's tolerance, with and without the restarts from x at
+    every power of ten of the residual (the mixed form's default).  With
+    Sommerfeld boundaries the residual passes 0.1 after step 2 and 0.01 after
+    step 7, so 5 and 9 steps include one and two restarts.  Without restarts
+    the iterates grow sensitive to the rounding of the preconditioner beyond
+    about six steps here (a relative change of 1e-7 in its output moves the
+    9-step iterate by 1e-4 in the oracle, by 3e-8 with restarts)."""
     shape = (17, 17, 33)
     h = 1 / 16
     k = hetero_k(shape, 11, 6.0, 14.0)
@@ -310,8 +317,10 @@ def test_fixed_iteration_iterates_mixed(bc, steps):
     h32 = build_hierarchy(k, h, bc, dtype=np.complex64)
     ref = O.bicgstab(lambda v: O.apply_A(v, lvl),
                      lambda v: vcycle(v.astype(np.complex64), h32).astype(np.complex128), b,
-                     fixed_iterations=steps, shadow_dtype=np.complex64)
+                     fixed_iterations=steps, shadow_dtype=np.complex64, restart_decade=bool(restart))
     s = _solver(shape, h, bc, prec="mixed")
+    assert s.get_option("restart_decade") == 1
+    s.set_option("restart_decade", restart)
     s.set_model(dev(k))
     s.set_point_sources(src)
     x, st = s.solve(rtol=1e-14, maxit=steps)
@@ -423,21 +432,29 @@ def test_graph_and_direct_launch_bitwise_and_repeatable():
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_traced_solve_bitwise_and_kernel_times(prec):
     """The event-traced solve runs the same kernels as the graph replay (same
-    result bit for bit) and times every fine-level launch of the full windows."""
+    result bit for bit, also with the mixed form's restarts from x) and times
+    every fine-level launch of the full windows (counted here without
+    restarts, whose windows a right-hand side leaves early)."""
     wl = W.wedge(10.0, 17, 17, 33)
     nodes = [(0, 8, 8), (0, 4, 12)]
     s = _solver(wl.shape, wl.h, SOMMERFELD, prec=prec, nrhs_max=2)
     s.set_model(dev(wl.k))
     s.set_point_sources(nodes)
-    x1, st1 = s.solve(rtol=1e-8)
-    x1 = host(x1)
-    s.set_option("trace", 1)
-    x2, st2 = s.solve(rtol=1e-8)
-    x2 = host(x2)
-    ms, n = s.kernel_times()
-    s.set_option("trace", 0)
-    assert np.array_equal(x1, x2)
-    assert [a.iterations for a in st1] == [b.iterations for b in st2]
+    for restart in ((1, 0) if prec == "mixed" else (0,)):
+        s.set_option("restart_decade", restart)
+        s.set_option("trace", 0)
+        x1, st1 = s.solve(rtol=1e-8)
+        x1 = host(x1)
+        s.set_option("trace", 1)
+        x2, st2 = s.solve(rtol=1e-8)
+        x2 = host(x2)
+        ms, n = s.kernel_times()
+        s.set_option("trace", 0)
+        assert np.array_equal(x1, x2), restart
+        assert [a.iterations for a in st1] == [b.iterations for b in st2]
+        assert [a.restarts for a in st1] == [b.restarts for b in st2]
+        if restart:
+            assert min(a.restarts for a in st1) >= 5
     # full windows: every right-hand side iterating; 4 steps per window
     steps = 4 * (int(min(a.iterations for a in st1)) // 4 - 1)
     assert steps > 0

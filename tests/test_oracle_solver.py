@@ -158,6 +158,69 @@ def test_sommerfeld_solution_is_an_outgoing_spherical_wave():
     assert 0.6 < amp_ratio < 1.6, amp_ratio
 
 
+def _restart_steps(history, n_steps):
+    """Full steps after which a restart at every power of ten of ||r|| / ||b||
+    falls due: step k (1-based) when history[k - 1] is below the next power
+    of ten, which then moves below that residual."""
+    steps, nxt = [], 0.1
+    for k, rel in enumerate(history[:n_steps], start=1):
+        if rel <= nxt and k < n_steps:
+            steps.append(k)
+            while nxt >= rel:
+                nxt *= 0.1
+    return steps
+
+
+@pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
+def test_decade_restarts_match_scipy_restarted_by_hand(bc):
+    """Bi-CGSTAB with restarts from x at every power of ten of the residual
+    (the mixed form's policy) equals scipy's bicgstab run in segments, each
+    started from the previous segment's x: a restart is the method started
+    afresh from the current iterate (r = b - A x, r_hat = r).  Also: without
+    a power of ten crossed the restart option changes nothing, and a restarted
+    solve still reaches the dense direct solution."""
+    lvl, hier, b = _problem(17, bc, kmax=12.0 if bc == SOMMERFELD else 5.0)
+    n = b.size
+    A = LinearOperator((n, n), matvec=lambda v: O.apply_A(v.reshape(lvl.shape), lvl).ravel(),
+                       dtype=np.complex128)
+    M = LinearOperator((n, n), matvec=lambda v: vcycle(v.reshape(lvl.shape), hier).ravel(),
+                       dtype=np.complex128)
+    N = 12
+    ours = O.bicgstab(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b,
+                      fixed_iterations=N, restart_decade=True)
+    cuts = _restart_steps(ours.history, N)
+    assert len(cuts) >= 2, ours.history          # the comparison crosses two restarts
+    assert ours.matvecs == 1 + 2 * N + len(cuts)  # one product with A per restart
+    x = np.zeros(n, dtype=np.complex128)
+    done = 0
+    for k in cuts + [N]:
+        x, _ = scipy_bicgstab(A, b.ravel(), x0=x, M=M, maxiter=k - done, rtol=1e-300, atol=0.0)
+        done = k
+    err = np.linalg.norm(ours.x.ravel() - x) / np.linalg.norm(x)
+    assert err <= 1e-10, (cuts, err)
+    # a tolerance above 0.1 is met before any power of ten is crossed
+    a = O.bicgstab(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, tol=0.5)
+    r = O.bicgstab(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, tol=0.5, restart_decade=True)
+    assert np.array_equal(a.x, r.x) and a.matvecs == r.matvecs
+
+
+@pytest.mark.parametrize("bc", [SOMMERFELD, DIRICHLET])
+def test_decade_restarted_solution_matches_dense_direct_solve(bc):
+    lvl, hier, b = _problem(9, bc, seed=1, kmax=9.0)
+    mask = unknown_mask(lvl.shape, bc)
+    idx = np.flatnonzero(mask.ravel())
+    cols = []
+    for j in idx:
+        e = np.zeros(lvl.shape, dtype=np.complex128)
+        e.ravel()[j] = 1
+        cols.append(O.apply_A(e, lvl).ravel()[idx])
+    x_direct = np.linalg.solve(np.array(cols).T, b.ravel()[idx])
+    res = O.bicgstab(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), b, tol=1e-12, restart_decade=True)
+    assert res.status == O.Status.OK and res.relres_true <= 1e-12
+    err = np.linalg.norm(res.x.ravel()[idx] - x_direct) / np.linalg.norm(x_direct)
+    assert err <= 1e-9, err
+
+
 def test_bicgstab_zero_rhs_and_maxit_status():
     lvl, hier, b = _problem(9, SOMMERFELD, seed=2)
     res = O.bicgstab(lambda x: O.apply_A(x, lvl), lambda r: vcycle(r, hier), np.zeros_like(b))
