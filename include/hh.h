@@ -247,8 +247,9 @@ hh_status hh_set_shadow(hh_ctx* ctx, const void* P, int s);
  * "restart_decade" (1 = Bi-CGSTAB restarts from the current x each time the
  * recursive residual falls below the next power of ten of ||b|| (0.1, 0.01,
  * ...): true residual r = b - A x, shadow residual r_hat = r, fresh
- * recurrences; the right-hand side waits for the next host check, at most
- * check_every steps.  Default 1 in the mixed form, whose complex64
+ * recurrences, one product with A; the restart runs before the next even
+ * step, so the right-hand side idles for one or two steps.  Default 1 in the
+ * mixed form, whose complex64
  * preconditioner is not exactly linear: without restarts Bi-CGSTAB can stall
  * where the FP64 solve converges.  0 = the plain method, the FP64 default),
  * "block" (threads per workgroup of the flat Krylov vector kernels: 64, 128,

@@ -602,7 +602,13 @@ void enqueue_iteration_t(hh_ctx* c, hipStream_t s, int nrhs, bool odd, cx<TH>* p
 // x += alpha p_hat in the x / r update and is marked converged by the next FIN_RHO.
 // Steps alternate between even (odd = false: p_hat, s_hat in ph, sh; x not
 // touched) and odd (p_hat, s_hat in ph2, sh2; x gets both steps' updates).
+void enqueue_restart(hh_ctx* c, hipStream_t s, int nrhs);
+
 void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs, bool odd, hipEvent_t* ev = nullptr) {
+    // a right-hand side that stopped for a restart resumes before the next even
+    // step, so every restart is followed by the same even/odd grouping of the
+    // solution updates wherever the host checks fall
+    if (!odd && c->restart_decade) enqueue_restart(c, s, nrhs);
     c128* ph = odd ? c->ph2 : c->ph;
     c128* sh = odd ? c->sh2 : c->sh;
     if (c->mixed)
@@ -624,6 +630,16 @@ void enqueue_flush_x(hh_ctx* c, hipStream_t s, int nrhs, int only = -1) {
                               reinterpret_cast<const c64*>(c->sh), c->st, F, only);
     else
         launch_flush_x<double>(s, n, nrhs, c->xk, c->ph, c->sh, c->st, F, only);
+}
+
+// Restart from x of the right-hand sides stopped for it (status ST_RESTART):
+// their outstanding x update, then r = b - A x, r_hat = r, p = v = 0 and fresh
+// recurrences; the others are untouched.
+void enqueue_restart(hh_ctx* c, hipStream_t s, int nrhs) {
+    enqueue_flush_x(c, s, nrhs, ST_RESTART);
+    launch_init(s, c->cfg.bc, c->lv[0].g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->mixed, c->p, c->v,
+                c->k2, c->kb, 1, c->part, NBLK_CAP, c->st, ST_RESTART);
+    launch_finalize(s, FIN_RESTART, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, 0.0);
 }
 
 // One IDR(s) cycle (s inner steps and the reduction step) for every
@@ -1412,13 +1428,10 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
         bool any_restart = false;
         for (int r = 0; r < nrhs; ++r) any_restart |= c->st_host[r].status == ST_RESTART;
         if (any_restart) {
-            // right-hand sides whose residual fell below the next power of ten:
-            // their outstanding x update, then r = b - A x, r_hat = r, p = v = 0,
-            // and a fresh start of the recurrences (the others wait unchanged)
-            enqueue_flush_x(c, c->stream, nrhs, ST_RESTART);
-            launch_init(c->stream, c->cfg.bc, g, c->L0, nrhs, c->bsrc, c->xk, c->r, c->rhat, c->mixed, c->p,
-                        c->v, c->k2, c->kb, 1, c->part, NBLK_CAP, c->st, ST_RESTART);
-            launch_finalize(c->stream, FIN_RESTART, nrhs, c->st, c->part, c->nblk0, NBLK_CAP, rtol);
+            // right-hand sides whose residual fell below the next power of ten
+            // in the last step of a window (the steps restart the others
+            // themselves, before their next even step)
+            enqueue_restart(c, c->stream, nrhs);
             HIPCHK(c, hipGetLastError());
             CHK(read_states(c, nrhs));
         }
@@ -1511,6 +1524,7 @@ hh_status hh_set_option(hh_ctx* c, const char* name, long long value) {
         c->check_every = (int)value;
     } else if (n == "restart_decade") {
         if (value != 0 && value != 1) return fail(c, HH_ERR_ARG, "restart_decade must be 0 or 1");
+        if ((int)value != c->restart_decade) invalidate_graphs(c);  // the even step holds the restart kernels
         c->restart_decade = (int)value;
     } else if (n == "trace") {
         c->trace = value != 0;
