@@ -1442,6 +1442,11 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
         }
         if (any_run) {
             const bool full_before = all_running();
+            // half steps done before the window: a window counts for the trace
+            // only if every right-hand side advanced through all of its steps
+            // (none stopped for a restart inside it and resumed)
+            std::vector<int> iters_before(nrhs);
+            for (int r = 0; r < nrhs; ++r) iters_before[r] = c->st_host[r].iters2;
             if (exec) {
                 for (int k = 0; k < pairs; ++k) HIPCHK(c, hipGraphLaunch(exec, c->stream));
             } else {
@@ -1450,7 +1455,9 @@ hh_status hh_solve(hh_ctx* c, void* x, double rtol, int maxit, int use_x0, hh_st
             }
             HIPCHK(c, hipGetLastError());
             CHK(read_states(c, nrhs));
-            if (c->trace && full_before && all_running()) {
+            bool full = full_before && all_running();
+            for (int r = 0; r < nrhs && full; ++r) full = c->st_host[r].iters2 - iters_before[r] == 2 * window;
+            if (c->trace && full) {
                 // every right-hand side iterated through the whole window: each
                 // traced launch did its full work
                 for (int k = 0; k < window; ++k)
