@@ -318,9 +318,10 @@ hh_status hh_time_kernel(hh_ctx* ctx, int which, int nrhs, int reps, float* ms_a
  * (no graph replay) with HIP events on the context stream around the
  * fine-level kernels of each step that runs; "trace" 0 returns to graph
  * replay.  Only check windows (check_every steps rounded up to an even
- * number) through which every
- * right-hand side kept iterating are counted, so each counted launch did the
- * full work of all right-hand sides.  hh_kernel_times returns, per kernel id
+ * number) through which every right-hand side kept iterating and advanced by
+ * every step are counted (not one with a restart inside, see
+ * "restart_decade"), so each counted launch did the full work of all
+ * right-hand sides.  hh_kernel_times returns, per kernel id
  * of hh_time_kernel (0 = the operator apply with its dot products, both
  * launches of a step; 1 = x / r update, even and odd steps alike; 2 / 3 = finest-level multigrid
  * down / up pass, both V-cycles; 4 = p update; 5 = s update) and id 6 (an
