@@ -597,13 +597,13 @@ void enqueue_iteration_t(hh_ctx* c, hipStream_t s, int nrhs, bool odd, cx<TH>* p
     mark(TL_UPDATE_XR, 1);
 }
 
+void enqueue_restart(hh_ctx* c, hipStream_t s, int nrhs);
+
 // One Bi-CGSTAB step for all right-hand sides still iterating (device-side
 // scalars).  A right-hand side that meets the tolerance at the half step gets
 // x += alpha p_hat in the x / r update and is marked converged by the next FIN_RHO.
 // Steps alternate between even (odd = false: p_hat, s_hat in ph, sh; x not
 // touched) and odd (p_hat, s_hat in ph2, sh2; x gets both steps' updates).
-void enqueue_restart(hh_ctx* c, hipStream_t s, int nrhs);
-
 void enqueue_iteration(hh_ctx* c, hipStream_t s, int nrhs, bool odd, hipEvent_t* ev = nullptr) {
     // a right-hand side that stopped for a restart resumes before the next even
     // step, so every restart is followed by the same even/odd grouping of the
