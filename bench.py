@@ -606,7 +606,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "unknowns": dof(wl), "nrhs": nrhs, "rtol": 1e-6,
                    "precision": "mixed", "cycle": args.cycle,
-                   "method": {"idrs": "IDR(4)", "gmres": "GMRES"}.get(args.method, "Bi-CGSTAB")},
+                   "method": {"idrs": "IDR(4)", "gmres": "GMRES"}.get(args.method, "Bi-CGSTAB"),
+                   # the library's default for the mixed form: Bi-CGSTAB restarts from x
+                   # each time the residual falls below another power of ten
+                   "mixed_bicgstab_restarts": "at every power of ten of the residual"
+                   if args.method == "bicgstab" else "none"},
         "iterations": head["iterations"],
         "relres_true_max": head["relres_true_max"],
         "hbm_per_iteration": head["hbm_per_iteration"],
